@@ -1,0 +1,202 @@
+/*
+ * amrmg.h -- C ABI of the MI355X (gfx950) composite-grid AMR multigrid
+ * Poisson path for electrostatic particle-in-cell, after Frey, Adelmann &
+ * Locans, "On Architecture and Performance of Adaptive Mesh Refinement in an
+ * Electrostatics Particle-In-Cell Code" (arXiv:1812.03689).
+ *
+ * The path (the space-charge workflow of Fig. 2 of the paper, without the
+ * frame transforms): cloud-in-cell charge deposition -> charge tagging and
+ * box generation (Sec. 4.1) -> composite AMR multigrid solve of
+ * L_comp phi = -rho / eps0 (Sec. 5.4, Alg. 1-3) -> E = -grad phi (Alg. 2) ->
+ * interpolation of E to the particles.
+ *
+ * Conventions shared by every call:
+ *   - Domain [lo, hi) with n0 cells per axis on level 0; refinement ratio 2
+ *     (Eq. mesh_spacing with r = 2); cell-centred data (Sec. 3).
+ *   - A level is a list of disjoint boxes [lo, hi) (hi exclusive) in that
+ *     level's index space, every edge a multiple of the blocking factor 8.
+ *     Level 0 is one box covering the domain.
+ *   - Level arrays ("user layout") concatenate the boxes in box-list order;
+ *     each box is stored x-fastest: cell (i,j,k) of box b sits at
+ *     offsets[b] + (i-lo_x) + nx*((j-lo_y) + ny*(k-lo_z)).
+ *   - All particle and field arrays are DEVICE memory owned by the caller;
+ *     the library never frees them.  Host arrays are marked "host".
+ *   - Every call enqueues on the stream given to amrmg_create.  deposit and
+ *     gather are asynchronous; build_hierarchy, hierarchy_info and solve
+ *     synchronise the stream.
+ *   - Calls return an amrmg_status; no exception crosses the ABI.  On error
+ *     amrmg_last_error() returns a thread-local message.  A context is not
+ *     thread-safe.
+ */
+#ifndef AMRMG_H
+#define AMRMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amrmg_ctx amrmg_ctx;
+
+typedef enum {
+    AMRMG_OK = 0,
+    AMRMG_E_INVALID = -1,         /* bad argument or parameter */
+    AMRMG_E_HIP = -2,             /* a HIP runtime call failed */
+    AMRMG_E_NOT_CONVERGED = -3,   /* max_iters reached; phi, E and stats are still written */
+    AMRMG_E_NESTING = -4,         /* explicit boxes violate alignment or proper nesting */
+    AMRMG_E_OOM = -5,             /* device allocation failed or workspace too small */
+    AMRMG_E_STATE = -6,           /* call out of order (e.g. solve before build_hierarchy) */
+    AMRMG_E_NOT_IMPLEMENTED = -7
+} amrmg_status;
+
+enum { AMRMG_POS_F64 = 0, AMRMG_POS_F32 = 1 };
+enum { AMRMG_FP64 = 0, AMRMG_MIXED = 1 };
+enum { AMRMG_GSRB = 0, AMRMG_JACOBI = 1 };
+enum { AMRMG_MAX_LEVELS = 8 };
+
+/* Solver and hierarchy parameters.  amrmg_default_params fills the defaults
+ * named in brackets. */
+typedef struct amrmg_params {
+    double lo[3], hi[3];        /* domain [0,0,0]-[1,1,1] */
+    int32_t n0[3];              /* level-0 cells per axis, multiples of 8 [32] */
+    int32_t max_level;          /* finest level index allowed, 0..7 [2] */
+    int32_t ref_ratio;          /* must be 2 [2] */
+    int32_t blocking_factor;    /* must be 8 [8] */
+    int32_t max_grid_size;      /* max box edge on refined levels, multiple of 8 [32] */
+    int32_t n_buffer;           /* tag dilation in cells [1] */
+    int32_t n_proper;           /* proper-nesting margin in coarse cells [2] */
+    double eps0;                /* vacuum permittivity [1] */
+    int32_t n_monopoles;        /* Dirichlet data g(x) = sum q/(4 pi eps0 |x-x_k|); 0 -> g = 0 */
+    const double *monopoles;    /* host [n_monopoles][4] = q, x, y, z; copied by amrmg_create */
+    int32_t precision;          /* AMRMG_FP64 or AMRMG_MIXED [MIXED] */
+    int32_t smoother;           /* AMRMG_GSRB or AMRMG_JACOBI [GSRB] */
+    int32_t nu1, nu2;           /* pre / post smoothing sweeps [2, 2] */
+    double omega;               /* damped-Jacobi weight [6/7] */
+    int32_t norm_p;             /* residual norm: 1, 2, or 0 for max-norm [2] */
+    int32_t max_iters;          /* V-cycle cap i_max [50] */
+    double bottom_rtol;         /* CG tolerance on the coarsest grid [1e-6] */
+} amrmg_params;
+
+/* Per-solve statistics. */
+typedef struct amrmg_solve_stats {
+    int32_t iters;              /* V-cycles performed */
+    int32_t converged;          /* 1 when every level met the tolerance */
+    int32_t nlevels;
+    int32_t bottom_iters_max;   /* largest CG iteration count of one bottom solve */
+    double rel_residual[AMRMG_MAX_LEVELS]; /* final ||r^l||_p / ||b^l||_p */
+    double time_ms;             /* device time from the first kernel to the last (events) */
+    int64_t dof;                /* composite cells: sum over levels of uncovered cells */
+} amrmg_solve_stats;
+
+void amrmg_default_params(amrmg_params *p);
+
+/* Create a context bound to a HIP stream (NULL = the null stream).
+ * The parameters are validated and copied; *out receives the context. */
+amrmg_status amrmg_create(const amrmg_params *p, void *hip_stream, amrmg_ctx **out);
+void amrmg_destroy(amrmg_ctx *ctx);
+const char *amrmg_last_error(void);
+
+/* Build the level hierarchy (Sec. 3 and Sec. 4.1 of the paper).  For each
+ * level l < max_level in turn: deposit the particles on level l, tag the
+ * cells with |rho^l| > tag_rel[l] * max|rho^l|, dilate the tags by n_buffer
+ * cells, group them into 8-cell blocks of level l+1, drop blocks that break
+ * proper nesting, and merge the blocks greedily (x, then y, then z, at most
+ * max_grid_size cells per edge) into the boxes of level l+1.  The procedure is
+ * pure integer work after the tagging compare and is fully specified, so box
+ * lists are reproducible bit for bit.
+ *   pos_dtype      AMRMG_POS_F64 or AMRMG_POS_F32 (x, y, z device arrays of n)
+ *   q              device [n] charges (FP64)
+ *   tag_rel        host [max_level] relative thresholds (may be NULL when
+ *                  every refined level is given explicitly)
+ *   explicit_boxes host [n_explicit][7] = level, lo[3], hi[3] (level index
+ *                  space, hi exclusive) or NULL; a level with explicit boxes
+ *                  is not tagged.  Misaligned or badly nested boxes return
+ *                  AMRMG_E_NESTING.
+ * Levels with no tagged block end the hierarchy early.  Synchronises. */
+amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y,
+                                   const void *z, const double *q, int64_t n, const double *tag_rel,
+                                   const int32_t *explicit_boxes, int32_t n_explicit);
+
+/* Sizes of the built hierarchy: host outputs, arrays of at least
+ * AMRMG_MAX_LEVELS entries (any pointer may be NULL). */
+amrmg_status amrmg_hierarchy_info(const amrmg_ctx *ctx, int32_t *nlevels, int32_t *nboxes,
+                                  int64_t *ncells, int64_t *ndof);
+
+/* Box list of one level: host boxes[nb][6] = lo[3], hi[3] and offsets[nb+1]
+ * (cells, exclusive prefix sums of the box volumes). */
+amrmg_status amrmg_get_boxes(const amrmg_ctx *ctx, int32_t level, int32_t *boxes, int64_t *offsets);
+
+/* Coarse-fine ghost faces of a refined level: for every fine cell face that
+ * lies on the coarse-fine interface, host out[m][6] = i, j, k (fine cell,
+ * level index space), d (normal axis 0..2), s (-1 or +1, side of the face),
+ * pattern id (0..8: the quadratic windows of Tab. bit_pattern in the printed
+ * order of selection; 9..12: the bilinear windows of the following table;
+ * 13: centre value only).  cap bounds the rows written; *count receives the
+ * total number of such faces. */
+amrmg_status amrmg_cf_faces(const amrmg_ctx *ctx, int32_t level, int32_t *out, int64_t cap,
+                            int64_t *count);
+
+/* Device workspace for solve: the size needed for the current hierarchy and
+ * precision, and an optional caller-owned buffer (device, >= that size,
+ * 256-byte aligned) that the context then uses instead of allocating its own.
+ * Passing NULL returns to library-owned memory. */
+amrmg_status amrmg_workspace_size(const amrmg_ctx *ctx, size_t *bytes);
+amrmg_status amrmg_set_workspace(amrmg_ctx *ctx, void *dev, size_t bytes);
+
+/* Cloud-in-cell deposit on every level: rho[l] (device, user layout of level
+ * l, overwritten) receives sum_p q_p W(x_p - x_i) / (h_x h_y h_z) with the
+ * tensor-product linear (CIC) weights in FP64 (FP32 positions are promoted
+ * first).  Stencil indices are clamped to the level's index space; stencil
+ * cells outside the level's boxes receive nothing.  Particles outside
+ * [lo, hi) are skipped and counted in *n_outside (host, may be NULL; reading
+ * it synchronises).  Accumulation uses FP64 atomics, so the rounding order
+ * varies run to run. */
+amrmg_status amrmg_deposit(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y,
+                           const void *z, const double *q, int64_t n, double *const *rho,
+                           int64_t *n_outside);
+
+/* Solve the composite problem (Alg. 2 of the paper): A_comp phi = rho/eps0
+ * with A = -Laplacian discretised by flux differencing with flux matching at
+ * coarse-fine faces (Eqs. lap_flux_differencing, coarse_fluxes,
+ * flux_differencing), quadratic two-step Lagrange ghosts (Eq. 2d_lagrange,
+ * Tab. bit_pattern) and the Dirichlet data through a linear ghost
+ * 2 g - phi_in.  V-cycles (Alg. 3) run until ||r^l||_p <= tol ||b^l||_p on
+ * every level, b^l being the uncovered right-hand side including the
+ * Dirichlet data, or until max_iters.  In AMRMG_MIXED the cycle works in
+ * FP32 on the correction equation of an FP64 outer residual (iterative
+ * refinement).  Afterwards phi is averaged down onto covered cells and, if
+ * E != NULL, E[3*l + d] = -(phi_{+} - phi_{-}) / (2 h_d) on every cell.
+ *   rho  device [L] user-layout charge density (read)
+ *   phi  device [L] user layout: initial guess in, solution out
+ *   E    device [3L] or NULL
+ *   stats host, may be NULL.  Synchronises. */
+amrmg_status amrmg_solve(amrmg_ctx *ctx, double *const *rho, double *const *phi, double *const *E,
+                         double tol, amrmg_solve_stats *stats);
+
+/* Interpolate E to particles with the deposit's CIC weights, on the finest
+ * level whose boxes hold all 8 stencil cells.  Ex, Ey, Ez device [n];
+ * particles outside the domain get 0. */
+amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y,
+                          const void *z, int64_t n, double *const *E, double *Ex, double *Ey,
+                          double *Ez);
+
+/* The FP64 composite residual of Alg. 1 on every level for given rho and phi:
+ * r[l] = U^l (rho^l/eps0 - A_comp phi) (user layout, device, zero on covered
+ * cells).  Diagnostic entry point; it runs the same kernels as the solve's
+ * outer residual. */
+amrmg_status amrmg_residual(amrmg_ctx *ctx, double *const *rho, double *const *phi, double *const *r);
+
+/* Solve nb independent problems, each with its own context and hierarchy, as
+ * one batch: every kernel of the cycle runs once over the bricks of all
+ * problems.  All contexts must share stream, precision and smoother
+ * settings.  rho[i], phi[i] as in amrmg_solve; stats host [nb] or NULL. */
+amrmg_status amrmg_solve_batch(amrmg_ctx *const *ctxs, int32_t nb, double *const *const *rho,
+                               double *const *const *phi, double tol, amrmg_solve_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMRMG_H */

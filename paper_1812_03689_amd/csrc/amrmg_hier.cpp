@@ -1,0 +1,539 @@
+// amrmg_hier.cpp -- host-side hierarchy construction of libamrmg.
+//
+// Box generation: the paper leaves box generation to its AMR library (Sec.
+// 3, Sec. 4.1).  Here it is a fixed integer procedure on 8-cell blocks of the
+// finer level: tag dilation, block marking, proper nesting, greedy merge.
+//
+// Coarse-fine metadata follows Sec. 5.1 of the paper: for each fine brick face
+// on the coarse-fine interface, each of the 16 coarse cells of the coarse
+// layer across it gets the 5x5 availability mask of its layer (bit i + 5 j,
+// set when the coarse cell exists and is not covered), the first window of
+// Tab. bit_pattern that fits (or a bilinear window of the following table, or
+// the centre alone), and the coarse cells of that window.
+#include "amrmg_hier.hpp"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+
+namespace amrmg {
+
+static const double kPi = 3.14159265358979323846;
+
+int HostLevel::brick_at(int bx, int by, int bz) const
+{
+    if (bx < 0 || by < 0 || bz < 0 || bx >= nbk[0] || by >= nbk[1] || bz >= nbk[2]) return -1;
+    return bmap[(size_t)bx + (size_t)nbk[0] * ((size_t)by + (size_t)nbk[1] * (size_t)bz)];
+}
+
+bool HostLevel::has_cell(int i, int j, int k) const
+{
+    if (i < 0 || j < 0 || k < 0 || i >= n[0] || j >= n[1] || k >= n[2]) return false;
+    return brick_at(i >> 3, j >> 3, k >> 3) >= 0;
+}
+
+void level_init(HostLevel &L, const int n[3], const double lo[3], const double hi[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        L.n[d] = n[d];
+        L.h[d] = (hi[d] - lo[d]) / n[d];
+        L.nbk[d] = n[d] / 8;
+    }
+}
+
+void level_set_boxes(HostLevel &L, const std::vector<Box> &boxes)
+{
+    L.boxes = boxes;
+    L.off.assign(boxes.size() + 1, 0);
+    L.bmap.assign((size_t)L.nbk[0] * L.nbk[1] * L.nbk[2], -1);
+    L.bpos.clear();
+    L.bbox.clear();
+    for (size_t b = 0; b < boxes.size(); ++b) {
+        const Box &B = boxes[b];
+        L.off[b + 1] = L.off[b] + B.volume();
+        for (int bz = B.lo[2] / 8; bz < B.hi[2] / 8; ++bz)
+            for (int by = B.lo[1] / 8; by < B.hi[1] / 8; ++by)
+                for (int bx = B.lo[0] / 8; bx < B.hi[0] / 8; ++bx) {
+                    L.bmap[(size_t)bx + (size_t)L.nbk[0] * ((size_t)by + (size_t)L.nbk[1] * bz)] =
+                        (int32_t)L.bbox.size();
+                    L.bpos.push_back(bx);
+                    L.bpos.push_back(by);
+                    L.bpos.push_back(bz);
+                    L.bbox.push_back((int32_t)b);
+                }
+    }
+}
+
+// every cell of the axis-aligned cell box [lo, hi) belongs to level L
+static bool region_inside(const HostLevel &L, const int lo[3], const int hi[3])
+{
+    for (int bz = lo[2] >> 3; bz <= (hi[2] - 1) >> 3; ++bz)
+        for (int by = lo[1] >> 3; by <= (hi[1] - 1) >> 3; ++by)
+            for (int bx = lo[0] >> 3; bx <= (hi[0] - 1) >> 3; ++bx)
+                if (L.brick_at(bx, by, bz) < 0) return false;
+    return true;
+}
+
+// coarse footprint of fine block (bx,by,bz), grown by np cells and clipped to
+// the coarse index space
+static void grown_footprint(const HostLevel &C, const int blk[3], int half, int np, int lo[3], int hi[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = std::max(0, blk[d] * half - np);
+        hi[d] = std::min(C.n[d], (blk[d] + 1) * half + np);
+    }
+}
+
+std::vector<Box> generate_boxes(const HostLevel &L, const uint8_t *tags, int n_buffer, int n_proper, int bf,
+                                int max_grid_size)
+{
+    const int half = bf / 2;  // coarse cells per fine block edge
+    int g[3];
+    for (int d = 0; d < 3; ++d) g[d] = 2 * L.n[d] / bf;
+    auto at = [&](int x, int y, int z) { return (size_t)x + (size_t)g[0] * ((size_t)y + (size_t)g[1] * z); };
+    std::vector<uint8_t> mark((size_t)g[0] * g[1] * g[2], 0);
+
+    // 1-2: dilated tags -> blocks of the finer level
+    for (size_t b = 0; b < L.boxes.size(); ++b) {
+        const Box &B = L.boxes[b];
+        int64_t t = L.off[b];
+        for (int k = B.lo[2]; k < B.hi[2]; ++k)
+            for (int j = B.lo[1]; j < B.hi[1]; ++j)
+                for (int i = B.lo[0]; i < B.hi[0]; ++i, ++t) {
+                    if (!tags[t]) continue;
+                    int zlo = std::max(0, k - n_buffer), zhi = std::min(L.n[2] - 1, k + n_buffer);
+                    int ylo = std::max(0, j - n_buffer), yhi = std::min(L.n[1] - 1, j + n_buffer);
+                    int xlo = std::max(0, i - n_buffer), xhi = std::min(L.n[0] - 1, i + n_buffer);
+                    for (int z = zlo / half; z <= zhi / half; ++z)
+                        for (int y = ylo / half; y <= yhi / half; ++y)
+                            for (int x = xlo / half; x <= xhi / half; ++x) mark[at(x, y, z)] = 1;
+                }
+    }
+    // 3: proper nesting
+    for (int z = 0; z < g[2]; ++z)
+        for (int y = 0; y < g[1]; ++y)
+            for (int x = 0; x < g[0]; ++x) {
+                if (!mark[at(x, y, z)]) continue;
+                int blk[3] = {x, y, z}, lo[3], hi[3];
+                grown_footprint(L, blk, half, n_proper, lo, hi);
+                if (!region_inside(L, lo, hi)) mark[at(x, y, z)] = 0;
+            }
+    // 4-5: greedy merge, z slowest, x fastest; mark value 2 = taken
+    const int maxb = max_grid_size / bf;
+    std::vector<Box> out;
+    auto avail = [&](int x, int y, int z) { return mark[at(x, y, z)] == 1; };
+    for (int z = 0; z < g[2]; ++z)
+        for (int y = 0; y < g[1]; ++y)
+            for (int x = 0; x < g[0]; ++x) {
+                if (!avail(x, y, z)) continue;
+                int ex = 1, ey = 1, ez = 1;
+                while (x + ex < g[0] && ex < maxb && avail(x + ex, y, z)) ++ex;
+                while (y + ey < g[1] && ey < maxb) {
+                    bool row = true;
+                    for (int a = 0; a < ex && row; ++a) row = avail(x + a, y + ey, z);
+                    if (!row) break;
+                    ++ey;
+                }
+                while (z + ez < g[2] && ez < maxb) {
+                    bool slab = true;
+                    for (int c = 0; c < ey && slab; ++c)
+                        for (int a = 0; a < ex && slab; ++a) slab = avail(x + a, y + c, z + ez);
+                    if (!slab) break;
+                    ++ez;
+                }
+                for (int c3 = 0; c3 < ez; ++c3)
+                    for (int c2 = 0; c2 < ey; ++c2)
+                        for (int c1 = 0; c1 < ex; ++c1) mark[at(x + c1, y + c2, z + c3)] = 2;
+                Box B;
+                B.lo[0] = x * bf;
+                B.lo[1] = y * bf;
+                B.lo[2] = z * bf;
+                B.hi[0] = (x + ex) * bf;
+                B.hi[1] = (y + ey) * bf;
+                B.hi[2] = (z + ez) * bf;
+                out.push_back(B);
+            }
+    return out;
+}
+
+std::string check_nesting(const HostLevel &C, const std::vector<Box> &fine, int n_proper)
+{
+    char msg[256];
+    int nf[3] = {2 * C.n[0], 2 * C.n[1], 2 * C.n[2]};
+    int g[3] = {nf[0] / 8, nf[1] / 8, nf[2] / 8};
+    std::vector<uint8_t> used((size_t)g[0] * g[1] * g[2], 0);
+    for (size_t b = 0; b < fine.size(); ++b) {
+        const Box &B = fine[b];
+        for (int d = 0; d < 3; ++d) {
+            if (B.lo[d] % 8 || B.hi[d] % 8) {
+                snprintf(msg, sizeof msg, "box %zu is not aligned to 8 cells", b);
+                return msg;
+            }
+            if (B.lo[d] < 0 || B.hi[d] > nf[d] || B.lo[d] >= B.hi[d]) {
+                snprintf(msg, sizeof msg, "box %zu is empty or outside the level", b);
+                return msg;
+            }
+        }
+        for (int z = B.lo[2] / 8; z < B.hi[2] / 8; ++z)
+            for (int y = B.lo[1] / 8; y < B.hi[1] / 8; ++y)
+                for (int x = B.lo[0] / 8; x < B.hi[0] / 8; ++x) {
+                    size_t t = (size_t)x + (size_t)g[0] * ((size_t)y + (size_t)g[1] * z);
+                    if (used[t]) {
+                        snprintf(msg, sizeof msg, "box %zu overlaps an earlier box", b);
+                        return msg;
+                    }
+                    used[t] = 1;
+                    int blk[3] = {x, y, z}, lo[3], hi[3];
+                    grown_footprint(C, blk, 4, n_proper, lo, hi);
+                    if (!region_inside(C, lo, hi)) {
+                        snprintf(msg, sizeof msg, "box %zu is not properly nested in the coarser level", b);
+                        return msg;
+                    }
+                }
+    }
+    return "";
+}
+
+// ---------------------------------------------------------------------------
+// interpolation patterns
+// ---------------------------------------------------------------------------
+
+// window origins (first node offset along u, v from the centre cell) of the
+// nine quadratic cases in the order of Tab. bit_pattern: centred, shifted
+// towards -v, -u, +v, +u, then the corners (+u,-v), (-u,-v), (-u,+v), (+u,+v)
+static const int kQuadWin[9][2] = {{-1, -1}, {-1, -2}, {-2, -1}, {-1, 0}, {0, -1},
+                                   {0, -2},  {-2, -2}, {-2, 0},  {0, 0}};
+// the four bilinear windows in the printed order: (-u,-v), (-u,+v), (+u,+v), (+u,-v)
+static const int kLinWin[4][2] = {{-1, -1}, {-1, 0}, {0, 0}, {0, -1}};
+
+void pattern_window(int pat, int &u0, int &v0, int &np)
+{
+    if (pat < 9) {
+        u0 = kQuadWin[pat][0];
+        v0 = kQuadWin[pat][1];
+        np = 3;
+    } else if (pat < 13) {
+        u0 = kLinWin[pat - 9][0];
+        v0 = kLinWin[pat - 9][1];
+        np = 2;
+    } else {
+        u0 = 0;
+        v0 = 0;
+        np = 1;
+    }
+}
+
+static uint32_t window_mask(int pat)
+{
+    int u0, v0, np;
+    pattern_window(pat, u0, v0, np);
+    uint32_t m = 0;
+    for (int b = 0; b < np; ++b)
+        for (int a = 0; a < np; ++a) m |= 1u << ((u0 + a + 2) + 5 * (v0 + b + 2));
+    return m;
+}
+
+uint32_t quadratic_mask(int pat) { return window_mask(pat); }
+
+int select_pattern(uint32_t mask5)
+{
+    for (int p = 0; p < 13; ++p) {
+        uint32_t w = window_mask(p);
+        if ((mask5 & w) == w) return p;
+    }
+    return 13;
+}
+
+// Lagrange basis of node a (offset u0 + a) over nodes u0 .. u0+np-1 at t
+static double lagrange_basis(int a, int u0, int np, double t)
+{
+    double v = 1.0;
+    for (int m = 0; m < np; ++m)
+        if (m != a) v *= (t - (u0 + m)) / (double)(a - m);
+    return v;
+}
+
+std::vector<double> cf_weight_table()
+{
+    std::vector<double> W(14 * 4 * 9, 0.0);
+    for (int p = 0; p < 14; ++p) {
+        int u0, v0, np;
+        pattern_window(p, u0, v0, np);
+        for (int q = 0; q < 4; ++q) {
+            double tu = (q & 1) ? 0.25 : -0.25, tv = (q >> 1) ? 0.25 : -0.25;
+            for (int b = 0; b < np; ++b)
+                for (int a = 0; a < np; ++a)
+                    W[(p * 4 + q) * 9 + a + 3 * b] =
+                        (8.0 / 15.0) * lagrange_basis(a, u0, np, tu) * lagrange_basis(b, v0, np, tv);
+        }
+    }
+    return W;
+}
+
+void add_levels_below(Problem &P)
+{
+    std::vector<HostLevel> below;
+    int n[3] = {P.lev[0].n[0], P.lev[0].n[1], P.lev[0].n[2]};
+    while (n[0] % 16 == 0 && n[1] % 16 == 0 && n[2] % 16 == 0) {
+        for (int d = 0; d < 3; ++d) n[d] /= 2;
+        HostLevel L;
+        level_init(L, n, P.lo, P.hi);
+        L.amr = -1;
+        Box B{{0, 0, 0}, {n[0], n[1], n[2]}};
+        level_set_boxes(L, {B});
+        below.insert(below.begin(), L);
+    }
+    P.kg = (int)below.size();
+    below.insert(below.end(), P.lev.begin(), P.lev.end());
+    P.lev.swap(below);
+}
+
+// ---------------------------------------------------------------------------
+// merged metadata
+// ---------------------------------------------------------------------------
+static double dirichlet_value(const Problem &P, const double x[3])
+{
+    double g = 0.0;
+    for (size_t m = 0; m + 3 < P.mono.size(); m += 4) {
+        double dx = x[0] - P.mono[m + 1], dy = x[1] - P.mono[m + 2], dz = x[2] - P.mono[m + 3];
+        g += P.mono[m] / (4.0 * kPi * P.eps0 * std::sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    return g;
+}
+
+static inline void tdirs(int d, int &du, int &dv)
+{
+    du = (d == 0) ? 1 : 0;
+    dv = (d == 2) ? 1 : 2;
+}
+
+void build_meta(const std::vector<const Problem *> &probs, Meta &M)
+{
+    M = Meta();
+    const int np = (int)probs.size();
+    M.K = 0;
+    for (auto *p : probs) M.K = std::max(M.K, (int)p->lev.size());
+    M.prob_ent.assign(np, std::vector<int>());
+    for (int i = 0; i < np; ++i) M.prob_ent[i].assign(probs[i]->lev.size(), -1);
+    // entries and brick ranges
+    int nb = 0;
+    for (int k = 0; k < M.K; ++k) {
+        M.step_ent0.push_back((int)M.ent.size());
+        for (int i = 0; i < np; ++i) {
+            const Problem &P = *probs[i];
+            if (k >= (int)P.lev.size()) continue;
+            const HostLevel &L = P.lev[k];
+            Meta::Entry e{};
+            e.prob = i;
+            e.k = k;
+            e.amr = L.amr;
+            e.b0 = nb;
+            e.nb = L.nbrick();
+            for (int d = 0; d < 3; ++d) e.h[d] = L.h[d];
+            nb += e.nb;
+            M.prob_ent[i][k] = (int)M.ent.size();
+            M.ent.push_back(e);
+        }
+    }
+    M.step_ent0.push_back((int)M.ent.size());
+    M.nbrick = nb;
+    M.org.assign((size_t)nb * 4, 0);
+    M.nbr.assign((size_t)nb * 6, 0);
+    M.child.assign((size_t)nb * 8, -1);
+    M.par.assign(nb, -1);
+    M.cmask.assign(nb, 0);
+    M.ubase.assign(nb, 0);
+    M.ustr.assign((size_t)nb * 2, 0);
+
+    struct Face {
+        int brick, dir, ent;
+    };
+    std::vector<Face> bcf, cff;
+    const int CF_TAG = INT_MIN / 2;
+    for (size_t ei = 0; ei < M.ent.size(); ++ei) {
+        Meta::Entry &e = M.ent[ei];
+        const Problem &P = *probs[e.prob];
+        const HostLevel &L = P.lev[e.k];
+        const HostLevel *F = (e.k + 1 < (int)P.lev.size()) ? &P.lev[e.k + 1] : nullptr;
+        const HostLevel *Cc = (e.k > 0) ? &P.lev[e.k - 1] : nullptr;
+        int efine = F ? M.prob_ent[e.prob][e.k + 1] : -1;
+        int ecrse = Cc ? M.prob_ent[e.prob][e.k - 1] : -1;
+        e.cf0 = (int)cff.size();
+        for (int lb = 0; lb < L.nbrick(); ++lb) {
+            int g = e.b0 + lb;
+            int Pb[3] = {L.bpos[3 * lb], L.bpos[3 * lb + 1], L.bpos[3 * lb + 2]};
+            for (int d = 0; d < 3; ++d) M.org[(size_t)g * 4 + d] = 8 * Pb[d];
+            M.org[(size_t)g * 4 + 3] = (int32_t)ei;
+            for (int d = 0; d < 3; ++d)
+                for (int s = -1; s <= 1; s += 2) {
+                    int Q[3] = {Pb[0], Pb[1], Pb[2]};
+                    Q[d] += s;
+                    int dir = 2 * d + (s > 0);
+                    int32_t v;
+                    if (Q[d] < 0 || Q[d] >= L.nbk[d]) {
+                        v = -1 - (int32_t)bcf.size();
+                        bcf.push_back({g, dir, (int)ei});
+                    } else {
+                        int q = L.brick_at(Q[0], Q[1], Q[2]);
+                        if (q >= 0) {
+                            v = e.b0 + q;
+                        } else {
+                            v = CF_TAG + (int32_t)cff.size();
+                            cff.push_back({g, dir, (int)ei});
+                        }
+                    }
+                    M.nbr[(size_t)g * 6 + dir] = v;
+                }
+            if (F) {
+                uint8_t cm = 0;
+                for (int o = 0; o < 8; ++o) {
+                    int q = F->brick_at(2 * Pb[0] + (o & 1), 2 * Pb[1] + ((o >> 1) & 1), 2 * Pb[2] + (o >> 2));
+                    if (q >= 0) {
+                        M.child[(size_t)g * 8 + o] = M.ent[efine].b0 + q;
+                        cm |= (uint8_t)(1u << o);
+                    }
+                }
+                M.cmask[g] = L.amr >= 0 ? cm : 0;
+            }
+            if (Cc) {
+                int q = Cc->brick_at(Pb[0] >> 1, Pb[1] >> 1, Pb[2] >> 1);
+                int oc = (Pb[0] & 1) | ((Pb[1] & 1) << 1) | ((Pb[2] & 1) << 2);
+                if (q < 0) {
+                    M.error = "a brick has no parent on the coarser level (nesting violated)";
+                    q = 0;
+                }
+                M.par[g] = ((M.ent[ecrse].b0 + q) << 3) | oc;
+            }
+            if (L.amr >= 0) {
+                const Box &B = L.boxes[L.bbox[lb]];
+                int64_t nx = B.hi[0] - B.lo[0], ny = B.hi[1] - B.lo[1];
+                M.ubase[g] = L.off[L.bbox[lb]] + (8 * Pb[0] - B.lo[0]) +
+                             nx * ((8 * Pb[1] - B.lo[1]) + ny * (int64_t)(8 * Pb[2] - B.lo[2]));
+                M.ustr[(size_t)g * 2] = (int32_t)nx;
+                M.ustr[(size_t)g * 2 + 1] = (int32_t)(nx * ny);
+            }
+        }
+        e.ncf = (int)cff.size() - e.cf0;
+    }
+    M.nbc = (int)bcf.size();
+    M.ncf = (int)cff.size();
+    for (auto &v : M.nbr)
+        if (v < 0 && v <= CF_TAG + (int32_t)cff.size() && v >= CF_TAG) v = -1 - (M.nbc + (v - CF_TAG));
+    M.gf_owner.resize(M.nbc + M.ncf);
+    for (int t = 0; t < M.nbc; ++t) M.gf_owner[t] = (bcf[t].brick << 3) | bcf[t].dir;
+    for (int t = 0; t < M.ncf; ++t) M.gf_owner[M.nbc + t] = (cff[t].brick << 3) | cff[t].dir;
+
+    // Dirichlet data at the centres of the boundary faces of AMR levels
+    M.gbc.assign((size_t)M.nbc * 64, 0.0);
+    for (int t = 0; t < M.nbc; ++t) {
+        const Meta::Entry &e = M.ent[bcf[t].ent];
+        const Problem &P = *probs[e.prob];
+        if (e.amr < 0 || P.mono.empty()) continue;
+        int g = bcf[t].brick, d = bcf[t].dir >> 1, s = (bcf[t].dir & 1) ? 1 : -1;
+        int du, dv;
+        tdirs(d, du, dv);
+        for (int f = 0; f < 64; ++f) {
+            int l[3];
+            l[d] = s > 0 ? 7 : 0;
+            l[du] = f & 7;
+            l[dv] = f >> 3;
+            double x[3];
+            for (int a = 0; a < 3; ++a) x[a] = P.lo[a] + (M.org[(size_t)g * 4 + a] + l[a] + 0.5) * e.h[a];
+            x[d] += 0.5 * s * e.h[d];
+            M.gbc[(size_t)t * 64 + f] = dirichlet_value(P, x);
+        }
+    }
+
+    // coarse-fine faces: pattern and window cells per coarse cell
+    M.cf_pat.assign((size_t)M.ncf * 16, 0);
+    M.cf_idx.assign((size_t)M.ncf * 16 * 9, 0);
+    for (int t = 0; t < M.ncf; ++t) {
+        const Meta::Entry &e = M.ent[cff[t].ent];
+        const Problem &P = *probs[e.prob];
+        const HostLevel &Lf = P.lev[e.k];
+        const HostLevel &Lc = P.lev[e.k - 1];
+        const Meta::Entry &ec = M.ent[M.prob_ent[e.prob][e.k - 1]];
+        int g = cff[t].brick, d = cff[t].dir >> 1, s = (cff[t].dir & 1) ? 1 : -1;
+        int du, dv;
+        tdirs(d, du, dv);
+        int O[3] = {M.org[(size_t)g * 4], M.org[(size_t)g * 4 + 1], M.org[(size_t)g * 4 + 2]};
+        int ghost_d = s > 0 ? O[d] + 8 : O[d] - 1;
+        for (int m = 0; m < 16; ++m) {
+            int C[3];
+            C[d] = ghost_d >> 1;
+            C[du] = O[du] / 2 + (m & 3);
+            C[dv] = O[dv] / 2 + (m >> 2);
+            uint32_t mask = 0;
+            for (int jv = 0; jv < 5; ++jv)
+                for (int iu = 0; iu < 5; ++iu) {
+                    int Pc[3] = {C[0], C[1], C[2]};
+                    Pc[du] += iu - 2;
+                    Pc[dv] += jv - 2;
+                    if (Lc.has_cell(Pc[0], Pc[1], Pc[2]) && !Lf.has_cell(2 * Pc[0], 2 * Pc[1], 2 * Pc[2]))
+                        mask |= 1u << (iu + 5 * jv);
+                }
+            int pat = select_pattern(mask);
+            int u0, v0, npn;
+            pattern_window(pat, u0, v0, npn);
+            M.cf_pat[(size_t)t * 16 + m] = (uint8_t)pat;
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) {
+                    int Nd[3] = {C[0], C[1], C[2]};
+                    if (a < npn && b < npn) {
+                        Nd[du] += u0 + a;
+                        Nd[dv] += v0 + b;
+                    }
+                    int q = Lc.brick_at(Nd[0] >> 3, Nd[1] >> 3, Nd[2] >> 3);
+                    if (q < 0 || !Lc.has_cell(Nd[0], Nd[1], Nd[2])) {
+                        M.error = "coarse-fine window leaves the coarser level (nesting violated)";
+                        q = 0;
+                        Nd[0] = Nd[1] = Nd[2] = 0;
+                    }
+                    int gb = ec.b0 + q;
+                    M.cf_idx[((size_t)t * 16 + m) * 9 + a + 3 * b] =
+                        gb * 512 + (Nd[0] & 7) + 8 * (Nd[1] & 7) + 64 * (Nd[2] & 7);
+                }
+        }
+    }
+
+    // bricks of AMR levels with uncovered cells next to covered ones; AMR
+    // brick list; composite cell counts
+    M.dof.assign(np, std::vector<int64_t>());
+    for (size_t ei = 0; ei < M.ent.size(); ++ei) {
+        Meta::Entry &e = M.ent[ei];
+        e.rf0 = (int)M.reflux.size();
+        const Problem &P = *probs[e.prob];
+        if (e.amr >= 0) {
+            int64_t dof = 0;
+            for (int g = e.b0; g < e.b0 + e.nb; ++g) {
+                M.amr_bricks.push_back(g);
+                uint8_t cm = M.cmask[g];
+                dof += 64 * (8 - __builtin_popcount(cm));
+                bool want = false;
+                for (int o = 0; o < 8 && !want && cm != 0xFF; ++o) {
+                    if ((cm >> o) & 1) continue;
+                    for (int d = 0; d < 3 && !want; ++d)
+                        for (int s = -1; s <= 1 && !want; s += 2) {
+                            int od = (o >> d) & 1;
+                            int on = o ^ (1 << d);
+                            bool inside = (s > 0) ? od == 0 : od == 1;
+                            if (inside) {
+                                want = (cm >> on) & 1;
+                            } else {
+                                int f = M.nbr[(size_t)g * 6 + 2 * d + (s > 0)];
+                                if (f >= 0) want = (M.cmask[f] >> on) & 1;
+                            }
+                        }
+                }
+                if (want) M.reflux.push_back(g);
+            }
+            if ((int)M.dof[e.prob].size() <= e.amr) M.dof[e.prob].resize(e.amr + 1, 0);
+            M.dof[e.prob][e.amr] = dof;
+        }
+        e.nrf = (int)M.reflux.size() - e.rf0;
+        (void)P;
+    }
+}
+
+}  // namespace amrmg

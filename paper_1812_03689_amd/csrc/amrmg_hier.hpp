@@ -1,0 +1,115 @@
+// amrmg_hier.hpp -- host-side hierarchy of libamrmg: box lists, the brick
+// decomposition, box generation from tags, and the metadata the kernels read
+// (neighbour and parent/child tables, boundary and coarse-fine faces with
+// their interpolation patterns).  Plain C++ (no HIP), so that it also builds
+// and runs on a machine without a GPU.
+#pragma once
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace amrmg {
+
+struct Box {
+    int lo[3], hi[3];
+    int64_t volume() const { return (int64_t)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]); }
+};
+
+// One level of one problem.  AMR levels carry the caller's box list; the
+// multigrid levels below level 0 are a single box of the coarsened domain.
+struct HostLevel {
+    int n[3] = {0, 0, 0};       // index extent
+    double h[3] = {0, 0, 0};
+    int amr = -1;               // AMR level number, -1 below level 0
+    std::vector<Box> boxes;
+    std::vector<int64_t> off;   // user-layout offsets (nb + 1)
+    int nbk[3] = {0, 0, 0};     // brick grid extent
+    std::vector<int32_t> bmap;  // brick grid -> local brick or -1
+    std::vector<int32_t> bpos;  // local brick -> brick grid position (3 each)
+    std::vector<int32_t> bbox;  // local brick -> box
+    int nbrick() const { return (int)bbox.size(); }
+    int64_t ncells() const { return off.empty() ? (int64_t)nbrick() * 512 : off.back(); }
+    int brick_at(int bx, int by, int bz) const;  // local brick or -1 (also outside the grid)
+    bool has_cell(int i, int j, int k) const;
+};
+
+// build offsets and bricks of a level from its boxes (boxes must be 8-aligned)
+void level_set_boxes(HostLevel &L, const std::vector<Box> &boxes);
+// make level geometry: index extent n, spacing from the domain
+void level_init(HostLevel &L, const int n[3], const double lo[3], const double hi[3]);
+
+// Box generation for level l+1 from the tags (user layout) of level L: dilate
+// by n_buffer cells, mark 8-fine-cell blocks, drop blocks that break proper
+// nesting by n_proper coarse cells, and merge greedily along x, then y, then z
+// with edges of at most max_grid_size cells.
+std::vector<Box> generate_boxes(const HostLevel &L, const uint8_t *tags, int n_buffer, int n_proper, int bf,
+                                int max_grid_size);
+
+// Check boxes of a refined level against its coarser level: 8-alignment,
+// inside the index space, disjoint, and proper nesting.  Empty string = ok.
+std::string check_nesting(const HostLevel &coarse, const std::vector<Box> &fine, int n_proper);
+
+// coarse-fine interpolation patterns: 0..8 quadratic (printed order),
+// 9..12 bilinear, 13 centre only
+int select_pattern(uint32_t mask5);
+void pattern_window(int pat, int &u0, int &v0, int &np);
+// [14][4][9] step-1 weights times 8/15 (see amrmg_kernels.hip)
+std::vector<double> cf_weight_table();
+// the 25-bit masks of the 9 quadratic windows, built from pattern_window
+uint32_t quadratic_mask(int pat);
+
+// One problem (one context): its levels coarsest first; kg = index of AMR
+// level 0.
+struct Problem {
+    double lo[3], hi[3];
+    double eps0 = 1.0;
+    std::vector<double> mono;  // [n][4] q, x, y, z
+    std::vector<HostLevel> lev;
+    int kg = 0;
+    int namr() const { return (int)lev.size() - kg; }
+};
+
+// add the multigrid levels below AMR level 0 (halving while every edge stays
+// a multiple of 16); lev[0..] must hold the AMR levels on entry
+void add_levels_below(Problem &P);
+
+// Merged metadata of one or more problems.  Levels are numbered coarsest
+// first across problems: level entry (k, i) = level k (counted from each
+// problem's coarsest) of problem i, in order k-major; bricks follow the
+// level entries.
+struct Meta {
+    struct Entry {
+        int prob, k;      // problem, level index inside it
+        int amr;          // AMR level number or -1
+        int b0, nb;       // brick range
+        int cf0, ncf;     // coarse-fine faces of this level (ids from 0 = first CF face)
+        int rf0, nrf;     // reflux list range (bricks of this level with coarse-fine coarse cells)
+        double h[3];
+    };
+    std::vector<Entry> ent;
+    std::vector<int> step_ent0;      // per k: first entry of that step (size K+1)
+    int K = 0;                       // steps (max levels over problems)
+    int nbrick = 0;
+    std::vector<int32_t> org;        // [nbrick*4]
+    std::vector<int32_t> nbr;        // [nbrick*6]
+    std::vector<int32_t> child;      // [nbrick*8]
+    std::vector<int32_t> par;        // [nbrick]
+    std::vector<uint8_t> cmask;      // [nbrick]
+    std::vector<int64_t> ubase;      // [nbrick]
+    std::vector<int32_t> ustr;       // [nbrick*2]
+    int nbc = 0, ncf = 0;
+    std::vector<int32_t> gf_owner;   // [nbc + ncf]
+    std::vector<double> gbc;         // [nbc*64]
+    std::vector<uint8_t> cf_pat;     // [ncf*16]
+    std::vector<int32_t> cf_idx;     // [ncf*16*9]
+    std::vector<int32_t> reflux;     // brick ids
+    std::vector<int32_t> amr_bricks; // all AMR bricks, in entry order
+    std::vector<std::vector<int>> prob_ent;  // per problem: entry index of each level k
+    std::vector<std::vector<int64_t>> dof;   // per problem, per AMR level: uncovered cells
+    std::string error;                       // non-empty when the hierarchy is inconsistent
+};
+
+void build_meta(const std::vector<const Problem *> &probs, Meta &M);
+
+}  // namespace amrmg

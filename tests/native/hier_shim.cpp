@@ -1,0 +1,89 @@
+// Test shim: exposes the product's host hierarchy code (amrmg_hier.cpp) to
+// Python on a machine without a GPU.  Links only product code.
+#include <cstring>
+#include <vector>
+
+#include "amrmg_hier.hpp"
+
+using namespace amrmg;
+
+extern "C" int hs_generate_boxes(const int32_t *n, int nb, const int32_t *boxes, const uint8_t *tags, int nbuf,
+                                 int nprop, int bf, int mgs, int32_t *out, int cap)
+{
+    HostLevel L;
+    double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+    int nn[3] = {n[0], n[1], n[2]};
+    level_init(L, nn, lo, hi);
+    std::vector<Box> bx(nb);
+    for (int b = 0; b < nb; ++b)
+        for (int d = 0; d < 3; ++d) {
+            bx[b].lo[d] = boxes[6 * b + d];
+            bx[b].hi[d] = boxes[6 * b + 3 + d];
+        }
+    level_set_boxes(L, bx);
+    std::vector<Box> o = generate_boxes(L, tags, nbuf, nprop, bf, mgs);
+    if ((int)o.size() > cap) return -1;
+    for (size_t b = 0; b < o.size(); ++b)
+        for (int d = 0; d < 3; ++d) {
+            out[6 * b + d] = o[b].lo[d];
+            out[6 * b + 3 + d] = o[b].hi[d];
+        }
+    return (int)o.size();
+}
+
+// levels given as box lists; returns rows (i,j,k,d,s,pattern) of the CF ghost
+// faces of AMR level `level`
+extern "C" long hs_cf_patterns(const int32_t *n0, int nlev, const int32_t *nbox, const int32_t *boxes, int level,
+                               int32_t *out, long cap)
+{
+    Problem P;
+    for (int d = 0; d < 3; ++d) {
+        P.lo[d] = 0;
+        P.hi[d] = 1;
+    }
+    const int32_t *bp = boxes;
+    for (int l = 0; l < nlev; ++l) {
+        HostLevel L;
+        int n[3] = {n0[0] << l, n0[1] << l, n0[2] << l};
+        level_init(L, n, P.lo, P.hi);
+        L.amr = l;
+        std::vector<Box> bx(nbox[l]);
+        for (int b = 0; b < nbox[l]; ++b, bp += 6)
+            for (int d = 0; d < 3; ++d) {
+                bx[b].lo[d] = bp[d];
+                bx[b].hi[d] = bp[3 + d];
+            }
+        level_set_boxes(L, bx);
+        P.lev.push_back(L);
+    }
+    add_levels_below(P);
+    Meta M;
+    build_meta({&P}, M);
+    const Meta::Entry &e = M.ent[M.prob_ent[0][P.kg + level]];
+    long k = 0;
+    for (int c = e.cf0; c < e.cf0 + e.ncf; ++c) {
+        int ow = M.gf_owner[M.nbc + c];
+        int g = ow >> 3, dir = ow & 7, d = dir >> 1, s = (dir & 1) ? 1 : -1;
+        int du = (d == 0) ? 1 : 0, dv = (d == 2) ? 1 : 2;
+        for (int t = 0; t < 64; ++t, ++k) {
+            if (k >= cap) continue;
+            int l[3];
+            l[d] = s > 0 ? 7 : 0;
+            l[du] = t & 7;
+            l[dv] = t >> 3;
+            for (int a = 0; a < 3; ++a) out[6 * k + a] = M.org[(size_t)g * 4 + a] + l[a];
+            out[6 * k + 3] = d;
+            out[6 * k + 4] = s;
+            out[6 * k + 5] = M.cf_pat[(size_t)c * 16 + ((t & 7) >> 1) + 4 * ((t >> 3) >> 1)];
+        }
+    }
+    return k;
+}
+
+// the weight table and quadratic masks, for checks against the printed table
+extern "C" void hs_tables(double *w, uint32_t *qmask)
+{
+    std::vector<double> W = cf_weight_table();
+    std::memcpy(w, W.data(), sizeof(double) * W.size());
+    for (int p = 0; p < 9; ++p) qmask[p] = quadratic_mask(p);
+}
