@@ -195,6 +195,25 @@ amrmg_status amrmg_residual(amrmg_ctx *ctx, double *const *rho, double *const *p
 amrmg_status amrmg_solve_batch(amrmg_ctx *const *ctxs, int32_t nb, double *const *const *rho,
                                double *const *const *phi, double tol, amrmg_solve_stats *stats);
 
+/* Kernel classes for amrmg_profile_* (per-launch HIP events on the context's
+ * stream; algorithmic bytes per launch as defined in the design notes). */
+enum {
+    AMRMG_K_GSRB = 0, AMRMG_K_JACOBI, AMRMG_K_RESTRICT, AMRMG_K_PROLONG, AMRMG_K_REFLUX, AMRMG_K_CPART,
+    AMRMG_K_RESIDUAL, AMRMG_K_PHI_UPDATE, AMRMG_K_BOTTOM, AMRMG_K_EFIELD, AMRMG_K_AVGDOWN, AMRMG_K_DEPOSIT,
+    AMRMG_K_GATHER, AMRMG_K_NCLASS
+};
+
+/* Enable (mask != 0: bit c = class c) or disable per-launch event timing of
+ * the listed kernel classes, and clear the counters.  Off by default.
+ * Timing adds two event records per recorded launch. */
+amrmg_status amrmg_profile_enable(amrmg_ctx *ctx, uint32_t mask);
+
+/* Totals since the last enable for one class: summed device milliseconds of
+ * the recorded launches, their count and their algorithmic bytes (host
+ * outputs, any may be NULL).  Synchronises the stream. */
+amrmg_status amrmg_profile_read(amrmg_ctx *ctx, int32_t kclass, double *ms, int64_t *launches,
+                                double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,10 @@ AMRMG_MAX_LEVELS = 8
 EXPORTED = ["amrmg_default_params", "amrmg_create", "amrmg_destroy", "amrmg_last_error",
             "amrmg_build_hierarchy", "amrmg_hierarchy_info", "amrmg_get_boxes", "amrmg_cf_faces",
             "amrmg_workspace_size", "amrmg_set_workspace", "amrmg_deposit", "amrmg_solve",
-            "amrmg_gather", "amrmg_residual", "amrmg_solve_batch"]
+            "amrmg_gather", "amrmg_residual", "amrmg_solve_batch", "amrmg_profile_enable",
+            "amrmg_profile_read"]
+KCLASS = ["gsrb", "jacobi", "restrict", "prolong", "reflux", "cpart", "residual", "phi_update", "bottom",
+          "efield", "avgdown", "deposit", "gather"]
 
 
 class amrmg_params(C.Structure):
@@ -91,6 +94,8 @@ def lib():
         L.amrmg_gather.argtypes = [vp, C.c_int, vp, vp, vp, i64, vp, vp, vp, vp]
         L.amrmg_residual.argtypes = [vp, vp, vp, vp]
         L.amrmg_solve_batch.argtypes = [vp, i32, vp, vp, dbl, C.POINTER(amrmg_solve_stats)]
+        L.amrmg_profile_enable.argtypes = [vp, C.c_uint32]
+        L.amrmg_profile_read.argtypes = [vp, i32, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -237,6 +242,20 @@ def amrmg_solve_batch(handles: Sequence, rho: Sequence[Sequence], phi: Sequence[
     for d in out:
         d["status"] = rc
     return out
+
+
+def amrmg_profile_enable(h, classes) -> None:
+    mask = 0
+    for c in classes:
+        mask |= 1 << (KCLASS.index(c) if isinstance(c, str) else int(c))
+    _check(lib().amrmg_profile_enable(h, mask))
+
+
+def amrmg_profile_read(h, kclass):
+    k = KCLASS.index(kclass) if isinstance(kclass, str) else int(kclass)
+    ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+    _check(lib().amrmg_profile_read(h, k, C.byref(ms), C.byref(n), C.byref(b)))
+    return dict(ms=ms.value, launches=n.value, bytes=b.value)
 
 
 # --- convenience wrapper ----------------------------------------------------

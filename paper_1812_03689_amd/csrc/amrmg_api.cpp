@@ -264,6 +264,57 @@ static amrmg_status ensure_ws(DevState &D, int prec, void *user, size_t user_byt
 }
 
 // ---------------------------------------------------------------------------
+// per-launch event timing of selected kernel classes
+// ---------------------------------------------------------------------------
+struct Prof {
+    uint32_t mask = 0;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec {
+        int cls;
+        size_t ev;  // index of the start event; end = ev + 1
+        double bytes;
+    };
+    std::vector<Rec> recs;
+    hipStream_t st = nullptr;
+    size_t pending = (size_t)-1;
+    int pending_cls = -1;
+
+    bool on(int cls) const { return (mask >> cls) & 1; }
+    void begin(int cls)
+    {
+        pending = (size_t)-1;
+        if (!on(cls) || used + 2 > pool.size()) return;
+        pending = used;
+        pending_cls = cls;
+        (void)hipEventRecord(pool[used], st);
+        used += 2;
+    }
+    void end(int cls, double bytes)
+    {
+        if (pending == (size_t)-1 || pending_cls != cls) return;
+        (void)hipEventRecord(pool[pending + 1], st);
+        recs.push_back({cls, pending, bytes});
+        pending = (size_t)-1;
+    }
+    void reset(uint32_t m, hipStream_t s)
+    {
+        mask = m;
+        st = s;
+        used = 0;
+        recs.clear();
+        if (m && pool.empty()) {
+            pool.resize(1 << 16);
+            for (auto &e : pool) (void)hipEventCreate(&e);
+        }
+    }
+    ~Prof()
+    {
+        for (auto &e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
 struct amrmg_ctx {
@@ -281,6 +332,7 @@ struct amrmg_ctx {
     std::vector<amrmg_ctx *> batch_ctx;
     std::vector<int> batch_gen;
     DevState *batch = nullptr;
+    Prof prof;
     ~amrmg_ctx()
     {
         for (auto p : d_bmap) (void)hipFree(p);
@@ -621,8 +673,11 @@ extern "C" amrmg_status amrmg_deposit(amrmg_ctx *ctx, int pos_dtype, const void 
         const HostLevel &L = pr.lev[pr.kg + l];
         launch_fill(ctx->st, rho[l], L.ncells(), 0.0);
         DepLevel D = dep_level(pr, L, ctx->d_bmap[l]);
+        ctx->prof.begin(AMRMG_K_DEPOSIT);
         launch_deposit(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, D, ctx->ds.M.ubase, ctx->ds.M.ustr, rho[l],
                        l == 0 ? dout : nullptr);
+        ctx->prof.end(AMRMG_K_DEPOSIT, (double)n * (3.0 * (pos_dtype == AMRMG_POS_F32 ? 4 : 8) + 8.0) +
+                                           8.0 * (double)L.ncells());
     }
     HIP_TRY(hipGetLastError());
     if (n_outside) {
@@ -652,7 +707,9 @@ extern "C" amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *
             G.E[3 * l + d] = E[3 * l + d];
         }
     }
+    ctx->prof.begin(AMRMG_K_GATHER);
     launch_gather(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, G, ctx->ds.M.ubase, ctx->ds.M.ustr, Ex, Ey, Ez);
+    ctx->prof.end(AMRMG_K_GATHER, (double)n * (3.0 * (pos_dtype == AMRMG_POS_F32 ? 4 : 8) + 24.0));
     HIP_TRY(hipGetLastError());
     return AMRMG_OK;
 }
@@ -672,10 +729,20 @@ struct Driver {
     SolveOpts o;
     const Meta &m;
     T *e, *r, *et, *cpe;
+    Prof *P;
+    static constexpr double W = sizeof(T);
 
-    Driver(DevState &D_, hipStream_t s, const SolveOpts &op)
-        : D(D_), st(s), o(op), m(D_.meta), e((T *)D_.e), r((T *)D_.r), et((T *)D_.et), cpe((T *)D_.cpe)
+    Driver(DevState &D_, hipStream_t s, const SolveOpts &op, Prof *p)
+        : D(D_), st(s), o(op), m(D_.meta), e((T *)D_.e), r((T *)D_.r), et((T *)D_.et), cpe((T *)D_.cpe), P(p)
     {
+    }
+    void pb(int c)
+    {
+        if (P) P->begin(c);
+    }
+    void pe(int c, double bytes)
+    {
+        if (P) P->end(c, bytes);
     }
 
     bool single() const { return m.prob_ent.size() == 1; }
@@ -704,9 +771,15 @@ struct Driver {
         int b0, nb;
         const int32_t *list;
         amr_range(b0, nb, list);
-        if (!zero_phi) launch_cpart_user(st, D.M, 0, m.ncf, D.d_phi, D.cpphi);
+        if (!zero_phi) {
+            pb(AMRMG_K_CPART);
+            launch_cpart_user(st, D.M, 0, m.ncf, D.d_phi, D.cpphi);
+            pe(AMRMG_K_CPART, (double)m.ncf * 16 * (9 + 4) * 8);
+        }
+        pb(AMRMG_K_RESIDUAL);
         launch_outer_residual<T>(st, D.M, b0, nb, list, D.d_phi, D.d_rho, o.inv_eps0, zero_phi ? nullptr : D.cpphi,
                                  (zero_phi || rout_user) ? nullptr : r, D.part, o.norm_p, zero_phi, rout_user);
+        pe(AMRMG_K_RESIDUAL, (double)nb * BRICK_CELLS * (zero_phi ? 8.0 : 16.0 + W));
         launch_level_norms(st, D.d_ranges, (int)D.range_prob.size(), D.part, D.dnorm + noff, o.norm_p);
     }
 
@@ -714,10 +787,14 @@ struct Driver {
     {
         int b0 = step_b0(k), nb = step_nb(k);
         const T *cp = pre ? nullptr : cpe;
+        const double n = (double)nb * BRICK_CELLS;
         if (o.smoother == AMRMG_GSRB) {
             for (int it = 0; it < nu; ++it) {
-                launch_gsrb<T>(st, D.M, b0, nb, e, r, cp, 0, pre && it == 0);
-                launch_gsrb<T>(st, D.M, b0, nb, e, r, cp, 1, false);
+                for (int colour = 0; colour < 2; ++colour) {
+                    pb(AMRMG_K_GSRB);
+                    launch_gsrb<T>(st, D.M, b0, nb, e, r, cp, colour, pre && it == 0 && colour == 0);
+                    pe(AMRMG_K_GSRB, 1.5 * n * W);
+                }
             }
             return;
         }
@@ -749,35 +826,50 @@ struct Driver {
     {
         for (int k = m.K - 1; k >= 1; --k) {
             smooth(k, o.nu1, true);
+            double n = (double)step_nb(k) * BRICK_CELLS;
+            pb(AMRMG_K_RESTRICT);
             launch_restrict<T>(st, D.M, step_b0(k), step_nb(k), e, r, r);
+            pe(AMRMG_K_RESTRICT, (2.0 + 0.125) * n * W);
             // coarse cells of level k-1 next to level k
             const auto &e0 = m.ent[m.step_ent0[k - 1]];
             const auto &e1 = m.ent[m.step_ent0[k] - 1];
             int rf0 = e0.rf0, nrf = e1.rf0 + e1.nrf - e0.rf0;
+            pb(AMRMG_K_REFLUX);
             launch_reflux<T>(st, D.M, D.d_reflux + rf0, nrf, e, r);
+            pe(AMRMG_K_REFLUX, 2.0 * nrf * BRICK_CELLS * W);
         }
+        pb(AMRMG_K_BOTTOM);
         launch_bottom_cg<T>(st, D.M, D.d_jobs, D.njobs, r, e, D.cgw, o.bottom_rtol, 10000, D.cgit);
+        pe(AMRMG_K_BOTTOM, (double)D.cg_doubles / 4 * (2 * W));
         for (int k = 1; k < m.K; ++k) {
             const auto &e0 = m.ent[m.step_ent0[k]];
             const auto &e1 = m.ent[m.step_ent0[k + 1] - 1];
-            launch_cpart_brick<T>(st, D.M, e0.cf0, e1.cf0 + e1.ncf - e0.cf0, e, cpe);
+            int ncf = e1.cf0 + e1.ncf - e0.cf0;
+            double n = (double)step_nb(k) * BRICK_CELLS;
+            pb(AMRMG_K_CPART);
+            launch_cpart_brick<T>(st, D.M, e0.cf0, ncf, e, cpe);
+            pe(AMRMG_K_CPART, (double)ncf * 16 * (9 + 4) * W);
+            pb(AMRMG_K_PROLONG);
             launch_prolong<T>(st, D.M, step_b0(k), step_nb(k), e);
+            pe(AMRMG_K_PROLONG, (2.0 + 0.125) * n * W);
             smooth(k, o.nu2, false);
         }
         int b0, nb;
         const int32_t *list;
         amr_range(b0, nb, list);
+        pb(AMRMG_K_PHI_UPDATE);
         launch_phi_update<T>(st, D.M, b0, nb, list, D.d_phi, e);
+        pe(AMRMG_K_PHI_UPDATE, (double)nb * BRICK_CELLS * (16.0 + W));
     }
 };
 
 // run a solve on a DevState whose pointer tables are set; per-problem stats
 template <class T>
 static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, double tol,
-                              std::vector<amrmg_solve_stats> &stats, bool want_E)
+                              std::vector<amrmg_solve_stats> &stats, bool want_E, Prof *prof)
 {
     const Meta &m = D.meta;
-    Driver<T> drv(D, st, o);
+    Driver<T> drv(D, st, o, prof);
     const int nr = (int)D.range_prob.size();
     const int np = (int)m.prob_ent.size();
     hipEvent_t ev0, ev1;
@@ -830,12 +922,18 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
     // average down, finest first, then the field
     for (int k = m.K - 1; k >= 1; --k)
         for (int ei = m.step_ent0[k]; ei < m.step_ent0[k + 1]; ++ei)
-            if (m.ent[ei].amr >= 1) launch_avgdown(st, D.M, m.ent[ei].b0, m.ent[ei].nb, D.d_phi);
+            if (m.ent[ei].amr >= 1) {
+                drv.pb(AMRMG_K_AVGDOWN);
+                launch_avgdown(st, D.M, m.ent[ei].b0, m.ent[ei].nb, D.d_phi);
+                drv.pe(AMRMG_K_AVGDOWN, (double)m.ent[ei].nb * BRICK_CELLS * 8.0 * (1.0 + 0.125));
+            }
     if (want_E) {
         int b0, nb;
         const int32_t *list;
         drv.amr_range(b0, nb, list);
+        drv.pb(AMRMG_K_EFIELD);
         launch_efield(st, D.M, b0, nb, list, D.d_phi, D.cpphi, D.d_E);
+        drv.pe(AMRMG_K_EFIELD, (double)nb * BRICK_CELLS * 32.0);
     }
     HIP_TRY(hipEventRecord(ev1, st));
     HIP_TRY(hipEventSynchronize(ev1));
@@ -915,8 +1013,9 @@ extern "C" amrmg_status amrmg_solve(amrmg_ctx *ctx, double *const *rho, double *
     ST_TRY(set_tables(D, ctx->st));
     std::vector<amrmg_solve_stats> sv;
     SolveOpts o = opts_of(ctx->P);
-    amrmg_status rc = ctx->P.precision == AMRMG_MIXED ? run_solve<float>(D, ctx->st, o, tol, sv, E != nullptr)
-                                                      : run_solve<double>(D, ctx->st, o, tol, sv, E != nullptr);
+    Prof *pf = ctx->prof.mask ? &ctx->prof : nullptr;
+    amrmg_status rc = ctx->P.precision == AMRMG_MIXED ? run_solve<float>(D, ctx->st, o, tol, sv, E != nullptr, pf)
+                                                      : run_solve<double>(D, ctx->st, o, tol, sv, E != nullptr, pf);
     if (stats && !sv.empty()) *stats = sv[0];
     if (rc == AMRMG_E_NOT_CONVERGED) g_err = "not converged within max_iters";
     return rc;
@@ -944,7 +1043,7 @@ extern "C" amrmg_status amrmg_residual(amrmg_ctx *ctx, double *const *rho, doubl
     size_t ne = D.meta.ent.size();
     HIP_TRY(hipMemcpyAsync(D.d_rout, D.h_rout.data(), sizeof(double *) * ne, hipMemcpyHostToDevice, ctx->st));
     SolveOpts o = opts_of(ctx->P);
-    Driver<double> drv(D, ctx->st, o);
+    Driver<double> drv(D, ctx->st, o, nullptr);
     drv.outer(false, 0, D.d_rout);
     HIP_TRY(hipStreamSynchronize(ctx->st));
     HIP_TRY(hipGetLastError());
@@ -961,4 +1060,34 @@ extern "C" amrmg_status amrmg_solve_batch(amrmg_ctx *const *ctxs, int32_t nb, do
     (void)tol;
     (void)stats;
     return fail(AMRMG_E_NOT_IMPLEMENTED, "amrmg_solve_batch");
+}
+
+extern "C" amrmg_status amrmg_profile_enable(amrmg_ctx *ctx, uint32_t mask)
+{
+    if (!ctx) return fail(AMRMG_E_INVALID, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(ctx->st));
+    ctx->prof.reset(mask, ctx->st);
+    return AMRMG_OK;
+}
+
+extern "C" amrmg_status amrmg_profile_read(amrmg_ctx *ctx, int32_t kclass, double *ms, int64_t *launches,
+                                           double *bytes)
+{
+    if (!ctx) return fail(AMRMG_E_INVALID, "ctx is NULL");
+    if (kclass < 0 || kclass >= AMRMG_K_NCLASS) return fail(AMRMG_E_INVALID, "bad kernel class");
+    HIP_TRY(hipStreamSynchronize(ctx->st));
+    double t = 0.0, b = 0.0;
+    int64_t n = 0;
+    for (const auto &r : ctx->prof.recs) {
+        if (r.cls != kclass) continue;
+        float e = 0.f;
+        HIP_TRY(hipEventElapsedTime(&e, ctx->prof.pool[r.ev], ctx->prof.pool[r.ev + 1]));
+        t += e;
+        b += r.bytes;
+        ++n;
+    }
+    if (ms) *ms = t;
+    if (launches) *launches = n;
+    if (bytes) *bytes = b;
+    return AMRMG_OK;
 }
