@@ -99,8 +99,9 @@ def main():
     prof_all = {c: amrmg.amrmg_profile_read(cm.h, c) for c in amrmg.KCLASS}
     dominant = max(prof_all, key=lambda c: prof_all[c]["ms"])
 
-    # timed region: only the dominant class carries events
-    amrmg.amrmg_profile_enable(cm.h, [dominant])
+    # timed region (no profiling: the outer iterations replay as a graph)
+    amrmg.amrmg_profile_enable(cm.h, [])
+    step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = []
@@ -109,10 +110,40 @@ def main():
         iters.append(st["iters"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    dom = amrmg.amrmg_profile_read(cm.h, dominant)
-    amrmg.amrmg_profile_enable(cm.h, [])
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = dof / (ms_step * 1e-3)
+
+    # the same steps again with kernel-execution timestamps (HIP events
+    # recorded by hipExtLaunchKernelGGL on the library's stream) on every
+    # launch of the dominant kernel class
+    amrmg.amrmg_profile_enable(cm.h, [dominant])
+    for _ in range(args.steps):
+        step()
+    dom = amrmg.amrmg_profile_read(cm.h, dominant)
+    amrmg.amrmg_profile_enable(cm.h, [])
+
+    # per-phase wall time of a step (synchronised phases, outside the timed region)
+    ph = {"build_hierarchy": [], "deposit": [], "solve": [], "gather": []}
+    for _ in range(3):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        cm.build_hierarchy(x, y, z, q, tag_rel=w.tag_rel, explicit_boxes=w.explicit_boxes)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        amrmg.amrmg_deposit(cm.h, x, y, z, q, rho)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        for t in phi:
+            t.zero_()
+        amrmg.amrmg_solve(cm.h, rho, phi, E, tol)
+        torch.cuda.synchronize()
+        d = time.perf_counter()
+        amrmg.amrmg_gather(cm.h, x, y, z, E, Ex, Ey, Ez)
+        torch.cuda.synchronize()
+        e = time.perf_counter()
+        for k, v in zip(ph, (b - a, c - b, d - c, e - d)):
+            ph[k].append(v * 1e3)
+    breakdown = {k: round(float(np.median(v)), 3) for k, v in ph.items()}
 
     # solve alone, mixed vs plain FP64 on the same hierarchy (device events)
     cf = ctx_for("fp64")
@@ -154,6 +185,7 @@ def main():
         "solve": solve,
         "iters": iters[-1],
         "kernel_ms_warmup": {c: round(v["ms"], 4) for c, v in prof_all.items() if v["launches"]},
+        "step_breakdown_ms": breakdown,
     }
 
     if not args.no_check or not args.no_cpu:

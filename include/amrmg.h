@@ -53,7 +53,13 @@ typedef enum {
 
 enum { AMRMG_POS_F64 = 0, AMRMG_POS_F32 = 1 };
 enum { AMRMG_FP64 = 0, AMRMG_MIXED = 1 };
-enum { AMRMG_GSRB = 0, AMRMG_JACOBI = 1 };
+/* Smoothers: AMRMG_GSRB = red-black Gauss-Seidel inside each 8^3 brick with
+ * the brick halo taken from the previous sweep (one pass per sweep, the way a
+ * parallel Gauss-Seidel works inside and between subdomains);
+ * AMRMG_GSRB_GLOBAL = red-black over the whole level (two passes per sweep);
+ * AMRMG_JACOBI = damped Jacobi.  The small levels at the bottom of the cycle
+ * always use whole-level red-black inside one workgroup. */
+enum { AMRMG_GSRB = 0, AMRMG_JACOBI = 1, AMRMG_GSRB_GLOBAL = 2 };
 enum { AMRMG_MAX_LEVELS = 8 };
 
 /* Solver and hierarchy parameters.  amrmg_default_params fills the defaults
@@ -71,12 +77,14 @@ typedef struct amrmg_params {
     int32_t n_monopoles;        /* Dirichlet data g(x) = sum q/(4 pi eps0 |x-x_k|); 0 -> g = 0 */
     const double *monopoles;    /* host [n_monopoles][4] = q, x, y, z; copied by amrmg_create */
     int32_t precision;          /* AMRMG_FP64 or AMRMG_MIXED [MIXED] */
-    int32_t smoother;           /* AMRMG_GSRB or AMRMG_JACOBI [GSRB] */
+    int32_t smoother;           /* AMRMG_GSRB, AMRMG_JACOBI or AMRMG_GSRB_GLOBAL [GSRB] */
     int32_t nu1, nu2;           /* pre / post smoothing sweeps [2, 2] */
     double omega;               /* damped-Jacobi weight [6/7] */
     int32_t norm_p;             /* residual norm: 1, 2, or 0 for max-norm [2] */
     int32_t max_iters;          /* V-cycle cap i_max [50] */
-    double bottom_rtol;         /* CG tolerance on the coarsest grid [1e-6] */
+    double bottom_rtol;         /* CG tolerance on the coarsest grid, relative to its right-hand
+                                   side; it bounds only how well each cycle treats the smoothest
+                                   modes, not the accuracy of the result [1e-2] */
 } amrmg_params;
 
 /* Per-solve statistics. */

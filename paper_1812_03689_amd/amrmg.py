@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_HIP", -3: "E_NOT_CONVERGED", -4
                 -5: "E_OOM", -6: "E_STATE", -7: "E_NOT_IMPLEMENTED"}
 AMRMG_POS_F64, AMRMG_POS_F32 = 0, 1
 AMRMG_FP64, AMRMG_MIXED = 0, 1
-AMRMG_GSRB, AMRMG_JACOBI = 0, 1
+AMRMG_GSRB, AMRMG_JACOBI, AMRMG_GSRB_GLOBAL = 0, 1, 2
 AMRMG_MAX_LEVELS = 8
 
 EXPORTED = ["amrmg_default_params", "amrmg_create", "amrmg_destroy", "amrmg_last_error",
@@ -261,7 +261,7 @@ def amrmg_profile_read(h, kclass):
 # --- convenience wrapper ----------------------------------------------------
 
 def make_params(n0, max_level=2, monopoles=(), precision="mixed", smoother="gsrb", nu1=2, nu2=2,
-                max_grid_size=32, max_iters=50, norm_p=2, bottom_rtol=1e-6, lo=(0, 0, 0), hi=(1, 1, 1),
+                max_grid_size=32, max_iters=50, norm_p=2, bottom_rtol=1e-2, lo=(0, 0, 0), hi=(1, 1, 1),
                 eps0=1.0, n_buffer=1, n_proper=2, omega=6.0 / 7.0):
     p = amrmg_default_params()
     for d in range(3):
@@ -275,7 +275,7 @@ def make_params(n0, max_level=2, monopoles=(), precision="mixed", smoother="gsrb
     p.n_monopoles = len(monopoles)
     p.monopoles = C.cast(p._mono_keep, C.POINTER(C.c_double)) if mono else None
     p.precision = {"fp64": AMRMG_FP64, "mixed": AMRMG_MIXED}[precision]
-    p.smoother = {"gsrb": AMRMG_GSRB, "jacobi": AMRMG_JACOBI}[smoother]
+    p.smoother = {"gsrb": AMRMG_GSRB, "jacobi": AMRMG_JACOBI, "gsrb_global": AMRMG_GSRB_GLOBAL}[smoother]
     p.nu1, p.nu2 = int(nu1), int(nu2)
     p.omega = float(omega)
     p.norm_p = int(norm_p)

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -45,58 +46,84 @@ static amrmg_status fail(amrmg_status s, const std::string &m)
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // ---------------------------------------------------------------------------
-// device copy of merged metadata plus the solve workspace
+// grow-only device and pinned host buffers (allocation happens only when a
+// hierarchy outgrows its predecessor, so regrids do not reallocate)
 // ---------------------------------------------------------------------------
-struct DevState {
-    Meta meta;
-    DevMeta M{};
-    std::vector<void *> allocs;
-    int32_t *d_reflux = nullptr, *d_amr = nullptr;
-    int2 *d_ranges = nullptr;  // brick range of each AMR level of each problem
-    std::vector<int> range_prob, range_amr;
-    int4 *d_jobs = nullptr;
-    int njobs = 0;
-    size_t cg_doubles = 0;
-    double **d_phi = nullptr, **d_rho = nullptr, **d_E = nullptr, **d_rout = nullptr;
-    std::vector<double *> h_phi, h_rho, h_E, h_rout;
-    // workspace
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
-    bool ws_owned = false;
-    int ws_prec = -1;
-    void *e = nullptr, *r = nullptr, *et = nullptr, *cpe = nullptr;
-    double *cpphi = nullptr, *part = nullptr, *dnorm = nullptr;
-    double *cgw = nullptr;
-    int *cgit = nullptr;
-    double *h_norm = nullptr;  // pinned
-
+struct DBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t n)
+    {
+        if (n <= cap && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t c = n + n / 4 + 4096;
+        hipError_t e = hipMalloc(&p, c);
+        if (e == hipSuccess) cap = c;
+        return e;
+    }
     void release()
     {
-        for (void *p : allocs) (void)hipFree(p);
-        allocs.clear();
-        if (ws_owned && ws) (void)hipFree(ws);
-        ws = nullptr;
-        ws_owned = false;
-        ws_bytes = 0;
-        ws_prec = -1;
-        if (h_norm) (void)hipHostFree(h_norm);
-        h_norm = nullptr;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
     }
-    ~DevState() { release(); }
+    ~DBuf() { release(); }
 };
 
-template <class V>
-static amrmg_status up(DevState &D, const std::vector<V> &v, V **out)
-{
-    *out = nullptr;
-    if (v.empty()) return AMRMG_OK;
+struct PBuf {
     void *p = nullptr;
-    HIP_TRY(hipMalloc(&p, sizeof(V) * v.size()));
-    D.allocs.push_back(p);
-    HIP_TRY(hipMemcpy(p, v.data(), sizeof(V) * v.size(), hipMemcpyHostToDevice));
-    *out = (V *)p;
-    return AMRMG_OK;
-}
+    size_t cap = 0;
+    hipError_t ensure(size_t n)
+    {
+        if (n <= cap && p) return hipSuccess;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t c = n + n / 4 + 4096;
+        hipError_t e = hipHostMalloc(&p, c);
+        if (e == hipSuccess) cap = c;
+        return e;
+    }
+    ~PBuf()
+    {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
+// Packs host arrays into one pinned staging buffer and one device buffer
+// with a single host-to-device copy.
+struct Packer {
+    struct Item {
+        const void *src;
+        size_t bytes, off;
+        void **dst;
+    };
+    std::vector<Item> items;
+    size_t total = 0;
+    template <class V>
+    void add(const std::vector<V> &v, V **dst)
+    {
+        add_raw(v.data(), sizeof(V) * v.size(), (void **)dst);
+    }
+    void add_raw(const void *src, size_t bytes, void **dst)
+    {
+        items.push_back({src, bytes, total, dst});
+        total += align256(bytes ? bytes : 1);
+    }
+    amrmg_status run(DBuf &dev, PBuf &stage, hipStream_t st)
+    {
+        HIP_TRY(stage.ensure(total));
+        HIP_TRY(dev.ensure(total));
+        for (auto &it : items) {
+            if (it.bytes) std::memcpy((char *)stage.p + it.off, it.src, it.bytes);
+            *it.dst = (char *)dev.p + it.off;
+        }
+        HIP_TRY(hipMemcpyAsync(dev.p, stage.p, total, hipMemcpyHostToDevice, st));
+        return AMRMG_OK;
+    }
+};
 
 #define ST_TRY(x)                                \
     do {                                         \
@@ -104,9 +131,64 @@ static amrmg_status up(DevState &D, const std::vector<V> &v, V **out)
         if (s_ != AMRMG_OK) return s_;           \
     } while (0)
 
+// ---------------------------------------------------------------------------
+// device copy of merged metadata plus the solve workspace
+// ---------------------------------------------------------------------------
+struct DevState {
+    Meta meta;
+    DevMeta M{};
+    DBuf metabuf;
+    PBuf stage;
+    int32_t *d_reflux = nullptr, *d_amr = nullptr;
+    int2 *d_ranges = nullptr;  // brick range of each AMR level of each problem
+    std::vector<int> range_prob, range_amr;
+    int4 *d_jobs = nullptr;
+    int njobs = 0;
+    size_t cg_doubles = 0;
+    CoarseJob *d_cjobs = nullptr;
+    int kc = 0;  // levels 0..kc of every problem run in the one-workgroup coarse cycle
+    // per-level pointer tables: phi[ne], rho[ne], rout[ne], E[3 ne]
+    DBuf ptrbuf;
+    PBuf ptrstage;
+    double **d_phi = nullptr, **d_rho = nullptr, **d_E = nullptr, **d_rout = nullptr;
+    std::vector<double *> h_phi, h_rho, h_E, h_rout;
+    // workspace
+    DBuf ws_own;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    int ws_prec = -1;
+    void *e = nullptr, *r = nullptr, *et = nullptr, *cpe = nullptr;
+    double *cpphi = nullptr, *part = nullptr, *dnorm = nullptr;
+    double *cgw = nullptr;
+    int *cgit = nullptr;
+    unsigned *ncounter = nullptr;
+    int cg_threads = 1024;
+    PBuf h_normbuf;
+    double *h_norm = nullptr;
+    // AMR-level brick maps with global brick ids (single problems)
+    std::vector<int32_t *> d_bmap;
+    // captured outer iteration (V-cycle, phi update, FP64 residual, norms)
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int64_t> gkey;
+    int meta_gen = 0;
+    hipStream_t cap_stream = nullptr;  // capture needs a stream other than the null stream
+    void drop_graph()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+        gkey.clear();
+    }
+    ~DevState()
+    {
+        drop_graph();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+};
+
 static bool g_weights_ok = false;
 
-static amrmg_status upload_meta(DevState &D)
+// upload D.meta (plus optional extra arrays) in one copy
+static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<std::vector<int32_t>> *bmaps)
 {
     const Meta &m = D.meta;
     if (!g_weights_ok) {
@@ -114,32 +196,97 @@ static amrmg_status upload_meta(DevState &D)
         HIP_TRY(upload_cf_weights(W.data()));
         g_weights_ok = true;
     }
-    int32_t *org = nullptr, *nbr = nullptr, *child = nullptr, *par = nullptr, *ustr = nullptr, *gfo = nullptr,
-            *cfi = nullptr;
-    uint8_t *cm = nullptr, *cfp = nullptr;
-    int64_t *ub = nullptr;
-    double *gbc = nullptr;
-    ST_TRY(up(D, m.org, &org));
-    ST_TRY(up(D, m.nbr, &nbr));
-    ST_TRY(up(D, m.child, &child));
-    ST_TRY(up(D, m.par, &par));
-    ST_TRY(up(D, m.cmask, &cm));
-    ST_TRY(up(D, m.ubase, &ub));
-    ST_TRY(up(D, m.ustr, &ustr));
-    ST_TRY(up(D, m.gf_owner, &gfo));
-    ST_TRY(up(D, m.gbc, &gbc));
-    ST_TRY(up(D, m.cf_pat, &cfp));
-    ST_TRY(up(D, m.cf_idx, &cfi));
-    ST_TRY(up(D, m.reflux, &D.d_reflux));
-    ST_TRY(up(D, m.amr_bricks, &D.d_amr));
-    std::vector<LevelConst> lc(m.ent.size());
+    static thread_local std::vector<LevelConst> lc;
+    lc.assign(m.ent.size(), LevelConst{});
     for (size_t i = 0; i < m.ent.size(); ++i)
         for (int d = 0; d < 3; ++d) {
             lc[i].h[d] = m.ent[i].h[d];
             lc[i].ih2[d] = 1.0 / (m.ent[i].h[d] * m.ent[i].h[d]);
         }
+    // norm ranges: every AMR level of every problem, entry order
+    static thread_local std::vector<int32_t> rg, jobs;
+    rg.clear();
+    D.range_prob.clear();
+    D.range_amr.clear();
+    for (const auto &e : m.ent)
+        if (e.amr >= 0) {
+            rg.push_back(e.b0);
+            rg.push_back(e.nb);
+            D.range_prob.push_back(e.prob);
+            D.range_amr.push_back(e.amr);
+        }
+    // bottom solves: the coarsest level of each problem
+    jobs.clear();
+    size_t off = 0;
+    for (size_t i = 0; i < m.prob_ent.size(); ++i) {
+        const auto &e = m.ent[m.prob_ent[i][0]];
+        jobs.push_back(e.b0);
+        jobs.push_back(e.nb);
+        jobs.push_back((int32_t)off);
+        jobs.push_back(0);
+        off += (size_t)4 * e.nb * BRICK_CELLS;
+    }
+    D.njobs = (int)m.prob_ent.size();
+    D.cg_doubles = off;
+    // coarse part: levels 0..kc with at most 8 bricks above level 0 and no
+    // coarse-fine faces (at most AMR level 0), the same kc for all problems
+    const int kMaxCoarseBricks = 0;  // the coarse kernel runs the CG on the coarsest grid only
+    int kc = 1 << 20;
+    for (size_t i = 0; i < m.prob_ent.size(); ++i) {
+        int ki = 0;
+        const auto &pe = m.prob_ent[i];
+        for (int k = 1; k < (int)pe.size() && k < 8; ++k) {
+            const auto &e = m.ent[pe[k]];
+            if (e.amr > 0 || e.nb > kMaxCoarseBricks) break;
+            ki = k;
+        }
+        kc = std::min(kc, ki);
+    }
+    D.kc = kc;
+    {
+        int maxn = 0;
+        for (size_t i = 0; i < m.prob_ent.size(); ++i) maxn = std::max(maxn, m.ent[m.prob_ent[i][0]].nb * BRICK_CELLS);
+        D.cg_threads = maxn <= 512 ? 512 : 1024;
+    }
+    static thread_local std::vector<CoarseJob> cj;
+    cj.assign(m.prob_ent.size(), CoarseJob{});
+    for (size_t i = 0; i < m.prob_ent.size(); ++i) {
+        cj[i].nlev = kc + 1;
+        for (int k = 0; k <= kc; ++k) {
+            cj[i].b0[k] = m.ent[m.prob_ent[i][k]].b0;
+            cj[i].nb[k] = m.ent[m.prob_ent[i][k]].nb;
+        }
+        cj[i].cg_off = jobs[4 * i + 2];
+    }
+
+    Packer P;
+    int32_t *org = nullptr, *nbr = nullptr, *child = nullptr, *par = nullptr, *ustr = nullptr, *gfo = nullptr,
+            *cfi = nullptr, *drg = nullptr, *dj = nullptr;
+    uint8_t *cm = nullptr, *cfp = nullptr;
+    int64_t *ub = nullptr;
+    double *gbc = nullptr;
     LevelConst *dlc = nullptr;
-    ST_TRY(up(D, lc, &dlc));
+    P.add(m.org, &org);
+    P.add(m.nbr, &nbr);
+    P.add(m.child, &child);
+    P.add(m.par, &par);
+    P.add(m.cmask, &cm);
+    P.add(m.ubase, &ub);
+    P.add(m.ustr, &ustr);
+    P.add(m.gf_owner, &gfo);
+    P.add(m.gbc, &gbc);
+    P.add(m.cf_pat, &cfp);
+    P.add(m.cf_idx, &cfi);
+    P.add(m.reflux, &D.d_reflux);
+    P.add(m.amr_bricks, &D.d_amr);
+    P.add(lc, &dlc);
+    P.add(rg, &drg);
+    P.add(jobs, &dj);
+    P.add(cj, &D.d_cjobs);
+    D.d_bmap.assign(bmaps ? bmaps->size() : 0, nullptr);
+    if (bmaps)
+        for (size_t l = 0; l < bmaps->size(); ++l) P.add((*bmaps)[l], &D.d_bmap[l]);
+    ST_TRY(P.run(D.metabuf, D.stage, st));
     D.M.org = (const int4 *)org;
     D.M.nbr = nbr;
     D.M.child = child;
@@ -154,55 +301,25 @@ static amrmg_status upload_meta(DevState &D)
     D.M.lc = dlc;
     D.M.nbc = m.nbc;
     D.M.ncf = m.ncf;
-    // norm ranges: every AMR level of every problem, entry order
-    std::vector<int32_t> rg;
-    D.range_prob.clear();
-    D.range_amr.clear();
-    for (const auto &e : m.ent)
-        if (e.amr >= 0) {
-            rg.push_back(e.b0);
-            rg.push_back(e.nb);
-            D.range_prob.push_back(e.prob);
-            D.range_amr.push_back(e.amr);
-        }
-    int32_t *drg = nullptr;
-    ST_TRY(up(D, rg, &drg));
     D.d_ranges = (int2 *)drg;
-    // bottom solves: the coarsest level of each problem
-    std::vector<int32_t> jobs;
-    size_t off = 0;
-    for (size_t i = 0; i < m.prob_ent.size(); ++i) {
-        const auto &e = m.ent[m.prob_ent[i][0]];
-        jobs.push_back(e.b0);
-        jobs.push_back(e.nb);
-        jobs.push_back((int32_t)off);
-        jobs.push_back(0);
-        off += (size_t)4 * e.nb * BRICK_CELLS;
-    }
-    int32_t *dj = nullptr;
-    ST_TRY(up(D, jobs, &dj));
     D.d_jobs = (int4 *)dj;
-    D.njobs = (int)m.prob_ent.size();
-    D.cg_doubles = off;
     // per-level pointer tables (filled per call)
     size_t ne = m.ent.size();
     D.h_phi.assign(ne, nullptr);
     D.h_rho.assign(ne, nullptr);
     D.h_rout.assign(ne, nullptr);
     D.h_E.assign(3 * ne, nullptr);
-    for (double ***pp : {&D.d_phi, &D.d_rho, &D.d_rout}) {
-        void *p = nullptr;
-        HIP_TRY(hipMalloc(&p, sizeof(double *) * ne));
-        D.allocs.push_back(p);
-        *pp = (double **)p;
-    }
-    {
-        void *p = nullptr;
-        HIP_TRY(hipMalloc(&p, sizeof(double *) * 3 * ne));
-        D.allocs.push_back(p);
-        D.d_E = (double **)p;
-    }
-    if (!D.h_norm) HIP_TRY(hipHostMalloc((void **)&D.h_norm, sizeof(double) * 2 * (D.range_prob.size() + 1)));
+    HIP_TRY(D.ptrbuf.ensure(sizeof(double *) * 6 * ne));
+    HIP_TRY(D.ptrstage.ensure(sizeof(double *) * 6 * ne));
+    D.d_phi = (double **)D.ptrbuf.p;
+    D.d_rho = D.d_phi + ne;
+    D.d_rout = D.d_rho + ne;
+    D.d_E = D.d_rout + ne;
+    HIP_TRY(D.h_normbuf.ensure(sizeof(double) * 2 * (D.range_prob.size() + 1)));
+    D.h_norm = (double *)D.h_normbuf.p;
+    D.ws_prec = -1;  // carve the workspace again for the new hierarchy
+    D.drop_graph();
+    ++D.meta_gen;
     return AMRMG_OK;
 }
 
@@ -228,18 +345,14 @@ static amrmg_status ensure_ws(DevState &D, int prec, void *user, size_t user_byt
     char *base = nullptr;
     if (user) {
         if (user_bytes < need) return fail(AMRMG_E_OOM, "caller workspace smaller than amrmg_workspace_size");
-        if (D.ws_owned && D.ws) (void)hipFree(D.ws);
+        if (D.ws == user && D.ws_prec == prec) return AMRMG_OK;
         D.ws = user;
-        D.ws_owned = false;
         D.ws_bytes = user_bytes;
-    } else if (!(D.ws_owned && D.ws && D.ws_bytes >= need)) {
-        if (D.ws_owned && D.ws) (void)hipFree(D.ws);
-        D.ws = nullptr;
-        D.ws_owned = false;
-        hipError_t e = hipMalloc(&D.ws, need);
-        if (e != hipSuccess) return fail(AMRMG_E_OOM, "workspace allocation failed");
-        D.ws_owned = true;
-        D.ws_bytes = need;
+    } else {
+        if (D.ws == D.ws_own.p && D.ws && D.ws_bytes >= need && D.ws_prec == prec) return AMRMG_OK;
+        if (D.ws_own.ensure(need) != hipSuccess) return fail(AMRMG_E_OOM, "workspace allocation failed");
+        D.ws = D.ws_own.p;
+        D.ws_bytes = D.ws_own.cap;
     }
     base = (char *)D.ws;
     const Meta &m = D.meta;
@@ -259,6 +372,8 @@ static amrmg_status ensure_ws(DevState &D, int prec, void *user, size_t user_byt
     D.dnorm = (double *)take(sizeof(double) * 2 * (D.range_prob.size() + 1));
     D.cgw = (double *)take(D.cg_doubles * 8);
     D.cgit = (int *)take(64);
+    D.ncounter = (unsigned *)((char *)D.cgit + 32);
+    HIP_TRY(hipMemset(D.ncounter, 0, sizeof(unsigned)));
     D.ws_prec = prec;
     return AMRMG_OK;
 }
@@ -276,7 +391,8 @@ struct Prof {
         double bytes;
     };
     std::vector<Rec> recs;
-    hipStream_t st = nullptr;
+    double tot_ms[AMRMG_K_NCLASS] = {}, tot_bytes[AMRMG_K_NCLASS] = {};
+    int64_t tot_n[AMRMG_K_NCLASS] = {};
     size_t pending = (size_t)-1;
     int pending_cls = -1;
 
@@ -284,27 +400,48 @@ struct Prof {
     void begin(int cls)
     {
         pending = (size_t)-1;
-        if (!on(cls) || used + 2 > pool.size()) return;
+        if (!on(cls)) return;
+        if (used + 2 > pool.size()) flush();
+        if (used + 2 > pool.size()) return;
         pending = used;
         pending_cls = cls;
-        (void)hipEventRecord(pool[used], st);
+        set_launch_timing(pool[used], pool[used + 1]);
         used += 2;
     }
     void end(int cls, double bytes)
     {
         if (pending == (size_t)-1 || pending_cls != cls) return;
-        (void)hipEventRecord(pool[pending + 1], st);
-        recs.push_back({cls, pending, bytes});
+        if (launch_timing_pending()) {  // the launcher launched nothing
+            set_launch_timing(nullptr, nullptr);
+            used -= 2;
+        } else {
+            recs.push_back({cls, pending, bytes});
+        }
         pending = (size_t)-1;
     }
-    void reset(uint32_t m, hipStream_t s)
+    // fold the recorded launches into the totals (waits for them)
+    void flush()
+    {
+        for (const auto &r : recs) {
+            float e = 0.f;
+            if (hipEventSynchronize(pool[r.ev + 1]) == hipSuccess &&
+                hipEventElapsedTime(&e, pool[r.ev], pool[r.ev + 1]) == hipSuccess) {
+                tot_ms[r.cls] += e;
+                tot_bytes[r.cls] += r.bytes;
+                tot_n[r.cls] += 1;
+            }
+        }
+        recs.clear();
+        used = 0;
+    }
+    void reset(uint32_t m)
     {
         mask = m;
-        st = s;
         used = 0;
         recs.clear();
+        for (int c = 0; c < AMRMG_K_NCLASS; ++c) tot_ms[c] = tot_bytes[c] = 0.0, tot_n[c] = 0;
         if (m && pool.empty()) {
-            pool.resize(1 << 16);
+            pool.resize(1 << 12);
             for (auto &e : pool) (void)hipEventCreate(&e);
         }
     }
@@ -324,7 +461,15 @@ struct amrmg_ctx {
     Problem prob;
     bool built = false;
     DevState ds;
-    std::vector<int32_t *> d_bmap;  // per AMR level: brick grid -> global brick
+    // scratch of the tagging passes of build_hierarchy
+    DBuf tag_rho, tag_marks, tag_scratch, tag_geom;
+    PBuf tag_stage, tag_host;
+    // spatial visiting order of the particles (a performance hint for the
+    // deposit; any order gives the same sums up to rounding)
+    DBuf sort_keys, sort_vals, sort_tmp;
+    uint32_t *perm = nullptr;
+    int64_t perm_n = -1;
+    DBuf dep_count;
     void *user_ws = nullptr;
     size_t user_ws_bytes = 0;
     int generation = 0;
@@ -333,11 +478,7 @@ struct amrmg_ctx {
     std::vector<int> batch_gen;
     DevState *batch = nullptr;
     Prof prof;
-    ~amrmg_ctx()
-    {
-        for (auto p : d_bmap) (void)hipFree(p);
-        delete batch;
-    }
+    ~amrmg_ctx() { delete batch; }
 };
 
 extern "C" void amrmg_default_params(amrmg_params *p)
@@ -364,7 +505,7 @@ extern "C" void amrmg_default_params(amrmg_params *p)
     p->omega = 6.0 / 7.0;
     p->norm_p = 2;
     p->max_iters = 50;
-    p->bottom_rtol = 1e-6;
+    p->bottom_rtol = 1e-2;
 }
 
 extern "C" const char *amrmg_last_error(void) { return g_err.c_str(); }
@@ -384,7 +525,8 @@ static amrmg_status check_params(const amrmg_params *p)
     if (!(p->eps0 > 0)) return fail(AMRMG_E_INVALID, "eps0 must be positive");
     if (p->n_monopoles < 0 || (p->n_monopoles > 0 && !p->monopoles)) return fail(AMRMG_E_INVALID, "bad monopoles");
     if (p->precision != AMRMG_FP64 && p->precision != AMRMG_MIXED) return fail(AMRMG_E_INVALID, "bad precision");
-    if (p->smoother != AMRMG_GSRB && p->smoother != AMRMG_JACOBI) return fail(AMRMG_E_INVALID, "bad smoother");
+    if (p->smoother != AMRMG_GSRB && p->smoother != AMRMG_JACOBI && p->smoother != AMRMG_GSRB_GLOBAL)
+        return fail(AMRMG_E_INVALID, "bad smoother");
     if (p->nu1 < 1 || p->nu2 < 1 || p->nu1 > 64 || p->nu2 > 64) return fail(AMRMG_E_INVALID, "nu1, nu2 in [1, 64]");
     if (p->norm_p != 0 && p->norm_p != 1 && p->norm_p != 2) return fail(AMRMG_E_INVALID, "norm_p must be 0, 1 or 2");
     if (p->max_iters < 0) return fail(AMRMG_E_INVALID, "max_iters must be >= 0");
@@ -409,20 +551,6 @@ extern "C" amrmg_status amrmg_create(const amrmg_params *p, void *hip_stream, am
 
 extern "C" void amrmg_destroy(amrmg_ctx *ctx) { delete ctx; }
 
-// device brick map and user mapping of one level, for deposits during the
-// build (local brick ids)
-struct LevelDev {
-    int32_t *bmap = nullptr;
-    int64_t *ubase = nullptr;
-    int2 *ustr = nullptr;
-    ~LevelDev()
-    {
-        if (bmap) (void)hipFree(bmap);
-        if (ubase) (void)hipFree(ubase);
-        if (ustr) (void)hipFree(ustr);
-    }
-};
-
 static DepLevel dep_level(const Problem &P, const HostLevel &L, const int32_t *bmap)
 {
     DepLevel D{};
@@ -438,24 +566,87 @@ static DepLevel dep_level(const Problem &P, const HostLevel &L, const int32_t *b
     return D;
 }
 
-static amrmg_status level_dev(const HostLevel &L, LevelDev &out)
+// Morton order of the particles at the resolution of the finest allowed level
+static amrmg_status compute_order(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y, const void *z,
+                                  int64_t n)
 {
-    std::vector<int64_t> ub(L.nbrick());
-    std::vector<int32_t> us(2 * (size_t)L.nbrick());
-    for (int b = 0; b < L.nbrick(); ++b) {
+    ctx->perm = nullptr;
+    ctx->perm_n = -1;
+    if (n <= 0 || n > (int64_t)0x7fffffff) return AMRMG_OK;
+    const amrmg_params &P = ctx->P;
+    int nf[3];
+    for (int d = 0; d < 3; ++d) nf[d] = P.n0[d] << P.max_level;
+    size_t tb = sort_temp_bytes(n);
+    HIP_TRY(ctx->sort_keys.ensure(sizeof(uint64_t) * 2 * n));
+    HIP_TRY(ctx->sort_vals.ensure(sizeof(uint32_t) * 2 * n));
+    HIP_TRY(ctx->sort_tmp.ensure(tb));
+    uint32_t *perm = nullptr;
+    HIP_TRY(particle_order(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, P.lo, P.hi, nf,
+                           (uint64_t *)ctx->sort_keys.p, (uint32_t *)ctx->sort_vals.p, ctx->sort_tmp.p,
+                           ctx->sort_tmp.cap, &perm));
+    ctx->perm = perm;
+    ctx->perm_n = n;
+    return AMRMG_OK;
+}
+
+// Tagging pass on level l: deposit, tag, dilate and mark the blocks of level
+// l+1 on the device; the host then applies nesting and the greedy merge.
+static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype, const void *x, const void *y,
+                              const void *z, const double *q, int64_t n, double lambda, std::vector<Box> &boxes)
+{
+    const amrmg_params &P = ctx->P;
+    hipStream_t st = ctx->st;
+    int nb = L.nbrick();
+    int64_t nc = L.ncells();
+    static thread_local std::vector<int32_t> borg;
+    static thread_local std::vector<int64_t> ub;
+    static thread_local std::vector<int32_t> us;
+    borg.resize(4 * (size_t)nb);
+    ub.resize(nb);
+    us.resize(2 * (size_t)nb);
+    for (int b = 0; b < nb; ++b) {
         const Box &B = L.boxes[L.bbox[b]];
         int64_t nx = B.hi[0] - B.lo[0], ny = B.hi[1] - B.lo[1];
+        for (int d = 0; d < 3; ++d) borg[4 * b + d] = 8 * L.bpos[3 * b + d];
+        borg[4 * b + 3] = 0;
         ub[b] = L.off[L.bbox[b]] + (8 * L.bpos[3 * b] - B.lo[0]) +
                 nx * ((8 * L.bpos[3 * b + 1] - B.lo[1]) + ny * (int64_t)(8 * L.bpos[3 * b + 2] - B.lo[2]));
         us[2 * b] = (int32_t)nx;
         us[2 * b + 1] = (int32_t)(nx * ny);
     }
-    HIP_TRY(hipMalloc(&out.bmap, sizeof(int32_t) * L.bmap.size()));
-    HIP_TRY(hipMemcpy(out.bmap, L.bmap.data(), sizeof(int32_t) * L.bmap.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&out.ubase, sizeof(int64_t) * ub.size()));
-    HIP_TRY(hipMemcpy(out.ubase, ub.data(), sizeof(int64_t) * ub.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&out.ustr, sizeof(int32_t) * us.size()));
-    HIP_TRY(hipMemcpy(out.ustr, us.data(), sizeof(int32_t) * us.size(), hipMemcpyHostToDevice));
+    Packer pk;
+    int32_t *d_borg = nullptr, *d_us = nullptr, *d_bmap = nullptr;
+    int64_t *d_ub = nullptr;
+    pk.add(borg, &d_borg);
+    pk.add(ub, &d_ub);
+    pk.add(us, &d_us);
+    pk.add(L.bmap, &d_bmap);
+    ST_TRY(pk.run(ctx->tag_geom, ctx->tag_stage, st));
+    const int half = P.blocking_factor / 2;
+    int3 nn = make_int3(L.n[0], L.n[1], L.n[2]);
+    int3 g = make_int3(2 * L.n[0] / P.blocking_factor, 2 * L.n[1] / P.blocking_factor, 2 * L.n[2] / P.blocking_factor);
+    size_t ng = (size_t)g.x * g.y * g.z;
+    HIP_TRY(ctx->tag_rho.ensure(sizeof(double) * nc));
+    HIP_TRY(ctx->tag_scratch.ensure(sizeof(double) * 1040));
+    HIP_TRY(ctx->tag_marks.ensure(ng));
+    HIP_TRY(ctx->tag_host.ensure(ng));
+    double *rho = (double *)ctx->tag_rho.p;
+    launch_fill(st, rho, nc, 0.0);
+    Problem &pr = ctx->prob;
+    DepArgs A{};
+    A.nlev = 1;
+    A.lev[0] = dep_level(pr, L, d_bmap);
+    A.rho[0] = rho;
+    A.ncell[0] = nc;
+    launch_deposit(st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, ctx->perm_n == n ? ctx->perm : nullptr, A, d_ub,
+                   (const int2 *)d_us, nullptr);
+    HIP_TRY(hipMemsetAsync(ctx->tag_marks.p, 0, ng, st));
+    launch_mark_blocks(st, rho, nc, (const int4 *)d_borg, d_ub, (const int2 *)d_us, nb, lambda, P.n_buffer, half, nn,
+                       g, (double *)ctx->tag_scratch.p, (uint8_t *)ctx->tag_marks.p);
+    HIP_TRY(hipMemcpyAsync(ctx->tag_host.p, ctx->tag_marks.p, ng, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipGetLastError());
+    boxes = merge_blocks(L, (uint8_t *)ctx->tag_host.p, P.n_proper, P.blocking_factor, P.max_grid_size);
     return AMRMG_OK;
 }
 
@@ -480,11 +671,8 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
         expl[e[0]].push_back(B);
     }
     ctx->built = false;
-    ctx->ds.release();
-    ctx->ds = DevState();
-    for (auto p : ctx->d_bmap) (void)hipFree(p);
-    ctx->d_bmap.clear();
     ++ctx->generation;
+    ST_TRY(compute_order(ctx, pos_dtype, x, y, z, n));
 
     Problem &pr = ctx->prob;
     pr = Problem();
@@ -509,28 +697,7 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
             boxes = expl[l + 1];
         } else {
             if (!tag_rel) return fail(AMRMG_E_INVALID, "tag_rel is NULL but a level needs tagging");
-            int64_t nc = L.ncells();
-            LevelDev ld;
-            ST_TRY(level_dev(L, ld));
-            double *rho = nullptr, *scratch = nullptr;
-            uint8_t *tags = nullptr;
-            HIP_TRY(hipMalloc(&rho, sizeof(double) * nc));
-            HIP_TRY(hipMalloc(&scratch, sizeof(double) * 1032));
-            HIP_TRY(hipMalloc(&tags, nc));
-            launch_fill(ctx->st, rho, nc, 0.0);
-            DepLevel D = dep_level(pr, L, ld.bmap);
-            launch_deposit(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, D, ld.ubase, ld.ustr, rho, nullptr);
-            launch_tag(ctx->st, rho, nc, tag_rel[l], scratch, tags);
-            std::vector<uint8_t> ht(nc);
-            hipError_t e1 = hipMemcpyAsync(ht.data(), tags, nc, hipMemcpyDeviceToHost, ctx->st);
-            hipError_t e2 = hipStreamSynchronize(ctx->st);
-            (void)hipFree(rho);
-            (void)hipFree(scratch);
-            (void)hipFree(tags);
-            HIP_TRY(e1);
-            HIP_TRY(e2);
-            HIP_TRY(hipGetLastError());
-            boxes = generate_boxes(L, ht.data(), P.n_buffer, P.n_proper, P.blocking_factor, P.max_grid_size);
+            ST_TRY(tag_level(ctx, L, pos_dtype, x, y, z, q, n, tag_rel[l], boxes));
         }
         if (boxes.empty()) break;
         std::string msg = check_nesting(L, boxes, P.n_proper);
@@ -545,19 +712,16 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
     add_levels_below(pr);
     build_meta({&pr}, ctx->ds.meta);
     if (!ctx->ds.meta.error.empty()) return fail(AMRMG_E_NESTING, ctx->ds.meta.error);
-    ST_TRY(upload_meta(ctx->ds));
     // per AMR level brick map with global brick ids
+    std::vector<std::vector<int32_t>> bmaps(pr.namr());
     for (int l = 0; l < pr.namr(); ++l) {
         const HostLevel &L = pr.lev[pr.kg + l];
         int b0 = ctx->ds.meta.ent[ctx->ds.meta.prob_ent[0][pr.kg + l]].b0;
-        std::vector<int32_t> bm(L.bmap);
-        for (auto &v : bm)
+        bmaps[l] = L.bmap;
+        for (auto &v : bmaps[l])
             if (v >= 0) v += b0;
-        int32_t *d = nullptr;
-        HIP_TRY(hipMalloc(&d, sizeof(int32_t) * bm.size()));
-        ctx->d_bmap.push_back(d);
-        HIP_TRY(hipMemcpy(d, bm.data(), sizeof(int32_t) * bm.size(), hipMemcpyHostToDevice));
     }
+    ST_TRY(upload_meta(ctx->ds, ctx->st, &bmaps));
     HIP_TRY(hipStreamSynchronize(ctx->st));
     ctx->built = true;
     return AMRMG_OK;
@@ -646,9 +810,10 @@ extern "C" amrmg_status amrmg_set_workspace(amrmg_ctx *ctx, void *dev, size_t by
     if (dev && ((uintptr_t)dev & 255)) return fail(AMRMG_E_INVALID, "workspace must be 256-byte aligned");
     if (dev && ctx->built && bytes < ws_need(ctx->ds, ctx->P.precision))
         return fail(AMRMG_E_OOM, "workspace smaller than amrmg_workspace_size");
-    if (!dev && ctx->ds.ws && !ctx->ds.ws_owned) {
+    if (!dev && ctx->ds.ws && ctx->ds.ws != ctx->ds.ws_own.p) {
         ctx->ds.ws = nullptr;
         ctx->ds.ws_bytes = 0;
+        ctx->ds.ws_prec = -1;
     }
     ctx->user_ws = dev;
     ctx->user_ws_bytes = dev ? bytes : 0;
@@ -665,25 +830,30 @@ extern "C" amrmg_status amrmg_deposit(amrmg_ctx *ctx, int pos_dtype, const void 
     const Problem &pr = ctx->prob;
     unsigned long long *dout = nullptr;
     if (n_outside) {
-        HIP_TRY(hipMallocAsync((void **)&dout, sizeof(unsigned long long), ctx->st));
+        HIP_TRY(ctx->dep_count.ensure(sizeof(unsigned long long)));
+        dout = (unsigned long long *)ctx->dep_count.p;
         HIP_TRY(hipMemsetAsync(dout, 0, sizeof(unsigned long long), ctx->st));
     }
+    DepArgs A{};
+    A.nlev = pr.namr();
     for (int l = 0; l < pr.namr(); ++l) {
         if (!rho[l]) return fail(AMRMG_E_INVALID, "rho[l] is NULL");
         const HostLevel &L = pr.lev[pr.kg + l];
-        launch_fill(ctx->st, rho[l], L.ncells(), 0.0);
-        DepLevel D = dep_level(pr, L, ctx->d_bmap[l]);
-        ctx->prof.begin(AMRMG_K_DEPOSIT);
-        launch_deposit(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, D, ctx->ds.M.ubase, ctx->ds.M.ustr, rho[l],
-                       l == 0 ? dout : nullptr);
-        ctx->prof.end(AMRMG_K_DEPOSIT, (double)n * (3.0 * (pos_dtype == AMRMG_POS_F32 ? 4 : 8) + 8.0) +
-                                           8.0 * (double)L.ncells());
+        A.lev[l] = dep_level(pr, L, ctx->ds.d_bmap[l]);
+        A.rho[l] = rho[l];
+        A.ncell[l] = L.ncells();
     }
+    launch_zero_levels(ctx->st, A);
+    int64_t cells = 0;
+    for (int l = 0; l < A.nlev; ++l) cells += A.ncell[l];
+    ctx->prof.begin(AMRMG_K_DEPOSIT);
+    launch_deposit(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, ctx->perm_n == n ? ctx->perm : nullptr, A,
+                   ctx->ds.M.ubase, ctx->ds.M.ustr, dout);
+    ctx->prof.end(AMRMG_K_DEPOSIT, (double)n * (3.0 * (pos_dtype == AMRMG_POS_F32 ? 4 : 8) + 8.0) + 8.0 * (double)cells);
     HIP_TRY(hipGetLastError());
     if (n_outside) {
         unsigned long long h = 0;
         HIP_TRY(hipMemcpyAsync(&h, dout, sizeof(h), hipMemcpyDeviceToHost, ctx->st));
-        HIP_TRY(hipFreeAsync(dout, ctx->st));
         HIP_TRY(hipStreamSynchronize(ctx->st));
         *n_outside = (int64_t)h;
     }
@@ -701,7 +871,7 @@ extern "C" amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *
     GatherArgs G{};
     G.nlev = pr.namr();
     for (int l = 0; l < G.nlev; ++l) {
-        G.lev[l] = dep_level(pr, pr.lev[pr.kg + l], ctx->d_bmap[l]);
+        G.lev[l] = dep_level(pr, pr.lev[pr.kg + l], ctx->ds.d_bmap[l]);
         for (int d = 0; d < 3; ++d) {
             if (!E[3 * l + d]) return fail(AMRMG_E_INVALID, "E component is NULL");
             G.E[3 * l + d] = E[3 * l + d];
@@ -717,6 +887,9 @@ extern "C" amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *
 // ---------------------------------------------------------------------------
 // the solve
 // ---------------------------------------------------------------------------
+// replay the outer iteration as a hipGraph (AMRMG_NO_GRAPH=1 disables)
+static bool g_use_graphs = getenv("AMRMG_NO_GRAPH") == nullptr;
+
 struct SolveOpts {
     int precision, smoother, nu1, nu2, norm_p, max_iters;
     double omega, bottom_rtol, inv_eps0;
@@ -776,9 +949,13 @@ struct Driver {
             launch_cpart_user(st, D.M, 0, m.ncf, D.d_phi, D.cpphi);
             pe(AMRMG_K_CPART, (double)m.ncf * 16 * (9 + 4) * 8);
         }
+        // (a last-workgroup reduction inside the residual kernel would need a
+        // device-scope fence per workgroup, which costs far more than this
+        // extra launch on a chip whose XCDs have separate L2 caches)
+        NormArgs NA{D.d_ranges, (int)D.range_prob.size(), D.dnorm + noff, nullptr};
         pb(AMRMG_K_RESIDUAL);
         launch_outer_residual<T>(st, D.M, b0, nb, list, D.d_phi, D.d_rho, o.inv_eps0, zero_phi ? nullptr : D.cpphi,
-                                 (zero_phi || rout_user) ? nullptr : r, D.part, o.norm_p, zero_phi, rout_user);
+                                 (zero_phi || rout_user) ? nullptr : r, D.part, o.norm_p, zero_phi, rout_user, NA);
         pe(AMRMG_K_RESIDUAL, (double)nb * BRICK_CELLS * (zero_phi ? 8.0 : 16.0 + W));
         launch_level_norms(st, D.d_ranges, (int)D.range_prob.size(), D.part, D.dnorm + noff, o.norm_p);
     }
@@ -788,7 +965,7 @@ struct Driver {
         int b0 = step_b0(k), nb = step_nb(k);
         const T *cp = pre ? nullptr : cpe;
         const double n = (double)nb * BRICK_CELLS;
-        if (o.smoother == AMRMG_GSRB) {
+        if (o.smoother == AMRMG_GSRB_GLOBAL) {
             for (int it = 0; it < nu; ++it) {
                 for (int colour = 0; colour < 2; ++colour) {
                     pb(AMRMG_K_GSRB);
@@ -822,10 +999,50 @@ struct Driver {
         }
     }
 
+    bool hybrid() const { return o.smoother == AMRMG_GSRB; }
+
+    void pre_hybrid(int k)
+    {
+        int b0 = step_b0(k), nb = step_nb(k);
+        const double n = (double)nb * BRICK_CELLS;
+        T *out = (o.nu1 % 2 == 1) ? e : et;
+        pb(AMRMG_K_GSRB);
+        launch_hgs<T>(st, D.M, b0, nb, nullptr, out, r, nullptr, D.d_phi, 1);
+        pe(AMRMG_K_GSRB, 2.0 * n * W);
+        T *src = out;
+        for (int i = 1; i < o.nu1; ++i) {
+            T *dst = (src == e) ? et : e;
+            pb(AMRMG_K_GSRB);
+            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, nullptr, D.d_phi, 0);
+            pe(AMRMG_K_GSRB, 3.0 * n * W);
+            src = dst;
+        }
+    }
+
+    void post_hybrid(int k)
+    {
+        int b0 = step_b0(k), nb = step_nb(k);
+        const double n = (double)nb * BRICK_CELLS;
+        T *src = e;
+        for (int i = 0; i < o.nu2; ++i) {
+            T *dst = (src == e) ? et : e;
+            int mode = (i == 0 ? 2 | 4 : 0) | (i == o.nu2 - 1 ? 8 : 0);
+            pb(AMRMG_K_GSRB);
+            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, cpe, D.d_phi, mode);
+            pe(AMRMG_K_GSRB, (3.0 + (i == 0 ? 0.125 : 0.0)) * n * W);
+            src = dst;
+        }
+        if (src != e) launch_copy<T>(st, et + (size_t)b0 * BRICK_CELLS, e + (size_t)b0 * BRICK_CELLS, (int64_t)nb * BRICK_CELLS);
+    }
+
     void vcycle()
     {
-        for (int k = m.K - 1; k >= 1; --k) {
-            smooth(k, o.nu1, true);
+        const int kc = D.kc;
+        for (int k = m.K - 1; k > kc; --k) {
+            if (hybrid())
+                pre_hybrid(k);
+            else
+                smooth(k, o.nu1, true);
             double n = (double)step_nb(k) * BRICK_CELLS;
             pb(AMRMG_K_RESTRICT);
             launch_restrict<T>(st, D.M, step_b0(k), step_nb(k), e, r, r);
@@ -839,9 +1056,14 @@ struct Driver {
             pe(AMRMG_K_REFLUX, 2.0 * nrf * BRICK_CELLS * W);
         }
         pb(AMRMG_K_BOTTOM);
-        launch_bottom_cg<T>(st, D.M, D.d_jobs, D.njobs, r, e, D.cgw, o.bottom_rtol, 10000, D.cgit);
+        launch_coarse_cycle<T>(st, D.M, D.d_cjobs, D.njobs, e, r, D.cgw, o.nu1, o.nu2, o.bottom_rtol, 10000, D.cgit,
+                               D.d_phi, hybrid(), D.cg_threads);
         pe(AMRMG_K_BOTTOM, (double)D.cg_doubles / 4 * (2 * W));
-        for (int k = 1; k < m.K; ++k) {
+        for (int k = kc + 1; k < m.K; ++k) {
+            if (hybrid()) {
+                post_hybrid(k);
+                continue;
+            }
             const auto &e0 = m.ent[m.step_ent0[k]];
             const auto &e1 = m.ent[m.step_ent0[k + 1] - 1];
             int ncf = e1.cf0 + e1.ncf - e0.cf0;
@@ -854,6 +1076,7 @@ struct Driver {
             pe(AMRMG_K_PROLONG, (2.0 + 0.125) * n * W);
             smooth(k, o.nu2, false);
         }
+        if (hybrid()) return;  // phi updated by the last sweep of each level and in the coarse cycle
         int b0, nb;
         const int32_t *list;
         amr_range(b0, nb, list);
@@ -861,7 +1084,47 @@ struct Driver {
         launch_phi_update<T>(st, D.M, b0, nb, list, D.d_phi, e);
         pe(AMRMG_K_PHI_UPDATE, (double)nb * BRICK_CELLS * (16.0 + W));
     }
+
+    // one outer iteration: V-cycle, phi += e, FP64 residual and its norms
+    void iteration(int nr)
+    {
+        vcycle();
+        outer(false, nr, nullptr);
+    }
 };
+
+// Run one outer iteration, through a captured graph when possible.  The
+// graph is instantiated once per hierarchy, workspace and option set.
+template <class T>
+static amrmg_status iterate(DevState &D, Driver<T> &drv, hipStream_t st, int nr, const SolveOpts &o, bool graphs)
+{
+    if (!graphs || drv.P) {
+        drv.iteration(nr);
+        return AMRMG_OK;
+    }
+    std::vector<int64_t> key = {D.meta_gen, (int64_t)(intptr_t)D.ws, (int64_t)sizeof(T), o.smoother, o.nu1, o.nu2,
+                                o.norm_p, (int64_t)(o.omega * 1e12), (int64_t)(o.bottom_rtol * 1e15),
+                                (int64_t)(o.inv_eps0 * 1e12)};
+    if (!D.gexec || D.gkey != key) {
+        D.drop_graph();
+        if (!D.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&D.cap_stream, hipStreamNonBlocking));
+        Driver<T> cap(D, D.cap_stream, o, nullptr);
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(D.cap_stream, hipStreamCaptureModeThreadLocal));
+        cap.iteration(nr);
+        hipError_t ec = hipStreamEndCapture(D.cap_stream, &g);
+        if (ec != hipSuccess) return fail(AMRMG_E_HIP, std::string("graph capture: ") + hipGetErrorString(ec));
+        hipError_t ei = hipGraphInstantiate(&D.gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            D.gexec = nullptr;
+            return fail(AMRMG_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        }
+        D.gkey = key;
+    }
+    HIP_TRY(hipGraphLaunch(D.gexec, st));
+    return AMRMG_OK;
+}
 
 // run a solve on a DevState whose pointer tables are set; per-problem stats
 template <class T>
@@ -910,8 +1173,7 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
     int it = 0;
     bool all = check(0);
     while (!all && it < o.max_iters) {
-        drv.vcycle();
-        drv.outer(false, nr, nullptr);
+        ST_TRY(iterate<T>(D, drv, st, nr, o, g_use_graphs));
         HIP_TRY(hipMemcpyAsync(D.h_norm + nr, D.dnorm + nr, sizeof(double) * nr, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         HIP_TRY(hipGetLastError());
@@ -981,9 +1243,12 @@ static SolveOpts opts_of(const amrmg_params &P)
 static amrmg_status set_tables(DevState &D, hipStream_t st)
 {
     size_t ne = D.meta.ent.size();
-    HIP_TRY(hipMemcpyAsync(D.d_phi, D.h_phi.data(), sizeof(double *) * ne, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(D.d_rho, D.h_rho.data(), sizeof(double *) * ne, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(D.d_E, D.h_E.data(), sizeof(double *) * 3 * ne, hipMemcpyHostToDevice, st));
+    double **h = (double **)D.ptrstage.p;
+    std::memcpy(h, D.h_phi.data(), sizeof(double *) * ne);
+    std::memcpy(h + ne, D.h_rho.data(), sizeof(double *) * ne);
+    std::memcpy(h + 2 * ne, D.h_rout.data(), sizeof(double *) * ne);
+    std::memcpy(h + 3 * ne, D.h_E.data(), sizeof(double *) * 3 * ne);
+    HIP_TRY(hipMemcpyAsync(D.ptrbuf.p, h, sizeof(double *) * 6 * ne, hipMemcpyHostToDevice, st));
     return AMRMG_OK;
 }
 
@@ -999,6 +1264,7 @@ extern "C" amrmg_status amrmg_solve(amrmg_ctx *ctx, double *const *rho, double *
     std::fill(D.h_phi.begin(), D.h_phi.end(), nullptr);
     std::fill(D.h_rho.begin(), D.h_rho.end(), nullptr);
     std::fill(D.h_E.begin(), D.h_E.end(), nullptr);
+    std::fill(D.h_rout.begin(), D.h_rout.end(), nullptr);
     for (int l = 0; l < pr.namr(); ++l) {
         if (!rho[l] || !phi[l]) return fail(AMRMG_E_INVALID, "rho[l] and phi[l] must be set");
         int ei = D.meta.prob_ent[0][pr.kg + l];
@@ -1031,6 +1297,7 @@ extern "C" amrmg_status amrmg_residual(amrmg_ctx *ctx, double *const *rho, doubl
     std::fill(D.h_phi.begin(), D.h_phi.end(), nullptr);
     std::fill(D.h_rho.begin(), D.h_rho.end(), nullptr);
     std::fill(D.h_rout.begin(), D.h_rout.end(), nullptr);
+    std::fill(D.h_E.begin(), D.h_E.end(), nullptr);
     for (int l = 0; l < pr.namr(); ++l) {
         if (!rho[l] || !phi[l] || !r[l]) return fail(AMRMG_E_INVALID, "level arrays must be set");
         int ei = D.meta.prob_ent[0][pr.kg + l];
@@ -1040,8 +1307,6 @@ extern "C" amrmg_status amrmg_residual(amrmg_ctx *ctx, double *const *rho, doubl
     }
     ST_TRY(ensure_ws(D, ctx->P.precision, ctx->user_ws, ctx->user_ws_bytes));
     ST_TRY(set_tables(D, ctx->st));
-    size_t ne = D.meta.ent.size();
-    HIP_TRY(hipMemcpyAsync(D.d_rout, D.h_rout.data(), sizeof(double *) * ne, hipMemcpyHostToDevice, ctx->st));
     SolveOpts o = opts_of(ctx->P);
     Driver<double> drv(D, ctx->st, o, nullptr);
     drv.outer(false, 0, D.d_rout);
@@ -1066,7 +1331,7 @@ extern "C" amrmg_status amrmg_profile_enable(amrmg_ctx *ctx, uint32_t mask)
 {
     if (!ctx) return fail(AMRMG_E_INVALID, "ctx is NULL");
     HIP_TRY(hipStreamSynchronize(ctx->st));
-    ctx->prof.reset(mask, ctx->st);
+    ctx->prof.reset(mask);
     return AMRMG_OK;
 }
 
@@ -1076,18 +1341,9 @@ extern "C" amrmg_status amrmg_profile_read(amrmg_ctx *ctx, int32_t kclass, doubl
     if (!ctx) return fail(AMRMG_E_INVALID, "ctx is NULL");
     if (kclass < 0 || kclass >= AMRMG_K_NCLASS) return fail(AMRMG_E_INVALID, "bad kernel class");
     HIP_TRY(hipStreamSynchronize(ctx->st));
-    double t = 0.0, b = 0.0;
-    int64_t n = 0;
-    for (const auto &r : ctx->prof.recs) {
-        if (r.cls != kclass) continue;
-        float e = 0.f;
-        HIP_TRY(hipEventElapsedTime(&e, ctx->prof.pool[r.ev], ctx->prof.pool[r.ev + 1]));
-        t += e;
-        b += r.bytes;
-        ++n;
-    }
-    if (ms) *ms = t;
-    if (launches) *launches = n;
-    if (bytes) *bytes = b;
+    ctx->prof.flush();
+    if (ms) *ms = ctx->prof.tot_ms[kclass];
+    if (launches) *launches = ctx->prof.tot_n[kclass];
+    if (bytes) *bytes = ctx->prof.tot_bytes[kclass];
     return AMRMG_OK;
 }

@@ -85,16 +85,13 @@ static void grown_footprint(const HostLevel &C, const int blk[3], int half, int 
     }
 }
 
-std::vector<Box> generate_boxes(const HostLevel &L, const uint8_t *tags, int n_buffer, int n_proper, int bf,
-                                int max_grid_size)
+void mark_blocks(const HostLevel &L, const uint8_t *tags, int n_buffer, int bf, std::vector<uint8_t> &mark)
 {
     const int half = bf / 2;  // coarse cells per fine block edge
     int g[3];
     for (int d = 0; d < 3; ++d) g[d] = 2 * L.n[d] / bf;
     auto at = [&](int x, int y, int z) { return (size_t)x + (size_t)g[0] * ((size_t)y + (size_t)g[1] * z); };
-    std::vector<uint8_t> mark((size_t)g[0] * g[1] * g[2], 0);
-
-    // 1-2: dilated tags -> blocks of the finer level
+    mark.assign((size_t)g[0] * g[1] * g[2], 0);
     for (size_t b = 0; b < L.boxes.size(); ++b) {
         const Box &B = L.boxes[b];
         int64_t t = L.off[b];
@@ -110,6 +107,14 @@ std::vector<Box> generate_boxes(const HostLevel &L, const uint8_t *tags, int n_b
                             for (int x = xlo / half; x <= xhi / half; ++x) mark[at(x, y, z)] = 1;
                 }
     }
+}
+
+std::vector<Box> merge_blocks(const HostLevel &L, uint8_t *mark, int n_proper, int bf, int max_grid_size)
+{
+    const int half = bf / 2;
+    int g[3];
+    for (int d = 0; d < 3; ++d) g[d] = 2 * L.n[d] / bf;
+    auto at = [&](int x, int y, int z) { return (size_t)x + (size_t)g[0] * ((size_t)y + (size_t)g[1] * z); };
     // 3: proper nesting
     for (int z = 0; z < g[2]; ++z)
         for (int y = 0; y < g[1]; ++y)
@@ -155,6 +160,14 @@ std::vector<Box> generate_boxes(const HostLevel &L, const uint8_t *tags, int n_b
                 out.push_back(B);
             }
     return out;
+}
+
+std::vector<Box> generate_boxes(const HostLevel &L, const uint8_t *tags, int n_buffer, int n_proper, int bf,
+                                int max_grid_size)
+{
+    std::vector<uint8_t> mark;
+    mark_blocks(L, tags, n_buffer, bf, mark);
+    return merge_blocks(L, mark.data(), n_proper, bf, max_grid_size);
 }
 
 std::string check_nesting(const HostLevel &C, const std::vector<Box> &fine, int n_proper)
@@ -238,10 +251,15 @@ uint32_t quadratic_mask(int pat) { return window_mask(pat); }
 
 int select_pattern(uint32_t mask5)
 {
-    for (int p = 0; p < 13; ++p) {
-        uint32_t w = window_mask(p);
-        if ((mask5 & w) == w) return p;
-    }
+    static const struct Masks {
+        uint32_t m[13];
+        Masks()
+        {
+            for (int p = 0; p < 13; ++p) m[p] = window_mask(p);
+        }
+    } W;
+    for (int p = 0; p < 13; ++p)
+        if ((mask5 & W.m[p]) == W.m[p]) return p;
     return 13;
 }
 
@@ -459,40 +477,46 @@ void build_meta(const std::vector<const Problem *> &probs, Meta &M)
         tdirs(d, du, dv);
         int O[3] = {M.org[(size_t)g * 4], M.org[(size_t)g * 4 + 1], M.org[(size_t)g * 4 + 2]};
         int ghost_d = s > 0 ? O[d] + 8 : O[d] - 1;
+        // the coarse layer cells within 2 of the face's 4x4 coarse cells:
+        // their cycle-array index (or -1 when not on the coarser level) and
+        // availability (on the coarser level and not covered)
+        int32_t gidx[8][8];
+        uint8_t av[8][8];
+        for (int jv = 0; jv < 8; ++jv)
+            for (int iu = 0; iu < 8; ++iu) {
+                int Pc[3];
+                Pc[d] = ghost_d >> 1;
+                Pc[du] = O[du] / 2 - 2 + iu;
+                Pc[dv] = O[dv] / 2 - 2 + jv;
+                int q = -1;
+                if (Pc[0] >= 0 && Pc[1] >= 0 && Pc[2] >= 0 && Pc[0] < Lc.n[0] && Pc[1] < Lc.n[1] && Pc[2] < Lc.n[2])
+                    q = Lc.brick_at(Pc[0] >> 3, Pc[1] >> 3, Pc[2] >> 3);
+                gidx[jv][iu] = q < 0 ? -1 : (ec.b0 + q) * 512 + (Pc[0] & 7) + 8 * (Pc[1] & 7) + 64 * (Pc[2] & 7);
+                av[jv][iu] = q >= 0 && !Lf.has_cell(2 * Pc[0], 2 * Pc[1], 2 * Pc[2]);
+            }
         for (int m = 0; m < 16; ++m) {
-            int C[3];
-            C[d] = ghost_d >> 1;
-            C[du] = O[du] / 2 + (m & 3);
-            C[dv] = O[dv] / 2 + (m >> 2);
+            int mu = m & 3, mv = m >> 2;
             uint32_t mask = 0;
             for (int jv = 0; jv < 5; ++jv)
-                for (int iu = 0; iu < 5; ++iu) {
-                    int Pc[3] = {C[0], C[1], C[2]};
-                    Pc[du] += iu - 2;
-                    Pc[dv] += jv - 2;
-                    if (Lc.has_cell(Pc[0], Pc[1], Pc[2]) && !Lf.has_cell(2 * Pc[0], 2 * Pc[1], 2 * Pc[2]))
-                        mask |= 1u << (iu + 5 * jv);
-                }
+                for (int iu = 0; iu < 5; ++iu)
+                    if (av[mv + jv][mu + iu]) mask |= 1u << (iu + 5 * jv);
             int pat = select_pattern(mask);
             int u0, v0, npn;
             pattern_window(pat, u0, v0, npn);
             M.cf_pat[(size_t)t * 16 + m] = (uint8_t)pat;
             for (int b = 0; b < 3; ++b)
                 for (int a = 0; a < 3; ++a) {
-                    int Nd[3] = {C[0], C[1], C[2]};
+                    int ou = 0, ov = 0;  // unused nodes point at the centre (weight 0)
                     if (a < npn && b < npn) {
-                        Nd[du] += u0 + a;
-                        Nd[dv] += v0 + b;
+                        ou = u0 + a;
+                        ov = v0 + b;
                     }
-                    int q = Lc.brick_at(Nd[0] >> 3, Nd[1] >> 3, Nd[2] >> 3);
-                    if (q < 0 || !Lc.has_cell(Nd[0], Nd[1], Nd[2])) {
+                    int32_t gi = gidx[mv + 2 + ov][mu + 2 + ou];
+                    if (gi < 0) {
                         M.error = "coarse-fine window leaves the coarser level (nesting violated)";
-                        q = 0;
-                        Nd[0] = Nd[1] = Nd[2] = 0;
+                        gi = 0;
                     }
-                    int gb = ec.b0 + q;
-                    M.cf_idx[((size_t)t * 16 + m) * 9 + a + 3 * b] =
-                        gb * 512 + (Nd[0] & 7) + 8 * (Nd[1] & 7) + 64 * (Nd[2] & 7);
+                    M.cf_idx[((size_t)t * 16 + m) * 9 + a + 3 * b] = gi;
                 }
         }
     }

@@ -45,6 +45,11 @@ void level_init(HostLevel &L, const int n[3], const double lo[3], const double h
 // with edges of at most max_grid_size cells.
 std::vector<Box> generate_boxes(const HostLevel &L, const uint8_t *tags, int n_buffer, int n_proper, int bf,
                                 int max_grid_size);
+// the same procedure split in two: marking the blocks of the finer level
+// (size (2 n / bf)^3, 1 = tagged) from cell tags, and nesting + merge of a
+// block mask (which it modifies)
+void mark_blocks(const HostLevel &L, const uint8_t *tags, int n_buffer, int bf, std::vector<uint8_t> &mark);
+std::vector<Box> merge_blocks(const HostLevel &L, uint8_t *mark, int n_proper, int bf, int max_grid_size);
 
 // Check boxes of a refined level against its coarser level: 8-alignment,
 // inside the index space, disjoint, and proper nesting.  Empty string = ok.

@@ -12,6 +12,7 @@
 // receive workgroups round robin) walks a contiguous run of bricks and keeps
 // neighbouring halos in its own L2.  Arithmetic is FP64; the cycle arrays are
 // stored in T (float in mixed precision, double otherwise).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "amrmg_internal.hpp"
@@ -22,6 +23,27 @@ namespace amrmg {
 // step-1 weights of the coarse-fine ghost, already multiplied by the step-2
 // weight 8/15 of the coarse node: [pattern 0..13][quadrant 0..3][node 0..8]
 __constant__ double c_cfw[14 * 4 * 9];
+
+// optional kernel-execution timestamps for the next launch (profiling)
+static thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+
+void set_launch_timing(hipEvent_t start, hipEvent_t stop)
+{
+    g_ev_start = start;
+    g_ev_stop = stop;
+}
+
+bool launch_timing_pending() { return g_ev_start != nullptr; }
+
+#define AMRMG_LAUNCH(kernel, grid, block, shmem, stream, ...)                                              \
+    do {                                                                                                   \
+        if (g_ev_start) {                                                                                  \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, g_ev_start, g_ev_stop, 0, __VA_ARGS__); \
+            g_ev_start = g_ev_stop = nullptr;                                                              \
+        } else {                                                                                           \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                           \
+        }                                                                                                  \
+    } while (0)
 
 hipError_t upload_cf_weights(const double *w)
 {
@@ -171,6 +193,146 @@ __device__ double block_reduce_256(double v, int op)
     return r;
 }
 
+// The last workgroup of a launch to finish reduces the per-brick partials to
+// one norm per listed brick range, in a fixed order, and resets the counter
+// for the next launch.
+__device__ void level_norms_last_block(const double *part, const NormArgs &NA, int norm_p)
+{
+    if (!NA.counter) return;
+    __shared__ int last;
+    __threadfence();
+    if (threadIdx.x == 0) last = (atomicAdd(NA.counter, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int l = 0; l < NA.n; ++l) {
+        int2 rg = NA.ranges[l];
+        double acc = 0.0;
+        for (int b = rg.x + (int)threadIdx.x; b < rg.x + rg.y; b += 256)
+            acc = norm_p == 0 ? fmax(acc, part[b]) : acc + part[b];
+        acc = block_reduce_256(acc, norm_p == 0);
+        if (threadIdx.x == 0) NA.out[l] = norm_p == 2 ? sqrt(acc) : acc;
+    }
+    if (threadIdx.x == 0) *NA.counter = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// LDS tile of one brick: the 8^3 cells plus one halo layer on the six faces
+// (edges and corners are never read by the 7-point stencil).  A halo cell
+// across a same-level face holds the neighbour's value; across a boundary or
+// coarse-fine face it holds bv of the ghost a*u_c + bv, and alpha[face] holds
+// a.  All loads of a tile are independent and issued before one barrier.
+// ---------------------------------------------------------------------------
+constexpr int TE = 10;
+__device__ __forceinline__ int tix(int x, int y, int z) { return (x + 1) + TE * ((y + 1) + TE * (z + 1)); }
+
+template <class T>
+struct SrcB {  // brick-layout array
+    const T *u;
+    __device__ double operator()(int b, int c) const { return (double)u[(size_t)b * BRICK_CELLS + c]; }
+};
+struct SrcZ {
+    __device__ double operator()(int, int) const { return 0.0; }
+};
+struct SrcU {  // caller's layout, level looked up from the brick
+    double *const *p;
+    const int4 *org;
+    const int64_t *ubase;
+    const int2 *ustr;
+    __device__ double operator()(int b, int c) const
+    {
+        int2 s = ustr[b];
+        return p[org[b].w][ubase[b] + (c & 7) + (int64_t)s.x * ((c >> 3) & 7) + (int64_t)s.y * (c >> 6)];
+    }
+};
+
+// coarse parts of coarse-fine ghosts, by face id and face-local cell
+struct CpNone {
+    __device__ double operator()(size_t, int) const { return 0.0; }
+};
+template <class T>
+struct CpArr {
+    const T *cp;
+    __device__ double operator()(size_t cf, int fl) const { return cp ? (double)cp[cf * 64 + fl] : 0.0; }
+};
+// computed on the spot from the coarse level's cycle array (step 1 of the
+// two-step interpolation times 8/15), optionally stored for later sweeps
+template <class T>
+struct CpInline {
+    const DevMeta *M;
+    const T *ec;
+    T *store;
+    __device__ double operator()(size_t cf, int fl) const
+    {
+        int iu = fl & 7, iv = fl >> 3;
+        int m = (iu >> 1) + 4 * (iv >> 1), q = (iu & 1) + 2 * (iv & 1);
+        size_t e = cf * 16 + m;
+        int pat = M->cf_pat[e];
+        const double *W = c_cfw + (pat * 4 + q) * 9;
+        double v = 0.0;
+        for (int w = 0; w < 9; ++w) v += W[w] * (double)ec[M->cf_idx[e * 9 + w]];
+        if (store) store[cf * 64 + fl] = (T)v;
+        return v;
+    }
+};
+
+template <class S, bool ZERO = false, class CP = CpNone>
+__device__ void stage_tile(const DevMeta &M, int b, const S &src, const CP &cp, bool inhom, double *tile,
+                           double *alpha)
+{
+    for (int c = threadIdx.x; c < BRICK_CELLS; c += blockDim.x)
+        tile[tix(c & 7, (c >> 3) & 7, c >> 6)] = ZERO ? 0.0 : src(b, c);
+    for (int t = threadIdx.x; t < 384; t += blockDim.x) {
+        int f = t >> 6, d = f >> 1, s = (f & 1) ? 1 : -1;
+        int iu = t & 7, iv = (t >> 3) & 7, fl = t & 63;
+        int du, dv;
+        transverse(d, du, dv);
+        int l[3];
+        l[du] = iu;
+        l[dv] = iv;
+        l[d] = s > 0 ? 8 : -1;
+        int nb = M.nbr[b * 6 + f];
+        double v, a = 0.0;
+        if (nb >= 0) {
+            int m[3] = {l[0], l[1], l[2]};
+            m[d] = s > 0 ? 0 : 7;
+            v = ZERO ? 0.0 : src(nb, m[0] + 8 * m[1] + 64 * m[2]);
+        } else {
+            int g = -1 - nb;
+            if (g < M.nbc) {
+                a = -1.0;
+                v = inhom ? 2.0 * M.gbc[(size_t)g * 64 + fl] : 0.0;
+            } else {
+                a = 2.0 / 3.0;
+                v = cp((size_t)(g - M.nbc), fl);
+            }
+        }
+        tile[tix(l[0], l[1], l[2])] = v;
+        if (fl == 0) alpha[f] = a;
+    }
+    __syncthreads();
+}
+
+// Ghost form a * u_c + bv of the neighbour of tile cell (x,y,z) across
+// (d, s).  A coarse-fine halo slot holds the coarse part; the -u_in/5 term
+// uses the current value of the cell further inside.
+__device__ __forceinline__ void tile_ab(const double *tile, const double *alpha, int x, int y, int z, int d, int s,
+                                        double &a, double &bv)
+{
+    int l[3] = {x, y, z};
+    l[d] += s;
+    bv = tile[tix(l[0], l[1], l[2])];
+    a = 0.0;
+    if (l[d] < 0 || l[d] > 7) {
+        a = alpha[2 * d + (s > 0)];
+        if (a > 0.0) {
+            int in[3] = {x, y, z};
+            in[d] -= s;
+            bv -= 0.2 * tile[tix(in[0], in[1], in[2])];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // FP64 composite residual (Alg. 1) on a range of bricks of the AMR levels
 // ---------------------------------------------------------------------------
@@ -212,51 +374,52 @@ template <class T, bool ZERO>
 __global__ void __launch_bounds__(256) k_outer_residual(DevMeta M, int b0, int nb, double *const *phi, double *const *rho,
                                                         double inv_eps0, const double *cp_phi, T *r_out,
                                                         double *part, int norm_p, const int32_t *list,
-                                                        double *const *r_user)
+                                                        double *const *r_user, NormArgs NA)
 {
+    __shared__ double tile[TE * TE * TE];
+    __shared__ double alpha[6];
+    __shared__ uint8_t ncm[6];
     int b = pick_brick(b0, nb, list, blockIdx.x);
     int4 o = M.org[b];
     int lev = o.w;
     LevelConst L = M.lc[lev];
     uint8_t cm = M.cmask[b];
-    UserAcc uacc{phi[lev], M.ubase, M.ustr};
+    if (threadIdx.x < 6) {
+        int f = M.nbr[b * 6 + threadIdx.x];
+        ncm[threadIdx.x] = f >= 0 ? M.cmask[f] : 0;
+    }
+    SrcU src{phi, M.org, M.ubase, M.ustr};
+    stage_tile<SrcU, ZERO, CpArr<double>>(M, b, src, CpArr<double>{ZERO ? nullptr : cp_phi}, true, tile, alpha);
     UserAccL facc{phi, M.org, M.ubase, M.ustr};
     const double *rh = rho[lev];
     int64_t ub = M.ubase[b];
     int2 us = M.ustr[b];
     double acc = 0.0;
     for (int c = threadIdx.x; c < BRICK_CELLS; c += 256) {
-        int lc[3] = {c & 7, (c >> 3) & 7, c >> 6};
-        int64_t ui = ub + lc[0] + (int64_t)us.x * lc[1] + (int64_t)us.y * lc[2];
+        int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+        int64_t ui = ub + x + (int64_t)us.x * y + (int64_t)us.y * z;
         double rv = 0.0;
-        if (!((cm >> oct_of(lc[0], lc[1], lc[2])) & 1)) {
-            double uc = 0.0;
-            if (!ZERO) uc = uacc(b, lc);
+        if (!((cm >> oct_of(x, y, z)) & 1)) {
+            double uc = tile[tix(x, y, z)];
             double Au = 0.0;
             for (int d = 0; d < 3; ++d)
                 for (int s = -1; s <= 1; s += 2) {
-                    int nl[3] = {lc[0], lc[1], lc[2]};
+                    int nl[3] = {x, y, z};
                     int n = nl[d] + s, nbk = b;
-                    bool cov = false;
+                    bool cov;
                     if (n >= 0 && n < BRICK) {
                         nl[d] = n;
                         cov = (cm >> oct_of(nl[0], nl[1], nl[2])) & 1;
                     } else {
-                        int f = M.nbr[b * 6 + 2 * d + (s > 0)];
-                        if (f >= 0) {
-                            nl[d] = (s > 0) ? 0 : BRICK - 1;
-                            nbk = f;
-                            cov = (M.cmask[f] >> oct_of(nl[0], nl[1], nl[2])) & 1;
-                        }
+                        nl[d] = (s > 0) ? 0 : BRICK - 1;
+                        cov = (ncm[2 * d + (s > 0)] >> oct_of(nl[0], nl[1], nl[2])) & 1;
+                        if (cov) nbk = M.nbr[b * 6 + 2 * d + (s > 0)];
                     }
                     if (cov) {
                         if (!ZERO) Au += -0.5 * L.ih2[d] * fine_face_sum(M, nbk, nl, d, s, facc, cp_phi);
                     } else {
                         double a, bv;
-                        if (ZERO)
-                            face_nb(M, b, lc, d, s, ZeroAcc{}, nullptr, nullptr, true, a, bv);
-                        else
-                            face_nb(M, b, lc, d, s, uacc, cp_phi, nullptr, true, a, bv);
+                        tile_ab(tile, alpha, x, y, z, d, s, a, bv);
                         Au += L.ih2[d] * ((1.0 - a) * uc - bv);
                     }
                 }
@@ -269,6 +432,7 @@ __global__ void __launch_bounds__(256) k_outer_residual(DevMeta M, int b0, int n
     }
     acc = block_reduce_256(acc, norm_p == 0);
     if (threadIdx.x == 0) part[b] = acc;
+    level_norms_last_block(part, NA, norm_p);
 }
 
 // norm of each listed brick range (one AMR level of one problem) from the
@@ -337,24 +501,25 @@ template <class T>
 __global__ void __launch_bounds__(256) k_gsrb(DevMeta M, int b0, int nb, T *e, const T *r, const T *cp,
                                               int colour, int init)
 {
+    __shared__ double tile[TE * TE * TE];
+    __shared__ double alpha[6];
     int b = b0 + xcd_remap(blockIdx.x, nb);
     int lev = M.org[b].w;
     LevelConst L = M.lc[lev];
     int t = threadIdx.x;
     int z = t >> 5, y = (t >> 2) & 7, xx = (t & 3) << 1;
     int x = xx + (((y + z) & 1) ^ colour);  // brick origins are even
-    int lc[3] = {x, y, z};
     size_t li = (size_t)b * BRICK_CELLS + x + 8 * y + 64 * z;
-    double num = (double)r[li], den = 0.0;
-    const double *cpd = CpPtr<T>::d(cp);
-    const float *cpf = CpPtr<T>::f(cp);
+    double rv = (double)r[li];
+    if (init)
+        stage_tile<SrcZ, true>(M, b, SrcZ{}, CpNone{}, false, tile, alpha);
+    else
+        stage_tile<SrcB<T>, false, CpArr<T>>(M, b, SrcB<T>{e}, CpArr<T>{cp}, false, tile, alpha);
+    double num = rv, den = 0.0;
     for (int d = 0; d < 3; ++d)
         for (int s = -1; s <= 1; s += 2) {
             double a, bv;
-            if (init)
-                face_nb(M, b, lc, d, s, ZeroAcc{}, nullptr, nullptr, false, a, bv);
-            else
-                face_nb(M, b, lc, d, s, BrickAcc<T>{e}, cpd, cpf, false, a, bv);
+            tile_ab(tile, alpha, x, y, z, d, s, a, bv);
             num += L.ih2[d] * bv;
             den += L.ih2[d] * (1.0 - a);
         }
@@ -367,27 +532,106 @@ template <class T>
 __global__ void __launch_bounds__(256) k_jacobi(DevMeta M, int b0, int nb, const T *ein, T *eout, const T *r,
                                                 const T *cp, double omega, int init)
 {
+    __shared__ double tile[TE * TE * TE];
+    __shared__ double alpha[6];
     int b = b0 + xcd_remap(blockIdx.x, nb);
     int lev = M.org[b].w;
     LevelConst L = M.lc[lev];
-    const double *cpd = CpPtr<T>::d(cp);
-    const float *cpf = CpPtr<T>::f(cp);
-    for (int c = threadIdx.x; c < BRICK_CELLS; c += 256) {
-        int lc[3] = {c & 7, (c >> 3) & 7, c >> 6};
-        size_t li = (size_t)b * BRICK_CELLS + c;
-        double num = (double)r[li], den = 0.0;
+    double rv[2];
+    for (int k = 0; k < 2; ++k) rv[k] = (double)r[(size_t)b * BRICK_CELLS + threadIdx.x + 256 * k];
+    if (init)
+        stage_tile<SrcZ, true>(M, b, SrcZ{}, CpNone{}, false, tile, alpha);
+    else
+        stage_tile<SrcB<T>, false, CpArr<T>>(M, b, SrcB<T>{ein}, CpArr<T>{cp}, false, tile, alpha);
+    for (int k = 0; k < 2; ++k) {
+        int c = threadIdx.x + 256 * k;
+        int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+        double num = rv[k], den = 0.0;
         for (int d = 0; d < 3; ++d)
             for (int s = -1; s <= 1; s += 2) {
                 double a, bv;
-                if (init)
-                    face_nb(M, b, lc, d, s, ZeroAcc{}, nullptr, nullptr, false, a, bv);
-                else
-                    face_nb(M, b, lc, d, s, BrickAcc<T>{ein}, cpd, cpf, false, a, bv);
+                tile_ab(tile, alpha, x, y, z, d, s, a, bv);
                 num += L.ih2[d] * bv;
                 den += L.ih2[d] * (1.0 - a);
             }
-        double uc = init ? 0.0 : (double)ein[li];
-        eout[li] = (T)(uc + omega * (num / den - uc));
+        double uc = tile[tix(x, y, z)];
+        eout[(size_t)b * BRICK_CELLS + c] = (T)(uc + omega * (num / den - uc));
+    }
+}
+
+// cycle array plus the injected parent value (prolongation I e^{l-1})
+template <class T>
+struct SrcProl {
+    const T *u;
+    const int32_t *par;
+    __device__ double operator()(int b, int c) const
+    {
+        int p = par[b];
+        int pb = p >> 3, oc = p & 7;
+        int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+        int pc = ((oc & 1) * 4 + (x >> 1)) + 8 * (((oc >> 1) & 1) * 4 + (y >> 1)) + 64 * ((oc >> 2) * 4 + (z >> 1));
+        return (double)u[(size_t)b * BRICK_CELLS + c] + (double)u[(size_t)pb * BRICK_CELLS + pc];
+    }
+};
+
+// Brick-hybrid Gauss-Seidel sweep: red then black over the cells of one
+// brick in LDS, with the halo taken from the previous sweep (Gauss-Seidel
+// inside a brick, Jacobi between bricks, as a parallel Gauss-Seidel works
+// inside and between subdomains).  Reads ein, writes eout.
+// MODE bits: 1 input is zero; 2 input plus the parent correction (fused
+// prolongation); 4 coarse parts of the coarse-fine ghosts computed from the
+// coarse level's values in ein and stored into cp (else read from cp);
+// 8 phi += result on AMR bricks (fused phi update).
+enum { HG_ZERO = 1, HG_PROL = 2, HG_CPIN = 4, HG_PHI = 8 };
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(256) k_hgs(DevMeta M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
+                                             double *const *phi)
+{
+    __shared__ double tile[TE * TE * TE];
+    __shared__ double alpha[6];
+    int b = b0 + xcd_remap(blockIdx.x, nb);
+    int lev = M.org[b].w;
+    LevelConst L = M.lc[lev];
+    int t = threadIdx.x;
+    int z = t >> 5, y = (t >> 2) & 7, xx = (t & 3) << 1;
+    int xc[2] = {xx + ((y + z) & 1), xx + (((y + z) & 1) ^ 1)};  // colour 0, colour 1 (brick origins are even)
+    double rv[2];
+    for (int k = 0; k < 2; ++k) rv[k] = (double)r[(size_t)b * BRICK_CELLS + xc[k] + 8 * y + 64 * z];
+    if (MODE & HG_ZERO) {
+        stage_tile<SrcZ, true>(M, b, SrcZ{}, CpNone{}, false, tile, alpha);
+    } else if (MODE & HG_PROL) {
+        if (MODE & HG_CPIN)
+            stage_tile<SrcProl<T>, false, CpInline<T>>(M, b, SrcProl<T>{ein, M.par}, CpInline<T>{&M, ein, cp}, false,
+                                                       tile, alpha);
+        else
+            stage_tile<SrcProl<T>, false, CpArr<T>>(M, b, SrcProl<T>{ein, M.par}, CpArr<T>{cp}, false, tile, alpha);
+    } else {
+        stage_tile<SrcB<T>, false, CpArr<T>>(M, b, SrcB<T>{ein}, CpArr<T>{cp}, false, tile, alpha);
+    }
+    double v[2];
+    for (int k = 0; k < 2; ++k) {
+        int x = xc[k];
+        double num = rv[k], den = 0.0;
+        for (int d = 0; d < 3; ++d)
+            for (int s = -1; s <= 1; s += 2) {
+                double a, bv;
+                tile_ab(tile, alpha, x, y, z, d, s, a, bv);
+                num += L.ih2[d] * bv;
+                den += L.ih2[d] * (1.0 - a);
+            }
+        v[k] = num / den;
+        tile[tix(x, y, z)] = v[k];
+        __syncthreads();
+    }
+    for (int k = 0; k < 2; ++k) eout[(size_t)b * BRICK_CELLS + xc[k] + 8 * y + 64 * z] = (T)v[k];
+    if (MODE & HG_PHI) {
+        double *ph = phi[lev];
+        if (ph) {
+            int64_t ub = M.ubase[b];
+            int2 us = M.ustr[b];
+            for (int k = 0; k < 2; ++k) ph[ub + xc[k] + (int64_t)us.x * y + (int64_t)us.y * z] += v[k];
+        }
     }
 }
 
@@ -409,30 +653,44 @@ __device__ __forceinline__ double cell_residual(const DevMeta &M, const LevelCon
 
 // r^{l-1} on covered cells = mean over the 8 children of (r^l - A_nf e^l)
 // (Alg. 3, restriction onto the covered domain; e^{l-1} = 0 at that point).
-// Four fine bricks per workgroup, one coarse cell per thread.
+// One fine brick per workgroup: residuals in LDS, then 64 coarse cells.
 template <class T>
 __global__ void __launch_bounds__(256) k_restrict(DevMeta M, int b0, int nb, const T *e, const T *r, T *rc)
 {
-    int nwg = (nb + 3) >> 2;
-    int w = xcd_remap(blockIdx.x, nwg);
-    int k = w * 4 + (threadIdx.x >> 6);
-    if (k >= nb) return;
-    int b = b0 + k;
+    __shared__ double tile[TE * TE * TE];
+    __shared__ double alpha[6];
+    __shared__ double res[BRICK_CELLS];
+    int b = b0 + xcd_remap(blockIdx.x, nb);
     int lev = M.org[b].w;
     LevelConst L = M.lc[lev];
-    int t = threadIdx.x & 63;
-    int cx = t & 3, cy = (t >> 2) & 3, cz = t >> 4;
-    double sum = 0.0;
-    for (int dz = 0; dz < 2; ++dz)
-        for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx) {
-                int lc[3] = {2 * cx + dx, 2 * cy + dy, 2 * cz + dz};
-                sum += cell_residual(M, L, b, lc, e, r);
+    double rv[2];
+    for (int k = 0; k < 2; ++k) rv[k] = (double)r[(size_t)b * BRICK_CELLS + threadIdx.x + 256 * k];
+    stage_tile<SrcB<T>>(M, b, SrcB<T>{e}, CpNone{}, false, tile, alpha);
+    for (int k = 0; k < 2; ++k) {
+        int c = threadIdx.x + 256 * k;
+        int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+        double uc = tile[tix(x, y, z)], Au = 0.0;
+        for (int d = 0; d < 3; ++d)
+            for (int s = -1; s <= 1; s += 2) {
+                double a, bv;
+                tile_ab(tile, alpha, x, y, z, d, s, a, bv);
+                Au += L.ih2[d] * ((1.0 - a) * uc - bv);
             }
-    int par = M.par[b];
-    int pb = par >> 3, oc = par & 7;
-    int X = (oc & 1) * 4 + cx, Y = ((oc >> 1) & 1) * 4 + cy, Z = (oc >> 2) * 4 + cz;
-    rc[(size_t)pb * BRICK_CELLS + X + 8 * Y + 64 * Z] = (T)(0.125 * sum);
+        res[c] = rv[k] - Au;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        int t = threadIdx.x;
+        int cx = t & 3, cy = (t >> 2) & 3, cz = t >> 4;
+        double sum = 0.0;
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) sum += res[(2 * cx + dx) + 8 * (2 * cy + dy) + 64 * (2 * cz + dz)];
+        int par = M.par[b];
+        int pb = par >> 3, oc = par & 7;
+        int X = (oc & 1) * 4 + cx, Y = ((oc >> 1) & 1) * 4 + cy, Z = (oc >> 2) * 4 + cz;
+        rc[(size_t)pb * BRICK_CELLS + X + 8 * Y + 64 * Z] = (T)(0.125 * sum);
+    }
 }
 
 // Uncovered coarse cells next to covered ones: r -= B_fine e^l, i.e. add
@@ -536,22 +794,25 @@ __global__ void __launch_bounds__(256) k_avgdown(DevMeta M, int b0, int nb, doub
 __global__ void __launch_bounds__(256) k_efield(DevMeta M, int b0, int nb, double *const *phi, const double *cp_phi,
                                                 double *const *E, const int32_t *list)
 {
+    __shared__ double tile[TE * TE * TE];
+    __shared__ double alpha[6];
     int b = pick_brick(b0, nb, list, blockIdx.x);
     int lev = M.org[b].w;
     LevelConst L = M.lc[lev];
-    UserAcc uacc{phi[lev], M.ubase, M.ustr};
+    SrcU src{phi, M.org, M.ubase, M.ustr};
+    stage_tile<SrcU, false, CpArr<double>>(M, b, src, CpArr<double>{cp_phi}, true, tile, alpha);
     int64_t ub = M.ubase[b];
     int2 us = M.ustr[b];
     for (int c = threadIdx.x; c < BRICK_CELLS; c += 256) {
-        int lc[3] = {c & 7, (c >> 3) & 7, c >> 6};
-        int64_t ui = ub + lc[0] + (int64_t)us.x * lc[1] + (int64_t)us.y * lc[2];
-        double uc = uacc(b, lc);
+        int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+        int64_t ui = ub + x + (int64_t)us.x * y + (int64_t)us.y * z;
+        double uc = tile[tix(x, y, z)];
         for (int d = 0; d < 3; ++d) {
-            double a, bv, up, um;
-            face_nb(M, b, lc, d, +1, uacc, cp_phi, nullptr, true, a, bv);
-            up = a * uc + bv;
-            face_nb(M, b, lc, d, -1, uacc, cp_phi, nullptr, true, a, bv);
-            um = a * uc + bv;
+            double a, bv;
+            tile_ab(tile, alpha, x, y, z, d, +1, a, bv);
+            double up = a * uc + bv;
+            tile_ab(tile, alpha, x, y, z, d, -1, a, bv);
+            double um = a * uc + bv;
             E[3 * lev + d][ui] = -(up - um) / (2.0 * L.h[d]);
         }
     }
@@ -569,23 +830,21 @@ __device__ double block_reduce_1024(double v)
     if (lane == 0) sh[wid] = v;
     __syncthreads();
     double r = 0.0;
-    for (int i = 0; i < 16; ++i) r += sh[i];
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) r += sh[i];
     __syncthreads();
     return r;
 }
 
-// one workgroup per job: jobs[i] = (first brick, bricks, offset of its four
-// work vectors in doubles)
+// CG on bricks [b0, b0+nb) of one level with four FP64 work vectors; called
+// by a whole workgroup of 1024 threads.  Returns the iteration count.
 template <class T>
-__global__ void __launch_bounds__(1024) k_bottom_cg(DevMeta M, const int4 *jobs, const T *rhs, T *e, double *work,
-                                                    double rtol, int maxit, int *iters)
+__device__ int cg_solve(const DevMeta &M, int b0, int nb, const T *rhs, T *e, double *work, double rtol, int maxit)
 {
-    int4 jb = jobs[blockIdx.x];
-    const int b0 = jb.x, nb = jb.y;
     const int n = nb * BRICK_CELLS;
-    double *x = work + jb.z, *r = x + n, *p = x + 2 * (size_t)n, *q = x + 3 * (size_t)n;
+    double *x = work, *r = x + n, *p = x + 2 * (size_t)n, *q = x + 3 * (size_t)n;
     double rho = 0.0;
-    for (int i = threadIdx.x; i < n; i += 1024) {
+    for (int i = threadIdx.x; i < n; i += (int)blockDim.x) {
         double v = (double)rhs[(size_t)b0 * BRICK_CELLS + i];
         x[i] = 0.0;
         r[i] = v;
@@ -596,12 +855,12 @@ __global__ void __launch_bounds__(1024) k_bottom_cg(DevMeta M, const int4 *jobs,
     double stop = rtol * rtol * rho;
     int it = 0;
     OffsetAcc pacc{p, b0};
+    const LevelConst L = M.lc[M.org[b0].w];
     while (it < maxit && rho > stop && rho > 0.0) {
         double pq = 0.0;
-        for (int i = threadIdx.x; i < n; i += 1024) {
+        for (int i = threadIdx.x; i < n; i += (int)blockDim.x) {
             int b = b0 + (i >> 9), c = i & 511;
             int lc[3] = {c & 7, (c >> 3) & 7, c >> 6};
-            LevelConst L = M.lc[M.org[b].w];
             double pc = p[i], Ap = 0.0;
             for (int d = 0; d < 3; ++d)
                 for (int s = -1; s <= 1; s += 2) {
@@ -615,7 +874,7 @@ __global__ void __launch_bounds__(1024) k_bottom_cg(DevMeta M, const int4 *jobs,
         pq = block_reduce_1024(pq);
         double alpha = rho / pq;
         double rho1 = 0.0;
-        for (int i = threadIdx.x; i < n; i += 1024) {
+        for (int i = threadIdx.x; i < n; i += (int)blockDim.x) {
             x[i] += alpha * p[i];
             double rv = r[i] - alpha * q[i];
             r[i] = rv;
@@ -623,13 +882,229 @@ __global__ void __launch_bounds__(1024) k_bottom_cg(DevMeta M, const int4 *jobs,
         }
         rho1 = block_reduce_1024(rho1);
         double beta = rho1 / rho;
-        for (int i = threadIdx.x; i < n; i += 1024) p[i] = r[i] + beta * p[i];
+        for (int i = threadIdx.x; i < n; i += (int)blockDim.x) p[i] = r[i] + beta * p[i];
         rho = rho1;
         ++it;
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < n; i += 1024) e[(size_t)b0 * BRICK_CELLS + i] = (T)x[i];
+    for (int i = threadIdx.x; i < n; i += (int)blockDim.x) e[(size_t)b0 * BRICK_CELLS + i] = (T)x[i];
+    __syncthreads();
+    return it;
+}
+
+// CG as above for grids of at most 4096 cells: the search direction lives in
+// LDS, each thread keeps its (at most four) cells of x, r and q in registers,
+// and a reduction costs one barrier.
+constexpr int CG_LDS_MAX = 4096;
+constexpr int CG_PER = 8;  // cells per thread: CG_LDS_MAX / CG_PER threads at least
+
+__device__ __forceinline__ double wg_sum_1024(double v, double *red, int slot)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[slot * 16 + (threadIdx.x >> 6)] = v;
+    __syncthreads();
+    double s = 0.0;
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) s += red[slot * 16 + i];
+    return s;
+}
+
+template <class T>
+__device__ int cg_solve_lds(const DevMeta &M, int b0, int nb, const T *rhs, T *e, double rtol, int maxit)
+{
+    __shared__ double p[CG_LDS_MAX];
+    __shared__ double red[3 * 16];
+    const int n = nb * BRICK_CELLS;
+    const LevelConst L = M.lc[M.org[b0].w];
+    // neighbours of each owned cell (at most CG_PER per thread), resolved once: LDS index, or -1 for a
+    // homogeneous Dirichlet ghost (-p_c); the coarsest grid has no
+    // coarse-fine faces
+    int nbi[CG_PER][6];
+    double diag[CG_PER];
+    for (int k = 0; k < CG_PER; ++k) {
+        int i = threadIdx.x + (int)blockDim.x * k;
+        diag[k] = 0.0;
+        for (int f = 0; f < 6; ++f) nbi[k][f] = -1;
+        if (i >= n) continue;
+        int b = b0 + (i >> 9), c = i & 511;
+        int l[3] = {c & 7, (c >> 3) & 7, c >> 6};
+        for (int f = 0; f < 6; ++f) {
+            int d = f >> 1, s = (f & 1) ? 1 : -1;
+            int m[3] = {l[0], l[1], l[2]};
+            m[d] += s;
+            int bb = b;
+            if (m[d] < 0 || m[d] > 7) {
+                bb = M.nbr[b * 6 + f];
+                m[d] = s > 0 ? 0 : 7;
+            }
+            if (bb >= 0) {
+                nbi[k][f] = (bb - b0) * BRICK_CELLS + m[0] + 8 * m[1] + 64 * m[2];
+                diag[k] += L.ih2[d];
+            } else {
+                diag[k] += 2.0 * L.ih2[d];
+            }
+        }
+    }
+    double x[CG_PER], r[CG_PER];
+    double rho = 0.0;
+    for (int k = 0; k < CG_PER; ++k) {
+        int i = threadIdx.x + (int)blockDim.x * k;
+        double v = i < n ? (double)rhs[(size_t)b0 * BRICK_CELLS + i] : 0.0;
+        x[k] = 0.0;
+        r[k] = v;
+        if (i < n) p[i] = v;
+        rho += v * v;
+    }
+    int slot = 0;
+    rho = wg_sum_1024(rho, red, slot);
+    slot = (slot + 1) % 3;
+    double stop = rtol * rtol * rho;
+    int it = 0;
+    while (it < maxit && rho > stop && rho > 0.0) {
+        double q[CG_PER], pk[CG_PER], pq = 0.0;
+        for (int k = 0; k < CG_PER; ++k) {
+            int i = threadIdx.x + (int)blockDim.x * k;
+            q[k] = 0.0;
+            pk[k] = 0.0;
+            if (i >= n) continue;
+            double pc = p[i], off = 0.0;
+            for (int f = 0; f < 6; ++f)
+                if (nbi[k][f] >= 0) off += L.ih2[f >> 1] * p[nbi[k][f]];
+            pk[k] = pc;
+            q[k] = diag[k] * pc - off;
+            pq += pc * q[k];
+        }
+        pq = wg_sum_1024(pq, red, slot);
+        slot = (slot + 1) % 3;
+        double alpha = rho / pq;
+        double rho1 = 0.0;
+        for (int k = 0; k < CG_PER; ++k) {
+            x[k] += alpha * pk[k];
+            r[k] -= alpha * q[k];
+            rho1 += r[k] * r[k];
+        }
+        rho1 = wg_sum_1024(rho1, red, slot);
+        slot = (slot + 1) % 3;
+        double beta = rho1 / rho;
+        for (int k = 0; k < CG_PER; ++k) {
+            int i = threadIdx.x + (int)blockDim.x * k;
+            if (i < n) p[i] = r[k] + beta * pk[k];
+        }
+        __syncthreads();
+        rho = rho1;
+        ++it;
+    }
+    for (int k = 0; k < CG_PER; ++k) {
+        int i = threadIdx.x + (int)blockDim.x * k;
+        if (i < n) e[(size_t)b0 * BRICK_CELLS + i] = (T)x[k];
+    }
+    __syncthreads();
+    return it;
+}
+
+// one workgroup per job: jobs[i] = (first brick, bricks, offset of its four
+// work vectors in doubles)
+template <class T>
+__global__ void __launch_bounds__(1024) k_bottom_cg(DevMeta M, const int4 *jobs, const T *rhs, T *e, double *work,
+                                                    double rtol, int maxit, int *iters)
+{
+    int4 jb = jobs[blockIdx.x];
+    int it = cg_solve<T>(M, jb.x, jb.y, rhs, e, work + jb.z, rtol, maxit);
     if (threadIdx.x == 0 && iters) atomicMax(iters, it);
+}
+
+// exact red-black Gauss-Seidel pass over a whole level by one workgroup
+template <class T>
+__device__ void wg_gs_pass(const DevMeta &M, int b0, int nb, T *e, const T *r, int colour)
+{
+    const LevelConst L = M.lc[M.org[b0].w];
+    for (int i = threadIdx.x; i < nb * 256; i += (int)blockDim.x) {
+        int b = b0 + (i >> 8), t = i & 255;
+        int z = t >> 5, y = (t >> 2) & 7, xx = (t & 3) << 1;
+        int lc[3] = {xx + (((y + z) & 1) ^ colour), y, z};
+        size_t li = (size_t)b * BRICK_CELLS + lc[0] + 8 * y + 64 * z;
+        double num = (double)r[li], den = 0.0;
+        for (int d = 0; d < 3; ++d)
+            for (int s = -1; s <= 1; s += 2) {
+                double a, bv;
+                face_nb(M, b, lc, d, s, BrickAcc<T>{e}, nullptr, nullptr, false, a, bv);
+                num += L.ih2[d] * bv;
+                den += L.ih2[d] * (1.0 - a);
+            }
+        e[li] = (T)(num / den);
+    }
+    __syncthreads();
+}
+
+// The part of the V-cycle on the small levels 0..nlev-1 of one problem (no
+// coarse-fine faces there) in one workgroup: pre-smoothing and restriction
+// down, CG on level 0, prolongation and post-smoothing up, and phi += e on
+// AMR levels when phi_update is set.
+template <class T>
+__global__ void __launch_bounds__(1024) k_coarse_cycle(DevMeta M, const CoarseJob *jobs, T *e, T *r, double *work,
+                                                       int nu1, int nu2, double rtol, int maxit, int *iters,
+                                                       double *const *phi, int phi_update)
+{
+    const CoarseJob J = jobs[blockIdx.x];
+    for (int k = J.nlev - 1; k >= 1; --k) {
+        const int b0 = J.b0[k], nb = J.nb[k];
+        for (int i = threadIdx.x; i < nb * BRICK_CELLS; i += (int)blockDim.x) e[(size_t)b0 * BRICK_CELLS + i] = (T)0;
+        __syncthreads();
+        for (int it = 0; it < nu1; ++it) {
+            wg_gs_pass<T>(M, b0, nb, e, r, 0);
+            wg_gs_pass<T>(M, b0, nb, e, r, 1);
+        }
+        const LevelConst L = M.lc[M.org[b0].w];
+        for (int i = threadIdx.x; i < nb * 64; i += (int)blockDim.x) {
+            int b = b0 + (i >> 6), t = i & 63;
+            int cx = t & 3, cy = (t >> 2) & 3, cz = t >> 4;
+            double sum = 0.0;
+            for (int dz = 0; dz < 2; ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        int lc[3] = {2 * cx + dx, 2 * cy + dy, 2 * cz + dz};
+                        sum += cell_residual(M, L, b, lc, e, r);
+                    }
+            int par = M.par[b];
+            int pb = par >> 3, oc = par & 7;
+            int X = (oc & 1) * 4 + cx, Y = ((oc >> 1) & 1) * 4 + cy, Z = (oc >> 2) * 4 + cz;
+            r[(size_t)pb * BRICK_CELLS + X + 8 * Y + 64 * Z] = (T)(0.125 * sum);
+        }
+        __syncthreads();
+    }
+    int it = J.nb[0] * BRICK_CELLS <= CG_PER * (int)blockDim.x && J.nb[0] * BRICK_CELLS <= CG_LDS_MAX
+                 ? cg_solve_lds<T>(M, J.b0[0], J.nb[0], r, e, rtol, maxit)
+                                                   : cg_solve<T>(M, J.b0[0], J.nb[0], r, e, work + J.cg_off, rtol, maxit);
+    if (threadIdx.x == 0 && iters) atomicMax(iters, it);
+    for (int k = 0; k < J.nlev; ++k) {
+        const int b0 = J.b0[k], nb = J.nb[k];
+        if (k > 0) {
+            for (int i = threadIdx.x; i < nb * BRICK_CELLS; i += (int)blockDim.x) {
+                int b = b0 + (i >> 9), c = i & 511;
+                int par = M.par[b];
+                int pb = par >> 3, oc = par & 7;
+                int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+                size_t pi = (size_t)pb * BRICK_CELLS + ((oc & 1) * 4 + (x >> 1)) +
+                            8 * (((oc >> 1) & 1) * 4 + (y >> 1)) + 64 * ((oc >> 2) * 4 + (z >> 1));
+                size_t li = (size_t)b * BRICK_CELLS + c;
+                e[li] = (T)((double)e[li] + (double)e[pi]);
+            }
+            __syncthreads();
+            for (int it2 = 0; it2 < nu2; ++it2) {
+                wg_gs_pass<T>(M, b0, nb, e, r, 0);
+                wg_gs_pass<T>(M, b0, nb, e, r, 1);
+            }
+        }
+        double *ph = phi_update ? phi[M.org[b0].w] : nullptr;
+        if (ph) {
+            for (int i = threadIdx.x; i < nb * BRICK_CELLS; i += (int)blockDim.x) {
+                int b = b0 + (i >> 9), c = i & 511;
+                int2 us = M.ustr[b];
+                ph[M.ubase[b] + (c & 7) + (int64_t)us.x * ((c >> 3) & 7) + (int64_t)us.y * (c >> 6)] +=
+                    (double)e[(size_t)b * BRICK_CELLS + c];
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -664,27 +1139,61 @@ __device__ __forceinline__ int64_t user_index(const DepLevel &D, const int64_t *
     return ubase[g] + (i & 7) + (int64_t)s.x * (j & 7) + (int64_t)s.y * (k & 7);
 }
 
+// Add v to rho[addr] for every active lane (addr >= 0), combining lanes of
+// the wavefront that share an address: up to 8 distinct addresses are summed
+// across the wavefront and issued as one atomic each by their first lane; the
+// remaining lanes issue their own atomics.
+__device__ __forceinline__ void wave_atomic_add(double *rho, int64_t addr, double v)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t active = __ballot(addr >= 0);
+    for (int round = 0; round < 8 && active; ++round) {
+        int leader = __builtin_ctzll(active);
+        int64_t A = __shfl(addr, leader, 64);
+        uint64_t match = __ballot(addr == A) & active;
+        double s = ((match >> lane) & 1) ? v : 0.0;
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == leader) atomicAdd(rho + A, s);
+        active &= ~match;
+    }
+    if ((active >> lane) & 1) atomicAdd(rho + addr, v);
+}
+
+// Deposit every particle on every listed level: each particle is read once
+// (in the given visiting order) and its 8 CIC weights per level are added
+// with wavefront-combined FP64 atomics.
 template <class P>
 __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P *y, const P *z, const double *q,
-                                                 DepLevel D, const int64_t *ubase, const int2 *ustr, double *rho,
-                                                 unsigned long long *nout)
+                                                 const uint32_t *perm, DepArgs A, const int64_t *ubase,
+                                                 const int2 *ustr, unsigned long long *nout)
 {
-    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= n) return;
-    int i0[3], i1[3];
-    double f[3];
-    if (!cic_stencil<P>(D, (double)x[p], (double)y[p], (double)z[p], i0, i1, f)) {
-        if (nout) atomicAdd(nout, 1ull);
-        return;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool valid = i < n;
+    int64_t p = valid ? (perm ? (int64_t)perm[i] : i) : 0;
+    double X = 0.0, Y = 0.0, Z = 0.0, qp = 0.0;
+    if (valid) {
+        X = (double)x[p];
+        Y = (double)y[p];
+        Z = (double)z[p];
+        qp = q[p];
     }
-    double qv = q[p] * D.ivol;
-    for (int c = 0; c < 8; ++c) {
-        int ii = (c & 1) ? i1[0] : i0[0];
-        int jj = (c & 2) ? i1[1] : i0[1];
-        int kk = (c & 4) ? i1[2] : i0[2];
-        double w = ((c & 1) ? f[0] : 1.0 - f[0]) * ((c & 2) ? f[1] : 1.0 - f[1]) * ((c & 4) ? f[2] : 1.0 - f[2]);
-        int64_t u = user_index(D, ubase, ustr, ii, jj, kk);
-        if (u >= 0) atomicAdd(rho + u, qv * w);
+    for (int l = 0; l < A.nlev; ++l) {
+        const DepLevel &D = A.lev[l];
+        int i0[3] = {0, 0, 0}, i1[3] = {0, 0, 0};
+        double f[3] = {0, 0, 0};
+        bool ok = valid && cic_stencil<P>(D, X, Y, Z, i0, i1, f);
+        if (valid && !ok && l == 0 && nout) atomicAdd(nout, 1ull);
+        double qv = ok ? qp * D.ivol : 0.0;
+        // all lanes stay in the loop: the combination uses wavefront shuffles
+        for (int c = 0; c < 8; ++c) {
+            int ii = (c & 1) ? i1[0] : i0[0];
+            int jj = (c & 2) ? i1[1] : i0[1];
+            int kk = (c & 4) ? i1[2] : i0[2];
+            double w = ((c & 1) ? f[0] : 1.0 - f[0]) * ((c & 2) ? f[1] : 1.0 - f[1]) *
+                       ((c & 4) ? f[2] : 1.0 - f[2]);
+            int64_t u = ok ? user_index(D, ubase, ustr, ii, jj, kk) : -1;
+            wave_atomic_add(A.rho[l], u, qv * w);
+        }
     }
 }
 
@@ -756,6 +1265,46 @@ __global__ void __launch_bounds__(256) k_copy(const T *a, T *b, int64_t n)
     if (i < n) b[i] = a[i];
 }
 
+// Tag cells of one level (|rho| > lambda * max|rho|) and mark the blocks of
+// the finer level (bf fine cells = half coarse cells per edge) that a tag
+// dilated by nbuf cells reaches.  Same value written by every marker.
+__global__ void __launch_bounds__(256) k_mark_blocks(const double *rho, const int4 *borg, const int64_t *ubase,
+                                                     const int2 *ustr, int nb, const double *vmax, double lambda,
+                                                     int nbuf, int half, int3 n, int3 g, uint8_t *marks)
+{
+    int b = xcd_remap(blockIdx.x, nb);
+    int4 o = borg[b];
+    int64_t ub = ubase[b];
+    int2 us = ustr[b];
+    double thr = lambda * (*vmax);
+    for (int c = threadIdx.x; c < BRICK_CELLS; c += 256) {
+        int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+        double v = rho[ub + x + (int64_t)us.x * y + (int64_t)us.y * z];
+        if (!(fabs(v) > thr)) continue;
+        int gi = o.x + x, gj = o.y + y, gk = o.z + z;
+        int x0 = max(0, gi - nbuf) / half, x1 = min(n.x - 1, gi + nbuf) / half;
+        int y0 = max(0, gj - nbuf) / half, y1 = min(n.y - 1, gj + nbuf) / half;
+        int z0 = max(0, gk - nbuf) / half, z1 = min(n.z - 1, gk + nbuf) / half;
+        for (int bz = z0; bz <= z1; ++bz)
+            for (int by = y0; by <= y1; ++by)
+                for (int bx = x0; bx <= x1; ++bx) marks[(size_t)bx + (size_t)g.x * ((size_t)by + (size_t)g.y * bz)] = 1;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fill_multi(DepArgs A, int64_t total, const int64_t *dummy)
+{
+    (void)dummy;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (int l = 0; l < A.nlev; ++l) {
+        if (i < A.ncell[l]) {
+            A.rho[l][i] = 0.0;
+            return;
+        }
+        i -= A.ncell[l];
+    }
+    (void)total;
+}
+
 __global__ void __launch_bounds__(256) k_fill(double *v, int64_t n, double val)
 {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -770,28 +1319,28 @@ static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + p
 template <class T>
 void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list,
                            double *const *phi, double *const *rho, double inv_eps0, const double *cp_phi, T *r_out,
-                           double *part, int norm_p, bool zero_phi, double *const *r_user)
+                           double *part, int norm_p, bool zero_phi, double *const *r_user, const NormArgs &NA)
 {
     if (nb <= 0) return;
     if (zero_phi)
-        hipLaunchKernelGGL((k_outer_residual<T, true>), dim3(nb), dim3(256), 0, st, M, b0, nb, phi, rho, inv_eps0,
-                           cp_phi, r_out, part, norm_p, list, r_user);
+        AMRMG_LAUNCH((k_outer_residual<T, true>), dim3(nb), dim3(256), 0, st, M, b0, nb, phi, rho, inv_eps0,
+                     cp_phi, r_out, part, norm_p, list, r_user, NA);
     else
-        hipLaunchKernelGGL((k_outer_residual<T, false>), dim3(nb), dim3(256), 0, st, M, b0, nb, phi, rho,
-                           inv_eps0, cp_phi, r_out, part, norm_p, list, r_user);
+        AMRMG_LAUNCH((k_outer_residual<T, false>), dim3(nb), dim3(256), 0, st, M, b0, nb, phi, rho, inv_eps0,
+                     cp_phi, r_out, part, norm_p, list, r_user, NA);
 }
 
 void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double *part, double *out, int norm_p)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_level_norms, dim3(n), dim3(256), 0, st, ranges, n, part, out, norm_p);
+    AMRMG_LAUNCH(k_level_norms, dim3(n), dim3(256), 0, st, ranges, n, part, out, norm_p);
 }
 
 void launch_cpart_user(hipStream_t st, const DevMeta &M, int cf0, int ncf, double *const *phi, double *cp)
 {
     if (ncf <= 0) return;
     SrcUser s{phi, M.org, M.ubase, M.ustr};
-    hipLaunchKernelGGL((k_cpart<double, SrcUser>), dim3(blocks_for((int64_t)ncf * 16, 256)), dim3(256), 0, st, M,
+    AMRMG_LAUNCH((k_cpart<double, SrcUser>), dim3(blocks_for((int64_t)ncf * 16, 256)), dim3(256), 0, st, M,
                        cf0, ncf, s, cp);
 }
 
@@ -800,7 +1349,7 @@ void launch_cpart_brick(hipStream_t st, const DevMeta &M, int cf0, int ncf, cons
 {
     if (ncf <= 0) return;
     SrcBrick<T> s{src};
-    hipLaunchKernelGGL((k_cpart<T, SrcBrick<T>>), dim3(blocks_for((int64_t)ncf * 16, 256)), dim3(256), 0, st, M,
+    AMRMG_LAUNCH((k_cpart<T, SrcBrick<T>>), dim3(blocks_for((int64_t)ncf * 16, 256)), dim3(256), 0, st, M,
                        cf0, ncf, s, cp);
 }
 
@@ -809,7 +1358,7 @@ void launch_gsrb(hipStream_t st, const DevMeta &M, int b0, int nb, T *e, const T
                  bool init)
 {
     if (nb <= 0) return;
-    hipLaunchKernelGGL((k_gsrb<T>), dim3(nb), dim3(256), 0, st, M, b0, nb, e, r, cp, colour, (int)init);
+    AMRMG_LAUNCH((k_gsrb<T>), dim3(nb), dim3(256), 0, st, M, b0, nb, e, r, cp, colour, (int)init);
 }
 
 template <class T>
@@ -817,28 +1366,28 @@ void launch_jacobi(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ei
                    double omega, bool init)
 {
     if (nb <= 0) return;
-    hipLaunchKernelGGL((k_jacobi<T>), dim3(nb), dim3(256), 0, st, M, b0, nb, ein, eout, r, cp, omega, (int)init);
+    AMRMG_LAUNCH((k_jacobi<T>), dim3(nb), dim3(256), 0, st, M, b0, nb, ein, eout, r, cp, omega, (int)init);
 }
 
 template <class T>
 void launch_restrict(hipStream_t st, const DevMeta &M, int b0, int nb, const T *e, const T *r, T *rc)
 {
     if (nb <= 0) return;
-    hipLaunchKernelGGL((k_restrict<T>), dim3((nb + 3) / 4), dim3(256), 0, st, M, b0, nb, e, r, rc);
+    AMRMG_LAUNCH((k_restrict<T>), dim3(nb), dim3(256), 0, st, M, b0, nb, e, r, rc);
 }
 
 template <class T>
 void launch_reflux(hipStream_t st, const DevMeta &M, const int32_t *list, int n, const T *e, T *r)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL((k_reflux<T>), dim3(n), dim3(256), 0, st, M, list, n, e, r);
+    AMRMG_LAUNCH((k_reflux<T>), dim3(n), dim3(256), 0, st, M, list, n, e, r);
 }
 
 template <class T>
 void launch_prolong(hipStream_t st, const DevMeta &M, int b0, int nb, T *e)
 {
     if (nb <= 0) return;
-    hipLaunchKernelGGL((k_prolong<T>), dim3(nb), dim3(256), 0, st, M, b0, nb, e);
+    AMRMG_LAUNCH((k_prolong<T>), dim3(nb), dim3(256), 0, st, M, b0, nb, e);
 }
 
 template <class T>
@@ -846,20 +1395,20 @@ void launch_phi_update(hipStream_t st, const DevMeta &M, int b0, int nb, const i
                        const T *e)
 {
     if (nb <= 0) return;
-    hipLaunchKernelGGL((k_phi_update<T>), dim3(nb), dim3(256), 0, st, M, b0, nb, phi, e, list);
+    AMRMG_LAUNCH((k_phi_update<T>), dim3(nb), dim3(256), 0, st, M, b0, nb, phi, e, list);
 }
 
 void launch_avgdown(hipStream_t st, const DevMeta &M, int b0, int nb, double *const *phi)
 {
     if (nb <= 0) return;
-    hipLaunchKernelGGL(k_avgdown, dim3((nb + 3) / 4), dim3(256), 0, st, M, b0, nb, phi);
+    AMRMG_LAUNCH(k_avgdown, dim3((nb + 3) / 4), dim3(256), 0, st, M, b0, nb, phi);
 }
 
 void launch_efield(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, double *const *phi,
                    const double *cp_phi, double *const *E)
 {
     if (nb <= 0) return;
-    hipLaunchKernelGGL(k_efield, dim3(nb), dim3(256), 0, st, M, b0, nb, phi, cp_phi, E, list);
+    AMRMG_LAUNCH(k_efield, dim3(nb), dim3(256), 0, st, M, b0, nb, phi, cp_phi, E, list);
 }
 
 template <class T>
@@ -867,21 +1416,21 @@ void launch_bottom_cg(hipStream_t st, const DevMeta &M, const int4 *jobs, int nj
                       double *work, double rtol, int maxit, int *iters)
 {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL((k_bottom_cg<T>), dim3(njobs), dim3(1024), 0, st, M, jobs, rhs, e, work, rtol, maxit, iters);
+    AMRMG_LAUNCH((k_bottom_cg<T>), dim3(njobs), dim3(1024), 0, st, M, jobs, rhs, e, work, rtol, maxit, iters);
 }
 
 void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
-                    const double *q, const DepLevel &D, const int64_t *ubase, const int2 *ustr, double *rho,
+                    const double *q, const uint32_t *perm, const DepArgs &A, const int64_t *ubase, const int2 *ustr,
                     unsigned long long *nout)
 {
-    if (n <= 0) return;
+    if (n <= 0 || A.nlev <= 0) return;
     unsigned g = blocks_for(n, 256);
     if (pos_f32)
-        hipLaunchKernelGGL((k_deposit<float>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
-                           (const float *)z, q, D, ubase, ustr, rho, nout);
+        AMRMG_LAUNCH((k_deposit<float>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
+                     (const float *)z, q, perm, A, ubase, ustr, nout);
     else
-        hipLaunchKernelGGL((k_deposit<double>), dim3(g), dim3(256), 0, st, n, (const double *)x, (const double *)y,
-                           (const double *)z, q, D, ubase, ustr, rho, nout);
+        AMRMG_LAUNCH((k_deposit<double>), dim3(g), dim3(256), 0, st, n, (const double *)x, (const double *)y,
+                     (const double *)z, q, perm, A, ubase, ustr, nout);
 }
 
 void launch_gather(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
@@ -890,10 +1439,10 @@ void launch_gather(hipStream_t st, int pos_f32, int64_t n, const void *x, const 
     if (n <= 0) return;
     unsigned g = blocks_for(n, 256);
     if (pos_f32)
-        hipLaunchKernelGGL((k_gather<float>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
+        AMRMG_LAUNCH((k_gather<float>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
                            (const float *)z, G, ubase, ustr, Ex, Ey, Ez);
     else
-        hipLaunchKernelGGL((k_gather<double>), dim3(g), dim3(256), 0, st, n, (const double *)x, (const double *)y,
+        AMRMG_LAUNCH((k_gather<double>), dim3(g), dim3(256), 0, st, n, (const double *)x, (const double *)y,
                            (const double *)z, G, ubase, ustr, Ex, Ey, Ez);
 }
 
@@ -902,28 +1451,80 @@ void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, doubl
     if (n <= 0) return;
     int parts = (int)blocks_for(n, 256);
     if (parts > 1024) parts = 1024;
-    hipLaunchKernelGGL(k_absmax_part, dim3(parts), dim3(256), 0, st, v, n, scratch + 1);
-    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, st, scratch + 1, parts, scratch);
-    hipLaunchKernelGGL(k_tag, dim3(blocks_for(n, 256)), dim3(256), 0, st, v, n, scratch, lambda, tags);
+    AMRMG_LAUNCH(k_absmax_part, dim3(parts), dim3(256), 0, st, v, n, scratch + 1);
+    AMRMG_LAUNCH(k_absmax_final, dim3(1), dim3(256), 0, st, scratch + 1, parts, scratch);
+    AMRMG_LAUNCH(k_tag, dim3(blocks_for(n, 256)), dim3(256), 0, st, v, n, scratch, lambda, tags);
+}
+
+template <class T>
+void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
+                double *const *phi, int mode)
+{
+    if (nb <= 0) return;
+    dim3 g(nb), blk(256);
+    switch (mode) {
+    case HG_ZERO: AMRMG_LAUNCH((k_hgs<T, HG_ZERO>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phi); break;
+    case 0: AMRMG_LAUNCH((k_hgs<T, 0>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phi); break;
+    case HG_PHI: AMRMG_LAUNCH((k_hgs<T, HG_PHI>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phi); break;
+    case HG_PROL | HG_CPIN:
+        AMRMG_LAUNCH((k_hgs<T, HG_PROL | HG_CPIN>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phi);
+        break;
+    case HG_PROL | HG_CPIN | HG_PHI:
+        AMRMG_LAUNCH((k_hgs<T, HG_PROL | HG_CPIN | HG_PHI>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phi);
+        break;
+    default: break;
+    }
+}
+
+template <class T>
+void launch_coarse_cycle(hipStream_t st, const DevMeta &M, const CoarseJob *jobs, int njobs, T *e, T *r,
+                         double *work, int nu1, int nu2, double rtol, int maxit, int *iters, double *const *phi,
+                         bool phi_update, int threads_hint)
+{
+    if (njobs <= 0) return;
+    int threads = threads_hint > 0 ? threads_hint : 1024;
+    AMRMG_LAUNCH((k_coarse_cycle<T>), dim3(njobs), dim3(threads), 0, st, M, jobs, e, r, work, nu1, nu2, rtol, maxit,
+                 iters, phi, (int)phi_update);
 }
 
 template <class T>
 void launch_copy(hipStream_t st, const T *a, T *b, int64_t n)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL((k_copy<T>), dim3(blocks_for(n, 256)), dim3(256), 0, st, a, b, n);
+    AMRMG_LAUNCH((k_copy<T>), dim3(blocks_for(n, 256)), dim3(256), 0, st, a, b, n);
+}
+
+void launch_mark_blocks(hipStream_t st, const double *rho, int64_t ncell, const int4 *borg, const int64_t *ubase,
+                        const int2 *ustr, int nb, double lambda, int nbuf, int half, int3 n, int3 g, double *scratch,
+                        uint8_t *marks)
+{
+    if (nb <= 0) return;
+    int parts = (int)blocks_for(ncell, 256);
+    if (parts > 1024) parts = 1024;
+    AMRMG_LAUNCH(k_absmax_part, dim3(parts), dim3(256), 0, st, rho, ncell, scratch + 1);
+    AMRMG_LAUNCH(k_absmax_final, dim3(1), dim3(256), 0, st, scratch + 1, parts, scratch);
+    AMRMG_LAUNCH(k_mark_blocks, dim3(nb), dim3(256), 0, st, rho, borg, ubase, ustr, nb, scratch, lambda, nbuf,
+                       half, n, g, marks);
+}
+
+void launch_zero_levels(hipStream_t st, const DepArgs &A)
+{
+    int64_t total = 0;
+    for (int l = 0; l < A.nlev; ++l) total += A.ncell[l];
+    if (total <= 0) return;
+    hipLaunchKernelGGL(k_fill_multi, dim3(blocks_for(total, 256)), dim3(256), 0, st, A, total, nullptr);
 }
 
 void launch_fill(hipStream_t st, double *v, int64_t n, double val)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256)), dim3(256), 0, st, v, n, val);
+    AMRMG_LAUNCH(k_fill, dim3(blocks_for(n, 256)), dim3(256), 0, st, v, n, val);
 }
 
 #define AMRMG_INST(T)                                                                                            \
     template void launch_outer_residual<T>(hipStream_t, const DevMeta &, int, int, const int32_t *,               \
                                            double *const *, double *const *, double, const double *, T *,         \
-                                           double *, int, bool, double *const *);                                 \
+                                           double *, int, bool, double *const *, const NormArgs &);               \
     template void launch_cpart_brick<T>(hipStream_t, const DevMeta &, int, int, const T *, T *);                \
     template void launch_gsrb<T>(hipStream_t, const DevMeta &, int, int, T *, const T *, const T *, int, bool);  \
     template void launch_jacobi<T>(hipStream_t, const DevMeta &, int, int, const T *, T *, const T *, const T *, \
@@ -935,7 +1536,11 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val)
                                        const T *);                                                               \
     template void launch_bottom_cg<T>(hipStream_t, const DevMeta &, const int4 *, int, const T *, T *, double *, \
                                       double, int, int *);                                                      \
-    template void launch_copy<T>(hipStream_t, const T *, T *, int64_t);
+    template void launch_copy<T>(hipStream_t, const T *, T *, int64_t);                                         \
+    template void launch_hgs<T>(hipStream_t, const DevMeta &, int, int, const T *, T *, const T *, T *,         \
+                                double *const *, int);                                                          \
+    template void launch_coarse_cycle<T>(hipStream_t, const DevMeta &, const CoarseJob *, int, T *, T *,        \
+                                         double *, int, int, double, int, int *, double *const *, bool, int);
 AMRMG_INST(float)
 AMRMG_INST(double)
 #undef AMRMG_INST

@@ -17,18 +17,46 @@ struct DepLevel {
     const int32_t *bmap;  // brick grid -> global brick id, or -1
 };
 
+// the levels a deposit writes (caller's layout)
+struct DepArgs {
+    DepLevel lev[MAX_AMR];
+    double *rho[MAX_AMR];
+    int64_t ncell[MAX_AMR];
+    int nlev;
+};
+
 struct GatherArgs {
     DepLevel lev[MAX_AMR];
     int nlev;
     const double *E[3 * MAX_AMR];
 };
 
+// per-level norms folded into a launch by its last workgroup
+struct NormArgs {
+    const int2 *ranges;  // brick ranges, one per norm
+    int n;
+    double *out;
+    unsigned *counter;   // zero between launches (reset by the last workgroup)
+};
+
+// the small bottom levels of one problem, handled by one workgroup
+struct CoarseJob {
+    int nlev;
+    int b0[8];
+    int nb[8];
+    int cg_off;
+};
+
 hipError_t upload_cf_weights(const double *w);
+// the next kernel launched by a launcher records kernel-execution timestamps
+// into these events (hipExtLaunchKernelGGL); cleared after that launch
+void set_launch_timing(hipEvent_t start, hipEvent_t stop);
+bool launch_timing_pending();
 
 template <class T>
 void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list,
                            double *const *phi, double *const *rho, double inv_eps0, const double *cp_phi, T *r_out,
-                           double *part, int norm_p, bool zero_phi, double *const *r_user = nullptr);
+                           double *part, int norm_p, bool zero_phi, double *const *r_user, const NormArgs &NA);
 void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double *part, double *out, int norm_p);
 void launch_cpart_user(hipStream_t st, const DevMeta &M, int cf0, int ncf, double *const *phi, double *cp);
 template <class T>
@@ -56,12 +84,30 @@ void launch_bottom_cg(hipStream_t st, const DevMeta &M, const int4 *jobs, int nj
                       double *work, double rtol, int maxit, int *iters);
 template <class T>
 void launch_copy(hipStream_t st, const T *a, T *b, int64_t n);
+// brick-hybrid Gauss-Seidel sweep; mode = bits of HG_ZERO 1, HG_PROL 2, HG_CPIN 4, HG_PHI 8
+template <class T>
+void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
+                double *const *phi, int mode);
+template <class T>
+void launch_coarse_cycle(hipStream_t st, const DevMeta &M, const CoarseJob *jobs, int njobs, T *e, T *r,
+                         double *work, int nu1, int nu2, double rtol, int maxit, int *iters, double *const *phi,
+                         bool phi_update, int threads_hint);
 void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
-                    const double *q, const DepLevel &D, const int64_t *ubase, const int2 *ustr, double *rho,
+                    const double *q, const uint32_t *perm, const DepArgs &A, const int64_t *ubase, const int2 *ustr,
                     unsigned long long *nout);
+void launch_zero_levels(hipStream_t st, const DepArgs &A);
 void launch_gather(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                    const GatherArgs &G, const int64_t *ubase, const int2 *ustr, double *Ex, double *Ey, double *Ez);
 void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, double *scratch, uint8_t *tags);
 void launch_fill(hipStream_t st, double *v, int64_t n, double val);
+// spatial (Morton) visiting order of particles: keys [2n], vals [2n]; on
+// success *perm_out points at the sorted indices (vals + n)
+size_t sort_temp_bytes(int64_t n);
+hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
+                          const double *lo, const double *hi, const int *nf, uint64_t *keys, uint32_t *vals,
+                          void *temp, size_t temp_bytes, uint32_t **perm_out);
+void launch_mark_blocks(hipStream_t st, const double *rho, int64_t ncell, const int4 *borg, const int64_t *ubase,
+                        const int2 *ustr, int nb, double lambda, int nbuf, int half, int3 n, int3 g, double *scratch,
+                        uint8_t *marks);
 
 }  // namespace amrmg

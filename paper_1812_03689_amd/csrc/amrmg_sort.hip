@@ -1,0 +1,85 @@
+// amrmg_sort.hip -- spatial visiting order of the particles for the deposit:
+// a Morton (Z-order) key of each particle's cell at a fine resolution, sorted
+// with the rocPRIM radix sort (through hipCUB).  In Z-order every cell of
+// every coarser level is a contiguous key range, so after the sort the
+// particles that a wavefront deposits fall into a few cells on every level and
+// their charges can be combined inside the wavefront before the atomics.
+#include <hip/hip_runtime.h>
+
+#include <hipcub/hipcub.hpp>
+
+#include "amrmg_kernels.hpp"
+
+namespace amrmg {
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v)
+{
+    uint64_t x = v & 0x1fffff;  // 21 bits
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+template <class P>
+__global__ void __launch_bounds__(256) k_morton_keys(int64_t n, const P *x, const P *y, const P *z, double lo0,
+                                                     double lo1, double lo2, double hi0, double hi1, double hi2,
+                                                     int3 nf, uint64_t *keys, uint32_t *vals)
+{
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    double X[3] = {(double)x[p], (double)y[p], (double)z[p]};
+    double lo[3] = {lo0, lo1, lo2}, hi[3] = {hi0, hi1, hi2};
+    int nn[3] = {nf.x, nf.y, nf.z};
+    uint64_t key = 0;
+    bool inside = true;
+    for (int d = 0; d < 3; ++d) {
+        if (!(X[d] >= lo[d] && X[d] < hi[d])) inside = false;
+        double s = (X[d] - lo[d]) / (hi[d] - lo[d]) * nn[d];
+        int c = (int)floor(s);
+        c = c < 0 ? 0 : (c >= nn[d] ? nn[d] - 1 : c);
+        key |= spread3((uint32_t)c) << d;
+    }
+    keys[p] = inside ? key : ~0ull;
+    vals[p] = (uint32_t)p;
+}
+
+size_t sort_temp_bytes(int64_t n)
+{
+    size_t bytes = 0;
+    hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                       (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n, 0, 63);
+    return bytes;
+}
+
+hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
+                          const double *lo, const double *hi, const int *nf, uint64_t *keys, uint32_t *vals,
+                          void *temp, size_t temp_bytes, uint32_t **perm_out)
+{
+    *perm_out = nullptr;
+    if (n <= 0) return hipSuccess;
+    unsigned g = (unsigned)((n + 255) / 256);
+    int3 nn = make_int3(nf[0], nf[1], nf[2]);
+    if (pos_f32)
+        hipLaunchKernelGGL((k_morton_keys<float>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
+                           (const float *)z, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], nn, keys, vals);
+    else
+        hipLaunchKernelGGL((k_morton_keys<double>), dim3(g), dim3(256), 0, st, n, (const double *)x,
+                           (const double *)y, (const double *)z, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], nn, keys,
+                           vals);
+    int bits = 0;
+    int m = nf[0] > nf[1] ? nf[0] : nf[1];
+    m = m > nf[2] ? m : nf[2];
+    while ((1 << bits) < m) ++bits;
+    int end_bit = 3 * bits < 63 ? 3 * bits : 63;
+    size_t tb = temp_bytes;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, tb, keys, keys + n, vals, vals + n, (int)n, 0, end_bit,
+                                                      st);
+    if (e != hipSuccess) return e;
+    *perm_out = vals + n;
+    return hipGetLastError();
+}
+
+}  // namespace amrmg
