@@ -60,6 +60,12 @@ enum { AMRMG_FP64 = 0, AMRMG_MIXED = 1 };
  * AMRMG_JACOBI = damped Jacobi.  The small levels at the bottom of the cycle
  * always use whole-level red-black inside one workgroup. */
 enum { AMRMG_GSRB = 0, AMRMG_JACOBI = 1, AMRMG_GSRB_GLOBAL = 2 };
+/* Bottom solvers of the coarsest grid: AMRMG_BOTTOM_AUTO solves it directly
+ * (separable eigendecomposition of the Dirichlet Laplacian on its one box)
+ * when the grid plus its transform tables fit in 152 KiB of LDS (up to 24^3
+ * cells), and by CG to bottom_rtol otherwise; AMRMG_BOTTOM_CG always uses
+ * CG. */
+enum { AMRMG_BOTTOM_AUTO = 0, AMRMG_BOTTOM_CG = 1 };
 enum { AMRMG_MAX_LEVELS = 8 };
 
 /* Solver and hierarchy parameters.  amrmg_default_params fills the defaults
@@ -85,6 +91,7 @@ typedef struct amrmg_params {
     double bottom_rtol;         /* CG tolerance on the coarsest grid, relative to its right-hand
                                    side; it bounds only how well each cycle treats the smoothest
                                    modes, not the accuracy of the result [1e-2] */
+    int32_t bottom;             /* AMRMG_BOTTOM_AUTO or AMRMG_BOTTOM_CG [AUTO] */
 } amrmg_params;
 
 /* Per-solve statistics. */

@@ -146,6 +146,7 @@ struct DevState {
     int njobs = 0;
     size_t cg_doubles = 0;
     CoarseJob *d_cjobs = nullptr;
+    double *d_dtab = nullptr;  // direct-solve tables of the coarsest grids
     int kc = 0;  // levels 0..kc of every problem run in the one-workgroup coarse cycle
     // per-level pointer tables: phi[ne], rho[ne], rout[ne], E[3 ne]
     DBuf ptrbuf;
@@ -161,12 +162,16 @@ struct DevState {
     double *cpphi = nullptr, *part = nullptr, *dnorm = nullptr;
     double *cgw = nullptr;
     int *cgit = nullptr;
-    unsigned *ncounter = nullptr;
     int cg_threads = 1024;
     PBuf h_normbuf;
     double *h_norm = nullptr;
-    // AMR-level brick maps with global brick ids (single problems)
+    // AMR-level brick maps with global brick ids of the first problem (views
+    // into the map pool)
     std::vector<int32_t *> d_bmap;
+    // face data generated on the device: gbc, cf_pat, cf_idx, error flag
+    DBuf facebuf;
+    int *d_face_err = nullptr;
+    PBuf h_face_err;
     // captured outer iteration (V-cycle, phi update, FP64 residual, norms)
     hipGraphExec_t gexec = nullptr;
     std::vector<int64_t> gkey;
@@ -187,15 +192,59 @@ struct DevState {
 
 static bool g_weights_ok = false;
 
-// upload D.meta (plus optional extra arrays) in one copy
-static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<std::vector<int32_t>> *bmaps)
+// Upload D.meta (built without face data) in one copy, then generate the
+// face data (boundary values, coarse-fine windows) on the device.
+static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<const Problem *> &probs,
+                                bool direct)
 {
     const Meta &m = D.meta;
     if (!g_weights_ok) {
         std::vector<double> W = cf_weight_table();
         HIP_TRY(upload_cf_weights(W.data()));
+        uint32_t masks[13];
+        int org[42];
+        pattern_tables(masks, org);
+        HIP_TRY(upload_pattern_tables(masks, org));
         g_weights_ok = true;
     }
+    // level table, brick maps of the AMR levels (global ids) and monopoles
+    static thread_local std::vector<EntryDev> ed;
+    static thread_local std::vector<int32_t> pool;
+    static thread_local std::vector<double> mono;
+    static thread_local std::vector<int> mono_off;
+    ed.assign(m.ent.size(), EntryDev{});
+    pool.clear();
+    mono.clear();
+    mono_off.assign(probs.size(), 0);
+    for (size_t i = 0; i < probs.size(); ++i) {
+        mono_off[i] = (int)(mono.size() / 4);
+        mono.insert(mono.end(), probs[i]->mono.begin(), probs[i]->mono.begin() + (probs[i]->mono.size() / 4) * 4);
+    }
+    std::vector<int> amr_off;  // pool offset of AMR level l of problem 0
+    for (size_t ei = 0; ei < m.ent.size(); ++ei) {
+        const Meta::Entry &e = m.ent[ei];
+        const Problem &P = *probs[e.prob];
+        const HostLevel &L = P.lev[e.k];
+        EntryDev &E = ed[ei];
+        for (int d = 0; d < 3; ++d) {
+            E.lo[d] = P.lo[d];
+            E.h[d] = L.h[d];
+            E.n[d] = L.n[d];
+            E.nbk[d] = L.nbk[d];
+        }
+        E.eps0 = P.eps0;
+        E.amr = L.amr;
+        E.crse = e.k > 0 ? m.prob_ent[e.prob][e.k - 1] : -1;
+        E.mono_off = mono_off[e.prob];
+        E.mono_n = (int)(P.mono.size() / 4);
+        E.bmap_off = -1;
+        if (L.amr >= 0) {
+            E.bmap_off = (int)pool.size();
+            if (e.prob == 0) amr_off.push_back(E.bmap_off);
+            for (int32_t v : L.bmap) pool.push_back(v >= 0 ? v + e.b0 : -1);
+        }
+    }
+    if (mono.empty()) mono.push_back(0.0);
     static thread_local std::vector<LevelConst> lc;
     lc.assign(m.ent.size(), LevelConst{});
     for (size_t i = 0; i < m.ent.size(); ++i)
@@ -249,7 +298,9 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<s
         D.cg_threads = maxn <= 512 ? 512 : 1024;
     }
     static thread_local std::vector<CoarseJob> cj;
+    static thread_local std::vector<double> dtab;
     cj.assign(m.prob_ent.size(), CoarseJob{});
+    dtab.clear();
     for (size_t i = 0; i < m.prob_ent.size(); ++i) {
         cj[i].nlev = kc + 1;
         for (int k = 0; k <= kc; ++k) {
@@ -257,7 +308,21 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<s
             cj[i].nb[k] = m.ent[m.prob_ent[i][k]].nb;
         }
         cj[i].cg_off = jobs[4 * i + 2];
+        // direct solve of the coarsest grid when it is one full box that fits
+        const HostLevel &L = probs[m.ent[m.prob_ent[i][0]].prob]->lev[0];
+        int64_t ntab = 0;
+        for (int d = 0; d < 3; ++d) ntab += 2 * (int64_t)L.n[d] * L.n[d] + L.n[d];
+        bool fits = direct && L.boxes.size() == 1 && (int64_t)L.n[0] * L.n[1] * L.n[2] + ntab <= DIRECT_LDS;
+        for (int d = 0; d < 3 && fits; ++d) fits = L.boxes[0].lo[d] == 0 && L.boxes[0].hi[d] == L.n[d];
+        cj[i].dtab = -1;
+        for (int d = 0; d < 3; ++d) cj[i].dn[d] = L.n[d];
+        if (fits) {
+            cj[i].dtab = (int)dtab.size();
+            std::vector<double> t = direct_tables(L.n, L.h);
+            dtab.insert(dtab.end(), t.begin(), t.end());
+        }
     }
+    if (dtab.empty()) dtab.push_back(0.0);
 
     Packer P;
     int32_t *org = nullptr, *nbr = nullptr, *child = nullptr, *par = nullptr, *ustr = nullptr, *gfo = nullptr,
@@ -274,19 +339,33 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<s
     P.add(m.ubase, &ub);
     P.add(m.ustr, &ustr);
     P.add(m.gf_owner, &gfo);
-    P.add(m.gbc, &gbc);
-    P.add(m.cf_pat, &cfp);
-    P.add(m.cf_idx, &cfi);
     P.add(m.reflux, &D.d_reflux);
     P.add(m.amr_bricks, &D.d_amr);
     P.add(lc, &dlc);
     P.add(rg, &drg);
     P.add(jobs, &dj);
     P.add(cj, &D.d_cjobs);
-    D.d_bmap.assign(bmaps ? bmaps->size() : 0, nullptr);
-    if (bmaps)
-        for (size_t l = 0; l < bmaps->size(); ++l) P.add((*bmaps)[l], &D.d_bmap[l]);
+    EntryDev *dent = nullptr;
+    int32_t *dpool = nullptr;
+    double *dmono = nullptr;
+    P.add(dtab, &D.d_dtab);
+    P.add(ed, &dent);
+    P.add(pool, &dpool);
+    P.add(mono, &dmono);
     ST_TRY(P.run(D.metabuf, D.stage, st));
+    D.d_bmap.assign(amr_off.size(), nullptr);
+    for (size_t l = 0; l < amr_off.size(); ++l) D.d_bmap[l] = dpool + amr_off[l];
+    // face data buffers: gbc [nbc*64], cf_idx [ncf*144], cf_pat [ncf*16], error flag
+    size_t o_gbc = 0, o_idx = align256((size_t)m.nbc * 64 * 8 + 8);
+    size_t o_pat = o_idx + align256((size_t)m.ncf * 144 * 4 + 4);
+    size_t o_err = o_pat + align256((size_t)m.ncf * 16 + 1);
+    HIP_TRY(D.facebuf.ensure(o_err + 256));
+    HIP_TRY(D.h_face_err.ensure(sizeof(int)));
+    char *fb = (char *)D.facebuf.p;
+    gbc = (double *)(fb + o_gbc);
+    cfi = (int32_t *)(fb + o_idx);
+    cfp = (uint8_t *)(fb + o_pat);
+    D.d_face_err = (int *)(fb + o_err);
     D.M.org = (const int4 *)org;
     D.M.nbr = nbr;
     D.M.child = child;
@@ -303,6 +382,11 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<s
     D.M.ncf = m.ncf;
     D.d_ranges = (int2 *)drg;
     D.d_jobs = (int4 *)dj;
+    HIP_TRY(hipMemsetAsync(D.d_face_err, 0, sizeof(int), st));
+    launch_face_data(st, D.M, dent, dpool, dmono, gbc, cfp, cfi, D.d_face_err);
+    HIP_TRY(hipGetLastError());
+    *(int *)D.h_face_err.p = 0;
+    HIP_TRY(hipMemcpyAsync(D.h_face_err.p, D.d_face_err, sizeof(int), hipMemcpyDeviceToHost, st));
     // per-level pointer tables (filled per call)
     size_t ne = m.ent.size();
     D.h_phi.assign(ne, nullptr);
@@ -372,8 +456,6 @@ static amrmg_status ensure_ws(DevState &D, int prec, void *user, size_t user_byt
     D.dnorm = (double *)take(sizeof(double) * 2 * (D.range_prob.size() + 1));
     D.cgw = (double *)take(D.cg_doubles * 8);
     D.cgit = (int *)take(64);
-    D.ncounter = (unsigned *)((char *)D.cgit + 32);
-    HIP_TRY(hipMemset(D.ncounter, 0, sizeof(unsigned)));
     D.ws_prec = prec;
     return AMRMG_OK;
 }
@@ -506,6 +588,7 @@ extern "C" void amrmg_default_params(amrmg_params *p)
     p->norm_p = 2;
     p->max_iters = 50;
     p->bottom_rtol = 1e-2;
+    p->bottom = AMRMG_BOTTOM_AUTO;
 }
 
 extern "C" const char *amrmg_last_error(void) { return g_err.c_str(); }
@@ -531,6 +614,7 @@ static amrmg_status check_params(const amrmg_params *p)
     if (p->norm_p != 0 && p->norm_p != 1 && p->norm_p != 2) return fail(AMRMG_E_INVALID, "norm_p must be 0, 1 or 2");
     if (p->max_iters < 0) return fail(AMRMG_E_INVALID, "max_iters must be >= 0");
     if (!(p->bottom_rtol > 0 && p->bottom_rtol < 1)) return fail(AMRMG_E_INVALID, "bottom_rtol in (0, 1)");
+    if (p->bottom != AMRMG_BOTTOM_AUTO && p->bottom != AMRMG_BOTTOM_CG) return fail(AMRMG_E_INVALID, "bad bottom");
     if (!(p->omega > 0 && p->omega <= 1)) return fail(AMRMG_E_INVALID, "omega in (0, 1]");
     return AMRMG_OK;
 }
@@ -710,19 +794,12 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
         pr.lev.push_back(F);
     }
     add_levels_below(pr);
-    build_meta({&pr}, ctx->ds.meta);
+    build_meta({&pr}, ctx->ds.meta, false);
     if (!ctx->ds.meta.error.empty()) return fail(AMRMG_E_NESTING, ctx->ds.meta.error);
-    // per AMR level brick map with global brick ids
-    std::vector<std::vector<int32_t>> bmaps(pr.namr());
-    for (int l = 0; l < pr.namr(); ++l) {
-        const HostLevel &L = pr.lev[pr.kg + l];
-        int b0 = ctx->ds.meta.ent[ctx->ds.meta.prob_ent[0][pr.kg + l]].b0;
-        bmaps[l] = L.bmap;
-        for (auto &v : bmaps[l])
-            if (v >= 0) v += b0;
-    }
-    ST_TRY(upload_meta(ctx->ds, ctx->st, &bmaps));
+    ST_TRY(upload_meta(ctx->ds, ctx->st, {&pr}, P.bottom == AMRMG_BOTTOM_AUTO));
     HIP_TRY(hipStreamSynchronize(ctx->st));
+    if (*(int *)ctx->ds.h_face_err.p)
+        return fail(AMRMG_E_NESTING, "coarse-fine window leaves the coarser level (nesting violated)");
     ctx->built = true;
     return AMRMG_OK;
 }
@@ -773,6 +850,11 @@ extern "C" amrmg_status amrmg_cf_faces(const amrmg_ctx *ctx, int32_t level, int3
     if (level < 0 || level >= pr.namr()) return fail(AMRMG_E_INVALID, "level out of range");
     const Meta &m = ctx->ds.meta;
     const Meta::Entry &e = m.ent[m.prob_ent[0][pr.kg + level]];
+    std::vector<uint8_t> pat((size_t)e.ncf * 16);
+    if (e.ncf > 0) {
+        HIP_TRY(hipStreamSynchronize(ctx->st));
+        HIP_TRY(hipMemcpy(pat.data(), ctx->ds.M.cf_pat + (size_t)e.cf0 * 16, pat.size(), hipMemcpyDeviceToHost));
+    }
     int64_t k = 0;
     for (int c = e.cf0; c < e.cf0 + e.ncf; ++c) {
         int32_t ow = m.gf_owner[m.nbc + c];
@@ -789,7 +871,7 @@ extern "C" amrmg_status amrmg_cf_faces(const amrmg_ctx *ctx, int32_t level, int3
             o[3] = d;
             o[4] = s;
             int mm = ((t & 7) >> 1) + 4 * ((t >> 3) >> 1);
-            o[5] = m.cf_pat[(size_t)c * 16 + mm];
+            o[5] = pat[(size_t)(c - e.cf0) * 16 + mm];
         }
     }
     if (count) *count = k;
@@ -952,10 +1034,9 @@ struct Driver {
         // (a last-workgroup reduction inside the residual kernel would need a
         // device-scope fence per workgroup, which costs far more than this
         // extra launch on a chip whose XCDs have separate L2 caches)
-        NormArgs NA{D.d_ranges, (int)D.range_prob.size(), D.dnorm + noff, nullptr};
         pb(AMRMG_K_RESIDUAL);
         launch_outer_residual<T>(st, D.M, b0, nb, list, D.d_phi, D.d_rho, o.inv_eps0, zero_phi ? nullptr : D.cpphi,
-                                 (zero_phi || rout_user) ? nullptr : r, D.part, o.norm_p, zero_phi, rout_user, NA);
+                                 (zero_phi || rout_user) ? nullptr : r, D.part, o.norm_p, zero_phi, rout_user);
         pe(AMRMG_K_RESIDUAL, (double)nb * BRICK_CELLS * (zero_phi ? 8.0 : 16.0 + W));
         launch_level_norms(st, D.d_ranges, (int)D.range_prob.size(), D.part, D.dnorm + noff, o.norm_p);
     }
@@ -1056,8 +1137,8 @@ struct Driver {
             pe(AMRMG_K_REFLUX, 2.0 * nrf * BRICK_CELLS * W);
         }
         pb(AMRMG_K_BOTTOM);
-        launch_coarse_cycle<T>(st, D.M, D.d_cjobs, D.njobs, e, r, D.cgw, o.nu1, o.nu2, o.bottom_rtol, 10000, D.cgit,
-                               D.d_phi, hybrid(), D.cg_threads);
+        launch_coarse_cycle<T>(st, D.M, D.d_cjobs, D.njobs, e, r, D.cgw, D.d_dtab, o.nu1, o.nu2, o.bottom_rtol,
+                               10000, D.cgit, D.d_phi, hybrid(), D.cg_threads);
         pe(AMRMG_K_BOTTOM, (double)D.cg_doubles / 4 * (2 * W));
         for (int k = kc + 1; k < m.K; ++k) {
             if (hybrid()) {

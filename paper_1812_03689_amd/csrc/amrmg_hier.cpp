@@ -249,6 +249,14 @@ static uint32_t window_mask(int pat)
 
 uint32_t quadratic_mask(int pat) { return window_mask(pat); }
 
+void pattern_tables(uint32_t masks13[13], int org14x3[42])
+{
+    for (int p = 0; p < 14; ++p) {
+        if (p < 13) masks13[p] = window_mask(p);
+        pattern_window(p, org14x3[3 * p], org14x3[3 * p + 1], org14x3[3 * p + 2]);
+    }
+}
+
 int select_pattern(uint32_t mask5)
 {
     static const struct Masks {
@@ -289,6 +297,30 @@ std::vector<double> cf_weight_table()
     return W;
 }
 
+std::vector<double> direct_tables(const int n[3], const double h[3])
+{
+    std::vector<double> t;
+    for (int d = 0; d < 3; ++d) {
+        const int N = n[d];
+        std::vector<double> S((size_t)N * N);
+        for (int i = 0; i < N; ++i)
+            for (int k = 0; k < N; ++k) {
+                double c = (k == N - 1) ? std::sqrt(1.0 / N) : std::sqrt(2.0 / N);
+                S[(size_t)i * N + k] = c * std::sin(kPi * (k + 1) * (i + 0.5) / N);
+            }
+        for (int k = 0; k < N; ++k)
+            for (int i = 0; i < N; ++i) t.push_back(S[(size_t)i * N + k]);
+        for (int i = 0; i < N; ++i)
+            for (int k = 0; k < N; ++k) t.push_back(S[(size_t)i * N + k]);
+    }
+    for (int d = 0; d < 3; ++d)
+        for (int k = 0; k < n[d]; ++k) {
+            double s = std::sin(kPi * (k + 1) / (2.0 * n[d]));
+            t.push_back(4.0 * s * s / (h[d] * h[d]));
+        }
+    return t;
+}
+
 void add_levels_below(Problem &P)
 {
     std::vector<HostLevel> below;
@@ -326,7 +358,7 @@ static inline void tdirs(int d, int &du, int &dv)
     dv = (d == 2) ? 1 : 2;
 }
 
-void build_meta(const std::vector<const Problem *> &probs, Meta &M)
+void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_data)
 {
     M = Meta();
     const int np = (int)probs.size();
@@ -443,8 +475,8 @@ void build_meta(const std::vector<const Problem *> &probs, Meta &M)
     for (int t = 0; t < M.ncf; ++t) M.gf_owner[M.nbc + t] = (cff[t].brick << 3) | cff[t].dir;
 
     // Dirichlet data at the centres of the boundary faces of AMR levels
-    M.gbc.assign((size_t)M.nbc * 64, 0.0);
-    for (int t = 0; t < M.nbc; ++t) {
+    M.gbc.assign(face_data ? (size_t)M.nbc * 64 : 0, 0.0);
+    for (int t = 0; t < M.nbc && face_data; ++t) {
         const Meta::Entry &e = M.ent[bcf[t].ent];
         const Problem &P = *probs[e.prob];
         if (e.amr < 0 || P.mono.empty()) continue;
@@ -464,9 +496,9 @@ void build_meta(const std::vector<const Problem *> &probs, Meta &M)
     }
 
     // coarse-fine faces: pattern and window cells per coarse cell
-    M.cf_pat.assign((size_t)M.ncf * 16, 0);
-    M.cf_idx.assign((size_t)M.ncf * 16 * 9, 0);
-    for (int t = 0; t < M.ncf; ++t) {
+    M.cf_pat.assign(face_data ? (size_t)M.ncf * 16 : 0, 0);
+    M.cf_idx.assign(face_data ? (size_t)M.ncf * 16 * 9 : 0, 0);
+    for (int t = 0; t < M.ncf && face_data; ++t) {
         const Meta::Entry &e = M.ent[cff[t].ent];
         const Problem &P = *probs[e.prob];
         const HostLevel &Lf = P.lev[e.k];

@@ -63,6 +63,20 @@ void pattern_window(int pat, int &u0, int &v0, int &np);
 std::vector<double> cf_weight_table();
 // the 25-bit masks of the 9 quadratic windows, built from pattern_window
 uint32_t quadratic_mask(int pat);
+// the tables the device pattern selection reads: window masks of patterns
+// 0..12 and (u0, v0, nodes per axis) of patterns 0..13
+void pattern_tables(uint32_t masks13[13], int org14x3[42]);
+
+// Direct solve of the coarsest grid: the cell-centred Laplacian with
+// homogeneous Dirichlet ghosts (-u_c) on a full box of n cells is separable;
+// along an axis of N cells its 1-D matrix (2 on the diagonal, 3 at both ends,
+// -1 off the diagonal, times 1/h^2) has the orthonormal eigenvectors
+// S[i][k] = c_k sin(pi (k+1) (i+1/2) / N), c_k = sqrt(2/N) (k < N-1) or
+// sqrt(1/N) (k = N-1), with eigenvalues 4 sin^2(pi (k+1) / (2N)) / h^2.
+// Layout per axis d (N = n[d]): the forward matrix F[k][i] = S[i][k] and the
+// inverse matrix B[i][k] = S[i][k], each N x N, output-major; then the three
+// eigenvalue vectors.  Size 2 (n0^2 + n1^2 + n2^2) + n0 + n1 + n2 doubles.
+std::vector<double> direct_tables(const int n[3], const double h[3]);
 
 // One problem (one context): its levels coarsest first; kg = index of AMR
 // level 0.
@@ -115,6 +129,8 @@ struct Meta {
     std::string error;                       // non-empty when the hierarchy is inconsistent
 };
 
-void build_meta(const std::vector<const Problem *> &probs, Meta &M);
+// face_data: also compute gbc, cf_pat and cf_idx on the host (the library
+// generates them on the device instead, from the same pattern tables)
+void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_data = true);
 
 }  // namespace amrmg

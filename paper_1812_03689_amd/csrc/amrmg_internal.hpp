@@ -45,4 +45,19 @@ struct DevMeta {
     int32_t ncf;              // coarse-fine faces are gface [nbc, nbc+ncf)
 };
 
+// per level id: what the kernels that generate face data (Dirichlet values
+// of boundary faces, coarse-fine windows) need to know about its level
+struct EntryDev {
+    double lo[3];    // problem domain lower corner
+    double h[3];     // cell size
+    double eps0;
+    int n[3];        // index extent
+    int nbk[3];      // brick grid extent
+    int amr;         // AMR level number, -1 below level 0
+    int crse;        // level id of the next coarser level of the problem, -1 if none
+    int bmap_off;    // offset of the brick map (global brick ids, -1 = no brick) in the map pool, -1 if none
+    int mono_off;    // first monopole (q, x, y, z) of the problem in the monopole pool
+    int mono_n;      // number of monopoles
+};
+
 }  // namespace amrmg

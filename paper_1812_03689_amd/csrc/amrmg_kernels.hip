@@ -193,29 +193,6 @@ __device__ double block_reduce_256(double v, int op)
     return r;
 }
 
-// The last workgroup of a launch to finish reduces the per-brick partials to
-// one norm per listed brick range, in a fixed order, and resets the counter
-// for the next launch.
-__device__ void level_norms_last_block(const double *part, const NormArgs &NA, int norm_p)
-{
-    if (!NA.counter) return;
-    __shared__ int last;
-    __threadfence();
-    if (threadIdx.x == 0) last = (atomicAdd(NA.counter, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    for (int l = 0; l < NA.n; ++l) {
-        int2 rg = NA.ranges[l];
-        double acc = 0.0;
-        for (int b = rg.x + (int)threadIdx.x; b < rg.x + rg.y; b += 256)
-            acc = norm_p == 0 ? fmax(acc, part[b]) : acc + part[b];
-        acc = block_reduce_256(acc, norm_p == 0);
-        if (threadIdx.x == 0) NA.out[l] = norm_p == 2 ? sqrt(acc) : acc;
-    }
-    if (threadIdx.x == 0) *NA.counter = 0u;
-}
-
 // ---------------------------------------------------------------------------
 // LDS tile of one brick: the 8^3 cells plus one halo layer on the six faces
 // (edges and corners are never read by the 7-point stencil).  A halo cell
@@ -348,104 +325,206 @@ __device__ double fine_face_sum(const DevMeta &M, int nb, const int *nl, int d, 
 {
     int F = M.child[nb * 8 + oct_of(nl[0], nl[1], nl[2])];
     int4 co = M.org[nb], fo = M.org[F];
-    int gn[3] = {co.x + nl[0], co.y + nl[1], co.z + nl[2]};
-    int fob[3] = {fo.x, fo.y, fo.z};
-    int du, dv;
-    transverse(d, du, dv);
-    int gfc = -1 - M.nbr[F * 6 + 2 * d + (s < 0)];  // F's face towards the coarse cell
-    size_t cf = (size_t)(gfc - M.nbc);
+    // the fine cell at twice the coarse cell's index, relative to F
+    const int bx = 2 * (co.x + nl[0]) - fo.x, by = 2 * (co.y + nl[1]) - fo.y, bz = 2 * (co.z + nl[2]) - fo.z;
+    const int gfc = -1 - M.nbr[F * 6 + 2 * d + (s < 0)];  // F's face towards the coarse cell
+    const size_t cf = (size_t)(gfc - M.nbc);
+    const int nd = (s > 0) ? 0 : 1;  // the fine layer next to the face along d
     double sum = 0.0;
     for (int bb = 0; bb < 2; ++bb)
         for (int aa = 0; aa < 2; ++aa) {
-            int fl[3];
-            fl[d] = 2 * gn[d] + (s > 0 ? 0 : 1) - fob[d];
-            fl[du] = 2 * gn[du] + aa - fob[du];
-            fl[dv] = 2 * gn[dv] + bb - fob[dv];
-            int f2[3] = {fl[0], fl[1], fl[2]};
-            f2[d] += s;
-            int t = fl[du] + 8 * fl[dv];
-            double c = cp ? cp[cf * 64 + t] : 0.0;
+            // offsets along (d, du, dv) = (nd, aa, bb) with du < dv the other two axes
+            int ox = d == 0 ? nd : aa;
+            int oy = d == 1 ? nd : (d == 0 ? aa : bb);
+            int oz = d == 2 ? nd : bb;
+            int fl[3] = {bx + ox, by + oy, bz + oz};
+            int f2[3] = {fl[0] + (d == 0 ? s : 0), fl[1] + (d == 1 ? s : 0), fl[2] + (d == 2 ? s : 0)};
+            int tu = d == 0 ? fl[1] : fl[0], tv = d == 2 ? fl[1] : fl[2];
+            double c = cp ? cp[cf * 64 + tu + 8 * tv] : 0.0;
             sum += (1.0 / 3.0) * uf(F, fl) + 0.2 * uf(F, f2) - c;
         }
     return sum;
 }
 
+// Halo slots of a staged tile that hold the ghost form a * u_c + bv (boundary
+// and coarse-fine faces) are replaced by the ghost value itself, using the
+// staged interior: a coarse-fine ghost is cpart + 2/3 u_c - 1/5 u_in.  After
+// this the plain 7-point stencil on the tile is the operator.
+__device__ __forceinline__ void finish_ghosts(double *tile, const double *alpha)
+{
+    for (int t = threadIdx.x; t < 384; t += blockDim.x) {
+        int f = t >> 6, d = f >> 1;
+        double a = alpha[f];
+        if (a == 0.0) continue;
+        bool plus = f & 1;
+        int du, dv;
+        transverse(d, du, dv);
+        int l[3], c[3], in[3];
+        l[du] = c[du] = in[du] = t & 7;
+        l[dv] = c[dv] = in[dv] = (t >> 3) & 7;
+        l[d] = plus ? 8 : -1;
+        c[d] = plus ? 7 : 0;
+        in[d] = plus ? 6 : 1;
+        double g = tile[tix(l[0], l[1], l[2])] + a * tile[tix(c[0], c[1], c[2])];
+        if (a > 0.0) g -= 0.2 * tile[tix(in[0], in[1], in[2])];
+        tile[tix(l[0], l[1], l[2])] = g;
+    }
+}
+
+// Composite residual r = rho/eps0 - A_comp phi on uncovered cells (zero on
+// covered ones) of a range or list of AMR bricks, written as T in brick
+// layout (r_out) and/or FP64 in the caller's layout (r_user), with the
+// per-brick partial norm.  A face towards a covered cell takes the mean of the
+// four fine fluxes through it (flux matching).  Bricks with no covered cell
+// and no covered face neighbour (every brick of the finest level) take the
+// plain 7-point stencil on the tile.
 template <class T, bool ZERO>
 __global__ void __launch_bounds__(256) k_outer_residual(DevMeta M, int b0, int nb, double *const *phi, double *const *rho,
                                                         double inv_eps0, const double *cp_phi, T *r_out,
                                                         double *part, int norm_p, const int32_t *list,
-                                                        double *const *r_user, NormArgs NA)
+                                                        double *const *r_user)
 {
     __shared__ double tile[TE * TE * TE];
     __shared__ double alpha[6];
+    __shared__ int nbk[6];
     __shared__ uint8_t ncm[6];
-    int b = pick_brick(b0, nb, list, blockIdx.x);
-    int4 o = M.org[b];
-    int lev = o.w;
-    LevelConst L = M.lc[lev];
-    uint8_t cm = M.cmask[b];
+    const int b = pick_brick(b0, nb, list, blockIdx.x);
+    const int4 o = M.org[b];
+    const int lev = o.w;
+    const LevelConst L = M.lc[lev];
+    const uint8_t cm = M.cmask[b];
     if (threadIdx.x < 6) {
         int f = M.nbr[b * 6 + threadIdx.x];
+        nbk[threadIdx.x] = f;
         ncm[threadIdx.x] = f >= 0 ? M.cmask[f] : 0;
     }
-    SrcU src{phi, M.org, M.ubase, M.ustr};
-    stage_tile<SrcU, ZERO, CpArr<double>>(M, b, src, CpArr<double>{ZERO ? nullptr : cp_phi}, true, tile, alpha);
-    UserAccL facc{phi, M.org, M.ubase, M.ustr};
+    const int64_t ub = M.ubase[b];
+    const int2 us = M.ustr[b];
+    const double *ph = phi[lev];
     const double *rh = rho[lev];
-    int64_t ub = M.ubase[b];
-    int2 us = M.ustr[b];
+    int64_t ui[2];
+    double rv[2];
+    for (int k = 0; k < 2; ++k) {
+        int c = threadIdx.x + 256 * k;
+        ui[k] = ub + (c & 7) + (int64_t)us.x * ((c >> 3) & 7) + (int64_t)us.y * (c >> 6);
+        rv[k] = rh[ui[k]] * inv_eps0;
+        tile[tix(c & 7, (c >> 3) & 7, c >> 6)] = ZERO ? 0.0 : ph[ui[k]];
+    }
+    // halo layer (no interior: the loop above staged it); face neighbours
+    // are on the same level, so their values come from ph
+    {
+        CpArr<double> cp{ZERO ? nullptr : cp_phi};
+        for (int t = threadIdx.x; t < 384; t += 256) {
+            int f = t >> 6, d = f >> 1;
+            bool plus = f & 1;
+            int du, dv;
+            transverse(d, du, dv);
+            int iu = t & 7, iv = (t >> 3) & 7, fl = t & 63;
+            int l[3];
+            l[du] = iu;
+            l[dv] = iv;
+            l[d] = plus ? 8 : -1;
+            int nbr = M.nbr[b * 6 + f];
+            double v, a = 0.0;
+            if (nbr >= 0) {
+                int m[3] = {l[0], l[1], l[2]};
+                m[d] = plus ? 0 : 7;
+                v = 0.0;
+                if (!ZERO) {
+                    int2 ns = M.ustr[nbr];
+                    v = ph[M.ubase[nbr] + m[0] + (int64_t)ns.x * m[1] + (int64_t)ns.y * m[2]];
+                }
+            } else {
+                int g = -1 - nbr;
+                if (g < M.nbc) {
+                    a = -1.0;
+                    v = 2.0 * M.gbc[(size_t)g * 64 + fl];
+                } else {
+                    a = 2.0 / 3.0;
+                    v = cp((size_t)(g - M.nbc), fl);
+                }
+            }
+            tile[tix(l[0], l[1], l[2])] = v;
+            if (fl == 0) alpha[f] = a;
+        }
+    }
+    __syncthreads();
+    finish_ghosts(tile, alpha);
+    bool any_cov = cm != 0;
+    for (int f = 0; f < 6; ++f) any_cov = any_cov || ncm[f] != 0;  // uniform over the workgroup
+    __syncthreads();
     double acc = 0.0;
-    for (int c = threadIdx.x; c < BRICK_CELLS; c += 256) {
+    for (int k = 0; k < 2; ++k) {
+        int c = threadIdx.x + 256 * k;
         int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
-        int64_t ui = ub + x + (int64_t)us.x * y + (int64_t)us.y * z;
-        double rv = 0.0;
+        double r = 0.0;
         if (!((cm >> oct_of(x, y, z)) & 1)) {
             double uc = tile[tix(x, y, z)];
             double Au = 0.0;
-            for (int d = 0; d < 3; ++d)
-                for (int s = -1; s <= 1; s += 2) {
-                    int nl[3] = {x, y, z};
-                    int n = nl[d] + s, nbk = b;
-                    bool cov;
-                    if (n >= 0 && n < BRICK) {
-                        nl[d] = n;
-                        cov = (cm >> oct_of(nl[0], nl[1], nl[2])) & 1;
-                    } else {
-                        nl[d] = (s > 0) ? 0 : BRICK - 1;
-                        cov = (ncm[2 * d + (s > 0)] >> oct_of(nl[0], nl[1], nl[2])) & 1;
-                        if (cov) nbk = M.nbr[b * 6 + 2 * d + (s > 0)];
-                    }
-                    if (cov) {
-                        if (!ZERO) Au += -0.5 * L.ih2[d] * fine_face_sum(M, nbk, nl, d, s, facc, cp_phi);
-                    } else {
-                        double a, bv;
-                        tile_ab(tile, alpha, x, y, z, d, s, a, bv);
-                        Au += L.ih2[d] * ((1.0 - a) * uc - bv);
+            if (!any_cov) {
+                Au = L.ih2[0] * (2.0 * uc - tile[tix(x - 1, y, z)] - tile[tix(x + 1, y, z)]) +
+                     L.ih2[1] * (2.0 * uc - tile[tix(x, y - 1, z)] - tile[tix(x, y + 1, z)]) +
+                     L.ih2[2] * (2.0 * uc - tile[tix(x, y, z - 1)] - tile[tix(x, y, z + 1)]);
+            } else {
+#pragma unroll
+                for (int f = 0; f < 6; ++f) {
+                    const int d = f >> 1, s = (f & 1) ? 1 : -1;
+                    int qx = x + (d == 0 ? s : 0), qy = y + (d == 1 ? s : 0), qz = z + (d == 2 ? s : 0);
+                    bool inside = ((qx | qy | qz) & ~7) == 0;
+                    bool cov = ((inside ? cm : ncm[f]) >> oct_of(qx & 7, qy & 7, qz & 7)) & 1;
+                    if (!cov) {
+                        Au += L.ih2[d] * (uc - tile[tix(qx, qy, qz)]);
+                    } else if (!ZERO) {
+                        int nl[3] = {qx & 7, qy & 7, qz & 7};
+                        Au += -0.5 * L.ih2[d] *
+                              fine_face_sum(M, inside ? b : nbk[f], nl, d, s, UserAccL{phi, M.org, M.ubase, M.ustr},
+                                            cp_phi);
                     }
                 }
-            rv = rh[ui] * inv_eps0 - Au;
+            }
+            r = rv[k] - Au;
         }
-        if (r_out) r_out[(size_t)b * BRICK_CELLS + c] = (T)rv;
-        if (r_user) r_user[lev][ui] = rv;
-        double av = fabs(rv);
+        if (r_out) r_out[(size_t)b * BRICK_CELLS + c] = (T)r;
+        if (r_user) r_user[lev][ui[k]] = r;
+        double av = fabs(r);
         acc = norm_p == 2 ? acc + av * av : norm_p == 1 ? acc + av : fmax(acc, av);
     }
     acc = block_reduce_256(acc, norm_p == 0);
     if (threadIdx.x == 0) part[b] = acc;
-    level_norms_last_block(part, NA, norm_p);
 }
 
 // norm of each listed brick range (one AMR level of one problem) from the
 // per-brick partials, in a fixed order
-__global__ void k_level_norms(const int2 *ranges, int n, const double *part, double *out, int norm_p)
+__global__ void __launch_bounds__(1024) k_level_norms(const int2 *ranges, int n, const double *part, double *out,
+                                                      int norm_p)
 {
     int l = blockIdx.x;
     if (l >= n) return;
-    int b0 = ranges[l].x, b1 = ranges[l].x + ranges[l].y;
-    double acc = 0.0;
-    for (int b = b0 + (int)threadIdx.x; b < b1; b += 256) acc = norm_p == 0 ? fmax(acc, part[b]) : acc + part[b];
-    acc = block_reduce_256(acc, norm_p == 0);
-    if (threadIdx.x == 0) out[l] = norm_p == 2 ? sqrt(acc) : acc;
+    const int b0 = ranges[l].x, b1 = ranges[l].x + ranges[l].y;
+    const bool mx = norm_p == 0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = b0 + (int)threadIdx.x;
+    for (; b + 3 * 1024 < b1; b += 4 * 1024) {
+        double v0 = part[b], v1 = part[b + 1024], v2 = part[b + 2048], v3 = part[b + 3072];
+        a0 = mx ? fmax(a0, v0) : a0 + v0;
+        a1 = mx ? fmax(a1, v1) : a1 + v1;
+        a2 = mx ? fmax(a2, v2) : a2 + v2;
+        a3 = mx ? fmax(a3, v3) : a3 + v3;
+    }
+    for (; b < b1; b += 1024) a0 = mx ? fmax(a0, part[b]) : a0 + part[b];
+    double acc = mx ? fmax(fmax(a0, a1), fmax(a2, a3)) : (a0 + a1) + (a2 + a3);
+    for (int o = 32; o > 0; o >>= 1) {
+        double w = __shfl_xor(acc, o, 64);
+        acc = mx ? fmax(acc, w) : acc + w;
+    }
+    __shared__ double sh[16];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = sh[0];
+        for (int i = 1; i < 16; ++i) r = mx ? fmax(r, sh[i]) : r + sh[i];
+        out[l] = norm_p == 2 ? sqrt(r) : r;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -910,9 +989,8 @@ __device__ __forceinline__ double wg_sum_1024(double v, double *red, int slot)
 }
 
 template <class T>
-__device__ int cg_solve_lds(const DevMeta &M, int b0, int nb, const T *rhs, T *e, double rtol, int maxit)
+__device__ int cg_solve_lds(const DevMeta &M, int b0, int nb, const T *rhs, T *e, double rtol, int maxit, double *p)
 {
-    __shared__ double p[CG_LDS_MAX];
     __shared__ double red[3 * 16];
     const int n = nb * BRICK_CELLS;
     const LevelConst L = M.lc[M.org[b0].w];
@@ -1002,6 +1080,94 @@ __device__ int cg_solve_lds(const DevMeta &M, int b0, int nb, const T *rhs, T *e
     return it;
 }
 
+// Exact solve of the coarsest grid (one box of n = dn cells, homogeneous
+// Dirichlet ghosts) by its separable eigendecomposition: forward transforms
+// along x, y, z, division by the eigenvalue sum, inverse transforms along z,
+// y, x.  The grid lives in LDS (u, natural order x fastest); each transform
+// pass gives a thread up to four (line, group of four outputs) items, held in
+// registers until every thread has read its line.  FP64 arithmetic.
+template <class T>
+__device__ void direct_solve(const CoarseJob &J, const double *gtab, const T *rhs, T *e, double *u)
+{
+    const int nx = J.dn[0], ny = J.dn[1], nz = J.dn[2];
+    const int n = nx * ny * nz;
+    const int nbx = nx >> 3, nby = ny >> 3;
+    const int b0 = J.b0[0];
+    auto brick_index = [&](int idx) {
+        int i = idx % nx, jk = idx / nx, j = jk % ny, k = jk / ny;
+        int b = b0 + (i >> 3) + nbx * ((j >> 3) + nby * (k >> 3));
+        return (size_t)b * BRICK_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7);
+    };
+    // the grid, then the transform tables, in LDS (one round of loads)
+    double *tab = u + n;
+    const int ntab = 2 * (nx * nx + ny * ny + nz * nz) + nx + ny + nz;
+    for (int idx = threadIdx.x; idx < n; idx += (int)blockDim.x) u[idx] = (double)rhs[brick_index(idx)];
+    for (int i = threadIdx.x; i < ntab; i += (int)blockDim.x) tab[i] = gtab[i];
+    __syncthreads();
+    const double *mat[3][2];
+    size_t off = 0;
+    for (int d = 0; d < 3; ++d) {
+        const int N = J.dn[d];
+        mat[d][0] = tab + off;
+        mat[d][1] = tab + off + (size_t)N * N;
+        off += 2 * (size_t)N * N;
+    }
+    const double *mu[3] = {tab + off, tab + off + nx, tab + off + nx + ny};
+#pragma unroll
+    for (int pass = 0; pass < 6; ++pass) {
+        const int d = pass < 3 ? pass : 5 - pass;
+        const double *A = mat[d][pass < 3 ? 0 : 1];
+        const int N = J.dn[d];
+        const int stride = d == 0 ? 1 : (d == 1 ? nx : nx * ny);
+        const int groups = N >> 2, items = (n / N) * groups;
+        double out[4][4];
+        int obase[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            int it = threadIdx.x + (int)blockDim.x * w;
+            obase[w] = -1;
+            if (it >= items) continue;
+            int line = it / groups, g = it - line * groups;
+            int base;
+            if (d == 0) base = line * nx;
+            else if (d == 1) base = (line % nx) + nx * ny * (line / nx);
+            else base = line;
+            obase[w] = base + 4 * g * stride;
+            const double *a = A + (size_t)(4 * g) * N;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            for (int i = 0; i < N; ++i) {
+                double v = u[base + i * stride];
+                s0 += a[i] * v;
+                s1 += a[N + i] * v;
+                s2 += a[2 * N + i] * v;
+                s3 += a[3 * N + i] * v;
+            }
+            out[w][0] = s0;
+            out[w][1] = s1;
+            out[w][2] = s2;
+            out[w][3] = s3;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            if (obase[w] < 0) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                int idx = obase[w] + q * stride;
+                double v = out[w][q];
+                if (pass == 2) {  // all three forward transforms done: divide by the eigenvalue
+                    int i = idx % nx, jk = idx / nx, j = jk % ny, k = jk / ny;
+                    v /= mu[0][i] + mu[1][j] + mu[2][k];
+                }
+                u[idx] = v;
+            }
+        }
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < n; idx += (int)blockDim.x) e[brick_index(idx)] = (T)u[idx];
+    __syncthreads();
+}
+
 // one workgroup per job: jobs[i] = (first brick, bricks, offset of its four
 // work vectors in doubles)
 template <class T>
@@ -1042,9 +1208,10 @@ __device__ void wg_gs_pass(const DevMeta &M, int b0, int nb, T *e, const T *r, i
 // AMR levels when phi_update is set.
 template <class T>
 __global__ void __launch_bounds__(1024) k_coarse_cycle(DevMeta M, const CoarseJob *jobs, T *e, T *r, double *work,
-                                                       int nu1, int nu2, double rtol, int maxit, int *iters,
-                                                       double *const *phi, int phi_update)
+                                                       const double *dtab, int nu1, int nu2, double rtol, int maxit,
+                                                       int *iters, double *const *phi, int phi_update)
 {
+    __shared__ double lds[DIRECT_LDS];
     const CoarseJob J = jobs[blockIdx.x];
     for (int k = J.nlev - 1; k >= 1; --k) {
         const int b0 = J.b0[k], nb = J.nb[k];
@@ -1072,9 +1239,13 @@ __global__ void __launch_bounds__(1024) k_coarse_cycle(DevMeta M, const CoarseJo
         }
         __syncthreads();
     }
-    int it = J.nb[0] * BRICK_CELLS <= CG_PER * (int)blockDim.x && J.nb[0] * BRICK_CELLS <= CG_LDS_MAX
-                 ? cg_solve_lds<T>(M, J.b0[0], J.nb[0], r, e, rtol, maxit)
-                                                   : cg_solve<T>(M, J.b0[0], J.nb[0], r, e, work + J.cg_off, rtol, maxit);
+    int it = 1;
+    if (J.dtab >= 0)
+        direct_solve<T>(J, dtab + J.dtab, r, e, lds);
+    else if (J.nb[0] * BRICK_CELLS <= CG_PER * (int)blockDim.x && J.nb[0] * BRICK_CELLS <= CG_LDS_MAX)
+        it = cg_solve_lds<T>(M, J.b0[0], J.nb[0], r, e, rtol, maxit, lds);
+    else
+        it = cg_solve<T>(M, J.b0[0], J.nb[0], r, e, work + J.cg_off, rtol, maxit);
     if (threadIdx.x == 0 && iters) atomicMax(iters, it);
     for (int k = 0; k < J.nlev; ++k) {
         const int b0 = J.b0[k], nb = J.nb[k];
@@ -1319,21 +1490,21 @@ static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + p
 template <class T>
 void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list,
                            double *const *phi, double *const *rho, double inv_eps0, const double *cp_phi, T *r_out,
-                           double *part, int norm_p, bool zero_phi, double *const *r_user, const NormArgs &NA)
+                           double *part, int norm_p, bool zero_phi, double *const *r_user)
 {
     if (nb <= 0) return;
     if (zero_phi)
         AMRMG_LAUNCH((k_outer_residual<T, true>), dim3(nb), dim3(256), 0, st, M, b0, nb, phi, rho, inv_eps0,
-                     cp_phi, r_out, part, norm_p, list, r_user, NA);
+                     cp_phi, r_out, part, norm_p, list, r_user);
     else
         AMRMG_LAUNCH((k_outer_residual<T, false>), dim3(nb), dim3(256), 0, st, M, b0, nb, phi, rho, inv_eps0,
-                     cp_phi, r_out, part, norm_p, list, r_user, NA);
+                     cp_phi, r_out, part, norm_p, list, r_user);
 }
 
 void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double *part, double *out, int norm_p)
 {
     if (n <= 0) return;
-    AMRMG_LAUNCH(k_level_norms, dim3(n), dim3(256), 0, st, ranges, n, part, out, norm_p);
+    AMRMG_LAUNCH(k_level_norms, dim3(n), dim3(1024), 0, st, ranges, n, part, out, norm_p);
 }
 
 void launch_cpart_user(hipStream_t st, const DevMeta &M, int cf0, int ncf, double *const *phi, double *cp)
@@ -1478,13 +1649,13 @@ void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, 
 
 template <class T>
 void launch_coarse_cycle(hipStream_t st, const DevMeta &M, const CoarseJob *jobs, int njobs, T *e, T *r,
-                         double *work, int nu1, int nu2, double rtol, int maxit, int *iters, double *const *phi,
-                         bool phi_update, int threads_hint)
+                         double *work, const double *dtab, int nu1, int nu2, double rtol, int maxit, int *iters,
+                         double *const *phi, bool phi_update, int threads_hint)
 {
     if (njobs <= 0) return;
     int threads = threads_hint > 0 ? threads_hint : 1024;
-    AMRMG_LAUNCH((k_coarse_cycle<T>), dim3(njobs), dim3(threads), 0, st, M, jobs, e, r, work, nu1, nu2, rtol, maxit,
-                 iters, phi, (int)phi_update);
+    AMRMG_LAUNCH((k_coarse_cycle<T>), dim3(njobs), dim3(threads), 0, st, M, jobs, e, r, work, dtab, nu1, nu2, rtol,
+                 maxit, iters, phi, (int)phi_update);
 }
 
 template <class T>
@@ -1524,7 +1695,7 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val)
 #define AMRMG_INST(T)                                                                                            \
     template void launch_outer_residual<T>(hipStream_t, const DevMeta &, int, int, const int32_t *,               \
                                            double *const *, double *const *, double, const double *, T *,         \
-                                           double *, int, bool, double *const *, const NormArgs &);               \
+                                           double *, int, bool, double *const *);                                 \
     template void launch_cpart_brick<T>(hipStream_t, const DevMeta &, int, int, const T *, T *);                \
     template void launch_gsrb<T>(hipStream_t, const DevMeta &, int, int, T *, const T *, const T *, int, bool);  \
     template void launch_jacobi<T>(hipStream_t, const DevMeta &, int, int, const T *, T *, const T *, const T *, \
@@ -1540,7 +1711,8 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val)
     template void launch_hgs<T>(hipStream_t, const DevMeta &, int, int, const T *, T *, const T *, T *,         \
                                 double *const *, int);                                                          \
     template void launch_coarse_cycle<T>(hipStream_t, const DevMeta &, const CoarseJob *, int, T *, T *,        \
-                                         double *, int, int, double, int, int *, double *const *, bool, int);
+                                         double *, const double *, int, int, double, int, int *, double *const *, \
+                                         bool, int);
 AMRMG_INST(float)
 AMRMG_INST(double)
 #undef AMRMG_INST

@@ -31,23 +31,28 @@ struct GatherArgs {
     const double *E[3 * MAX_AMR];
 };
 
-// per-level norms folded into a launch by its last workgroup
-struct NormArgs {
-    const int2 *ranges;  // brick ranges, one per norm
-    int n;
-    double *out;
-    unsigned *counter;   // zero between launches (reset by the last workgroup)
-};
-
 // the small bottom levels of one problem, handled by one workgroup
 struct CoarseJob {
     int nlev;
     int b0[8];
     int nb[8];
     int cg_off;
+    int dn[3];  // cells per axis of the coarsest grid (one box)
+    int dtab;   // offset of its direct-solve tables (direct_tables) or -1: CG
 };
+// a coarsest grid of n cells with transform tables of t doubles is solved
+// directly when n + t fits this many doubles of LDS (24^3 does; the CG LDS
+// variant uses the first CG_LDS_MAX of them)
+constexpr int DIRECT_LDS = 19456;
 
 hipError_t upload_cf_weights(const double *w);
+// window masks of patterns 0..12 and (u0, v0, nodes) of patterns 0..13
+hipError_t upload_pattern_tables(const uint32_t *masks13, const int *org14x3);
+// Dirichlet values of the boundary faces (gbc) and the coarse-fine windows
+// (cf_pat, cf_idx) of the hierarchy in M; *err is set when a window leaves
+// the coarser level
+void launch_face_data(hipStream_t st, const DevMeta &M, const EntryDev *ent, const int32_t *pool,
+                      const double *mono, double *gbc, uint8_t *cf_pat, int32_t *cf_idx, int *err);
 // the next kernel launched by a launcher records kernel-execution timestamps
 // into these events (hipExtLaunchKernelGGL); cleared after that launch
 void set_launch_timing(hipEvent_t start, hipEvent_t stop);
@@ -56,7 +61,7 @@ bool launch_timing_pending();
 template <class T>
 void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list,
                            double *const *phi, double *const *rho, double inv_eps0, const double *cp_phi, T *r_out,
-                           double *part, int norm_p, bool zero_phi, double *const *r_user, const NormArgs &NA);
+                           double *part, int norm_p, bool zero_phi, double *const *r_user);
 void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double *part, double *out, int norm_p);
 void launch_cpart_user(hipStream_t st, const DevMeta &M, int cf0, int ncf, double *const *phi, double *cp);
 template <class T>
@@ -90,8 +95,8 @@ void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, 
                 double *const *phi, int mode);
 template <class T>
 void launch_coarse_cycle(hipStream_t st, const DevMeta &M, const CoarseJob *jobs, int njobs, T *e, T *r,
-                         double *work, int nu1, int nu2, double rtol, int maxit, int *iters, double *const *phi,
-                         bool phi_update, int threads_hint);
+                         double *work, const double *dtab, int nu1, int nu2, double rtol, int maxit, int *iters,
+                         double *const *phi, bool phi_update, int threads_hint);
 void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                     const double *q, const uint32_t *perm, const DepArgs &A, const int64_t *ubase, const int2 *ustr,
                     unsigned long long *nout);

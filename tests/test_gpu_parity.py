@@ -167,26 +167,29 @@ def test_other_smoothers_converge_to_same(smoother, nu):
 
 @pytest.mark.parametrize("n0,levels", [((16, 16, 16), []), ((24, 24, 24), [(1, 16, 16, 16, 32, 32, 32)]),
                                        ((16, 24, 32), [(1, 8, 16, 24, 24, 32, 40)]),
-                                       ((8, 8, 8), [(1, 0, 0, 0, 8, 8, 8), (2, 0, 0, 0, 8, 8, 8)])])
+                                       ((8, 8, 8), [(1, 0, 0, 0, 8, 8, 8), (2, 0, 0, 0, 8, 8, 8)]),
+                                       ((32, 32, 24), [(1, 8, 8, 8, 40, 40, 32)])])
 def test_small_and_ragged_hierarchies(n0, levels):
-    """Single level; a base without multigrid levels below it (24^3, CG on
-    27 bricks); unequal edges (anisotropic spacing); a corner box touching the
-    boundary on two refined levels over an 8^3 base."""
+    """Single level; a base without multigrid levels below it (24^3, 13824
+    cells solved directly); unequal edges (anisotropic spacing); a corner box
+    touching the boundary on two refined levels over an 8^3 base; a coarsest
+    grid above the direct-solve limit (32 x 32 x 24, CG).  Each with the
+    automatic bottom solver and with CG forced."""
     print("case", n0, levels, flush=True)
-    rng = np.random.default_rng(9)
     p = W.gaussian_bunch(20000, centre=(0.45, 0.5, 0.55), sigma=(0.12, 0.1, 0.15), seed=77)
     w = W.Workload("edge", p, n0, len(set(b[0] for b in levels)), [], [(1.0, 0.3, 0.6, 0.5)], 1e-10,
                    explicit_boxes=levels or None)
     H, orho, ophi, oE, ost = oracle_solution(w, ("edge", n0, tuple(levels)))
     for precision in ("fp64", "mixed"):
-        ctx, (x, y, z, q) = make_ctx(w, precision=precision)
-        rho, _ = ctx.deposit(x, y, z, q)
-        for l, (g, o) in enumerate(zip(np_list(rho), orho)):
-            assert np.linalg.norm(g - o) <= 1e-12 * np.linalg.norm(o)
-        phi, E, st = ctx.solve(rho, tol=1e-12)
-        assert st["converged"], st
-        assert rel_l2_composite(H, np_list(phi), ophi) <= (1e-9 if precision == "fp64" else 1e-8)
-    del rng
+        for bottom in ("auto", "cg"):
+            print("  ", precision, bottom, flush=True)
+            ctx, (x, y, z, q) = make_ctx(w, precision=precision, bottom=bottom)
+            rho, _ = ctx.deposit(x, y, z, q)
+            for l, (g, o) in enumerate(zip(np_list(rho), orho)):
+                assert np.linalg.norm(g - o) <= 1e-12 * np.linalg.norm(o)
+            phi, E, st = ctx.solve(rho, tol=1e-12)
+            assert st["converged"], st
+            assert rel_l2_composite(H, np_list(phi), ophi) <= (1e-9 if precision == "fp64" else 1e-8)
 
 
 def test_status_codes():

@@ -28,6 +28,8 @@ def shim(tmp_path_factory):
     L.hs_cf_patterns.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_long]
     L.hs_cf_patterns.restype = C.c_long
     L.hs_tables.argtypes = [C.c_void_p, C.c_void_p]
+    L.hs_direct_tables.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_long]
+    L.hs_direct_tables.restype = C.c_long
     return L
 
 
@@ -132,3 +134,54 @@ def test_cf_patterns_match_oracle(oracle_lib, shim, name):
                         count += 1
         assert count == rows.shape[0]
     assert seen
+
+
+def dirichlet_laplacian_dense(n, h):
+    """-L_h of the 7-point cell-centred Laplacian on one box with homogeneous
+    Dirichlet ghosts (ghost = -u of the boundary cell), x fastest."""
+    nx, ny, nz = n
+    N = nx * ny * nz
+    A = np.zeros((N, N))
+    idx = lambda i, j, k: i + nx * (j + ny * k)
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                r = idx(i, j, k)
+                for d, (m, hd) in enumerate(zip(n, h)):
+                    for s in (-1, 1):
+                        c = [i, j, k]
+                        c[d] += s
+                        A[r, r] += 1.0 / hd ** 2
+                        if 0 <= c[d] < m:
+                            A[r, idx(*c)] -= 1.0 / hd ** 2
+                        else:
+                            A[r, r] += 1.0 / hd ** 2
+    return A
+
+
+@pytest.mark.parametrize("n,h", [((8, 8, 8), (1 / 8, 1 / 8, 1 / 8)), ((8, 16, 24), (0.1, 0.05, 0.02))])
+def test_direct_tables_diagonalise_the_dirichlet_laplacian(shim, n, h):
+    """The coarsest-grid direct solve: Q diag(lambda) Q^T reproduces the dense
+    operator and Q is orthonormal, so Q diag(1/lambda) Q^T r = A^-1 r."""
+    n32 = np.asarray(n, dtype=np.int32)
+    hh = np.asarray(h, dtype=np.float64)
+    out = np.zeros(1 << 16)
+    k = shim.hs_direct_tables(n32.ctypes.data, hh.ctypes.data, out.ctypes.data, out.size)
+    assert k == 2 * sum(m * m for m in n) + sum(n)
+    off, F, B = 0, [], []
+    for m in n:
+        F.append(out[off:off + m * m].reshape(m, m))
+        B.append(out[off + m * m:off + 2 * m * m].reshape(m, m))
+        off += 2 * m * m
+    mu = [out[off:off + n[0]], out[off + n[0]:off + n[0] + n[1]], out[off + n[0] + n[1]:off + sum(n)]]
+    for d in range(3):
+        np.testing.assert_allclose(F[d] @ F[d].T, np.eye(n[d]), atol=1e-13)
+        np.testing.assert_array_equal(B[d], F[d].T)
+    # Q = kron over axes with x fastest: index i + nx (j + ny k)
+    Q = np.kron(B[2], np.kron(B[1], B[0]))
+    lam = (mu[2][:, None, None] + mu[1][None, :, None] + mu[0][None, None, :]).ravel()
+    A = dirichlet_laplacian_dense(n, h)
+    np.testing.assert_allclose(Q @ np.diag(lam) @ Q.T, A, atol=1e-9 * np.abs(A).max())
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal(A.shape[0])
+    np.testing.assert_allclose(Q @ ((Q.T @ r) / lam), np.linalg.solve(A, r), rtol=1e-10, atol=1e-14)
