@@ -960,7 +960,8 @@ extern "C" amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *
         }
     }
     ctx->prof.begin(AMRMG_K_GATHER);
-    launch_gather(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, G, ctx->ds.M.ubase, ctx->ds.M.ustr, Ex, Ey, Ez);
+    launch_gather(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, ctx->perm_n == n ? ctx->perm : nullptr, G,
+                  ctx->ds.M.ubase, ctx->ds.M.ustr, Ex, Ey, Ez);
     ctx->prof.end(AMRMG_K_GATHER, (double)n * (3.0 * (pos_dtype == AMRMG_POS_F32 ? 4 : 8) + 24.0));
     HIP_TRY(hipGetLastError());
     return AMRMG_OK;

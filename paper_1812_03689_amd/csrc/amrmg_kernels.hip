@@ -13,6 +13,7 @@
 // neighbouring halos in its own L2.  Arithmetic is FP64; the cycle arrays are
 // stored in T (float in mixed precision, double otherwise).
 #include <hip/hip_ext.h>
+#include <climits>
 #include <hip/hip_runtime.h>
 
 #include "amrmg_internal.hpp"
@@ -1330,51 +1331,129 @@ __device__ __forceinline__ void wave_atomic_add(double *rho, int64_t addr, doubl
     if ((active >> lane) & 1) atomicAdd(rho + addr, v);
 }
 
-// Deposit every particle on every listed level: each particle is read once
-// (in the given visiting order) and its 8 CIC weights per level are added
-// with wavefront-combined FP64 atomics.
-template <class P>
+// Deposit every particle on every listed level.  A workgroup takes 256 PPT
+// consecutive particles of the visiting order (spatially sorted, so they are
+// close together) and, per level, accumulates their CIC weights in an LDS
+// tile over the bounding box of their stencils, then adds the tile's nonzero
+// cells to rho with one FP64 atomic each.  When the box exceeds the tile the
+// workgroup adds its weights with wavefront-combined global atomics instead.
+constexpr int DEP_TILE = 4096;
+
+__device__ __forceinline__ void wg_minmax6(int *v, int *red)
+{
+    // v[0..2] minima, v[3..5] maxima over the workgroup of 256 threads
+    for (int o = 32; o > 0; o >>= 1)
+        for (int a = 0; a < 6; ++a) {
+            int w = __shfl_xor(v[a], o, 64);
+            v[a] = a < 3 ? min(v[a], w) : max(v[a], w);
+        }
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 6; ++a) red[a * 4 + wid] = v[a];
+    __syncthreads();
+    for (int a = 0; a < 6; ++a) {
+        int r = red[a * 4];
+        for (int k = 1; k < 4; ++k) r = a < 3 ? min(r, red[a * 4 + k]) : max(r, red[a * 4 + k]);
+        v[a] = r;
+    }
+    __syncthreads();
+}
+
+template <class P, int PPT>
 __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P *y, const P *z, const double *q,
                                                  const uint32_t *perm, DepArgs A, const int64_t *ubase,
                                                  const int2 *ustr, unsigned long long *nout)
 {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    bool valid = i < n;
-    int64_t p = valid ? (perm ? (int64_t)perm[i] : i) : 0;
-    double X = 0.0, Y = 0.0, Z = 0.0, qp = 0.0;
-    if (valid) {
-        X = (double)x[p];
-        Y = (double)y[p];
-        Z = (double)z[p];
-        qp = q[p];
+    __shared__ double acc[DEP_TILE];
+    __shared__ int red[24];
+    const int64_t first = (int64_t)blockIdx.x * 256 * PPT;
+    double X[PPT], Y[PPT], Z[PPT], Q[PPT];
+    bool valid[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        int64_t i = first + k * 256 + threadIdx.x;
+        valid[k] = i < n;
+        int64_t p = valid[k] ? (perm ? (int64_t)perm[i] : i) : 0;
+        X[k] = valid[k] ? (double)x[p] : 0.0;
+        Y[k] = valid[k] ? (double)y[p] : 0.0;
+        Z[k] = valid[k] ? (double)z[p] : 0.0;
+        Q[k] = valid[k] ? q[p] : 0.0;
     }
     for (int l = 0; l < A.nlev; ++l) {
         const DepLevel &D = A.lev[l];
-        int i0[3] = {0, 0, 0}, i1[3] = {0, 0, 0};
-        double f[3] = {0, 0, 0};
-        bool ok = valid && cic_stencil<P>(D, X, Y, Z, i0, i1, f);
-        if (valid && !ok && l == 0 && nout) atomicAdd(nout, 1ull);
-        double qv = ok ? qp * D.ivol : 0.0;
-        // all lanes stay in the loop: the combination uses wavefront shuffles
-        for (int c = 0; c < 8; ++c) {
-            int ii = (c & 1) ? i1[0] : i0[0];
-            int jj = (c & 2) ? i1[1] : i0[1];
-            int kk = (c & 4) ? i1[2] : i0[2];
-            double w = ((c & 1) ? f[0] : 1.0 - f[0]) * ((c & 2) ? f[1] : 1.0 - f[1]) *
-                       ((c & 4) ? f[2] : 1.0 - f[2]);
-            int64_t u = ok ? user_index(D, ubase, ustr, ii, jj, kk) : -1;
-            wave_atomic_add(A.rho[l], u, qv * w);
+        int i0[PPT][3], i1[PPT][3];
+        double f[PPT][3];
+        bool ok[PPT];
+        int bb[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            ok[k] = valid[k] && cic_stencil<P>(D, X[k], Y[k], Z[k], i0[k], i1[k], f[k]);
+            if (valid[k] && !ok[k] && l == 0 && nout) atomicAdd(nout, 1ull);
+            if (ok[k])
+                for (int d = 0; d < 3; ++d) {
+                    bb[d] = min(bb[d], i0[k][d]);
+                    bb[3 + d] = max(bb[3 + d], i1[k][d]);
+                }
+        }
+        wg_minmax6(bb, red);
+        if (bb[0] > bb[3]) continue;  // no particle of the workgroup inside the domain
+        const int ex = bb[3] - bb[0] + 1, ey = bb[4] - bb[1] + 1, ez = bb[5] - bb[2] + 1;
+        const int64_t vol = (int64_t)ex * ey * ez;
+        if (vol <= DEP_TILE) {
+            for (int t = threadIdx.x; t < vol; t += 256) acc[t] = 0.0;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                if (!ok[k]) continue;
+                const double qv = Q[k] * D.ivol;
+                for (int c = 0; c < 8; ++c) {
+                    int ii = ((c & 1) ? i1[k][0] : i0[k][0]) - bb[0];
+                    int jj = ((c & 2) ? i1[k][1] : i0[k][1]) - bb[1];
+                    int kk = ((c & 4) ? i1[k][2] : i0[k][2]) - bb[2];
+                    double w = ((c & 1) ? f[k][0] : 1.0 - f[k][0]) * ((c & 2) ? f[k][1] : 1.0 - f[k][1]) *
+                               ((c & 4) ? f[k][2] : 1.0 - f[k][2]);
+                    atomicAdd(&acc[ii + ex * (jj + ey * kk)], qv * w);
+                }
+            }
+            __syncthreads();
+            for (int t = threadIdx.x; t < vol; t += 256) {
+                double v = acc[t];
+                if (v == 0.0) continue;
+                int ii = t % ex, r = t / ex, jj = r % ey, kk = r / ey;
+                int64_t u = user_index(D, ubase, ustr, bb[0] + ii, bb[1] + jj, bb[2] + kk);
+                if (u >= 0) atomicAdd(A.rho[l] + u, v);
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const double qv = ok[k] ? Q[k] * D.ivol : 0.0;
+                // all lanes stay in the loop: the combination uses wavefront shuffles
+                for (int c = 0; c < 8; ++c) {
+                    int ii = (c & 1) ? i1[k][0] : i0[k][0];
+                    int jj = (c & 2) ? i1[k][1] : i0[k][1];
+                    int kk = (c & 4) ? i1[k][2] : i0[k][2];
+                    double w = ((c & 1) ? f[k][0] : 1.0 - f[k][0]) * ((c & 2) ? f[k][1] : 1.0 - f[k][1]) *
+                               ((c & 4) ? f[k][2] : 1.0 - f[k][2]);
+                    int64_t u = ok[k] ? user_index(D, ubase, ustr, ii, jj, kk) : -1;
+                    wave_atomic_add(A.rho[l], u, qv * w);
+                }
+            }
         }
     }
 }
 
+// E at every particle from the finest level whose boxes hold all 8 cells of
+// its CIC stencil; particles are visited in the given (spatially sorted)
+// order so that neighbouring threads read neighbouring field cells.
 template <class P>
-__global__ void __launch_bounds__(256) k_gather(int64_t n, const P *x, const P *y, const P *z, GatherArgs G,
-                                                const int64_t *ubase, const int2 *ustr, double *Ex, double *Ey,
-                                                double *Ez)
+__global__ void __launch_bounds__(256) k_gather(int64_t n, const P *x, const P *y, const P *z, const uint32_t *perm,
+                                                GatherArgs G, const int64_t *ubase, const int2 *ustr, double *Ex,
+                                                double *Ey, double *Ez)
 {
-    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= n) return;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    int64_t p = perm ? (int64_t)perm[i] : i;
     double X = (double)x[p], Y = (double)y[p], Z = (double)z[p];
     double e[3] = {0.0, 0.0, 0.0};
     for (int l = G.nlev - 1; l >= 0; --l) {
@@ -1595,26 +1674,39 @@ void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const
                     unsigned long long *nout)
 {
     if (n <= 0 || A.nlev <= 0) return;
-    unsigned g = blocks_for(n, 256);
-    if (pos_f32)
-        AMRMG_LAUNCH((k_deposit<float>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
-                     (const float *)z, q, perm, A, ubase, ustr, nout);
-    else
-        AMRMG_LAUNCH((k_deposit<double>), dim3(g), dim3(256), 0, st, n, (const double *)x, (const double *)y,
-                     (const double *)z, q, perm, A, ubase, ustr, nout);
+    // two particles per thread up to 4M particles (enough workgroups to fill
+    // the chip), four beyond
+    if (n <= (4 << 20)) {
+        unsigned g = blocks_for(n, 512);
+        if (pos_f32)
+            AMRMG_LAUNCH((k_deposit<float, 2>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
+                         (const float *)z, q, perm, A, ubase, ustr, nout);
+        else
+            AMRMG_LAUNCH((k_deposit<double, 2>), dim3(g), dim3(256), 0, st, n, (const double *)x, (const double *)y,
+                         (const double *)z, q, perm, A, ubase, ustr, nout);
+    } else {
+        unsigned g = blocks_for(n, 1024);
+        if (pos_f32)
+            AMRMG_LAUNCH((k_deposit<float, 4>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
+                         (const float *)z, q, perm, A, ubase, ustr, nout);
+        else
+            AMRMG_LAUNCH((k_deposit<double, 4>), dim3(g), dim3(256), 0, st, n, (const double *)x, (const double *)y,
+                         (const double *)z, q, perm, A, ubase, ustr, nout);
+    }
 }
 
 void launch_gather(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
-                   const GatherArgs &G, const int64_t *ubase, const int2 *ustr, double *Ex, double *Ey, double *Ez)
+                   const uint32_t *perm, const GatherArgs &G, const int64_t *ubase, const int2 *ustr, double *Ex,
+                   double *Ey, double *Ez)
 {
     if (n <= 0) return;
     unsigned g = blocks_for(n, 256);
     if (pos_f32)
         AMRMG_LAUNCH((k_gather<float>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
-                           (const float *)z, G, ubase, ustr, Ex, Ey, Ez);
+                     (const float *)z, perm, G, ubase, ustr, Ex, Ey, Ez);
     else
         AMRMG_LAUNCH((k_gather<double>), dim3(g), dim3(256), 0, st, n, (const double *)x, (const double *)y,
-                           (const double *)z, G, ubase, ustr, Ex, Ey, Ez);
+                     (const double *)z, perm, G, ubase, ustr, Ex, Ey, Ez);
 }
 
 void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, double *scratch, uint8_t *tags)

@@ -102,7 +102,8 @@ void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const
                     unsigned long long *nout);
 void launch_zero_levels(hipStream_t st, const DepArgs &A);
 void launch_gather(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
-                   const GatherArgs &G, const int64_t *ubase, const int2 *ustr, double *Ex, double *Ey, double *Ez);
+                   const uint32_t *perm, const GatherArgs &G, const int64_t *ubase, const int2 *ustr, double *Ex,
+                   double *Ey, double *Ez);
 void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, double *scratch, uint8_t *tags);
 void launch_fill(hipStream_t st, double *v, int64_t n, double val);
 // spatial (Morton) visiting order of particles: keys [2n], vals [2n]; on

@@ -2,8 +2,8 @@
 // a Morton (Z-order) key of each particle's cell at a fine resolution, sorted
 // with the rocPRIM radix sort (through hipCUB).  In Z-order every cell of
 // every coarser level is a contiguous key range, so after the sort the
-// particles that a wavefront deposits fall into a few cells on every level and
-// their charges can be combined inside the wavefront before the atomics.
+// particles that a workgroup deposits or gathers fall into a few cells and
+// the deposit of a workgroup stays inside a small LDS tile on every level.
 #include <hip/hip_runtime.h>
 
 #include <hipcub/hipcub.hpp>
@@ -23,10 +23,10 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v)
     return x;
 }
 
-template <class P>
+template <class P, class K>
 __global__ void __launch_bounds__(256) k_morton_keys(int64_t n, const P *x, const P *y, const P *z, double lo0,
                                                      double lo1, double lo2, double hi0, double hi1, double hi2,
-                                                     int3 nf, uint64_t *keys, uint32_t *vals)
+                                                     int3 nf, K *keys, uint32_t *vals)
 {
     int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
@@ -42,16 +42,38 @@ __global__ void __launch_bounds__(256) k_morton_keys(int64_t n, const P *x, cons
         c = c < 0 ? 0 : (c >= nn[d] ? nn[d] - 1 : c);
         key |= spread3((uint32_t)c) << d;
     }
-    keys[p] = inside ? key : ~0ull;
+    keys[p] = inside ? (K)key : ~(K)0;  // particles outside the domain go last
     vals[p] = (uint32_t)p;
 }
 
+// Keys are 32-bit when the Morton code of the grid fits (up to 1024 cells per
+// axis), 64-bit beyond.
 size_t sort_temp_bytes(int64_t n)
 {
-    size_t bytes = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr,
-                                       (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n, 0, 63);
-    return bytes;
+    size_t b32 = 0, b64 = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b32, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                             (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n, 0, 32);
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b64, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                             (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n, 0, 63);
+    return b32 > b64 ? b32 : b64;
+}
+
+template <class K>
+static hipError_t order_with(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
+                             const double *lo, const double *hi, int3 nn, int end_bit, K *keys, uint32_t *vals,
+                             void *temp, size_t temp_bytes)
+{
+    unsigned g = (unsigned)((n + 255) / 256);
+    if (pos_f32)
+        hipLaunchKernelGGL((k_morton_keys<float, K>), dim3(g), dim3(256), 0, st, n, (const float *)x,
+                           (const float *)y, (const float *)z, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], nn, keys,
+                           vals);
+    else
+        hipLaunchKernelGGL((k_morton_keys<double, K>), dim3(g), dim3(256), 0, st, n, (const double *)x,
+                           (const double *)y, (const double *)z, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], nn, keys,
+                           vals);
+    size_t tb = temp_bytes;
+    return hipcub::DeviceRadixSort::SortPairs(temp, tb, keys, keys + n, vals, vals + n, (int)n, 0, end_bit, st);
 }
 
 hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
@@ -60,23 +82,18 @@ hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x,
 {
     *perm_out = nullptr;
     if (n <= 0) return hipSuccess;
-    unsigned g = (unsigned)((n + 255) / 256);
     int3 nn = make_int3(nf[0], nf[1], nf[2]);
-    if (pos_f32)
-        hipLaunchKernelGGL((k_morton_keys<float>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
-                           (const float *)z, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], nn, keys, vals);
-    else
-        hipLaunchKernelGGL((k_morton_keys<double>), dim3(g), dim3(256), 0, st, n, (const double *)x,
-                           (const double *)y, (const double *)z, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], nn, keys,
-                           vals);
     int bits = 0;
     int m = nf[0] > nf[1] ? nf[0] : nf[1];
     m = m > nf[2] ? m : nf[2];
     while ((1 << bits) < m) ++bits;
-    int end_bit = 3 * bits < 63 ? 3 * bits : 63;
-    size_t tb = temp_bytes;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, tb, keys, keys + n, vals, vals + n, (int)n, 0, end_bit,
-                                                      st);
+    hipError_t e;
+    if (3 * bits <= 32)
+        e = order_with<uint32_t>(st, pos_f32, n, x, y, z, lo, hi, nn, 3 * bits, (uint32_t *)keys, vals, temp,
+                                 temp_bytes);
+    else
+        e = order_with<uint64_t>(st, pos_f32, n, x, y, z, lo, hi, nn, 3 * bits < 63 ? 3 * bits : 63, keys, vals,
+                                 temp, temp_bytes);
     if (e != hipSuccess) return e;
     *perm_out = vals + n;
     return hipGetLastError();
