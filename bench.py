@@ -33,6 +33,102 @@ def workload_for(cfg):
     return {1: W.config1, 2: W.config2, 3: W.config3, 4: W.config4}[cfg]()
 
 
+def bench_batch(args):
+    """64 independent small problems (base 16-48, 1-2 refined levels): one
+    step = build and deposit every hierarchy, then one batched mixed solve.
+    Also times the batch against 64 sequential solves (FP64 and mixed)."""
+    import numpy as np
+    import torch
+    from paper_1812_03689_amd import amrmg, workloads as W
+
+    ws = W.config5_instances(64)
+    dev = torch.device("cuda:0")
+    data = []
+    for w in ws:
+        p = w.particles
+        data.append(tuple(torch.as_tensor(a, device=dev) for a in (p.x, p.y, p.z, p.q)))
+
+    def ctxs(prec):
+        out = []
+        for w in ws:
+            prm = amrmg.make_params(w.n0, max_level=w.max_level, monopoles=w.monopoles, precision=prec,
+                                    max_grid_size=w.max_grid_size)
+            out.append(amrmg.Context(prm))
+        return out
+
+    cm, cf = ctxs("mixed"), ctxs("fp64")
+    rho, phi = [], []
+    for c, w, (x, y, z, q) in zip(cm, ws, data):
+        c.build_hierarchy(x, y, z, q, tag_rel=w.tag_rel)
+        rho.append(c.level_arrays())
+        phi.append(c.level_arrays())
+    dof = sum(c.info["ndof"] for c in cm)
+    tol = ws[0].tol
+
+    def step():
+        for c, w, (x, y, z, q), r in zip(cm, ws, data, rho):
+            c.build_hierarchy(x, y, z, q, tag_rel=w.tag_rel)
+            amrmg.amrmg_deposit(c.h, x, y, z, q, r)
+        for ph in phi:
+            for t in ph:
+                t.zero_()
+        return amrmg.amrmg_solve_batch([c.h for c in cm], rho, phi, tol)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    def timed(fn, reps=5):
+        ts = []
+        for _ in range(reps):
+            for ph in phi:
+                for t in ph:
+                    t.zero_()
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - a) * 1e3)
+        return float(np.median(ts))
+
+    batch_ms = timed(lambda: amrmg.amrmg_solve_batch([c.h for c in cm], rho, phi, tol))
+    for c, w, (x, y, z, q) in zip(cf, ws, data):
+        c.build_hierarchy(x, y, z, q, tag_rel=w.tag_rel)
+    per_size = {}
+    seq = {}
+    for name, cs in (("fp64", cf), ("mixed", cm)):
+        tot = 0.0
+        for i, c in enumerate(cs):
+            ms = timed(lambda: amrmg.amrmg_solve(c.h, rho[i], phi[i], None, tol), reps=3)
+            tot += ms
+            if name == "fp64":
+                per_size.setdefault(str(ws[i].n0[0]), [0, 0.0, 0])
+                per_size[str(ws[i].n0[0])][0] += 1
+                per_size[str(ws[i].n0[0])][1] += ms
+                per_size[str(ws[i].n0[0])][2] += c.info["ndof"] if c.info else 0
+        seq[name] = tot
+    out = {
+        "metric": METRIC, "value": dof / (ms_step * 1e-3), "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "64 independent problems: base 16/24/32/48, 1-2 refined levels (ratio 2, tag "
+                               "1e-3 x max|rho|), 1e4-1e5 Gaussian particles each, monopole Dirichlet, tol 1e-8",
+                   "dof": dof, "step": "64 x (build_hierarchy + deposit) + one batched mixed solve"},
+        "batch": {"batch_mixed_solve_ms": batch_ms, "sequential_fp64_solves_ms": seq["fp64"],
+                  "sequential_mixed_solves_ms": seq["mixed"], "batch_dof_per_s": dof / (batch_ms * 1e-3),
+                  "speedup_vs_sequential_fp64": seq["fp64"] / batch_ms,
+                  "iters_max": max(s["iters"] for s in st),
+                  "sequential_fp64_by_base_size": {k: {"instances": v[0], "ms": v[1], "dof": v[2]}
+                                                   for k, v in sorted(per_size.items(), key=lambda t: int(t[0]))}},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def describe(w):
     p = w.particles
     return (f"{w.name}: {p.n} particles, base {w.n0[0]}x{w.n0[1]}x{w.n0[2]} + {w.max_level} levels "
@@ -57,6 +153,10 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is not built.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.config == 5:
+        bench_batch(args)
+        return
 
     import numpy as np
     import torch

@@ -205,8 +205,14 @@ amrmg_status amrmg_residual(amrmg_ctx *ctx, double *const *rho, double *const *p
 
 /* Solve nb independent problems, each with its own context and hierarchy, as
  * one batch: every kernel of the cycle runs once over the bricks of all
- * problems.  All contexts must share stream, precision and smoother
- * settings.  rho[i], phi[i] as in amrmg_solve; stats host [nb] or NULL. */
+ * problems (level k of every problem, counted from its coarsest grid, in one
+ * launch).  The contexts must be distinct, built, and share the stream and
+ * the solver settings (precision, smoother, nu1, nu2, omega, norm_p,
+ * max_iters, bottom, bottom_rtol, eps0); otherwise AMRMG_E_INVALID.  rho[i],
+ * phi[i] as in amrmg_solve (no E).  The iteration runs until every problem
+ * meets tol; stats host [nb] or NULL gives each problem the iteration at which
+ * it met it.  The merged metadata is kept by ctxs[0] and rebuilt when any
+ * context builds a new hierarchy or the context list changes. */
 amrmg_status amrmg_solve_batch(amrmg_ctx *const *ctxs, int32_t nb, double *const *const *rho,
                                double *const *const *phi, double tol, amrmg_solve_stats *stats);
 

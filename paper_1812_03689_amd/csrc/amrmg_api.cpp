@@ -1400,13 +1400,67 @@ extern "C" amrmg_status amrmg_residual(amrmg_ctx *ctx, double *const *rho, doubl
 extern "C" amrmg_status amrmg_solve_batch(amrmg_ctx *const *ctxs, int32_t nb, double *const *const *rho,
                                           double *const *const *phi, double tol, amrmg_solve_stats *stats)
 {
-    (void)ctxs;
-    (void)nb;
-    (void)rho;
-    (void)phi;
-    (void)tol;
-    (void)stats;
-    return fail(AMRMG_E_NOT_IMPLEMENTED, "amrmg_solve_batch");
+    if (!ctxs || nb <= 0) return fail(AMRMG_E_INVALID, "need at least one context");
+    if (!rho || !phi) return fail(AMRMG_E_INVALID, "rho and phi are required");
+    if (!(tol > 0)) return fail(AMRMG_E_INVALID, "tol must be positive");
+    amrmg_ctx *c0 = ctxs[0];
+    for (int i = 0; i < nb; ++i) {
+        const amrmg_ctx *c = ctxs[i];
+        if (!c) return fail(AMRMG_E_INVALID, "context " + std::to_string(i) + " is NULL");
+        if (!c->built) return fail(AMRMG_E_STATE, "context " + std::to_string(i) + ": hierarchy not built");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return fail(AMRMG_E_INVALID, "a context appears twice in the batch");
+        const amrmg_params &a = c0->P, &b = c->P;
+        if (c->st != c0->st || a.precision != b.precision || a.smoother != b.smoother || a.nu1 != b.nu1 ||
+            a.nu2 != b.nu2 || a.norm_p != b.norm_p || a.omega != b.omega || a.max_iters != b.max_iters ||
+            a.bottom != b.bottom || a.bottom_rtol != b.bottom_rtol || a.eps0 != b.eps0)
+            return fail(AMRMG_E_INVALID, "context " + std::to_string(i) + ": stream or solver settings differ");
+        if (!rho[i] || !phi[i]) return fail(AMRMG_E_INVALID, "rho[i] and phi[i] are required");
+    }
+    // merged metadata of the batch, kept by the first context until one of
+    // the contexts builds a new hierarchy
+    std::vector<amrmg_ctx *> key(ctxs, ctxs + nb);
+    std::vector<int> gen(nb);
+    for (int i = 0; i < nb; ++i) gen[i] = ctxs[i]->generation;
+    if (!c0->batch || c0->batch_ctx != key || c0->batch_gen != gen) {
+        delete c0->batch;
+        c0->batch = new DevState();
+        c0->batch_ctx.clear();
+        std::vector<const Problem *> probs;
+        for (int i = 0; i < nb; ++i) probs.push_back(&ctxs[i]->prob);
+        build_meta(probs, c0->batch->meta, false);
+        if (!c0->batch->meta.error.empty()) return fail(AMRMG_E_NESTING, c0->batch->meta.error);
+        ST_TRY(upload_meta(*c0->batch, c0->st, probs, c0->P.bottom == AMRMG_BOTTOM_AUTO));
+        HIP_TRY(hipStreamSynchronize(c0->st));
+        if (*(int *)c0->batch->h_face_err.p)
+            return fail(AMRMG_E_NESTING, "coarse-fine window leaves the coarser level (nesting violated)");
+        c0->batch_ctx = key;
+        c0->batch_gen = gen;
+    }
+    DevState &D = *c0->batch;
+    std::fill(D.h_phi.begin(), D.h_phi.end(), nullptr);
+    std::fill(D.h_rho.begin(), D.h_rho.end(), nullptr);
+    std::fill(D.h_E.begin(), D.h_E.end(), nullptr);
+    std::fill(D.h_rout.begin(), D.h_rout.end(), nullptr);
+    for (int i = 0; i < nb; ++i) {
+        const Problem &pr = ctxs[i]->prob;
+        for (int l = 0; l < pr.namr(); ++l) {
+            if (!rho[i][l] || !phi[i][l]) return fail(AMRMG_E_INVALID, "rho[i][l] and phi[i][l] must be set");
+            int ei = D.meta.prob_ent[i][pr.kg + l];
+            D.h_phi[ei] = phi[i][l];
+            D.h_rho[ei] = rho[i][l];
+        }
+    }
+    ST_TRY(ensure_ws(D, c0->P.precision, nullptr, 0));
+    ST_TRY(set_tables(D, c0->st));
+    std::vector<amrmg_solve_stats> sv;
+    SolveOpts o = opts_of(c0->P);
+    amrmg_status rc = c0->P.precision == AMRMG_MIXED ? run_solve<float>(D, c0->st, o, tol, sv, false, nullptr)
+                                                     : run_solve<double>(D, c0->st, o, tol, sv, false, nullptr);
+    if (stats)
+        for (int i = 0; i < nb && i < (int)sv.size(); ++i) stats[i] = sv[i];
+    if (rc == AMRMG_E_NOT_CONVERGED) g_err = "not every problem converged within max_iters";
+    return rc;
 }
 
 extern "C" amrmg_status amrmg_profile_enable(amrmg_ctx *ctx, uint32_t mask)
