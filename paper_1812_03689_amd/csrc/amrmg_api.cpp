@@ -160,6 +160,7 @@ struct DevState {
     int ws_prec = -1;
     void *e = nullptr, *r = nullptr, *et = nullptr, *cpe = nullptr;
     double *cpphi = nullptr, *part = nullptr, *dnorm = nullptr;
+    double *phib = nullptr, *rhob = nullptr;  // FP64 phi and rho in brick layout during a solve
     double *cgw = nullptr;
     int *cgit = nullptr;
     int cg_threads = 1024;
@@ -247,11 +248,13 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
     if (mono.empty()) mono.push_back(0.0);
     static thread_local std::vector<LevelConst> lc;
     lc.assign(m.ent.size(), LevelConst{});
-    for (size_t i = 0; i < m.ent.size(); ++i)
+    for (size_t i = 0; i < m.ent.size(); ++i) {
         for (int d = 0; d < 3; ++d) {
             lc[i].h[d] = m.ent[i].h[d];
             lc[i].ih2[d] = 1.0 / (m.ent[i].h[d] * m.ent[i].h[d]);
         }
+        lc[i].amr = m.ent[i].amr;
+    }
     // norm ranges: every AMR level of every problem, entry order
     static thread_local std::vector<int32_t> rg, jobs;
     rg.clear();
@@ -414,6 +417,7 @@ static size_t ws_need(const DevState &D, int prec)
     size_t nc = (size_t)m.nbrick * BRICK_CELLS;
     size_t s = 0;
     s += 3 * align256(nc * w);                        // e, r, et
+    s += 2 * align256(nc * 8);                        // phi, rho in brick layout
     s += align256((size_t)m.ncf * 64 * w + 8);         // coarse parts of the cycle
     s += align256((size_t)m.ncf * 64 * 8 + 8);         // coarse parts of phi
     s += align256((size_t)m.nbrick * 8);               // per-brick partials
@@ -450,6 +454,8 @@ static amrmg_status ensure_ws(DevState &D, int prec, void *user, size_t user_byt
     D.e = take(nc * w);
     D.r = take(nc * w);
     D.et = take(nc * w);
+    D.phib = (double *)take(nc * 8);
+    D.rhob = (double *)take(nc * 8);
     D.cpe = take((size_t)m.ncf * 64 * w + 8);
     D.cpphi = (double *)take((size_t)m.ncf * 64 * 8 + 8);
     D.part = (double *)take((size_t)m.nbrick * 8);
@@ -1029,14 +1035,14 @@ struct Driver {
         amr_range(b0, nb, list);
         if (!zero_phi) {
             pb(AMRMG_K_CPART);
-            launch_cpart_user(st, D.M, 0, m.ncf, D.d_phi, D.cpphi);
+            launch_cpart_brick<double>(st, D.M, 0, m.ncf, D.phib, D.cpphi);
             pe(AMRMG_K_CPART, (double)m.ncf * 16 * (9 + 4) * 8);
         }
         // (a last-workgroup reduction inside the residual kernel would need a
         // device-scope fence per workgroup, which costs far more than this
         // extra launch on a chip whose XCDs have separate L2 caches)
         pb(AMRMG_K_RESIDUAL);
-        launch_outer_residual<T>(st, D.M, b0, nb, list, D.d_phi, D.d_rho, o.inv_eps0, zero_phi ? nullptr : D.cpphi,
+        launch_outer_residual<T>(st, D.M, b0, nb, list, D.phib, D.rhob, o.inv_eps0, zero_phi ? nullptr : D.cpphi,
                                  (zero_phi || rout_user) ? nullptr : r, D.part, o.norm_p, zero_phi, rout_user);
         pe(AMRMG_K_RESIDUAL, (double)nb * BRICK_CELLS * (zero_phi ? 8.0 : 16.0 + W));
         launch_level_norms(st, D.d_ranges, (int)D.range_prob.size(), D.part, D.dnorm + noff, o.norm_p);
@@ -1089,13 +1095,13 @@ struct Driver {
         const double n = (double)nb * BRICK_CELLS;
         T *out = (o.nu1 % 2 == 1) ? e : et;
         pb(AMRMG_K_GSRB);
-        launch_hgs<T>(st, D.M, b0, nb, nullptr, out, r, nullptr, D.d_phi, 1);
+        launch_hgs<T>(st, D.M, b0, nb, nullptr, out, r, nullptr, D.phib, 1);
         pe(AMRMG_K_GSRB, 2.0 * n * W);
         T *src = out;
         for (int i = 1; i < o.nu1; ++i) {
             T *dst = (src == e) ? et : e;
             pb(AMRMG_K_GSRB);
-            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, nullptr, D.d_phi, 0);
+            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, nullptr, D.phib, 0);
             pe(AMRMG_K_GSRB, 3.0 * n * W);
             src = dst;
         }
@@ -1110,7 +1116,7 @@ struct Driver {
             T *dst = (src == e) ? et : e;
             int mode = (i == 0 ? 2 | 4 : 0) | (i == o.nu2 - 1 ? 8 : 0);
             pb(AMRMG_K_GSRB);
-            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, cpe, D.d_phi, mode);
+            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, cpe, D.phib, mode);
             pe(AMRMG_K_GSRB, (3.0 + (i == 0 ? 0.125 : 0.0)) * n * W);
             src = dst;
         }
@@ -1139,7 +1145,7 @@ struct Driver {
         }
         pb(AMRMG_K_BOTTOM);
         launch_coarse_cycle<T>(st, D.M, D.d_cjobs, D.njobs, e, r, D.cgw, D.d_dtab, o.nu1, o.nu2, o.bottom_rtol,
-                               10000, D.cgit, D.d_phi, hybrid(), D.cg_threads);
+                               10000, D.cgit, D.phib, hybrid(), D.cg_threads);
         pe(AMRMG_K_BOTTOM, (double)D.cg_doubles / 4 * (2 * W));
         for (int k = kc + 1; k < m.K; ++k) {
             if (hybrid()) {
@@ -1163,8 +1169,25 @@ struct Driver {
         const int32_t *list;
         amr_range(b0, nb, list);
         pb(AMRMG_K_PHI_UPDATE);
-        launch_phi_update<T>(st, D.M, b0, nb, list, D.d_phi, e);
+        launch_phi_update<T>(st, D.M, b0, nb, list, D.phib, e);
         pe(AMRMG_K_PHI_UPDATE, (double)nb * BRICK_CELLS * (16.0 + W));
+    }
+
+    // phi (and rho) between the caller's layout and brick layout
+    void to_bricks(bool with_rho)
+    {
+        int b0, nb;
+        const int32_t *list;
+        amr_range(b0, nb, list);
+        launch_user_brick(st, D.M, b0, nb, list, true, D.d_phi, D.phib, with_rho ? D.d_rho : nullptr,
+                          with_rho ? D.rhob : nullptr);
+    }
+    void from_bricks()
+    {
+        int b0, nb;
+        const int32_t *list;
+        amr_range(b0, nb, list);
+        launch_user_brick(st, D.M, b0, nb, list, false, D.d_phi, D.phib, nullptr, nullptr);
     }
 
     // one outer iteration: V-cycle, phi += e, FP64 residual and its norms
@@ -1222,6 +1245,7 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
     HIP_TRY(hipEventCreate(&ev1));
     HIP_TRY(hipMemsetAsync(D.cgit, 0, sizeof(int), st));
     HIP_TRY(hipEventRecord(ev0, st));
+    drv.to_bricks(true);
     drv.outer(true, 0, nullptr);
     drv.outer(false, nr, nullptr);
     HIP_TRY(hipMemcpyAsync(D.h_norm, D.dnorm, sizeof(double) * 2 * nr, hipMemcpyDeviceToHost, st));
@@ -1268,7 +1292,7 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
         for (int ei = m.step_ent0[k]; ei < m.step_ent0[k + 1]; ++ei)
             if (m.ent[ei].amr >= 1) {
                 drv.pb(AMRMG_K_AVGDOWN);
-                launch_avgdown(st, D.M, m.ent[ei].b0, m.ent[ei].nb, D.d_phi);
+                launch_avgdown(st, D.M, m.ent[ei].b0, m.ent[ei].nb, D.phib);
                 drv.pe(AMRMG_K_AVGDOWN, (double)m.ent[ei].nb * BRICK_CELLS * 8.0 * (1.0 + 0.125));
             }
     if (want_E) {
@@ -1276,9 +1300,10 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
         const int32_t *list;
         drv.amr_range(b0, nb, list);
         drv.pb(AMRMG_K_EFIELD);
-        launch_efield(st, D.M, b0, nb, list, D.d_phi, D.cpphi, D.d_E);
+        launch_efield(st, D.M, b0, nb, list, D.phib, D.cpphi, D.d_E);
         drv.pe(AMRMG_K_EFIELD, (double)nb * BRICK_CELLS * 32.0);
     }
+    drv.from_bricks();
     HIP_TRY(hipEventRecord(ev1, st));
     HIP_TRY(hipEventSynchronize(ev1));
     HIP_TRY(hipGetLastError());
@@ -1391,6 +1416,7 @@ extern "C" amrmg_status amrmg_residual(amrmg_ctx *ctx, double *const *rho, doubl
     ST_TRY(set_tables(D, ctx->st));
     SolveOpts o = opts_of(ctx->P);
     Driver<double> drv(D, ctx->st, o, nullptr);
+    drv.to_bricks(true);
     drv.outer(false, 0, D.d_rout);
     HIP_TRY(hipStreamSynchronize(ctx->st));
     HIP_TRY(hipGetLastError());

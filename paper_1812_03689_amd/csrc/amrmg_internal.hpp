@@ -8,7 +8,8 @@
 // fastest inside the brick.  Bricks of all levels share one global
 // numbering, level by level, coarsest first; a kernel works on a contiguous
 // range of bricks.  phi, rho and E stay in the caller's box-list layout and
-// are reached through each brick's user-layout base and strides.
+// are reached through each brick's user-layout base and strides; inside a
+// solve, phi and rho are copied into brick layout (FP64) and back.
 #pragma once
 #include <cstdint>
 
@@ -21,6 +22,8 @@ constexpr int BRICK_CELLS = 512;
 struct LevelConst {
     double ih2[3];  // 1 / h_d^2
     double h[3];
+    int amr;        // AMR level number, -1 below level 0
+    int pad;
 };
 
 // Level ids: every level of every problem in a launch has an id (its entry in

@@ -98,29 +98,6 @@ struct ZeroAcc {
     __device__ double operator()(int, const int *) const { return 0.0; }
 };
 
-struct UserAcc {  // caller's box-list layout of one level
-    const double *base;
-    const int64_t *ubase;
-    const int2 *ustr;
-    __device__ double operator()(int b, const int *l) const
-    {
-        int2 s = ustr[b];
-        return base[ubase[b] + l[0] + (int64_t)s.x * l[1] + (int64_t)s.y * l[2]];
-    }
-};
-
-struct UserAccL {  // caller's layout, level looked up from the brick
-    double *const *p;
-    const int4 *org;
-    const int64_t *ubase;
-    const int2 *ustr;
-    __device__ double operator()(int b, const int *l) const
-    {
-        int2 s = ustr[b];
-        return p[org[b].w][ubase[b] + l[0] + (int64_t)s.x * l[1] + (int64_t)s.y * l[2]];
-    }
-};
-
 // The neighbour value that cell l of brick b sees across face (d, s), written
 // as a * u_c + bv:
 //   same level (in this brick or the face neighbour brick): a = 0, bv = u_nb
@@ -177,10 +154,10 @@ struct CpPtr<float> {
     static __device__ const float *f(const float *p) { return p; }
 };
 
-// sum over a workgroup of 256 threads (op 0: sum, 1: max)
-__device__ double block_reduce_256(double v, int op)
+// sum (op 0) or max (op 1) over a workgroup of up to 1024 threads
+__device__ double block_reduce(double v, int op)
 {
-    __shared__ double sh[4];
+    __shared__ double sh[16];
     for (int o = 32; o > 0; o >>= 1) {
         double w = __shfl_xor(v, o, 64);
         v = op ? fmax(v, w) : v + w;
@@ -189,7 +166,8 @@ __device__ double block_reduce_256(double v, int op)
     if (lane == 0) sh[wid] = v;
     __syncthreads();
     double r = sh[0];
-    for (int i = 1; i < 4; ++i) r = op ? fmax(r, sh[i]) : r + sh[i];
+    const int nw = blockDim.x >> 6;
+    for (int i = 1; i < nw; ++i) r = op ? fmax(r, sh[i]) : r + sh[i];
     __syncthreads();
     return r;
 }
@@ -212,18 +190,6 @@ struct SrcB {  // brick-layout array
 struct SrcZ {
     __device__ double operator()(int, int) const { return 0.0; }
 };
-struct SrcU {  // caller's layout, level looked up from the brick
-    double *const *p;
-    const int4 *org;
-    const int64_t *ubase;
-    const int2 *ustr;
-    __device__ double operator()(int b, int c) const
-    {
-        int2 s = ustr[b];
-        return p[org[b].w][ubase[b] + (c & 7) + (int64_t)s.x * ((c >> 3) & 7) + (int64_t)s.y * (c >> 6)];
-    }
-};
-
 // coarse parts of coarse-fine ghosts, by face id and face-local cell
 struct CpNone {
     __device__ double operator()(size_t, int) const { return 0.0; }
@@ -254,39 +220,65 @@ struct CpInline {
     }
 };
 
-template <class S, bool ZERO = false, class CP = CpNone>
+// NT = threads of the workgroup.  Every load of the tile is issued before the
+// first LDS store, so a thread waits for memory once.
+template <class S, bool ZERO = false, class CP = CpNone, int NT = 256>
 __device__ void stage_tile(const DevMeta &M, int b, const S &src, const CP &cp, bool inhom, double *tile,
                            double *alpha)
 {
-    for (int c = threadIdx.x; c < BRICK_CELLS; c += blockDim.x)
-        tile[tix(c & 7, (c >> 3) & 7, c >> 6)] = ZERO ? 0.0 : src(b, c);
-    for (int t = threadIdx.x; t < 384; t += blockDim.x) {
-        int f = t >> 6, d = f >> 1, s = (f & 1) ? 1 : -1;
-        int iu = t & 7, iv = (t >> 3) & 7, fl = t & 63;
+    constexpr int NI = BRICK_CELLS / NT, NH = (384 + NT - 1) / NT;
+    double vi[NI], vh[NH], ah[NH];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) vi[j] = ZERO ? 0.0 : src(b, (int)threadIdx.x + NT * j);
+#pragma unroll
+    for (int j = 0; j < NH; ++j) {
+        const int t = threadIdx.x + NT * j;
+        vh[j] = 0.0;
+        ah[j] = 0.0;
+        if (t >= 384) continue;
+        const int f = t >> 6, d = f >> 1;
+        const bool plus = f & 1;
+        const int fl = t & 63;
+        const int nb = M.nbr[b * 6 + f];
+        if (nb >= 0) {
+            if (!ZERO) {
+                int du, dv;
+                transverse(d, du, dv);
+                int m[3];
+                m[du] = fl & 7;
+                m[dv] = fl >> 3;
+                m[d] = plus ? 0 : 7;
+                vh[j] = src(nb, m[0] + 8 * m[1] + 64 * m[2]);
+            }
+        } else {
+            const int g = -1 - nb;
+            if (g < M.nbc) {
+                ah[j] = -1.0;
+                vh[j] = inhom ? 2.0 * M.gbc[(size_t)g * 64 + fl] : 0.0;
+            } else {
+                ah[j] = 2.0 / 3.0;
+                vh[j] = cp((size_t)(g - M.nbc), fl);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+        const int c = threadIdx.x + NT * j;
+        tile[tix(c & 7, (c >> 3) & 7, c >> 6)] = vi[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NH; ++j) {
+        const int t = threadIdx.x + NT * j;
+        if (t >= 384) continue;
+        const int f = t >> 6, d = f >> 1;
         int du, dv;
         transverse(d, du, dv);
         int l[3];
-        l[du] = iu;
-        l[dv] = iv;
-        l[d] = s > 0 ? 8 : -1;
-        int nb = M.nbr[b * 6 + f];
-        double v, a = 0.0;
-        if (nb >= 0) {
-            int m[3] = {l[0], l[1], l[2]};
-            m[d] = s > 0 ? 0 : 7;
-            v = ZERO ? 0.0 : src(nb, m[0] + 8 * m[1] + 64 * m[2]);
-        } else {
-            int g = -1 - nb;
-            if (g < M.nbc) {
-                a = -1.0;
-                v = inhom ? 2.0 * M.gbc[(size_t)g * 64 + fl] : 0.0;
-            } else {
-                a = 2.0 / 3.0;
-                v = cp((size_t)(g - M.nbc), fl);
-            }
-        }
-        tile[tix(l[0], l[1], l[2])] = v;
-        if (fl == 0) alpha[f] = a;
+        l[du] = t & 7;
+        l[dv] = (t >> 3) & 7;
+        l[d] = (f & 1) ? 8 : -1;
+        tile[tix(l[0], l[1], l[2])] = vh[j];
+        if ((t & 63) == 0) alpha[f] = ah[j];
     }
     __syncthreads();
 }
@@ -373,16 +365,16 @@ __device__ __forceinline__ void finish_ghosts(double *tile, const double *alpha)
 }
 
 // Composite residual r = rho/eps0 - A_comp phi on uncovered cells (zero on
-// covered ones) of a range or list of AMR bricks, written as T in brick
-// layout (r_out) and/or FP64 in the caller's layout (r_user), with the
-// per-brick partial norm.  A face towards a covered cell takes the mean of the
-// four fine fluxes through it (flux matching).  Bricks with no covered cell
-// and no covered face neighbour (every brick of the finest level) take the
-// plain 7-point stencil on the tile.
+// covered ones) of a range or list of AMR bricks, from FP64 phi and rho in
+// brick layout, written as T in brick layout (r_out) and/or FP64 in the
+// caller's layout (r_user), with the per-brick partial norm.  A face towards
+// a covered cell takes the mean of the four fine fluxes through it (flux
+// matching).  Bricks with no covered cell and no covered face neighbour
+// (every brick of the finest level) take the plain 7-point stencil.
 template <class T, bool ZERO>
-__global__ void __launch_bounds__(256) k_outer_residual(DevMeta M, int b0, int nb, double *const *phi, double *const *rho,
-                                                        double inv_eps0, const double *cp_phi, T *r_out,
-                                                        double *part, int norm_p, const int32_t *list,
+__global__ void __launch_bounds__(256) k_outer_residual(DevMeta M, int b0, int nb, const double *phib,
+                                                        const double *rhob, double inv_eps0, const double *cp_phi,
+                                                        T *r_out, double *part, int norm_p, const int32_t *list,
                                                         double *const *r_user)
 {
     __shared__ double tile[TE * TE * TE];
@@ -390,66 +382,17 @@ __global__ void __launch_bounds__(256) k_outer_residual(DevMeta M, int b0, int n
     __shared__ int nbk[6];
     __shared__ uint8_t ncm[6];
     const int b = pick_brick(b0, nb, list, blockIdx.x);
-    const int4 o = M.org[b];
-    const int lev = o.w;
-    const LevelConst L = M.lc[lev];
+    const LevelConst L = M.lc[M.org[b].w];
     const uint8_t cm = M.cmask[b];
     if (threadIdx.x < 6) {
         int f = M.nbr[b * 6 + threadIdx.x];
         nbk[threadIdx.x] = f;
         ncm[threadIdx.x] = f >= 0 ? M.cmask[f] : 0;
     }
-    const int64_t ub = M.ubase[b];
-    const int2 us = M.ustr[b];
-    const double *ph = phi[lev];
-    const double *rh = rho[lev];
-    int64_t ui[2];
     double rv[2];
-    for (int k = 0; k < 2; ++k) {
-        int c = threadIdx.x + 256 * k;
-        ui[k] = ub + (c & 7) + (int64_t)us.x * ((c >> 3) & 7) + (int64_t)us.y * (c >> 6);
-        rv[k] = rh[ui[k]] * inv_eps0;
-        tile[tix(c & 7, (c >> 3) & 7, c >> 6)] = ZERO ? 0.0 : ph[ui[k]];
-    }
-    // halo layer (no interior: the loop above staged it); face neighbours
-    // are on the same level, so their values come from ph
-    {
-        CpArr<double> cp{ZERO ? nullptr : cp_phi};
-        for (int t = threadIdx.x; t < 384; t += 256) {
-            int f = t >> 6, d = f >> 1;
-            bool plus = f & 1;
-            int du, dv;
-            transverse(d, du, dv);
-            int iu = t & 7, iv = (t >> 3) & 7, fl = t & 63;
-            int l[3];
-            l[du] = iu;
-            l[dv] = iv;
-            l[d] = plus ? 8 : -1;
-            int nbr = M.nbr[b * 6 + f];
-            double v, a = 0.0;
-            if (nbr >= 0) {
-                int m[3] = {l[0], l[1], l[2]};
-                m[d] = plus ? 0 : 7;
-                v = 0.0;
-                if (!ZERO) {
-                    int2 ns = M.ustr[nbr];
-                    v = ph[M.ubase[nbr] + m[0] + (int64_t)ns.x * m[1] + (int64_t)ns.y * m[2]];
-                }
-            } else {
-                int g = -1 - nbr;
-                if (g < M.nbc) {
-                    a = -1.0;
-                    v = 2.0 * M.gbc[(size_t)g * 64 + fl];
-                } else {
-                    a = 2.0 / 3.0;
-                    v = cp((size_t)(g - M.nbc), fl);
-                }
-            }
-            tile[tix(l[0], l[1], l[2])] = v;
-            if (fl == 0) alpha[f] = a;
-        }
-    }
-    __syncthreads();
+    for (int k = 0; k < 2; ++k) rv[k] = rhob[(size_t)b * BRICK_CELLS + threadIdx.x + 256 * k] * inv_eps0;
+    stage_tile<SrcB<double>, ZERO, CpArr<double>>(M, b, SrcB<double>{phib}, CpArr<double>{ZERO ? nullptr : cp_phi},
+                                                  true, tile, alpha);
     finish_ghosts(tile, alpha);
     bool any_cov = cm != 0;
     for (int f = 0; f < 6; ++f) any_cov = any_cov || ncm[f] != 0;  // uniform over the workgroup
@@ -478,20 +421,43 @@ __global__ void __launch_bounds__(256) k_outer_residual(DevMeta M, int b0, int n
                     } else if (!ZERO) {
                         int nl[3] = {qx & 7, qy & 7, qz & 7};
                         Au += -0.5 * L.ih2[d] *
-                              fine_face_sum(M, inside ? b : nbk[f], nl, d, s, UserAccL{phi, M.org, M.ubase, M.ustr},
-                                            cp_phi);
+                              fine_face_sum(M, inside ? b : nbk[f], nl, d, s, BrickAcc<double>{phib}, cp_phi);
                     }
                 }
             }
             r = rv[k] - Au;
         }
         if (r_out) r_out[(size_t)b * BRICK_CELLS + c] = (T)r;
-        if (r_user) r_user[lev][ui[k]] = r;
+        if (r_user) {
+            int2 us = M.ustr[b];
+            r_user[M.org[b].w][M.ubase[b] + x + (int64_t)us.x * y + (int64_t)us.y * z] = r;
+        }
         double av = fabs(r);
         acc = norm_p == 2 ? acc + av * av : norm_p == 1 ? acc + av : fmax(acc, av);
     }
-    acc = block_reduce_256(acc, norm_p == 0);
+    acc = block_reduce(acc, norm_p == 0);
     if (threadIdx.x == 0) part[b] = acc;
+}
+
+// Copies between the caller's box-list layout and brick layout on a range or
+// list of AMR bricks: to_brick: a -> ab and (when set) b -> bb; else ab -> a.
+__global__ void __launch_bounds__(256) k_user_brick(DevMeta M, int b0, int nb, const int32_t *list, int to_brick,
+                                                    double *const *a, double *ab, double *const *bu, double *bb)
+{
+    const int b = pick_brick(b0, nb, list, blockIdx.x);
+    const int w = M.org[b].w;
+    const int64_t ub = M.ubase[b];
+    const int2 us = M.ustr[b];
+    for (int c = threadIdx.x; c < BRICK_CELLS; c += 256) {
+        int64_t ui = ub + (c & 7) + (int64_t)us.x * ((c >> 3) & 7) + (int64_t)us.y * (c >> 6);
+        size_t bi = (size_t)b * BRICK_CELLS + c;
+        if (to_brick) {
+            ab[bi] = a[w][ui];
+            if (bb) bb[bi] = bu[w][ui];
+        } else {
+            a[w][ui] = ab[bi];
+        }
+    }
 }
 
 // norm of each listed brick range (one AMR level of one problem) from the
@@ -532,18 +498,6 @@ __global__ void __launch_bounds__(1024) k_level_norms(const int2 *ranges, int n,
 // coarse parts of the coarse-fine ghosts (step 1 of Eq. 2d_lagrange, times
 // the step-2 weight 8/15)
 // ---------------------------------------------------------------------------
-struct SrcUser {
-    double *const *p;
-    const int4 *org;
-    const int64_t *ubase;
-    const int2 *ustr;
-    __device__ double operator()(int32_t g) const
-    {
-        int b = g >> 9, c = g & 511;
-        int2 s = ustr[b];
-        return p[org[b].w][ubase[b] + (c & 7) + (int64_t)s.x * ((c >> 3) & 7) + (int64_t)s.y * (c >> 6)];
-    }
-};
 template <class T>
 struct SrcBrick {
     const T *u;
@@ -661,57 +615,77 @@ struct SrcProl {
 // MODE bits: 1 input is zero; 2 input plus the parent correction (fused
 // prolongation); 4 coarse parts of the coarse-fine ghosts computed from the
 // coarse level's values in ein and stored into cp (else read from cp);
-// 8 phi += result on AMR bricks (fused phi update).
+// 8 phi += result on AMR bricks (fused phi update; phi in brick layout).
 enum { HG_ZERO = 1, HG_PROL = 2, HG_CPIN = 4, HG_PHI = 8 };
 
+// threads per brick of the stencil kernels: two wavefronts, so that 16
+// bricks' workgroups fit a CU at once and more loads are in flight
+constexpr int BT = 128;
+
 template <class T, int MODE>
-__global__ void __launch_bounds__(256) k_hgs(DevMeta M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
-                                             double *const *phi)
+__global__ void __launch_bounds__(BT) k_hgs(DevMeta M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
+                                            double *phib)
 {
     __shared__ double tile[TE * TE * TE];
     __shared__ double alpha[6];
+    constexpr int PER = 256 / BT;  // cells of each colour per thread
     int b = b0 + xcd_remap(blockIdx.x, nb);
     int lev = M.org[b].w;
     LevelConst L = M.lc[lev];
-    int t = threadIdx.x;
-    int z = t >> 5, y = (t >> 2) & 7, xx = (t & 3) << 1;
-    int xc[2] = {xx + ((y + z) & 1), xx + (((y + z) & 1) ^ 1)};  // colour 0, colour 1 (brick origins are even)
-    double rv[2];
-    for (int k = 0; k < 2; ++k) rv[k] = (double)r[(size_t)b * BRICK_CELLS + xc[k] + 8 * y + 64 * z];
+    int cyz[PER], cx[2][PER];  // y + 8 z, and x of the colour-0 / colour-1 cell (brick origins are even)
+    double rv[2][PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int t = threadIdx.x + BT * j;
+        int z = t >> 5, y = (t >> 2) & 7, xx = (t & 3) << 1;
+        cyz[j] = y + 8 * z;
+        cx[0][j] = xx + ((y + z) & 1);
+        cx[1][j] = xx + (((y + z) & 1) ^ 1);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) rv[k][j] = (double)r[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]];
+    }
     if (MODE & HG_ZERO) {
-        stage_tile<SrcZ, true>(M, b, SrcZ{}, CpNone{}, false, tile, alpha);
+        stage_tile<SrcZ, true, CpNone, BT>(M, b, SrcZ{}, CpNone{}, false, tile, alpha);
     } else if (MODE & HG_PROL) {
         if (MODE & HG_CPIN)
-            stage_tile<SrcProl<T>, false, CpInline<T>>(M, b, SrcProl<T>{ein, M.par}, CpInline<T>{&M, ein, cp}, false,
-                                                       tile, alpha);
+            stage_tile<SrcProl<T>, false, CpInline<T>, BT>(M, b, SrcProl<T>{ein, M.par}, CpInline<T>{&M, ein, cp},
+                                                           false, tile, alpha);
         else
-            stage_tile<SrcProl<T>, false, CpArr<T>>(M, b, SrcProl<T>{ein, M.par}, CpArr<T>{cp}, false, tile, alpha);
+            stage_tile<SrcProl<T>, false, CpArr<T>, BT>(M, b, SrcProl<T>{ein, M.par}, CpArr<T>{cp}, false, tile,
+                                                        alpha);
     } else {
-        stage_tile<SrcB<T>, false, CpArr<T>>(M, b, SrcB<T>{ein}, CpArr<T>{cp}, false, tile, alpha);
+        stage_tile<SrcB<T>, false, CpArr<T>, BT>(M, b, SrcB<T>{ein}, CpArr<T>{cp}, false, tile, alpha);
     }
-    double v[2];
+    double v[2][PER];
+#pragma unroll
     for (int k = 0; k < 2; ++k) {
-        int x = xc[k];
-        double num = rv[k], den = 0.0;
-        for (int d = 0; d < 3; ++d)
-            for (int s = -1; s <= 1; s += 2) {
-                double a, bv;
-                tile_ab(tile, alpha, x, y, z, d, s, a, bv);
-                num += L.ih2[d] * bv;
-                den += L.ih2[d] * (1.0 - a);
-            }
-        v[k] = num / den;
-        tile[tix(x, y, z)] = v[k];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            int x = cx[k][j], y = cyz[j] & 7, z = cyz[j] >> 3;
+            double num = rv[k][j], den = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int s = -1; s <= 1; s += 2) {
+                    double a, bv;
+                    tile_ab(tile, alpha, x, y, z, d, s, a, bv);
+                    num += L.ih2[d] * bv;
+                    den += L.ih2[d] * (1.0 - a);
+                }
+            v[k][j] = num / den;
+            tile[tix(x, y, z)] = v[k][j];
+        }
         __syncthreads();
     }
-    for (int k = 0; k < 2; ++k) eout[(size_t)b * BRICK_CELLS + xc[k] + 8 * y + 64 * z] = (T)v[k];
-    if (MODE & HG_PHI) {
-        double *ph = phi[lev];
-        if (ph) {
-            int64_t ub = M.ubase[b];
-            int2 us = M.ustr[b];
-            for (int k = 0; k < 2; ++k) ph[ub + xc[k] + (int64_t)us.x * y + (int64_t)us.y * z] += v[k];
-        }
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) eout[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]] = (T)v[k][j];
+    if ((MODE & HG_PHI) && L.amr >= 0) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) phib[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]] += v[k][j];
     }
 }
 
@@ -828,50 +802,43 @@ __global__ void __launch_bounds__(256) k_prolong(DevMeta M, int b0, int nb, T *e
     }
 }
 
-// phi += e on AMR bricks (FP64 accumulation of the correction)
+// phi += e on AMR bricks (FP64 accumulation of the correction; brick layout)
 template <class T>
-__global__ void __launch_bounds__(256) k_phi_update(DevMeta M, int b0, int nb, double *const *phi, const T *e,
+__global__ void __launch_bounds__(256) k_phi_update(DevMeta M, int b0, int nb, double *phib, const T *e,
                                                     const int32_t *list)
 {
     int b = pick_brick(b0, nb, list, blockIdx.x);
-    double *ph = phi[M.org[b].w];
-    int64_t ub = M.ubase[b];
-    int2 us = M.ustr[b];
     for (int c = threadIdx.x; c < BRICK_CELLS; c += 256) {
-        int64_t ui = ub + (c & 7) + (int64_t)us.x * ((c >> 3) & 7) + (int64_t)us.y * (c >> 6);
-        ph[ui] += (double)e[(size_t)b * BRICK_CELLS + c];
+        size_t i = (size_t)b * BRICK_CELLS + c;
+        phib[i] += (double)e[i];
     }
 }
 
 // phi^{l} <- U phi^l + R phi^{l+1} for the covered cells under a range of
-// fine bricks (Alg. 2, average down)
-__global__ void __launch_bounds__(256) k_avgdown(DevMeta M, int b0, int nb, double *const *phi)
+// fine bricks (Alg. 2, average down; brick layout)
+__global__ void __launch_bounds__(256) k_avgdown(DevMeta M, int b0, int nb, double *phib)
 {
     int nwg = (nb + 3) >> 2;
     int w = xcd_remap(blockIdx.x, nwg);
     int k = w * 4 + (threadIdx.x >> 6);
     if (k >= nb) return;
     int b = b0 + k;
-    int lev = M.org[b].w;
     int t = threadIdx.x & 63;
     int cx = t & 3, cy = (t >> 2) & 3, cz = t >> 4;
-    UserAcc uf{phi[lev], M.ubase, M.ustr};
+    const double *u = phib + (size_t)b * BRICK_CELLS;
     double s = 0.0;
     for (int dz = 0; dz < 2; ++dz)
         for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx) {
-                int l[3] = {2 * cx + dx, 2 * cy + dy, 2 * cz + dz};
-                s += uf(b, l);
-            }
+            for (int dx = 0; dx < 2; ++dx) s += u[(2 * cx + dx) + 8 * (2 * cy + dy) + 64 * (2 * cz + dz)];
     int par = M.par[b];
     int pb = par >> 3, oc = par & 7;
     int X = (oc & 1) * 4 + cx, Y = ((oc >> 1) & 1) * 4 + cy, Z = (oc >> 2) * 4 + cz;
-    int2 us = M.ustr[pb];
-    phi[M.org[pb].w][M.ubase[pb] + X + (int64_t)us.x * Y + (int64_t)us.y * Z] = 0.125 * s;
+    phib[(size_t)pb * BRICK_CELLS + X + 8 * Y + 64 * Z] = 0.125 * s;
 }
 
-// E_d = -(u_+ - u_-) / (2 h_d) on every cell of a range of AMR bricks
-__global__ void __launch_bounds__(256) k_efield(DevMeta M, int b0, int nb, double *const *phi, const double *cp_phi,
+// E_d = -(u_+ - u_-) / (2 h_d) on every cell of a range of AMR bricks (phi in
+// brick layout, E in the caller's layout)
+__global__ void __launch_bounds__(256) k_efield(DevMeta M, int b0, int nb, const double *phib, const double *cp_phi,
                                                 double *const *E, const int32_t *list)
 {
     __shared__ double tile[TE * TE * TE];
@@ -879,8 +846,8 @@ __global__ void __launch_bounds__(256) k_efield(DevMeta M, int b0, int nb, doubl
     int b = pick_brick(b0, nb, list, blockIdx.x);
     int lev = M.org[b].w;
     LevelConst L = M.lc[lev];
-    SrcU src{phi, M.org, M.ubase, M.ustr};
-    stage_tile<SrcU, false, CpArr<double>>(M, b, src, CpArr<double>{cp_phi}, true, tile, alpha);
+    stage_tile<SrcB<double>, false, CpArr<double>>(M, b, SrcB<double>{phib}, CpArr<double>{cp_phi}, true, tile,
+                                                   alpha);
     int64_t ub = M.ubase[b];
     int2 us = M.ustr[b];
     for (int c = threadIdx.x; c < BRICK_CELLS; c += 256) {
@@ -1210,7 +1177,7 @@ __device__ void wg_gs_pass(const DevMeta &M, int b0, int nb, T *e, const T *r, i
 template <class T>
 __global__ void __launch_bounds__(1024) k_coarse_cycle(DevMeta M, const CoarseJob *jobs, T *e, T *r, double *work,
                                                        const double *dtab, int nu1, int nu2, double rtol, int maxit,
-                                                       int *iters, double *const *phi, int phi_update)
+                                                       int *iters, double *phib, int phi_update)
 {
     __shared__ double lds[DIRECT_LDS];
     const CoarseJob J = jobs[blockIdx.x];
@@ -1267,15 +1234,9 @@ __global__ void __launch_bounds__(1024) k_coarse_cycle(DevMeta M, const CoarseJo
                 wg_gs_pass<T>(M, b0, nb, e, r, 1);
             }
         }
-        double *ph = phi_update ? phi[M.org[b0].w] : nullptr;
-        if (ph) {
-            for (int i = threadIdx.x; i < nb * BRICK_CELLS; i += (int)blockDim.x) {
-                int b = b0 + (i >> 9), c = i & 511;
-                int2 us = M.ustr[b];
-                ph[M.ubase[b] + (c & 7) + (int64_t)us.x * ((c >> 3) & 7) + (int64_t)us.y * (c >> 6)] +=
-                    (double)e[(size_t)b * BRICK_CELLS + c];
-            }
-        }
+        if (phi_update && M.lc[M.org[b0].w].amr >= 0)
+            for (int i = threadIdx.x; i < nb * BRICK_CELLS; i += (int)blockDim.x)
+                phib[(size_t)b0 * BRICK_CELLS + i] += (double)e[(size_t)b0 * BRICK_CELLS + i];
     }
 }
 
@@ -1487,7 +1448,7 @@ __global__ void __launch_bounds__(256) k_absmax_part(const double *v, int64_t n,
     double m = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         m = fmax(m, fabs(v[i]));
-    m = block_reduce_256(m, 1);
+    m = block_reduce(m, 1);
     if (threadIdx.x == 0) part[blockIdx.x] = m;
 }
 
@@ -1495,7 +1456,7 @@ __global__ void __launch_bounds__(256) k_absmax_final(const double *part, int n,
 {
     double m = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, part[i]);
-    m = block_reduce_256(m, 1);
+    m = block_reduce(m, 1);
     if (threadIdx.x == 0) *out = m;
 }
 
@@ -1567,31 +1528,30 @@ __global__ void __launch_bounds__(256) k_fill(double *v, int64_t n, double val)
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 template <class T>
-void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list,
-                           double *const *phi, double *const *rho, double inv_eps0, const double *cp_phi, T *r_out,
-                           double *part, int norm_p, bool zero_phi, double *const *r_user)
+void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, const double *phib,
+                           const double *rhob, double inv_eps0, const double *cp_phi, T *r_out, double *part,
+                           int norm_p, bool zero_phi, double *const *r_user)
 {
     if (nb <= 0) return;
     if (zero_phi)
-        AMRMG_LAUNCH((k_outer_residual<T, true>), dim3(nb), dim3(256), 0, st, M, b0, nb, phi, rho, inv_eps0,
+        AMRMG_LAUNCH((k_outer_residual<T, true>), dim3(nb), dim3(256), 0, st, M, b0, nb, phib, rhob, inv_eps0,
                      cp_phi, r_out, part, norm_p, list, r_user);
     else
-        AMRMG_LAUNCH((k_outer_residual<T, false>), dim3(nb), dim3(256), 0, st, M, b0, nb, phi, rho, inv_eps0,
+        AMRMG_LAUNCH((k_outer_residual<T, false>), dim3(nb), dim3(256), 0, st, M, b0, nb, phib, rhob, inv_eps0,
                      cp_phi, r_out, part, norm_p, list, r_user);
+}
+
+void launch_user_brick(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, bool to_brick,
+                       double *const *a, double *ab, double *const *bu, double *bb)
+{
+    if (nb <= 0) return;
+    AMRMG_LAUNCH(k_user_brick, dim3(nb), dim3(256), 0, st, M, b0, nb, list, (int)to_brick, a, ab, bu, bb);
 }
 
 void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double *part, double *out, int norm_p)
 {
     if (n <= 0) return;
     AMRMG_LAUNCH(k_level_norms, dim3(n), dim3(1024), 0, st, ranges, n, part, out, norm_p);
-}
-
-void launch_cpart_user(hipStream_t st, const DevMeta &M, int cf0, int ncf, double *const *phi, double *cp)
-{
-    if (ncf <= 0) return;
-    SrcUser s{phi, M.org, M.ubase, M.ustr};
-    AMRMG_LAUNCH((k_cpart<double, SrcUser>), dim3(blocks_for((int64_t)ncf * 16, 256)), dim3(256), 0, st, M,
-                       cf0, ncf, s, cp);
 }
 
 template <class T>
@@ -1641,24 +1601,24 @@ void launch_prolong(hipStream_t st, const DevMeta &M, int b0, int nb, T *e)
 }
 
 template <class T>
-void launch_phi_update(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, double *const *phi,
+void launch_phi_update(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, double *phib,
                        const T *e)
 {
     if (nb <= 0) return;
-    AMRMG_LAUNCH((k_phi_update<T>), dim3(nb), dim3(256), 0, st, M, b0, nb, phi, e, list);
+    AMRMG_LAUNCH((k_phi_update<T>), dim3(nb), dim3(256), 0, st, M, b0, nb, phib, e, list);
 }
 
-void launch_avgdown(hipStream_t st, const DevMeta &M, int b0, int nb, double *const *phi)
+void launch_avgdown(hipStream_t st, const DevMeta &M, int b0, int nb, double *phib)
 {
     if (nb <= 0) return;
-    AMRMG_LAUNCH(k_avgdown, dim3((nb + 3) / 4), dim3(256), 0, st, M, b0, nb, phi);
+    AMRMG_LAUNCH(k_avgdown, dim3((nb + 3) / 4), dim3(256), 0, st, M, b0, nb, phib);
 }
 
-void launch_efield(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, double *const *phi,
+void launch_efield(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, const double *phib,
                    const double *cp_phi, double *const *E)
 {
     if (nb <= 0) return;
-    AMRMG_LAUNCH(k_efield, dim3(nb), dim3(256), 0, st, M, b0, nb, phi, cp_phi, E, list);
+    AMRMG_LAUNCH(k_efield, dim3(nb), dim3(256), 0, st, M, b0, nb, phib, cp_phi, E, list);
 }
 
 template <class T>
@@ -1721,19 +1681,19 @@ void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, doubl
 
 template <class T>
 void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
-                double *const *phi, int mode)
+                double *phib, int mode)
 {
     if (nb <= 0) return;
-    dim3 g(nb), blk(256);
+    dim3 g(nb), blk(BT);
     switch (mode) {
-    case HG_ZERO: AMRMG_LAUNCH((k_hgs<T, HG_ZERO>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phi); break;
-    case 0: AMRMG_LAUNCH((k_hgs<T, 0>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phi); break;
-    case HG_PHI: AMRMG_LAUNCH((k_hgs<T, HG_PHI>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phi); break;
+    case HG_ZERO: AMRMG_LAUNCH((k_hgs<T, HG_ZERO>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib); break;
+    case 0: AMRMG_LAUNCH((k_hgs<T, 0>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib); break;
+    case HG_PHI: AMRMG_LAUNCH((k_hgs<T, HG_PHI>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib); break;
     case HG_PROL | HG_CPIN:
-        AMRMG_LAUNCH((k_hgs<T, HG_PROL | HG_CPIN>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phi);
+        AMRMG_LAUNCH((k_hgs<T, HG_PROL | HG_CPIN>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib);
         break;
     case HG_PROL | HG_CPIN | HG_PHI:
-        AMRMG_LAUNCH((k_hgs<T, HG_PROL | HG_CPIN | HG_PHI>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phi);
+        AMRMG_LAUNCH((k_hgs<T, HG_PROL | HG_CPIN | HG_PHI>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib);
         break;
     default: break;
     }
@@ -1742,12 +1702,12 @@ void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, 
 template <class T>
 void launch_coarse_cycle(hipStream_t st, const DevMeta &M, const CoarseJob *jobs, int njobs, T *e, T *r,
                          double *work, const double *dtab, int nu1, int nu2, double rtol, int maxit, int *iters,
-                         double *const *phi, bool phi_update, int threads_hint)
+                         double *phib, bool phi_update, int threads_hint)
 {
     if (njobs <= 0) return;
     int threads = threads_hint > 0 ? threads_hint : 1024;
     AMRMG_LAUNCH((k_coarse_cycle<T>), dim3(njobs), dim3(threads), 0, st, M, jobs, e, r, work, dtab, nu1, nu2, rtol,
-                 maxit, iters, phi, (int)phi_update);
+                 maxit, iters, phib, (int)phi_update);
 }
 
 template <class T>
@@ -1786,8 +1746,8 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val)
 
 #define AMRMG_INST(T)                                                                                            \
     template void launch_outer_residual<T>(hipStream_t, const DevMeta &, int, int, const int32_t *,               \
-                                           double *const *, double *const *, double, const double *, T *,         \
-                                           double *, int, bool, double *const *);                                 \
+                                           const double *, const double *, double, const double *, T *, double *, \
+                                           int, bool, double *const *);                                           \
     template void launch_cpart_brick<T>(hipStream_t, const DevMeta &, int, int, const T *, T *);                \
     template void launch_gsrb<T>(hipStream_t, const DevMeta &, int, int, T *, const T *, const T *, int, bool);  \
     template void launch_jacobi<T>(hipStream_t, const DevMeta &, int, int, const T *, T *, const T *, const T *, \
@@ -1795,16 +1755,16 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val)
     template void launch_restrict<T>(hipStream_t, const DevMeta &, int, int, const T *, const T *, T *);         \
     template void launch_reflux<T>(hipStream_t, const DevMeta &, const int32_t *, int, const T *, T *);          \
     template void launch_prolong<T>(hipStream_t, const DevMeta &, int, int, T *);                                \
-    template void launch_phi_update<T>(hipStream_t, const DevMeta &, int, int, const int32_t *, double *const *, \
+    template void launch_phi_update<T>(hipStream_t, const DevMeta &, int, int, const int32_t *, double *,         \
                                        const T *);                                                               \
     template void launch_bottom_cg<T>(hipStream_t, const DevMeta &, const int4 *, int, const T *, T *, double *, \
                                       double, int, int *);                                                      \
     template void launch_copy<T>(hipStream_t, const T *, T *, int64_t);                                         \
     template void launch_hgs<T>(hipStream_t, const DevMeta &, int, int, const T *, T *, const T *, T *,         \
-                                double *const *, int);                                                          \
+                                double *, int);                                                                 \
     template void launch_coarse_cycle<T>(hipStream_t, const DevMeta &, const CoarseJob *, int, T *, T *,        \
-                                         double *, const double *, int, int, double, int, int *, double *const *, \
-                                         bool, int);
+                                         double *, const double *, int, int, double, int, int *, double *, bool, \
+                                         int);
 AMRMG_INST(float)
 AMRMG_INST(double)
 #undef AMRMG_INST

@@ -58,12 +58,15 @@ void launch_face_data(hipStream_t st, const DevMeta &M, const EntryDev *ent, con
 void set_launch_timing(hipEvent_t start, hipEvent_t stop);
 bool launch_timing_pending();
 
+// phib, rhob: FP64 phi and rho in brick layout
 template <class T>
-void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list,
-                           double *const *phi, double *const *rho, double inv_eps0, const double *cp_phi, T *r_out,
-                           double *part, int norm_p, bool zero_phi, double *const *r_user);
+void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, const double *phib,
+                           const double *rhob, double inv_eps0, const double *cp_phi, T *r_out, double *part,
+                           int norm_p, bool zero_phi, double *const *r_user);
+// caller's layout (per-level pointer tables a, bu) <-> brick layout (ab, bb)
+void launch_user_brick(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, bool to_brick,
+                       double *const *a, double *ab, double *const *bu, double *bb);
 void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double *part, double *out, int norm_p);
-void launch_cpart_user(hipStream_t st, const DevMeta &M, int cf0, int ncf, double *const *phi, double *cp);
 template <class T>
 void launch_cpart_brick(hipStream_t st, const DevMeta &M, int cf0, int ncf, const T *src, T *cp);
 template <class T>
@@ -79,10 +82,10 @@ void launch_reflux(hipStream_t st, const DevMeta &M, const int32_t *list, int n,
 template <class T>
 void launch_prolong(hipStream_t st, const DevMeta &M, int b0, int nb, T *e);
 template <class T>
-void launch_phi_update(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, double *const *phi,
+void launch_phi_update(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, double *phib,
                        const T *e);
-void launch_avgdown(hipStream_t st, const DevMeta &M, int b0, int nb, double *const *phi);
-void launch_efield(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, double *const *phi,
+void launch_avgdown(hipStream_t st, const DevMeta &M, int b0, int nb, double *phib);
+void launch_efield(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, const double *phib,
                    const double *cp_phi, double *const *E);
 template <class T>
 void launch_bottom_cg(hipStream_t st, const DevMeta &M, const int4 *jobs, int njobs, const T *rhs, T *e,
@@ -92,11 +95,11 @@ void launch_copy(hipStream_t st, const T *a, T *b, int64_t n);
 // brick-hybrid Gauss-Seidel sweep; mode = bits of HG_ZERO 1, HG_PROL 2, HG_CPIN 4, HG_PHI 8
 template <class T>
 void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
-                double *const *phi, int mode);
+                double *phib, int mode);
 template <class T>
 void launch_coarse_cycle(hipStream_t st, const DevMeta &M, const CoarseJob *jobs, int njobs, T *e, T *r,
                          double *work, const double *dtab, int nu1, int nu2, double rtol, int maxit, int *iters,
-                         double *const *phi, bool phi_update, int threads_hint);
+                         double *phib, bool phi_update, int threads_hint);
 void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                     const double *q, const uint32_t *perm, const DepArgs &A, const int64_t *ubase, const int2 *ustr,
                     unsigned long long *nout);
