@@ -60,11 +60,12 @@ enum { AMRMG_FP64 = 0, AMRMG_MIXED = 1 };
  * AMRMG_JACOBI = damped Jacobi.  The small levels at the bottom of the cycle
  * always use whole-level red-black inside one workgroup. */
 enum { AMRMG_GSRB = 0, AMRMG_JACOBI = 1, AMRMG_GSRB_GLOBAL = 2 };
-/* Bottom solvers of the coarsest grid: AMRMG_BOTTOM_AUTO solves it directly
- * (separable eigendecomposition of the Dirichlet Laplacian on its one box)
- * when the grid plus its transform tables fit in 152 KiB of LDS (up to 24^3
- * cells), and by CG to bottom_rtol otherwise; AMRMG_BOTTOM_CG always uses
- * CG. */
+/* Bottom solvers of the coarsest grid (the multigrid levels below level 0
+ * halve the base grid while every edge stays a multiple of 16 and some edge
+ * exceeds 64 cells): AMRMG_BOTTOM_AUTO solves it directly (separable
+ * eigendecomposition of the Dirichlet Laplacian on its one box) when every
+ * edge is at most 64 cells, and by CG to bottom_rtol otherwise;
+ * AMRMG_BOTTOM_CG always uses CG. */
 enum { AMRMG_BOTTOM_AUTO = 0, AMRMG_BOTTOM_CG = 1 };
 enum { AMRMG_MAX_LEVELS = 8 };
 

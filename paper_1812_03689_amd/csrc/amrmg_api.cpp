@@ -146,7 +146,14 @@ struct DevState {
     int njobs = 0;
     size_t cg_doubles = 0;
     CoarseJob *d_cjobs = nullptr;
-    double *d_dtab = nullptr;  // direct-solve tables of the coarsest grids
+    int n_cg = 0;  // problems whose coarsest grid is solved by CG
+    // direct solves of the coarsest grids: tables, jobs, work lists, scratch
+    double *d_dtab = nullptr;
+    DirectJob *d_djobs = nullptr;
+    int2 *d_planes = nullptr, *d_groups = nullptr;
+    int n_planes = 0, n_groups = 0, direct_maxdim = 0;
+    size_t dw_doubles = 0;
+    double *dw = nullptr;
     int kc = 0;  // levels 0..kc of every problem run in the one-workgroup coarse cycle
     // per-level pointer tables: phi[ne], rho[ne], rout[ne], E[3 ne]
     DBuf ptrbuf;
@@ -302,8 +309,16 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
     }
     static thread_local std::vector<CoarseJob> cj;
     static thread_local std::vector<double> dtab;
+    static thread_local std::vector<DirectJob> djl;
+    static thread_local std::vector<int2> planes, groups;
     cj.assign(m.prob_ent.size(), CoarseJob{});
     dtab.clear();
+    djl.clear();
+    planes.clear();
+    groups.clear();
+    D.n_cg = 0;
+    D.dw_doubles = 0;
+    D.direct_maxdim = 0;
     for (size_t i = 0; i < m.prob_ent.size(); ++i) {
         cj[i].nlev = kc + 1;
         for (int k = 0; k <= kc; ++k) {
@@ -311,21 +326,41 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
             cj[i].nb[k] = m.ent[m.prob_ent[i][k]].nb;
         }
         cj[i].cg_off = jobs[4 * i + 2];
-        // direct solve of the coarsest grid when it is one full box that fits
-        const HostLevel &L = probs[m.ent[m.prob_ent[i][0]].prob]->lev[0];
-        int64_t ntab = 0;
-        for (int d = 0; d < 3; ++d) ntab += 2 * (int64_t)L.n[d] * L.n[d] + L.n[d];
-        bool fits = direct && L.boxes.size() == 1 && (int64_t)L.n[0] * L.n[1] * L.n[2] + ntab <= DIRECT_LDS;
-        for (int d = 0; d < 3 && fits; ++d) fits = L.boxes[0].lo[d] == 0 && L.boxes[0].hi[d] == L.n[d];
-        cj[i].dtab = -1;
-        for (int d = 0; d < 3; ++d) cj[i].dn[d] = L.n[d];
-        if (fits) {
-            cj[i].dtab = (int)dtab.size();
-            std::vector<double> t = direct_tables(L.n, L.h);
-            dtab.insert(dtab.end(), t.begin(), t.end());
+        // direct solve of the coarsest grid when it is one full box of at
+        // most DIRECT_DIM cells per axis (the levels below level 0 stop there)
+        const auto &e0 = m.ent[m.prob_ent[i][0]];
+        const HostLevel &L = probs[e0.prob]->lev[0];
+        bool fits = direct && L.boxes.size() == 1;
+        for (int d = 0; d < 3 && fits; ++d)
+            fits = L.boxes[0].lo[d] == 0 && L.boxes[0].hi[d] == L.n[d] && L.n[d] <= DIRECT_DIM && L.n[d] % 4 == 0;
+        cj[i].direct = fits ? 1 : 0;
+        if (!fits) {
+            ++D.n_cg;
+            continue;
         }
+        DirectJob J{};
+        J.b0 = e0.b0;
+        for (int d = 0; d < 3; ++d) {
+            J.dn[d] = L.n[d];
+            D.direct_maxdim = std::max(D.direct_maxdim, L.n[d]);
+        }
+        J.tab = (int)dtab.size();
+        J.w = (int)D.dw_doubles;
+        J.amr = L.amr >= 0 ? 1 : 0;
+        std::vector<double> t = direct_tables(L.n, L.h);
+        dtab.insert(dtab.end(), t.begin(), t.end());
+        D.dw_doubles += (size_t)L.n[0] * L.n[1] * L.n[2];
+        const int jid = (int)djl.size();
+        djl.push_back(J);
+        for (int z = 0; z < L.n[2]; ++z) planes.push_back(make_int2(jid, z));
+        for (int c = 0; c < L.n[0] * L.n[1]; c += DIRECT_COLS) groups.push_back(make_int2(jid, c));
     }
+    D.n_planes = (int)planes.size();
+    D.n_groups = (int)groups.size();
     if (dtab.empty()) dtab.push_back(0.0);
+    if (djl.empty()) djl.push_back(DirectJob{});
+    if (planes.empty()) planes.push_back(make_int2(0, 0));
+    if (groups.empty()) groups.push_back(make_int2(0, 0));
 
     Packer P;
     int32_t *org = nullptr, *nbr = nullptr, *child = nullptr, *par = nullptr, *ustr = nullptr, *gfo = nullptr,
@@ -352,6 +387,9 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
     int32_t *dpool = nullptr;
     double *dmono = nullptr;
     P.add(dtab, &D.d_dtab);
+    P.add(djl, &D.d_djobs);
+    P.add(planes, &D.d_planes);
+    P.add(groups, &D.d_groups);
     P.add(ed, &dent);
     P.add(pool, &dpool);
     P.add(mono, &dmono);
@@ -420,9 +458,10 @@ static size_t ws_need(const DevState &D, int prec)
     s += 2 * align256(nc * 8);                        // phi, rho in brick layout
     s += align256((size_t)m.ncf * 64 * w + 8);         // coarse parts of the cycle
     s += align256((size_t)m.ncf * 64 * 8 + 8);         // coarse parts of phi
-    s += align256((size_t)m.nbrick * 8);               // per-brick partials
+    s += align256((size_t)m.nbrick * 16);              // per-wavefront partial norms (two per brick)
     s += align256(sizeof(double) * 2 * (D.range_prob.size() + 1));
     s += align256(D.cg_doubles * 8);
+    s += align256(D.dw_doubles * 8 + 8);             // direct-solve scratch
     s += align256(64);
     return s;
 }
@@ -458,9 +497,10 @@ static amrmg_status ensure_ws(DevState &D, int prec, void *user, size_t user_byt
     D.rhob = (double *)take(nc * 8);
     D.cpe = take((size_t)m.ncf * 64 * w + 8);
     D.cpphi = (double *)take((size_t)m.ncf * 64 * 8 + 8);
-    D.part = (double *)take((size_t)m.nbrick * 8);
+    D.part = (double *)take((size_t)m.nbrick * 16);
     D.dnorm = (double *)take(sizeof(double) * 2 * (D.range_prob.size() + 1));
     D.cgw = (double *)take(D.cg_doubles * 8);
+    D.dw = (double *)take(D.dw_doubles * 8 + 8);
     D.cgit = (int *)take(64);
     D.ws_prec = prec;
     return AMRMG_OK;
@@ -1144,8 +1184,11 @@ struct Driver {
             pe(AMRMG_K_REFLUX, 2.0 * nrf * BRICK_CELLS * W);
         }
         pb(AMRMG_K_BOTTOM);
-        launch_coarse_cycle<T>(st, D.M, D.d_cjobs, D.njobs, e, r, D.cgw, D.d_dtab, o.nu1, o.nu2, o.bottom_rtol,
-                               10000, D.cgit, D.phib, hybrid(), D.cg_threads);
+        launch_direct<T>(st, D.d_djobs, D.d_planes, D.n_planes, D.d_groups, D.n_groups, D.d_dtab, D.dw, r, e, D.phib,
+                         hybrid(), D.direct_maxdim);
+        if (D.n_cg > 0)
+            launch_coarse_cycle<T>(st, D.M, D.d_cjobs, D.njobs, e, r, D.cgw, o.nu1, o.nu2, o.bottom_rtol, 10000,
+                                   D.cgit, D.phib, hybrid(), D.cg_threads);
         pe(AMRMG_K_BOTTOM, (double)D.cg_doubles / 4 * (2 * W));
         for (int k = kc + 1; k < m.K; ++k) {
             if (hybrid()) {

@@ -325,7 +325,7 @@ void add_levels_below(Problem &P)
 {
     std::vector<HostLevel> below;
     int n[3] = {P.lev[0].n[0], P.lev[0].n[1], P.lev[0].n[2]};
-    while (n[0] % 16 == 0 && n[1] % 16 == 0 && n[2] % 16 == 0) {
+    while (n[0] % 16 == 0 && n[1] % 16 == 0 && n[2] % 16 == 0 && std::max(n[0], std::max(n[1], n[2])) > 64) {
         for (int d = 0; d < 3; ++d) n[d] /= 2;
         HostLevel L;
         level_init(L, n, P.lo, P.hi);

@@ -90,7 +90,9 @@ struct Problem {
 };
 
 // add the multigrid levels below AMR level 0 (halving while every edge stays
-// a multiple of 16); lev[0..] must hold the AMR levels on entry
+// a multiple of 16 and some edge exceeds 64 cells, so that the coarsest grid
+// is small enough for its direct solve); lev[0..] must hold the AMR levels on
+// entry
 void add_levels_below(Problem &P);
 
 // Merged metadata of one or more problems.  Levels are numbered coarsest

@@ -339,48 +339,35 @@ __device__ double fine_face_sum(const DevMeta &M, int nb, const int *nl, int d, 
     return sum;
 }
 
-// Halo slots of a staged tile that hold the ghost form a * u_c + bv (boundary
-// and coarse-fine faces) are replaced by the ghost value itself, using the
-// staged interior: a coarse-fine ghost is cpart + 2/3 u_c - 1/5 u_in.  After
-// this the plain 7-point stencil on the tile is the operator.
-__device__ __forceinline__ void finish_ghosts(double *tile, const double *alpha)
-{
-    for (int t = threadIdx.x; t < 384; t += blockDim.x) {
-        int f = t >> 6, d = f >> 1;
-        double a = alpha[f];
-        if (a == 0.0) continue;
-        bool plus = f & 1;
-        int du, dv;
-        transverse(d, du, dv);
-        int l[3], c[3], in[3];
-        l[du] = c[du] = in[du] = t & 7;
-        l[dv] = c[dv] = in[dv] = (t >> 3) & 7;
-        l[d] = plus ? 8 : -1;
-        c[d] = plus ? 7 : 0;
-        in[d] = plus ? 6 : 1;
-        double g = tile[tix(l[0], l[1], l[2])] + a * tile[tix(c[0], c[1], c[2])];
-        if (a > 0.0) g -= 0.2 * tile[tix(in[0], in[1], in[2])];
-        tile[tix(l[0], l[1], l[2])] = g;
-    }
-}
-
 // Composite residual r = rho/eps0 - A_comp phi on uncovered cells (zero on
 // covered ones) of a range or list of AMR bricks, from FP64 phi and rho in
 // brick layout, written as T in brick layout (r_out) and/or FP64 in the
-// caller's layout (r_user), with the per-brick partial norm.  A face towards
-// a covered cell takes the mean of the four fine fluxes through it (flux
-// matching).  Bricks with no covered cell and no covered face neighbour
-// (every brick of the finest level) take the plain 7-point stencil.
+// caller's layout (r_user), with one partial norm per wavefront (part[2 b],
+// part[2 b + 1]).  A face towards a covered cell takes the mean of the four
+// fine fluxes through it (flux matching).  Bricks with no covered cell and no
+// covered face neighbour (every brick of the finest level) take the plain
+// 7-point stencil on the tile, corrected on brick faces whose halo is a
+// boundary or coarse-fine ghost.  Two wavefronts per brick, one barrier.
+constexpr int RT = 128;
+
+// a u_c + bv - bv_halo for a ghost a u_c + bv whose halo slot holds bv_halo
+// (bv = bv_halo - u_in / 5 on a coarse-fine face)
+__device__ __forceinline__ double ghost_shift(double a, double uc, double uin)
+{
+    return a * uc - (a > 0.0 ? 0.2 * uin : 0.0);
+}
+
 template <class T, bool ZERO>
-__global__ void __launch_bounds__(256) k_outer_residual(DevMeta M, int b0, int nb, const double *phib,
-                                                        const double *rhob, double inv_eps0, const double *cp_phi,
-                                                        T *r_out, double *part, int norm_p, const int32_t *list,
-                                                        double *const *r_user)
+__global__ void __launch_bounds__(RT) k_outer_residual(DevMeta M, int b0, int nb, const double *phib,
+                                                       const double *rhob, double inv_eps0, const double *cp_phi,
+                                                       T *r_out, double *part, int norm_p, const int32_t *list,
+                                                       double *const *r_user)
 {
     __shared__ double tile[TE * TE * TE];
     __shared__ double alpha[6];
     __shared__ int nbk[6];
     __shared__ uint8_t ncm[6];
+    constexpr int PER = BRICK_CELLS / RT;
     const int b = pick_brick(b0, nb, list, blockIdx.x);
     const LevelConst L = M.lc[M.org[b].w];
     const uint8_t cm = M.cmask[b];
@@ -389,26 +376,32 @@ __global__ void __launch_bounds__(256) k_outer_residual(DevMeta M, int b0, int n
         nbk[threadIdx.x] = f;
         ncm[threadIdx.x] = f >= 0 ? M.cmask[f] : 0;
     }
-    double rv[2];
-    for (int k = 0; k < 2; ++k) rv[k] = rhob[(size_t)b * BRICK_CELLS + threadIdx.x + 256 * k] * inv_eps0;
-    stage_tile<SrcB<double>, ZERO, CpArr<double>>(M, b, SrcB<double>{phib}, CpArr<double>{ZERO ? nullptr : cp_phi},
-                                                  true, tile, alpha);
-    finish_ghosts(tile, alpha);
+    double rv[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) rv[k] = rhob[(size_t)b * BRICK_CELLS + threadIdx.x + RT * k] * inv_eps0;
+    stage_tile<SrcB<double>, ZERO, CpArr<double>, RT>(M, b, SrcB<double>{phib},
+                                                      CpArr<double>{ZERO ? nullptr : cp_phi}, true, tile, alpha);
     bool any_cov = cm != 0;
     for (int f = 0; f < 6; ++f) any_cov = any_cov || ncm[f] != 0;  // uniform over the workgroup
-    __syncthreads();
     double acc = 0.0;
-    for (int k = 0; k < 2; ++k) {
-        int c = threadIdx.x + 256 * k;
-        int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int c = threadIdx.x + RT * k;
+        const int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
         double r = 0.0;
         if (!((cm >> oct_of(x, y, z)) & 1)) {
-            double uc = tile[tix(x, y, z)];
+            const double uc = tile[tix(x, y, z)];
             double Au = 0.0;
             if (!any_cov) {
                 Au = L.ih2[0] * (2.0 * uc - tile[tix(x - 1, y, z)] - tile[tix(x + 1, y, z)]) +
                      L.ih2[1] * (2.0 * uc - tile[tix(x, y - 1, z)] - tile[tix(x, y + 1, z)]) +
                      L.ih2[2] * (2.0 * uc - tile[tix(x, y, z - 1)] - tile[tix(x, y, z + 1)]);
+                if (x == 0) Au -= L.ih2[0] * ghost_shift(alpha[0], uc, tile[tix(1, y, z)]);
+                if (x == 7) Au -= L.ih2[0] * ghost_shift(alpha[1], uc, tile[tix(6, y, z)]);
+                if (y == 0) Au -= L.ih2[1] * ghost_shift(alpha[2], uc, tile[tix(x, 1, z)]);
+                if (y == 7) Au -= L.ih2[1] * ghost_shift(alpha[3], uc, tile[tix(x, 6, z)]);
+                if (z == 0) Au -= L.ih2[2] * ghost_shift(alpha[4], uc, tile[tix(x, y, 1)]);
+                if (z == 7) Au -= L.ih2[2] * ghost_shift(alpha[5], uc, tile[tix(x, y, 6)]);
             } else {
 #pragma unroll
                 for (int f = 0; f < 6; ++f) {
@@ -417,7 +410,9 @@ __global__ void __launch_bounds__(256) k_outer_residual(DevMeta M, int b0, int n
                     bool inside = ((qx | qy | qz) & ~7) == 0;
                     bool cov = ((inside ? cm : ncm[f]) >> oct_of(qx & 7, qy & 7, qz & 7)) & 1;
                     if (!cov) {
-                        Au += L.ih2[d] * (uc - tile[tix(qx, qy, qz)]);
+                        double a, bv;
+                        tile_ab(tile, alpha, x, y, z, d, s, a, bv);
+                        Au += L.ih2[d] * ((1.0 - a) * uc - bv);
                     } else if (!ZERO) {
                         int nl[3] = {qx & 7, qy & 7, qz & 7};
                         Au += -0.5 * L.ih2[d] *
@@ -435,8 +430,11 @@ __global__ void __launch_bounds__(256) k_outer_residual(DevMeta M, int b0, int n
         double av = fabs(r);
         acc = norm_p == 2 ? acc + av * av : norm_p == 1 ? acc + av : fmax(acc, av);
     }
-    acc = block_reduce(acc, norm_p == 0);
-    if (threadIdx.x == 0) part[b] = acc;
+    for (int o = 32; o > 0; o >>= 1) {
+        double w = __shfl_xor(acc, o, 64);
+        acc = norm_p == 0 ? fmax(acc, w) : acc + w;
+    }
+    if ((threadIdx.x & 63) == 0) part[2 * (size_t)b + (threadIdx.x >> 6)] = acc;
 }
 
 // Copies between the caller's box-list layout and brick layout on a range or
@@ -461,13 +459,13 @@ __global__ void __launch_bounds__(256) k_user_brick(DevMeta M, int b0, int nb, c
 }
 
 // norm of each listed brick range (one AMR level of one problem) from the
-// per-brick partials, in a fixed order
+// partials (two per brick), in a fixed order
 __global__ void __launch_bounds__(1024) k_level_norms(const int2 *ranges, int n, const double *part, double *out,
                                                       int norm_p)
 {
     int l = blockIdx.x;
     if (l >= n) return;
-    const int b0 = ranges[l].x, b1 = ranges[l].x + ranges[l].y;
+    const int b0 = 2 * ranges[l].x, b1 = 2 * (ranges[l].x + ranges[l].y);
     const bool mx = norm_p == 0;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int b = b0 + (int)threadIdx.x;
@@ -707,39 +705,40 @@ __device__ __forceinline__ double cell_residual(const DevMeta &M, const LevelCon
 
 // r^{l-1} on covered cells = mean over the 8 children of (r^l - A_nf e^l)
 // (Alg. 3, restriction onto the covered domain; e^{l-1} = 0 at that point).
-// One fine brick per workgroup: residuals in LDS, then 64 coarse cells.
+// One fine brick per workgroup of 128 threads: two threads per coarse cell,
+// each with the four children of one z layer, combined by a shuffle.
 template <class T>
-__global__ void __launch_bounds__(256) k_restrict(DevMeta M, int b0, int nb, const T *e, const T *r, T *rc)
+__global__ void __launch_bounds__(RT) k_restrict(DevMeta M, int b0, int nb, const T *e, const T *r, T *rc)
 {
     __shared__ double tile[TE * TE * TE];
     __shared__ double alpha[6];
-    __shared__ double res[BRICK_CELLS];
     int b = b0 + xcd_remap(blockIdx.x, nb);
-    int lev = M.org[b].w;
-    LevelConst L = M.lc[lev];
-    double rv[2];
-    for (int k = 0; k < 2; ++k) rv[k] = (double)r[(size_t)b * BRICK_CELLS + threadIdx.x + 256 * k];
-    stage_tile<SrcB<T>>(M, b, SrcB<T>{e}, CpNone{}, false, tile, alpha);
-    for (int k = 0; k < 2; ++k) {
-        int c = threadIdx.x + 256 * k;
-        int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+    LevelConst L = M.lc[M.org[b].w];
+    const int cc = threadIdx.x >> 1, h = threadIdx.x & 1;
+    const int cx = cc & 3, cy = (cc >> 2) & 3, cz = cc >> 4;
+    const int z = 2 * cz + h;
+    double rv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        rv[q] = (double)r[(size_t)b * BRICK_CELLS + (2 * cx + (q & 1)) + 8 * (2 * cy + (q >> 1)) + 64 * z];
+    stage_tile<SrcB<T>, false, CpNone, RT>(M, b, SrcB<T>{e}, CpNone{}, false, tile, alpha);
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int x = 2 * cx + (q & 1), y = 2 * cy + (q >> 1);
         double uc = tile[tix(x, y, z)], Au = 0.0;
+#pragma unroll
         for (int d = 0; d < 3; ++d)
+#pragma unroll
             for (int s = -1; s <= 1; s += 2) {
                 double a, bv;
                 tile_ab(tile, alpha, x, y, z, d, s, a, bv);
                 Au += L.ih2[d] * ((1.0 - a) * uc - bv);
             }
-        res[c] = rv[k] - Au;
+        sum += rv[q] - Au;
     }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        int t = threadIdx.x;
-        int cx = t & 3, cy = (t >> 2) & 3, cz = t >> 4;
-        double sum = 0.0;
-        for (int dz = 0; dz < 2; ++dz)
-            for (int dy = 0; dy < 2; ++dy)
-                for (int dx = 0; dx < 2; ++dx) sum += res[(2 * cx + dx) + 8 * (2 * cy + dy) + 64 * (2 * cz + dz)];
+    sum += __shfl_xor(sum, 1, 64);
+    if (h == 0) {
         int par = M.par[b];
         int pb = par >> 3, oc = par & 7;
         int X = (oc & 1) * 4 + cx, Y = ((oc >> 1) & 1) * 4 + cy, Z = (oc >> 2) * 4 + cz;
@@ -1048,92 +1047,138 @@ __device__ int cg_solve_lds(const DevMeta &M, int b0, int nb, const T *rhs, T *e
     return it;
 }
 
-// Exact solve of the coarsest grid (one box of n = dn cells, homogeneous
-// Dirichlet ghosts) by its separable eigendecomposition: forward transforms
-// along x, y, z, division by the eigenvalue sum, inverse transforms along z,
-// y, x.  The grid lives in LDS (u, natural order x fastest); each transform
-// pass gives a thread up to four (line, group of four outputs) items, held in
-// registers until every thread has read its line.  FP64 arithmetic.
-template <class T>
-__device__ void direct_solve(const CoarseJob &J, const double *gtab, const T *rhs, T *e, double *u)
+// ---------------------------------------------------------------------------
+// Exact solve of the coarsest grid (one box, homogeneous Dirichlet ghosts) by
+// its separable eigendecomposition: e = Q diag(1/lambda) Q^T r with Q the
+// tensor product of the per-axis orthonormal eigenvector matrices.  Three
+// launches over all jobs: forward transforms along x and y per z plane; along
+// z per group of columns (forward, division by the eigenvalue sum, inverse);
+// inverse along x and y per plane.  FP64 arithmetic, FP64 scratch in natural
+// order (x fastest).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ size_t direct_cell(const DirectJob &J, int x, int y, int z)
 {
-    const int nx = J.dn[0], ny = J.dn[1], nz = J.dn[2];
-    const int n = nx * ny * nz;
-    const int nbx = nx >> 3, nby = ny >> 3;
-    const int b0 = J.b0[0];
-    auto brick_index = [&](int idx) {
-        int i = idx % nx, jk = idx / nx, j = jk % ny, k = jk / ny;
-        int b = b0 + (i >> 3) + nbx * ((j >> 3) + nby * (k >> 3));
-        return (size_t)b * BRICK_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7);
-    };
-    // the grid, then the transform tables, in LDS (one round of loads)
-    double *tab = u + n;
-    const int ntab = 2 * (nx * nx + ny * ny + nz * nz) + nx + ny + nz;
-    for (int idx = threadIdx.x; idx < n; idx += (int)blockDim.x) u[idx] = (double)rhs[brick_index(idx)];
-    for (int i = threadIdx.x; i < ntab; i += (int)blockDim.x) tab[i] = gtab[i];
-    __syncthreads();
-    const double *mat[3][2];
-    size_t off = 0;
-    for (int d = 0; d < 3; ++d) {
-        const int N = J.dn[d];
-        mat[d][0] = tab + off;
-        mat[d][1] = tab + off + (size_t)N * N;
-        off += 2 * (size_t)N * N;
+    const int nbx = J.dn[0] >> 3, nby = J.dn[1] >> 3;
+    int b = J.b0 + (x >> 3) + nbx * ((y >> 3) + nby * (z >> 3));
+    return (size_t)b * BRICK_CELLS + (x & 7) + 8 * (y & 7) + 64 * (z & 7);
+}
+
+__device__ __forceinline__ int pad16(int n) { return (n + 15) & ~15; }
+
+// copy an n x n table (row-major) into LDS with row stride ld, zero up to
+// the padded size pad16(n)
+__device__ __forceinline__ void stage_table(double *dst, int ld, const double *src, int n)
+{
+    const int p = pad16(n);
+    for (int t = threadIdx.x; t < p * p; t += blockDim.x) {
+        const int a = t / p, b = t - a * p;
+        dst[a * ld + b] = (a < n && b < n) ? src[a * n + b] : 0.0;
     }
-    const double *mu[3] = {tab + off, tab + off + nx, tab + off + nx + ny};
-#pragma unroll
-    for (int pass = 0; pass < 6; ++pass) {
-        const int d = pass < 3 ? pass : 5 - pass;
-        const double *A = mat[d][pass < 3 ? 0 : 1];
-        const int N = J.dn[d];
-        const int stride = d == 0 ? 1 : (d == 1 ? nx : nx * ny);
-        const int groups = N >> 2, items = (n / N) * groups;
-        double out[4][4];
-        int obase[4];
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            int it = threadIdx.x + (int)blockDim.x * w;
-            obase[w] = -1;
-            if (it >= items) continue;
-            int line = it / groups, g = it - line * groups;
-            int base;
-            if (d == 0) base = line * nx;
-            else if (d == 1) base = (line % nx) + nx * ny * (line / nx);
-            else base = line;
-            obase[w] = base + 4 * g * stride;
-            const double *a = A + (size_t)(4 * g) * N;
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            for (int i = 0; i < N; ++i) {
-                double v = u[base + i * stride];
-                s0 += a[i] * v;
-                s1 += a[N + i] * v;
-                s2 += a[2 * N + i] * v;
-                s3 += a[3 * N + i] * v;
-            }
-            out[w][0] = s0;
-            out[w][1] = s1;
-            out[w][2] = s2;
-            out[w][3] = s3;
+}
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// C[r][k] = sum_i A[r][i] M[k][i] for r < R, k < N (both multiples of 16, N at
+// most 64), i < K (multiple of 4); A and M in LDS with row stride ld.  On the
+// FP64 matrix cores: a wavefront takes a pair of 16 x 16 output tiles of one
+// 16-row strip and keeps both in flight; v_mfma_f64 16x16x4 takes A[r0 +
+// l%16][i0 + l/16] and M[k0 + l%16][i0 + l/16] from lane l and returns C[r0 +
+// l/16 + 4j][k0 + l%16] in element j.  out(r, k, v) is called for every
+// output.
+template <class F>
+__device__ __forceinline__ void mfma_nt(const double *A, const double *M, int ld, int R, int N, int K, F out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int tn = N >> 4, pairs = (tn + 1) >> 1, units = (R >> 4) * pairs;
+    for (int u = wave; u < units; u += nw) {
+        const int r0 = (u / pairs) << 4, t0 = 2 * (u % pairs);
+        const bool two = t0 + 1 < tn;
+        dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        const double *a = A + (r0 + lr) * ld + lk, *m0 = M + (16 * t0 + lr) * ld + lk, *m1 = m0 + 16 * ld;
+        for (int i0 = 0; i0 < K; i0 += 4) {
+            const double av = a[i0];
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, m0[i0], acc0, 0, 0, 0);
+            if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, m1[i0], acc1, 0, 0, 0);
         }
-        __syncthreads();
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            if (obase[w] < 0) continue;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                int idx = obase[w] + q * stride;
-                double v = out[w][q];
-                if (pass == 2) {  // all three forward transforms done: divide by the eigenvalue
-                    int i = idx % nx, jk = idx / nx, j = jk % ny, k = jk / ny;
-                    v /= mu[0][i] + mu[1][j] + mu[2][k];
-                }
-                u[idx] = v;
-            }
+        for (int j = 0; j < 4; ++j) {
+            out(r0 + lk + 4 * j, 16 * t0 + lr, acc0[j]);
+            if (two) out(r0 + lk + 4 * j, 16 * t0 + 16 + lr, acc1[j]);
         }
-        __syncthreads();
     }
-    for (int idx = threadIdx.x; idx < n; idx += (int)blockDim.x) e[brick_index(idx)] = (T)u[idx];
+}
+
+// transforms along x and y of one z plane; forward (r -> W) or inverse
+// (W -> e, phi += e).  Dynamic LDS: four ld x ld arrays, ld = padded
+// largest edge + 1.
+template <class T, bool INV>
+__global__ void __launch_bounds__(512) k_dst_plane(const DirectJob *jobs, const int2 *planes, const double *tab,
+                                                   double *W, const T *r, T *e, double *phib, int phi_update, int ld)
+{
+    extern __shared__ double sm[];
+    double *A = sm, *Bt = A + ld * ld, *Mx = Bt + ld * ld, *My = Mx + ld * ld;  // plane [y][x], [kx][y], tables
+    const int2 pl = planes[blockIdx.x];
+    const DirectJob J = jobs[pl.x];
+    const int nx = J.dn[0], ny = J.dn[1], z = pl.y, np = nx * ny;
+    const int px = pad16(nx), py = pad16(ny);
+    const double *tx = tab + J.tab, *ty = tx + 2 * nx * nx;
+    double *w = W + J.w + (size_t)np * z;
+    stage_table(Mx, ld, INV ? tx + nx * nx : tx, nx);
+    stage_table(My, ld, INV ? ty + ny * ny : ty, ny);
+    for (int i = threadIdx.x; i < px * py; i += blockDim.x) {
+        const int y = i / px, x = i - y * px;
+        double v = 0.0;
+        if (x < nx && y < ny) v = INV ? w[y * nx + x] : (double)r[direct_cell(J, x, y, z)];
+        A[y * ld + x] = v;
+    }
     __syncthreads();
+    // along x: out[y][kx] = sum_x A[y][x] Mx[kx][x], stored as Bt[kx][y]
+    mfma_nt(A, Mx, ld, py, px, px, [&](int y, int kx, double v) { Bt[kx * ld + y] = v; });
+    __syncthreads();
+    // along y: out[kx][ky] = sum_y Bt[kx][y] My[ky][y]
+    mfma_nt(Bt, My, ld, px, py, py, [&](int x, int y, double v) {
+        if (x >= nx || y >= ny) return;
+        if (!INV) {
+            w[y * nx + x] = v;
+        } else {
+            size_t bi = direct_cell(J, x, y, z);
+            e[bi] = (T)v;
+            if (phi_update && J.amr) phib[bi] += v;
+        }
+    });
+}
+
+// transform along z of a group of DIRECT_COLS columns: forward, division by
+// the eigenvalue sum, inverse.  Dynamic LDS: two DIRECT_COLS x ld arrays and
+// two ld x ld tables.
+__global__ void __launch_bounds__(512) k_dst_column(const DirectJob *jobs, const int2 *groups, const double *tab,
+                                                    double *W, int ld)
+{
+    extern __shared__ double sm[];
+    double *A = sm, *C = A + DIRECT_COLS * ld, *Fz = C + DIRECT_COLS * ld, *Bz = Fz + ld * ld;  // [col][z], [col][kz]
+    const int2 gr = groups[blockIdx.x];
+    const DirectJob J = jobs[gr.x];
+    const int nx = J.dn[0], ny = J.dn[1], nz = J.dn[2], np = nx * ny, pz = pad16(nz);
+    const int c0 = gr.y;  // np is a multiple of DIRECT_COLS
+    const double *tz = tab + J.tab + 2 * (nx * nx + ny * ny);
+    const double *mux = tz + 2 * nz * nz, *muy = mux + nx, *muz = muy + ny;
+    double *w = W + J.w;
+    stage_table(Fz, ld, tz, nz);
+    stage_table(Bz, ld, tz + nz * nz, nz);
+    for (int i = threadIdx.x; i < pz * DIRECT_COLS; i += blockDim.x) {
+        const int zz = i / DIRECT_COLS, c = i % DIRECT_COLS;
+        A[c * ld + zz] = zz < nz ? w[(size_t)np * zz + c0 + c] : 0.0;
+    }
+    __syncthreads();
+    mfma_nt(A, Fz, ld, DIRECT_COLS, pz, pz, [&](int c, int kz, double v) {
+        const int idx = c0 + c;
+        C[c * ld + kz] = kz < nz ? v / (mux[idx % nx] + muy[idx / nx] + muz[kz]) : 0.0;
+    });
+    __syncthreads();
+    mfma_nt(C, Bz, ld, DIRECT_COLS, pz, pz, [&](int c, int zz, double v) {
+        if (zz < nz) w[(size_t)np * zz + c0 + c] = v;
+    });
 }
 
 // one workgroup per job: jobs[i] = (first brick, bricks, offset of its four
@@ -1176,11 +1221,12 @@ __device__ void wg_gs_pass(const DevMeta &M, int b0, int nb, T *e, const T *r, i
 // AMR levels when phi_update is set.
 template <class T>
 __global__ void __launch_bounds__(1024) k_coarse_cycle(DevMeta M, const CoarseJob *jobs, T *e, T *r, double *work,
-                                                       const double *dtab, int nu1, int nu2, double rtol, int maxit,
-                                                       int *iters, double *phib, int phi_update)
+                                                       int nu1, int nu2, double rtol, int maxit, int *iters,
+                                                       double *phib, int phi_update)
 {
-    __shared__ double lds[DIRECT_LDS];
+    __shared__ double lds[CG_LDS_MAX];
     const CoarseJob J = jobs[blockIdx.x];
+    if (J.direct) return;  // solved by the transform kernels
     for (int k = J.nlev - 1; k >= 1; --k) {
         const int b0 = J.b0[k], nb = J.nb[k];
         for (int i = threadIdx.x; i < nb * BRICK_CELLS; i += (int)blockDim.x) e[(size_t)b0 * BRICK_CELLS + i] = (T)0;
@@ -1207,10 +1253,8 @@ __global__ void __launch_bounds__(1024) k_coarse_cycle(DevMeta M, const CoarseJo
         }
         __syncthreads();
     }
-    int it = 1;
-    if (J.dtab >= 0)
-        direct_solve<T>(J, dtab + J.dtab, r, e, lds);
-    else if (J.nb[0] * BRICK_CELLS <= CG_PER * (int)blockDim.x && J.nb[0] * BRICK_CELLS <= CG_LDS_MAX)
+    int it;
+    if (J.nb[0] * BRICK_CELLS <= CG_PER * (int)blockDim.x && J.nb[0] * BRICK_CELLS <= CG_LDS_MAX)
         it = cg_solve_lds<T>(M, J.b0[0], J.nb[0], r, e, rtol, maxit, lds);
     else
         it = cg_solve<T>(M, J.b0[0], J.nb[0], r, e, work + J.cg_off, rtol, maxit);
@@ -1534,10 +1578,10 @@ void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, con
 {
     if (nb <= 0) return;
     if (zero_phi)
-        AMRMG_LAUNCH((k_outer_residual<T, true>), dim3(nb), dim3(256), 0, st, M, b0, nb, phib, rhob, inv_eps0,
+        AMRMG_LAUNCH((k_outer_residual<T, true>), dim3(nb), dim3(RT), 0, st, M, b0, nb, phib, rhob, inv_eps0,
                      cp_phi, r_out, part, norm_p, list, r_user);
     else
-        AMRMG_LAUNCH((k_outer_residual<T, false>), dim3(nb), dim3(256), 0, st, M, b0, nb, phib, rhob, inv_eps0,
+        AMRMG_LAUNCH((k_outer_residual<T, false>), dim3(nb), dim3(RT), 0, st, M, b0, nb, phib, rhob, inv_eps0,
                      cp_phi, r_out, part, norm_p, list, r_user);
 }
 
@@ -1583,7 +1627,7 @@ template <class T>
 void launch_restrict(hipStream_t st, const DevMeta &M, int b0, int nb, const T *e, const T *r, T *rc)
 {
     if (nb <= 0) return;
-    AMRMG_LAUNCH((k_restrict<T>), dim3(nb), dim3(256), 0, st, M, b0, nb, e, r, rc);
+    AMRMG_LAUNCH((k_restrict<T>), dim3(nb), dim3(RT), 0, st, M, b0, nb, e, r, rc);
 }
 
 template <class T>
@@ -1701,13 +1745,36 @@ void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, 
 
 template <class T>
 void launch_coarse_cycle(hipStream_t st, const DevMeta &M, const CoarseJob *jobs, int njobs, T *e, T *r,
-                         double *work, const double *dtab, int nu1, int nu2, double rtol, int maxit, int *iters,
-                         double *phib, bool phi_update, int threads_hint)
+                         double *work, int nu1, int nu2, double rtol, int maxit, int *iters, double *phib,
+                         bool phi_update, int threads_hint)
 {
     if (njobs <= 0) return;
     int threads = threads_hint > 0 ? threads_hint : 1024;
-    AMRMG_LAUNCH((k_coarse_cycle<T>), dim3(njobs), dim3(threads), 0, st, M, jobs, e, r, work, dtab, nu1, nu2, rtol,
-                 maxit, iters, phib, (int)phi_update);
+    AMRMG_LAUNCH((k_coarse_cycle<T>), dim3(njobs), dim3(threads), 0, st, M, jobs, e, r, work, nu1, nu2, rtol, maxit,
+                 iters, phib, (int)phi_update);
+}
+
+template <class T>
+void launch_direct(hipStream_t st, const DirectJob *jobs, const int2 *planes, int nplanes, const int2 *groups,
+                   int ngroups, const double *tab, double *W, const T *r, T *e, double *phib, bool phi_update,
+                   int maxdim)
+{
+    if (nplanes <= 0) return;
+    const int ld = ((maxdim + 15) & ~15) + 1;
+    const size_t sp = sizeof(double) * 4 * ld * ld, sc = sizeof(double) * (2 * DIRECT_COLS * ld + 2 * ld * ld);
+    static bool attr = false;  // allow more than 64 KiB of dynamic LDS (up to 4 x 65^2 doubles)
+    if (!attr) {
+        const int lim = (int)(sizeof(double) * 4 * 65 * 65);
+        (void)hipFuncSetAttribute((const void *)k_dst_plane<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void *)k_dst_plane<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void *)k_dst_column, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        attr = true;
+    }
+    AMRMG_LAUNCH((k_dst_plane<T, false>), dim3(nplanes), dim3(512), sp, st, jobs, planes, tab, W, r, e, phib,
+                 (int)phi_update, ld);
+    AMRMG_LAUNCH(k_dst_column, dim3(ngroups), dim3(512), sc, st, jobs, groups, tab, W, ld);
+    AMRMG_LAUNCH((k_dst_plane<T, true>), dim3(nplanes), dim3(512), sp, st, jobs, planes, tab, W, r, e, phib,
+                 (int)phi_update, ld);
 }
 
 template <class T>
@@ -1763,8 +1830,9 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val)
     template void launch_hgs<T>(hipStream_t, const DevMeta &, int, int, const T *, T *, const T *, T *,         \
                                 double *, int);                                                                 \
     template void launch_coarse_cycle<T>(hipStream_t, const DevMeta &, const CoarseJob *, int, T *, T *,        \
-                                         double *, const double *, int, int, double, int, int *, double *, bool, \
-                                         int);
+                                         double *, int, int, double, int, int *, double *, bool, int);          \
+    template void launch_direct<T>(hipStream_t, const DirectJob *, const int2 *, int, const int2 *, int,         \
+                                   const double *, double *, const T *, T *, double *, bool, int);
 AMRMG_INST(float)
 AMRMG_INST(double)
 #undef AMRMG_INST

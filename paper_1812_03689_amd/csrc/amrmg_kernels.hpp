@@ -37,13 +37,22 @@ struct CoarseJob {
     int b0[8];
     int nb[8];
     int cg_off;
-    int dn[3];  // cells per axis of the coarsest grid (one box)
-    int dtab;   // offset of its direct-solve tables (direct_tables) or -1: CG
+    int direct;  // 1: the coarsest grid is solved by the transform kernels instead
 };
-// a coarsest grid of n cells with transform tables of t doubles is solved
-// directly when n + t fits this many doubles of LDS (24^3 does; the CG LDS
-// variant uses the first CG_LDS_MAX of them)
-constexpr int DIRECT_LDS = 19456;
+
+// coarsest grid solved directly by its separable eigendecomposition: one box
+// of dn cells (each at most DIRECT_DIM), bricks x-fastest from b0
+struct DirectJob {
+    int b0;
+    int dn[3];
+    int tab;  // offset of its tables (direct_tables layout) in the table pool
+    int w;    // offset of its FP64 scratch (n doubles, x fastest)
+    int amr;  // 1 when the grid is an AMR level (phi += e after the solve)
+    int pad;
+};
+constexpr int DIRECT_DIM = 64;
+// columns per workgroup of the transform along z
+constexpr int DIRECT_COLS = 64;
 
 hipError_t upload_cf_weights(const double *w);
 // window masks of patterns 0..12 and (u0, v0, nodes) of patterns 0..13
@@ -96,10 +105,17 @@ void launch_copy(hipStream_t st, const T *a, T *b, int64_t n);
 template <class T>
 void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
                 double *phib, int mode);
+// direct solve e = A^-1 r of the coarsest grids of the listed jobs: planes
+// (job, z) for the x/y transforms, column groups (job, first column) for the
+// z transform; FP64 scratch W; phi += e on AMR grids when phi_update
+template <class T>
+void launch_direct(hipStream_t st, const DirectJob *jobs, const int2 *planes, int nplanes, const int2 *groups,
+                   int ngroups, const double *tab, double *W, const T *r, T *e, double *phib, bool phi_update,
+                   int maxdim);
 template <class T>
 void launch_coarse_cycle(hipStream_t st, const DevMeta &M, const CoarseJob *jobs, int njobs, T *e, T *r,
-                         double *work, const double *dtab, int nu1, int nu2, double rtol, int maxit, int *iters,
-                         double *phib, bool phi_update, int threads_hint);
+                         double *work, int nu1, int nu2, double rtol, int maxit, int *iters, double *phib,
+                         bool phi_update, int threads_hint);
 void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                     const double *q, const uint32_t *perm, const DepArgs &A, const int64_t *ubase, const int2 *ustr,
                     unsigned long long *nout);

@@ -170,11 +170,10 @@ def test_other_smoothers_converge_to_same(smoother, nu):
                                        ((8, 8, 8), [(1, 0, 0, 0, 8, 8, 8), (2, 0, 0, 0, 8, 8, 8)]),
                                        ((32, 32, 24), [(1, 8, 8, 8, 40, 40, 32)])])
 def test_small_and_ragged_hierarchies(n0, levels):
-    """Single level; a base without multigrid levels below it (24^3, 13824
-    cells solved directly); unequal edges (anisotropic spacing); a corner box
-    touching the boundary on two refined levels over an 8^3 base; a coarsest
-    grid above the direct-solve limit (32 x 32 x 24, CG).  Each with the
-    automatic bottom solver and with CG forced."""
+    """Single level; bases solved directly without multigrid levels below them
+    (24^3, 32 x 32 x 24); unequal edges (anisotropic spacing); a corner box
+    touching the boundary on two refined levels over an 8^3 base.  Each with
+    the automatic bottom solver (direct) and with CG forced."""
     print("case", n0, levels, flush=True)
     p = W.gaussian_bunch(20000, centre=(0.45, 0.5, 0.55), sigma=(0.12, 0.1, 0.15), seed=77)
     w = W.Workload("edge", p, n0, len(set(b[0] for b in levels)), [], [(1.0, 0.3, 0.6, 0.5)], 1e-10,
