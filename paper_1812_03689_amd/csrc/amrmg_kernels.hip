@@ -1078,34 +1078,25 @@ __device__ __forceinline__ void stage_table(double *dst, int ld, const double *s
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// C[r][k] = sum_i A[r][i] M[k][i] for r < R, k < N (both multiples of 16, N at
-// most 64), i < K (multiple of 4); A and M in LDS with row stride ld.  On the
-// FP64 matrix cores: a wavefront takes a pair of 16 x 16 output tiles of one
-// 16-row strip and keeps both in flight; v_mfma_f64 16x16x4 takes A[r0 +
-// l%16][i0 + l/16] and M[k0 + l%16][i0 + l/16] from lane l and returns C[r0 +
-// l/16 + 4j][k0 + l%16] in element j.  out(r, k, v) is called for every
-// output.
+// C[r][k] = sum_i A[r][i] M[k][i] for r < R, k < N (both multiples of 16),
+// i < K (multiple of 4); A and M in LDS with row stride ld.  On the FP64
+// matrix cores, one 16 x 16 output tile per wavefront at a time:
+// v_mfma_f64 16x16x4 takes A[r0 + l%16][i0 + l/16] and M[k0 + l%16][i0 + l/16]
+// from lane l and returns C[r0 + l/16 + 4j][k0 + l%16] in element j.
+// out(r, k, v) is called for every output.
 template <class F>
 __device__ __forceinline__ void mfma_nt(const double *A, const double *M, int ld, int R, int N, int K, F out)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int tn = N >> 4, pairs = (tn + 1) >> 1, units = (R >> 4) * pairs;
-    for (int u = wave; u < units; u += nw) {
-        const int r0 = (u / pairs) << 4, t0 = 2 * (u % pairs);
-        const bool two = t0 + 1 < tn;
-        dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-        const double *a = A + (r0 + lr) * ld + lk, *m0 = M + (16 * t0 + lr) * ld + lk, *m1 = m0 + 16 * ld;
-        for (int i0 = 0; i0 < K; i0 += 4) {
-            const double av = a[i0];
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, m0[i0], acc0, 0, 0, 0);
-            if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, m1[i0], acc1, 0, 0, 0);
-        }
+    const int tn = N >> 4, tiles = (R >> 4) * tn;
+    for (int u = wave; u < tiles; u += nw) {
+        const int r0 = (u / tn) << 4, k0 = (u % tn) << 4;
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        const double *a = A + (r0 + lr) * ld + lk, *m = M + (k0 + lr) * ld + lk;
+        for (int i0 = 0; i0 < K; i0 += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i0], m[i0], acc, 0, 0, 0);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            out(r0 + lk + 4 * j, 16 * t0 + lr, acc0[j]);
-            if (two) out(r0 + lk + 4 * j, 16 * t0 + 16 + lr, acc1[j]);
-        }
+        for (int j = 0; j < 4; ++j) out(r0 + lk + 4 * j, k0 + lr, acc[j]);
     }
 }
 
@@ -1113,7 +1104,7 @@ __device__ __forceinline__ void mfma_nt(const double *A, const double *M, int ld
 // (W -> e, phi += e).  Dynamic LDS: four ld x ld arrays, ld = padded
 // largest edge + 1.
 template <class T, bool INV>
-__global__ void __launch_bounds__(512) k_dst_plane(const DirectJob *jobs, const int2 *planes, const double *tab,
+__global__ void __launch_bounds__(1024) k_dst_plane(const DirectJob *jobs, const int2 *planes, const double *tab,
                                                    double *W, const T *r, T *e, double *phib, int phi_update, int ld)
 {
     extern __shared__ double sm[];
@@ -1152,7 +1143,7 @@ __global__ void __launch_bounds__(512) k_dst_plane(const DirectJob *jobs, const 
 // transform along z of a group of DIRECT_COLS columns: forward, division by
 // the eigenvalue sum, inverse.  Dynamic LDS: two DIRECT_COLS x ld arrays and
 // two ld x ld tables.
-__global__ void __launch_bounds__(512) k_dst_column(const DirectJob *jobs, const int2 *groups, const double *tab,
+__global__ void __launch_bounds__(1024) k_dst_column(const DirectJob *jobs, const int2 *groups, const double *tab,
                                                     double *W, int ld)
 {
     extern __shared__ double sm[];
@@ -1770,10 +1761,10 @@ void launch_direct(hipStream_t st, const DirectJob *jobs, const int2 *planes, in
         (void)hipFuncSetAttribute((const void *)k_dst_column, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         attr = true;
     }
-    AMRMG_LAUNCH((k_dst_plane<T, false>), dim3(nplanes), dim3(512), sp, st, jobs, planes, tab, W, r, e, phib,
+    AMRMG_LAUNCH((k_dst_plane<T, false>), dim3(nplanes), dim3(1024), sp, st, jobs, planes, tab, W, r, e, phib,
                  (int)phi_update, ld);
-    AMRMG_LAUNCH(k_dst_column, dim3(ngroups), dim3(512), sc, st, jobs, groups, tab, W, ld);
-    AMRMG_LAUNCH((k_dst_plane<T, true>), dim3(nplanes), dim3(512), sp, st, jobs, planes, tab, W, r, e, phib,
+    AMRMG_LAUNCH(k_dst_column, dim3(ngroups), dim3(1024), sc, st, jobs, groups, tab, W, ld);
+    AMRMG_LAUNCH((k_dst_plane<T, true>), dim3(nplanes), dim3(1024), sp, st, jobs, planes, tab, W, r, e, phib,
                  (int)phi_update, ld);
 }
 
