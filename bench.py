@@ -26,6 +26,84 @@ sys.path.insert(0, ROOT)
 
 METRIC = "composite AMR-MG solve DOF/s to 1e-8 rel residual, mixed vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1812_03689_amd", "csrc", "amrmg_kernels.hip")
+# kernel names (FP32 cycle) of each timed kernel class, as rocprofv3 lists them
+CLASS_KERNELS = {"gsrb": r"k_hgs<float|k_gsrb<float|k_jacobi<float", "restrict": r"k_restrict<float",
+                 "residual": r"k_outer_residual<float, false", "reflux": r"k_reflux<float",
+                 "bottom": r"k_dst_|k_coarse_cycle<float", "deposit": r"k_deposit<", "gather": r"k_gather<"}
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_file(kclass, workload_tag):
+    return os.path.join(ROOT, "profiles", f"traffic_{kclass}_{workload_tag}.md")
+
+
+def read_traffic(kclass, workload_tag):
+    """HBM bytes per launch measured with hardware counters for this kernel
+    class and workload, or None when absent or taken on other kernel code."""
+    path = traffic_file(kclass, workload_tag)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel source sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def write_traffic(args):
+    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, WRITE_SIZE,
+    each with --calib-copy-mb) into the traffic figure of a kernel class."""
+    import csv
+    import re
+    kclass, tag, fetch_csv, write_csv, out_md = args.write_traffic
+    pat = re.compile(CLASS_KERNELS[kclass])
+
+    def load(path, counter):
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            d = int(r["Dispatch_Id"])
+            name, v = r["Kernel_Name"], float(r["Counter_Value"])
+            per.setdefault(d, [name, 0.0])[1] += v
+        ks = [v for n, v in per.values() if pat.search(n)]
+        copies = [v for n, v in per.values() if "copyBuffer" in n]
+        return ks, copies
+
+    fk, fc = load(fetch_csv, "FETCH_SIZE")
+    wk, wc = load(write_csv, "WRITE_SIZE")
+    calib = args.calib_copy_mb << 20
+    f_fetch = calib / (max(fc) * 1024.0)
+    f_write = calib / (max(wc) * 1024.0)
+    fetch = sum(fk) / len(fk) * 1024.0 * f_fetch
+    write = sum(wk) / len(wk) * 1024.0 * f_write
+    with open(out_md, "w") as f:
+        f.write(f"# HBM traffic of `{kclass}` kernels ({CLASS_KERNELS[kclass]}), workload {tag}\n\n")
+        f.write("Two rocprofv3 counter runs of the same bench command (FETCH_SIZE, then WRITE_SIZE, KiB per\n"
+                "dispatch), each scaled by what the counter reads for a plain device copy of a known size in the\n"
+                "same run.  Commands (from the repository root, `cd /tmp && export TMPDIR=/tmp` first):\n\n")
+        f.write("```\n" + args.traffic_cmd.replace(";", "\n") + "\n```\n\n")
+        f.write(f"- dispatches: {len(fk)}\n")
+        f.write(f"- copy size bytes: {calib}\n")
+        f.write(f"- fetch scale: {f_fetch:.4f}\n")
+        f.write(f"- write scale: {f_write:.4f}\n")
+        f.write(f"- fetch bytes per launch: {fetch:.1f}\n")
+        f.write(f"- write bytes per launch: {write:.1f}\n")
+        f.write(f"- traffic bytes per launch: {fetch + write:.1f}\n")
+        f.write(f"- kernel source sha256: `{kernel_source_hash()}`\n")
+    print(open(out_md).read())
 
 
 def workload_for(cfg):
@@ -148,7 +226,15 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB with a plain device copy (reference "
                          "for hardware byte counters)")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only warmup + steps of the workload (for profilers), then the calibration copy")
+    ap.add_argument("--write-traffic", nargs=5, metavar=("CLASS", "TAG", "FETCH_CSV", "WRITE_CSV", "OUT_MD"),
+                    help="write the traffic summary of a kernel class from two rocprofv3 counter CSVs")
+    ap.add_argument("--traffic-cmd", default="", help="the profiling commands, recorded in the summary")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is not built.",
               file=sys.stderr)
@@ -190,6 +276,14 @@ def main():
         st = amrmg.amrmg_solve(cm.h, rho, phi, E, tol)
         amrmg.amrmg_gather(cm.h, x, y, z, E, Ex, Ey, Ez)
         return st
+
+    if args.profile_run:
+        for _ in range(args.warmup + args.steps):
+            step()
+        torch.cuda.synchronize()
+        calib_copy(args, dev)
+        print("profile run done", flush=True)
+        return
 
     # warmup, with every kernel class timed once to find the dominant one
     amrmg.amrmg_profile_enable(cm.h, list(range(len(amrmg.KCLASS))))
@@ -269,8 +363,11 @@ def main():
     gphi = [t.cpu().numpy() for t in phi]
 
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
+    tag = w.name.split(":")[0]
+    tb = read_traffic(dominant, tag)  # measured HBM bytes per launch (hardware counters), or None
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": tb,
+                "traffic_gbs": tb / (dom["ms"] * 1e-3 / max(1, dom["launches"])) / 1e9 if tb else None,
                 "launches": dom["launches"], "avg_launch_us": dom["ms"] * 1e3 / max(1, dom["launches"]),
                 "algorithmic_bytes_per_launch": dom["bytes"] / max(1, dom["launches"])}
 
@@ -326,14 +423,21 @@ def main():
                        f"{est:.1f}s per step"),
             "host": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
     if args.calib_copy_mb:
-        nbytes = args.calib_copy_mb << 20
-        a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        out["calib_copy_bytes"] = nbytes
+        out["calib_copy_bytes"] = calib_copy(args, dev)
     print(json.dumps(out), flush=True)
+
+
+def calib_copy(args, dev):
+    """A plain device copy of --calib-copy-mb MiB (reference for byte counters)."""
+    import torch
+    if not args.calib_copy_mb:
+        return 0
+    nbytes = args.calib_copy_mb << 20
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return nbytes
 
 
 if __name__ == "__main__":

@@ -1061,6 +1061,13 @@ struct Driver {
         }
     }
     int step_b0(int k) const { return m.ent[m.step_ent0[k]].b0; }
+    double step_amr_cells(int k) const
+    {
+        double c = 0.0;
+        for (int ei = m.step_ent0[k]; ei < m.step_ent0[k + 1]; ++ei)
+            if (m.ent[ei].amr >= 0) c += (double)m.ent[ei].nb * BRICK_CELLS;
+        return c;
+    }
     int step_nb(int k) const
     {
         const auto &last = m.ent[m.step_ent0[k + 1] - 1];
@@ -1157,7 +1164,9 @@ struct Driver {
             int mode = (i == 0 ? 2 | 4 : 0) | (i == o.nu2 - 1 ? 8 : 0);
             pb(AMRMG_K_GSRB);
             launch_hgs<T>(st, D.M, b0, nb, src, dst, r, cpe, D.phib, mode);
-            pe(AMRMG_K_GSRB, (3.0 + (i == 0 ? 0.125 : 0.0)) * n * W);
+            // e, r in; e out; the parent value with the fused prolongation;
+            // phi read and written on AMR bricks with the fused update
+            pe(AMRMG_K_GSRB, (3.0 + (i == 0 ? 0.125 : 0.0)) * n * W + ((mode & 8) ? 16.0 * step_amr_cells(k) : 0.0));
             src = dst;
         }
         if (src != e) launch_copy<T>(st, et + (size_t)b0 * BRICK_CELLS, e + (size_t)b0 * BRICK_CELLS, (int64_t)nb * BRICK_CELLS);
