@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1812_03689_amd", "csrc", "amrmg_kernels.hip")
 # kernel names (FP32 cycle) of each timed kernel class, as rocprofv3 lists them
 CLASS_KERNELS = {"gsrb": r"k_hgs<float|k_gsrb<float|k_jacobi<float", "restrict": r"k_restrict<float",
-                 "residual": r"k_outer_residual<float, false", "reflux": r"k_reflux<float",
+                 "residual": r"k_outer_residual<float, false",
                  "bottom": r"k_dst_|k_coarse_cycle<float", "deposit": r"k_deposit<", "gather": r"k_gather<"}
 
 

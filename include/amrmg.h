@@ -218,7 +218,9 @@ amrmg_status amrmg_solve_batch(amrmg_ctx *const *ctxs, int32_t nb, double *const
                                double *const *const *phi, double tol, amrmg_solve_stats *stats);
 
 /* Kernel classes for amrmg_profile_* (per-launch HIP events on the context's
- * stream; algorithmic bytes per launch as defined in the design notes). */
+ * stream; algorithmic bytes per launch as defined in the design notes).  The
+ * coarse-fine residual update runs in the restriction's launch and is timed
+ * as AMRMG_K_RESTRICT; AMRMG_K_REFLUX records nothing. */
 enum {
     AMRMG_K_GSRB = 0, AMRMG_K_JACOBI, AMRMG_K_RESTRICT, AMRMG_K_PROLONG, AMRMG_K_REFLUX, AMRMG_K_CPART,
     AMRMG_K_RESIDUAL, AMRMG_K_PHI_UPDATE, AMRMG_K_BOTTOM, AMRMG_K_EFIELD, AMRMG_K_AVGDOWN, AMRMG_K_DEPOSIT,

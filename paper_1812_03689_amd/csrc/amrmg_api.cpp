@@ -5,10 +5,12 @@
 //
 // Solve structure (per outer iteration, Alg. 2):
 //   1. FP64 composite residual of every AMR level (Alg. 1) -> per-level norms,
-//      read back to the host (the only synchronisation per iteration);
+//      which the norms kernel writes into host memory with a sequence number
+//      that the host polls (no stream synchronisation per iteration);
 //   2. one V-cycle (Alg. 3) on the correction equation A_comp e = r, stored in
 //      T (float in mixed precision, double otherwise), continued below AMR
-//      level 0 through geometric coarsenings down to a CG bottom solve;
+//      level 0 through geometric coarsenings down to a grid of at most 64
+//      cells per edge, solved exactly (separable transforms) or by CG;
 //   3. phi += e in FP64.
 // With T = double this is Alg. 2 as printed (the V-cycle applied to the
 // correction form, which is algebraically the same cycle); with T = float it
@@ -16,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -70,6 +73,29 @@ struct DBuf {
         cap = 0;
     }
     ~DBuf() { release(); }
+};
+
+// host memory the device writes and the host polls (coherent, mapped)
+struct CBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t n)
+    {
+        if (n <= cap && p) return hipSuccess;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        hipError_t e = hipHostMalloc(&p, n, hipHostMallocCoherent | hipHostMallocMapped);
+        if (e == hipSuccess) {
+            cap = n;
+            std::memset(p, 0, n);
+        }
+        return e;
+    }
+    ~CBuf()
+    {
+        if (p) (void)hipHostFree(p);
+    }
 };
 
 struct PBuf {
@@ -173,6 +199,12 @@ struct DevState {
     int cg_threads = 1024;
     PBuf h_normbuf;
     double *h_norm = nullptr;
+    // norms of each outer iteration, published by the norms kernel: values,
+    // then a sequence number; the device keeps the count at d_seqc
+    CBuf pubbuf;
+    double *h_pub = nullptr;
+    unsigned *h_seq = nullptr, *d_seqc = nullptr;
+    unsigned seq = 0;
     // AMR-level brick maps with global brick ids of the first problem (views
     // into the map pool)
     std::vector<int32_t *> d_bmap;
@@ -442,6 +474,9 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
     D.d_E = D.d_rout + ne;
     HIP_TRY(D.h_normbuf.ensure(sizeof(double) * 2 * (D.range_prob.size() + 1)));
     D.h_norm = (double *)D.h_normbuf.p;
+    HIP_TRY(D.pubbuf.ensure(sizeof(double) * (D.range_prob.size() + 8)));
+    D.h_seq = (unsigned *)D.pubbuf.p;
+    D.h_pub = (double *)D.pubbuf.p + 1;
     D.ws_prec = -1;  // carve the workspace again for the new hierarchy
     D.drop_graph();
     ++D.meta_gen;
@@ -502,6 +537,7 @@ static amrmg_status ensure_ws(DevState &D, int prec, void *user, size_t user_byt
     D.cgw = (double *)take(D.cg_doubles * 8);
     D.dw = (double *)take(D.dw_doubles * 8 + 8);
     D.cgit = (int *)take(64);
+    D.d_seqc = (unsigned *)((char *)D.cgit + 32);
     D.ws_prec = prec;
     return AMRMG_OK;
 }
@@ -1074,8 +1110,9 @@ struct Driver {
         return last.b0 + last.nb - step_b0(k);
     }
 
-    // outer FP64 residual of every AMR level; norms into dnorm[off ..]
-    void outer(bool zero_phi, int noff, double *const *rout_user)
+    // outer FP64 residual of every AMR level; norms into dnorm[off ..] (and
+    // published to the host when publish is set)
+    void outer(bool zero_phi, int noff, double *const *rout_user, bool publish = false)
     {
         int b0, nb;
         const int32_t *list;
@@ -1092,7 +1129,8 @@ struct Driver {
         launch_outer_residual<T>(st, D.M, b0, nb, list, D.phib, D.rhob, o.inv_eps0, zero_phi ? nullptr : D.cpphi,
                                  (zero_phi || rout_user) ? nullptr : r, D.part, o.norm_p, zero_phi, rout_user);
         pe(AMRMG_K_RESIDUAL, (double)nb * BRICK_CELLS * (zero_phi ? 8.0 : 16.0 + W));
-        launch_level_norms(st, D.d_ranges, (int)D.range_prob.size(), D.part, D.dnorm + noff, o.norm_p);
+        launch_level_norms(st, D.d_ranges, (int)D.range_prob.size(), D.part, D.dnorm + noff, o.norm_p,
+                           publish ? D.h_pub : nullptr, D.h_seq, D.d_seqc);
     }
 
     void smooth(int k, int nu, bool pre)
@@ -1181,16 +1219,14 @@ struct Driver {
             else
                 smooth(k, o.nu1, true);
             double n = (double)step_nb(k) * BRICK_CELLS;
-            pb(AMRMG_K_RESTRICT);
-            launch_restrict<T>(st, D.M, step_b0(k), step_nb(k), e, r, r);
-            pe(AMRMG_K_RESTRICT, (2.0 + 0.125) * n * W);
-            // coarse cells of level k-1 next to level k
+            // restriction into level k-1 together with the coarse-fine
+            // update of its cells next to level k
             const auto &e0 = m.ent[m.step_ent0[k - 1]];
             const auto &e1 = m.ent[m.step_ent0[k] - 1];
             int rf0 = e0.rf0, nrf = e1.rf0 + e1.nrf - e0.rf0;
-            pb(AMRMG_K_REFLUX);
-            launch_reflux<T>(st, D.M, D.d_reflux + rf0, nrf, e, r);
-            pe(AMRMG_K_REFLUX, 2.0 * nrf * BRICK_CELLS * W);
+            pb(AMRMG_K_RESTRICT);
+            launch_restrict<T>(st, D.M, step_b0(k), step_nb(k), D.d_reflux + rf0, nrf, e, r);
+            pe(AMRMG_K_RESTRICT, (2.0 + 0.125) * n * W + 2.0 * nrf * BRICK_CELLS * W);
         }
         pb(AMRMG_K_BOTTOM);
         launch_direct<T>(st, D.d_djobs, D.d_planes, D.n_planes, D.d_groups, D.n_groups, D.d_dtab, D.dw, r, e, D.phib,
@@ -1246,7 +1282,7 @@ struct Driver {
     void iteration(int nr)
     {
         vcycle();
-        outer(false, nr, nullptr);
+        outer(false, nr, nullptr, true);
     }
 };
 
@@ -1295,7 +1331,9 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
     hipEvent_t ev0, ev1;
     HIP_TRY(hipEventCreate(&ev0));
     HIP_TRY(hipEventCreate(&ev1));
-    HIP_TRY(hipMemsetAsync(D.cgit, 0, sizeof(int), st));
+    HIP_TRY(hipMemsetAsync(D.cgit, 0, 64, st));  // CG iteration count and the norm sequence counter
+    D.seq = 0;
+    *(volatile unsigned *)D.h_seq = 0;
     HIP_TRY(hipEventRecord(ev0, st));
     drv.to_bricks(true);
     drv.outer(true, 0, nullptr);
@@ -1332,10 +1370,20 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
     bool all = check(0);
     while (!all && it < o.max_iters) {
         ST_TRY(iterate<T>(D, drv, st, nr, o, g_use_graphs));
-        HIP_TRY(hipMemcpyAsync(D.h_norm + nr, D.dnorm + nr, sizeof(double) * nr, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
+        // wait for the iteration's norms in host memory (no stream synchronisation);
+        // after a second without them, synchronise and look again
+        const unsigned want = ++D.seq;
+        auto t0 = std::chrono::steady_clock::now();
+        for (unsigned spin = 0; *(volatile unsigned *)D.h_seq != want; ++spin) {
+            if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) {
+                HIP_TRY(hipStreamSynchronize(st));
+                if (*(volatile unsigned *)D.h_seq != want)
+                    return fail(AMRMG_E_HIP, "the iteration's norms did not reach the host");
+                break;
+            }
+        }
         HIP_TRY(hipGetLastError());
-        rn.assign(D.h_norm + nr, D.h_norm + 2 * nr);
+        rn.assign(D.h_pub, D.h_pub + nr);
         ++it;
         all = check(it);
     }

@@ -458,37 +458,49 @@ __global__ void __launch_bounds__(256) k_user_brick(DevMeta M, int b0, int nb, c
     }
 }
 
-// norm of each listed brick range (one AMR level of one problem) from the
-// partials (two per brick), in a fixed order
+// Norm of each listed brick range (one AMR level of one problem) from the
+// partials (two per brick), in a fixed order, by one workgroup.  With hout
+// set, the norms are also written to host-visible memory followed by a
+// sequence number (the device counter plus one), so that the host can poll
+// for them without synchronising the stream.
 __global__ void __launch_bounds__(1024) k_level_norms(const int2 *ranges, int n, const double *part, double *out,
-                                                      int norm_p)
+                                                      int norm_p, double *hout, unsigned *hseq, unsigned *counter)
 {
-    int l = blockIdx.x;
-    if (l >= n) return;
-    const int b0 = 2 * ranges[l].x, b1 = 2 * (ranges[l].x + ranges[l].y);
-    const bool mx = norm_p == 0;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int b = b0 + (int)threadIdx.x;
-    for (; b + 3 * 1024 < b1; b += 4 * 1024) {
-        double v0 = part[b], v1 = part[b + 1024], v2 = part[b + 2048], v3 = part[b + 3072];
-        a0 = mx ? fmax(a0, v0) : a0 + v0;
-        a1 = mx ? fmax(a1, v1) : a1 + v1;
-        a2 = mx ? fmax(a2, v2) : a2 + v2;
-        a3 = mx ? fmax(a3, v3) : a3 + v3;
-    }
-    for (; b < b1; b += 1024) a0 = mx ? fmax(a0, part[b]) : a0 + part[b];
-    double acc = mx ? fmax(fmax(a0, a1), fmax(a2, a3)) : (a0 + a1) + (a2 + a3);
-    for (int o = 32; o > 0; o >>= 1) {
-        double w = __shfl_xor(acc, o, 64);
-        acc = mx ? fmax(acc, w) : acc + w;
-    }
     __shared__ double sh[16];
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double r = sh[0];
-        for (int i = 1; i < 16; ++i) r = mx ? fmax(r, sh[i]) : r + sh[i];
-        out[l] = norm_p == 2 ? sqrt(r) : r;
+    const bool mx = norm_p == 0;
+    for (int l = 0; l < n; ++l) {
+        const int b0 = 2 * ranges[l].x, b1 = 2 * (ranges[l].x + ranges[l].y);
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int b = b0 + (int)threadIdx.x;
+        for (; b + 3 * 1024 < b1; b += 4 * 1024) {
+            double v0 = part[b], v1 = part[b + 1024], v2 = part[b + 2048], v3 = part[b + 3072];
+            a0 = mx ? fmax(a0, v0) : a0 + v0;
+            a1 = mx ? fmax(a1, v1) : a1 + v1;
+            a2 = mx ? fmax(a2, v2) : a2 + v2;
+            a3 = mx ? fmax(a3, v3) : a3 + v3;
+        }
+        for (; b < b1; b += 1024) a0 = mx ? fmax(a0, part[b]) : a0 + part[b];
+        double acc = mx ? fmax(fmax(a0, a1), fmax(a2, a3)) : (a0 + a1) + (a2 + a3);
+        for (int o = 32; o > 0; o >>= 1) {
+            double w = __shfl_xor(acc, o, 64);
+            acc = mx ? fmax(acc, w) : acc + w;
+        }
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double r = sh[0];
+            for (int i = 1; i < 16; ++i) r = mx ? fmax(r, sh[i]) : r + sh[i];
+            r = norm_p == 2 ? sqrt(r) : r;
+            out[l] = r;
+            if (hout) hout[l] = r;
+        }
+        __syncthreads();
+    }
+    if (hout && threadIdx.x == 0) {
+        __threadfence_system();
+        const unsigned s = *counter + 1;
+        *counter = s;
+        *(volatile unsigned *)hseq = s;
     }
 }
 
@@ -708,11 +720,9 @@ __device__ __forceinline__ double cell_residual(const DevMeta &M, const LevelCon
 // One fine brick per workgroup of 128 threads: two threads per coarse cell,
 // each with the four children of one z layer, combined by a shuffle.
 template <class T>
-__global__ void __launch_bounds__(RT) k_restrict(DevMeta M, int b0, int nb, const T *e, const T *r, T *rc)
+__device__ __forceinline__ void restrict_brick(const DevMeta &M, int b, const T *e, const T *r, T *rc, double *tile,
+                                               double *alpha)
 {
-    __shared__ double tile[TE * TE * TE];
-    __shared__ double alpha[6];
-    int b = b0 + xcd_remap(blockIdx.x, nb);
     LevelConst L = M.lc[M.org[b].w];
     const int cc = threadIdx.x >> 1, h = threadIdx.x & 1;
     const int cx = cc & 3, cy = (cc >> 2) & 3, cz = cc >> 4;
@@ -750,39 +760,54 @@ __global__ void __launch_bounds__(RT) k_restrict(DevMeta M, int b0, int nb, cons
 // 1/(2 h_d^2) * sum over the 4 fine faces of (e_f/3 + e_in/5) per coarse-fine
 // face (the coarse correction is still zero).  FP64 arithmetic.
 template <class T>
-__global__ void __launch_bounds__(256) k_reflux(DevMeta M, const int32_t *list, int n, const T *e, T *r)
+__device__ __forceinline__ void reflux_brick(const DevMeta &M, int b, const T *e, T *r, int *nbk, uint8_t *ncm)
 {
-    int b = list[xcd_remap(blockIdx.x, n)];
-    int lev = M.org[b].w;
-    LevelConst L = M.lc[lev];
-    uint8_t cm = M.cmask[b];
-    for (int c = threadIdx.x; c < BRICK_CELLS; c += 256) {
-        int lc[3] = {c & 7, (c >> 3) & 7, c >> 6};
-        if ((cm >> oct_of(lc[0], lc[1], lc[2])) & 1) continue;
+    const LevelConst L = M.lc[M.org[b].w];
+    const uint8_t cm = M.cmask[b];
+    if (threadIdx.x < 6) {
+        int f = M.nbr[b * 6 + threadIdx.x];
+        nbk[threadIdx.x] = f;
+        ncm[threadIdx.x] = f >= 0 ? M.cmask[f] : 0;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < BRICK_CELLS; c += blockDim.x) {
+        const int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+        if ((cm >> oct_of(x, y, z)) & 1) continue;
         double add = 0.0;
-        for (int d = 0; d < 3; ++d)
-            for (int s = -1; s <= 1; s += 2) {
-                int nl[3] = {lc[0], lc[1], lc[2]};
-                int nn = nl[d] + s, nbk = b;
-                bool cov = false;
-                if (nn >= 0 && nn < BRICK) {
-                    nl[d] = nn;
-                    cov = (cm >> oct_of(nl[0], nl[1], nl[2])) & 1;
-                } else {
-                    int f = M.nbr[b * 6 + 2 * d + (s > 0)];
-                    if (f >= 0) {
-                        nl[d] = (s > 0) ? 0 : BRICK - 1;
-                        nbk = f;
-                        cov = (M.cmask[f] >> oct_of(nl[0], nl[1], nl[2])) & 1;
-                    }
-                }
-                if (cov) add += 0.5 * L.ih2[d] * fine_face_sum(M, nbk, nl, d, s, BrickAcc<T>{e}, nullptr);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int d = f >> 1, s = (f & 1) ? 1 : -1;
+            int qx = x + (d == 0 ? s : 0), qy = y + (d == 1 ? s : 0), qz = z + (d == 2 ? s : 0);
+            bool inside = ((qx | qy | qz) & ~7) == 0;
+            bool cov = ((inside ? cm : ncm[f]) >> oct_of(qx & 7, qy & 7, qz & 7)) & 1;
+            if (cov) {
+                int nl[3] = {qx & 7, qy & 7, qz & 7};
+                add += 0.5 * L.ih2[d] * fine_face_sum(M, inside ? b : nbk[f], nl, d, s, BrickAcc<T>{e}, nullptr);
             }
+        }
         if (add != 0.0) {
             size_t li = (size_t)b * BRICK_CELLS + c;
             r[li] = (T)((double)r[li] + add);
         }
     }
+}
+
+// One launch per level step: the restriction of the nb fine bricks from b0
+// into their parents (covered coarse cells), then the coarse-fine update of
+// the nrf listed coarse bricks (uncovered cells) -- disjoint cells, so the
+// two kinds of workgroups run together.
+template <class T>
+__global__ void __launch_bounds__(RT) k_restrict(DevMeta M, int b0, int nb, const int32_t *rlist, int nrf,
+                                                 const T *e, T *r)
+{
+    __shared__ double tile[TE * TE * TE];
+    __shared__ double alpha[6];
+    __shared__ int nbk[6];
+    __shared__ uint8_t ncm[6];
+    if ((int)blockIdx.x < nb)
+        restrict_brick<T>(M, b0 + xcd_remap(blockIdx.x, nb), e, r, r, tile, alpha);
+    else
+        reflux_brick<T>(M, rlist[xcd_remap(blockIdx.x - nb, nrf)], e, r, nbk, ncm);
 }
 
 // e^l += I e^{l-1}: piecewise-constant injection of the parent value
@@ -1583,10 +1608,11 @@ void launch_user_brick(hipStream_t st, const DevMeta &M, int b0, int nb, const i
     AMRMG_LAUNCH(k_user_brick, dim3(nb), dim3(256), 0, st, M, b0, nb, list, (int)to_brick, a, ab, bu, bb);
 }
 
-void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double *part, double *out, int norm_p)
+void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double *part, double *out, int norm_p,
+                        double *hout, unsigned *hseq, unsigned *counter)
 {
     if (n <= 0) return;
-    AMRMG_LAUNCH(k_level_norms, dim3(n), dim3(1024), 0, st, ranges, n, part, out, norm_p);
+    AMRMG_LAUNCH(k_level_norms, dim3(1), dim3(1024), 0, st, ranges, n, part, out, norm_p, hout, hseq, counter);
 }
 
 template <class T>
@@ -1615,17 +1641,11 @@ void launch_jacobi(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ei
 }
 
 template <class T>
-void launch_restrict(hipStream_t st, const DevMeta &M, int b0, int nb, const T *e, const T *r, T *rc)
+void launch_restrict(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *rlist, int nrf, const T *e,
+                     T *r)
 {
-    if (nb <= 0) return;
-    AMRMG_LAUNCH((k_restrict<T>), dim3(nb), dim3(RT), 0, st, M, b0, nb, e, r, rc);
-}
-
-template <class T>
-void launch_reflux(hipStream_t st, const DevMeta &M, const int32_t *list, int n, const T *e, T *r)
-{
-    if (n <= 0) return;
-    AMRMG_LAUNCH((k_reflux<T>), dim3(n), dim3(256), 0, st, M, list, n, e, r);
+    if (nb + nrf <= 0) return;
+    AMRMG_LAUNCH((k_restrict<T>), dim3(nb + nrf), dim3(RT), 0, st, M, b0, nb, rlist, nrf, e, r);
 }
 
 template <class T>
@@ -1810,8 +1830,8 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val)
     template void launch_gsrb<T>(hipStream_t, const DevMeta &, int, int, T *, const T *, const T *, int, bool);  \
     template void launch_jacobi<T>(hipStream_t, const DevMeta &, int, int, const T *, T *, const T *, const T *, \
                                    double, bool);                                                                \
-    template void launch_restrict<T>(hipStream_t, const DevMeta &, int, int, const T *, const T *, T *);         \
-    template void launch_reflux<T>(hipStream_t, const DevMeta &, const int32_t *, int, const T *, T *);          \
+    template void launch_restrict<T>(hipStream_t, const DevMeta &, int, int, const int32_t *, int, const T *,   \
+                                     T *);                                                                      \
     template void launch_prolong<T>(hipStream_t, const DevMeta &, int, int, T *);                                \
     template void launch_phi_update<T>(hipStream_t, const DevMeta &, int, int, const int32_t *, double *,         \
                                        const T *);                                                               \

@@ -75,7 +75,10 @@ void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, con
 // caller's layout (per-level pointer tables a, bu) <-> brick layout (ab, bb)
 void launch_user_brick(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, bool to_brick,
                        double *const *a, double *ab, double *const *bu, double *bb);
-void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double *part, double *out, int norm_p);
+// per-range norms into out (device); with hout, also into host-visible
+// memory followed by the sequence number *counter + 1 at hseq
+void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double *part, double *out, int norm_p,
+                        double *hout = nullptr, unsigned *hseq = nullptr, unsigned *counter = nullptr);
 template <class T>
 void launch_cpart_brick(hipStream_t st, const DevMeta &M, int cf0, int ncf, const T *src, T *cp);
 template <class T>
@@ -84,10 +87,11 @@ void launch_gsrb(hipStream_t st, const DevMeta &M, int b0, int nb, T *e, const T
 template <class T>
 void launch_jacobi(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, const T *cp,
                    double omega, bool init);
+// restriction of nb fine bricks from b0 (r -> parents' covered cells) and the
+// coarse-fine update of the nrf listed coarse bricks, in one launch
 template <class T>
-void launch_restrict(hipStream_t st, const DevMeta &M, int b0, int nb, const T *e, const T *r, T *rc);
-template <class T>
-void launch_reflux(hipStream_t st, const DevMeta &M, const int32_t *list, int n, const T *e, T *r);
+void launch_restrict(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *rlist, int nrf, const T *e,
+                     T *r);
 template <class T>
 void launch_prolong(hipStream_t st, const DevMeta &M, int b0, int nb, T *e);
 template <class T>
