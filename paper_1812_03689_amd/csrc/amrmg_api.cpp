@@ -232,6 +232,32 @@ struct DevState {
 
 static bool g_weights_ok = false;
 
+// direct-solve tables by grid shape and spacing (they depend on nothing else;
+// a regrid keeps level 0 and so its coarsest grid)
+static const std::vector<double> &cached_direct_tables(const int n[3], const double h[3])
+{
+    struct Key {
+        int n[3];
+        double h[3];
+        bool operator<(const Key &o) const
+        {
+            for (int d = 0; d < 3; ++d) {
+                if (n[d] != o.n[d]) return n[d] < o.n[d];
+                if (h[d] != o.h[d]) return h[d] < o.h[d];
+            }
+            return false;
+        }
+    };
+    static thread_local std::map<Key, std::vector<double>> cache;
+    Key k{{n[0], n[1], n[2]}, {h[0], h[1], h[2]}};
+    auto it = cache.find(k);
+    if (it == cache.end()) {
+        if (cache.size() > 64) cache.clear();
+        it = cache.emplace(k, direct_tables(n, h)).first;
+    }
+    return it->second;
+}
+
 // Upload D.meta (built without face data) in one copy, then generate the
 // face data (boundary values, coarse-fine windows) on the device.
 static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<const Problem *> &probs,
@@ -379,7 +405,7 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
         J.tab = (int)dtab.size();
         J.w = (int)D.dw_doubles;
         J.amr = L.amr >= 0 ? 1 : 0;
-        std::vector<double> t = direct_tables(L.n, L.h);
+        const std::vector<double> &t = cached_direct_tables(L.n, L.h);
         dtab.insert(dtab.end(), t.begin(), t.end());
         D.dw_doubles += (size_t)L.n[0] * L.n[1] * L.n[2];
         const int jid = (int)djl.size();
@@ -631,6 +657,7 @@ struct amrmg_ctx {
     // spatial visiting order of the particles (a performance hint for the
     // deposit; any order gives the same sums up to rounding)
     DBuf sort_keys, sort_vals, sort_tmp;
+    DBuf sorted;  // the particles in visiting order, for the tagging passes of one build
     uint32_t *perm = nullptr;
     int64_t perm_n = -1;
     DBuf dep_count;
@@ -758,7 +785,8 @@ static amrmg_status compute_order(amrmg_ctx *ctx, int pos_dtype, const void *x, 
 // Tagging pass on level l: deposit, tag, dilate and mark the blocks of level
 // l+1 on the device; the host then applies nesting and the greedy merge.
 static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype, const void *x, const void *y,
-                              const void *z, const double *q, int64_t n, double lambda, std::vector<Box> &boxes)
+                              const void *z, const double *q, int64_t n, double lambda, std::vector<Box> &boxes,
+                              const uint32_t *perm)
 {
     const amrmg_params &P = ctx->P;
     hipStream_t st = ctx->st;
@@ -804,8 +832,7 @@ static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype,
     A.lev[0] = dep_level(pr, L, d_bmap);
     A.rho[0] = rho;
     A.ncell[0] = nc;
-    launch_deposit(st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, ctx->perm_n == n ? ctx->perm : nullptr, A, d_ub,
-                   (const int2 *)d_us, nullptr);
+    launch_deposit(st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, perm, A, d_ub, (const int2 *)d_us, nullptr);
     HIP_TRY(hipMemsetAsync(ctx->tag_marks.p, 0, ng, st));
     launch_mark_blocks(st, rho, nc, (const int4 *)d_borg, d_ub, (const int2 *)d_us, nb, lambda, P.n_buffer, half, nn,
                        g, (double *)ctx->tag_scratch.p, (uint8_t *)ctx->tag_marks.p);
@@ -839,6 +866,25 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
     ctx->built = false;
     ++ctx->generation;
     ST_TRY(compute_order(ctx, pos_dtype, x, y, z, n));
+    // the tagging passes read the particles in visiting order from a copy
+    const void *tx = x, *ty = y, *tz = z;
+    const double *tq = q;
+    const uint32_t *tperm = ctx->perm_n == n ? ctx->perm : nullptr;
+    bool need_tags = false;
+    for (int l = 1; l <= P.max_level; ++l) need_tags = need_tags || !expl.count(l);
+    if (tperm && need_tags) {
+        const size_t ps = pos_dtype == AMRMG_POS_F32 ? 4 : 8;
+        HIP_TRY(ctx->sorted.ensure((size_t)n * (3 * ps + 8) + 1024));
+        char *base = (char *)ctx->sorted.p;
+        double *qs = (double *)base;
+        char *xs = base + align256((size_t)n * 8), *ys = xs + align256((size_t)n * ps), *zs = ys + align256((size_t)n * ps);
+        launch_permute(ctx->st, pos_dtype == AMRMG_POS_F32, n, tperm, x, y, z, q, xs, ys, zs, qs);
+        tx = xs;
+        ty = ys;
+        tz = zs;
+        tq = qs;
+        tperm = nullptr;
+    }
 
     Problem &pr = ctx->prob;
     pr = Problem();
@@ -863,7 +909,7 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
             boxes = expl[l + 1];
         } else {
             if (!tag_rel) return fail(AMRMG_E_INVALID, "tag_rel is NULL but a level needs tagging");
-            ST_TRY(tag_level(ctx, L, pos_dtype, x, y, z, q, n, tag_rel[l], boxes));
+            ST_TRY(tag_level(ctx, L, pos_dtype, tx, ty, tz, tq, n, tag_rel[l], boxes, tperm));
         }
         if (boxes.empty()) break;
         std::string msg = check_nesting(L, boxes, P.n_proper);

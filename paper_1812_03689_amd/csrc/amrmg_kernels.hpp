@@ -135,6 +135,9 @@ size_t sort_temp_bytes(int64_t n);
 hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                           const double *lo, const double *hi, const int *nf, uint64_t *keys, uint32_t *vals,
                           void *temp, size_t temp_bytes, uint32_t **perm_out);
+// particles in the visiting order perm (xs[i] = x[perm[i]], ...)
+void launch_permute(hipStream_t st, int pos_f32, int64_t n, const uint32_t *perm, const void *x, const void *y,
+                    const void *z, const double *q, void *xs, void *ys, void *zs, double *qs);
 void launch_mark_blocks(hipStream_t st, const double *rho, int64_t ncell, const int4 *borg, const int64_t *ubase,
                         const int2 *ustr, int nb, double lambda, int nbuf, int half, int3 n, int3 g, double *scratch,
                         uint8_t *marks);

@@ -99,4 +99,30 @@ hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x,
     return hipGetLastError();
 }
 
+template <class P>
+__global__ void __launch_bounds__(256) k_permute(int64_t n, const uint32_t *perm, const P *x, const P *y, const P *z,
+                                                 const double *q, P *xs, P *ys, P *zs, double *qs)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    int64_t p = perm[i];
+    xs[i] = x[p];
+    ys[i] = y[p];
+    zs[i] = z[p];
+    qs[i] = q[p];
+}
+
+void launch_permute(hipStream_t st, int pos_f32, int64_t n, const uint32_t *perm, const void *x, const void *y,
+                    const void *z, const double *q, void *xs, void *ys, void *zs, double *qs)
+{
+    if (n <= 0) return;
+    unsigned g = (unsigned)((n + 255) / 256);
+    if (pos_f32)
+        hipLaunchKernelGGL((k_permute<float>), dim3(g), dim3(256), 0, st, n, perm, (const float *)x,
+                           (const float *)y, (const float *)z, q, (float *)xs, (float *)ys, (float *)zs, qs);
+    else
+        hipLaunchKernelGGL((k_permute<double>), dim3(g), dim3(256), 0, st, n, perm, (const double *)x,
+                           (const double *)y, (const double *)z, q, (double *)xs, (double *)ys, (double *)zs, qs);
+}
+
 }  // namespace amrmg
