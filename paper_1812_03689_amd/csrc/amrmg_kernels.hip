@@ -222,9 +222,8 @@ struct CpInline {
 
 // NT = threads of the workgroup.  Every load of the tile is issued before the
 // first LDS store, so a thread waits for memory once.
-template <class S, bool ZERO = false, class CP = CpNone, int NT = 256>
-__device__ void stage_tile(const DevMeta &M, int b, const S &src, const CP &cp, bool inhom, double *tile,
-                           double *alpha)
+template <class S, bool ZERO = false, class CP = CpNone, int NT = 256, class V = double>
+__device__ void stage_tile(const DevMeta &M, int b, const S &src, const CP &cp, bool inhom, V *tile, V *alpha)
 {
     constexpr int NI = BRICK_CELLS / NT, NH = (384 + NT - 1) / NT;
     double vi[NI], vh[NH], ah[NH];
@@ -264,7 +263,7 @@ __device__ void stage_tile(const DevMeta &M, int b, const S &src, const CP &cp, 
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
         const int c = threadIdx.x + NT * j;
-        tile[tix(c & 7, (c >> 3) & 7, c >> 6)] = vi[j];
+        tile[tix(c & 7, (c >> 3) & 7, c >> 6)] = (V)vi[j];
     }
 #pragma unroll
     for (int j = 0; j < NH; ++j) {
@@ -277,8 +276,8 @@ __device__ void stage_tile(const DevMeta &M, int b, const S &src, const CP &cp, 
         l[du] = t & 7;
         l[dv] = (t >> 3) & 7;
         l[d] = (f & 1) ? 8 : -1;
-        tile[tix(l[0], l[1], l[2])] = vh[j];
-        if ((t & 63) == 0) alpha[f] = ah[j];
+        tile[tix(l[0], l[1], l[2])] = (V)vh[j];
+        if ((t & 63) == 0) alpha[f] = (V)ah[j];
     }
     __syncthreads();
 }
@@ -286,19 +285,19 @@ __device__ void stage_tile(const DevMeta &M, int b, const S &src, const CP &cp, 
 // Ghost form a * u_c + bv of the neighbour of tile cell (x,y,z) across
 // (d, s).  A coarse-fine halo slot holds the coarse part; the -u_in/5 term
 // uses the current value of the cell further inside.
-__device__ __forceinline__ void tile_ab(const double *tile, const double *alpha, int x, int y, int z, int d, int s,
-                                        double &a, double &bv)
+template <class V>
+__device__ __forceinline__ void tile_ab(const V *tile, const V *alpha, int x, int y, int z, int d, int s, V &a, V &bv)
 {
     int l[3] = {x, y, z};
     l[d] += s;
     bv = tile[tix(l[0], l[1], l[2])];
-    a = 0.0;
+    a = (V)0;
     if (l[d] < 0 || l[d] > 7) {
         a = alpha[2 * d + (s > 0)];
-        if (a > 0.0) {
+        if (a > (V)0) {
             int in[3] = {x, y, z};
             in[d] -= s;
-            bv -= 0.2 * tile[tix(in[0], in[1], in[2])];
+            bv -= (V)0.2 * tile[tix(in[0], in[1], in[2])];
         }
     }
 }
@@ -636,14 +635,15 @@ template <class T, int MODE>
 __global__ void __launch_bounds__(BT) k_hgs(DevMeta M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
                                             double *phib)
 {
-    __shared__ double tile[TE * TE * TE];
-    __shared__ double alpha[6];
+    __shared__ T tile[TE * TE * TE];  // arithmetic in the cycle's precision T
+    __shared__ T alpha[6];
     constexpr int PER = 256 / BT;  // cells of each colour per thread
     int b = b0 + xcd_remap(blockIdx.x, nb);
     int lev = M.org[b].w;
     LevelConst L = M.lc[lev];
     int cyz[PER], cx[2][PER];  // y + 8 z, and x of the colour-0 / colour-1 cell (brick origins are even)
-    double rv[2][PER];
+    T rv[2][PER];
+    const T ih2[3] = {(T)L.ih2[0], (T)L.ih2[1], (T)L.ih2[2]};
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         int t = threadIdx.x + BT * j;
@@ -652,35 +652,35 @@ __global__ void __launch_bounds__(BT) k_hgs(DevMeta M, int b0, int nb, const T *
         cx[0][j] = xx + ((y + z) & 1);
         cx[1][j] = xx + (((y + z) & 1) ^ 1);
 #pragma unroll
-        for (int k = 0; k < 2; ++k) rv[k][j] = (double)r[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]];
+        for (int k = 0; k < 2; ++k) rv[k][j] = r[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]];
     }
     if (MODE & HG_ZERO) {
-        stage_tile<SrcZ, true, CpNone, BT>(M, b, SrcZ{}, CpNone{}, false, tile, alpha);
+        stage_tile<SrcZ, true, CpNone, BT, T>(M, b, SrcZ{}, CpNone{}, false, tile, alpha);
     } else if (MODE & HG_PROL) {
         if (MODE & HG_CPIN)
-            stage_tile<SrcProl<T>, false, CpInline<T>, BT>(M, b, SrcProl<T>{ein, M.par}, CpInline<T>{&M, ein, cp},
-                                                           false, tile, alpha);
+            stage_tile<SrcProl<T>, false, CpInline<T>, BT, T>(M, b, SrcProl<T>{ein, M.par},
+                                                              CpInline<T>{&M, ein, cp}, false, tile, alpha);
         else
-            stage_tile<SrcProl<T>, false, CpArr<T>, BT>(M, b, SrcProl<T>{ein, M.par}, CpArr<T>{cp}, false, tile,
-                                                        alpha);
+            stage_tile<SrcProl<T>, false, CpArr<T>, BT, T>(M, b, SrcProl<T>{ein, M.par}, CpArr<T>{cp}, false, tile,
+                                                           alpha);
     } else {
-        stage_tile<SrcB<T>, false, CpArr<T>, BT>(M, b, SrcB<T>{ein}, CpArr<T>{cp}, false, tile, alpha);
+        stage_tile<SrcB<T>, false, CpArr<T>, BT, T>(M, b, SrcB<T>{ein}, CpArr<T>{cp}, false, tile, alpha);
     }
-    double v[2][PER];
+    T v[2][PER];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             int x = cx[k][j], y = cyz[j] & 7, z = cyz[j] >> 3;
-            double num = rv[k][j], den = 0.0;
+            T num = rv[k][j], den = (T)0;
 #pragma unroll
             for (int d = 0; d < 3; ++d)
 #pragma unroll
                 for (int s = -1; s <= 1; s += 2) {
-                    double a, bv;
+                    T a, bv;
                     tile_ab(tile, alpha, x, y, z, d, s, a, bv);
-                    num += L.ih2[d] * bv;
-                    den += L.ih2[d] * (1.0 - a);
+                    num += ih2[d] * bv;
+                    den += ih2[d] * ((T)1 - a);
                 }
             v[k][j] = num / den;
             tile[tix(x, y, z)] = v[k][j];
@@ -690,12 +690,12 @@ __global__ void __launch_bounds__(BT) k_hgs(DevMeta M, int b0, int nb, const T *
 #pragma unroll
     for (int j = 0; j < PER; ++j)
 #pragma unroll
-        for (int k = 0; k < 2; ++k) eout[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]] = (T)v[k][j];
+        for (int k = 0; k < 2; ++k) eout[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]] = v[k][j];
     if ((MODE & HG_PHI) && L.amr >= 0) {
 #pragma unroll
         for (int j = 0; j < PER; ++j)
 #pragma unroll
-            for (int k = 0; k < 2; ++k) phib[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]] += v[k][j];
+            for (int k = 0; k < 2; ++k) phib[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]] += (double)v[k][j];
     }
 }
 
@@ -720,30 +720,31 @@ __device__ __forceinline__ double cell_residual(const DevMeta &M, const LevelCon
 // One fine brick per workgroup of 128 threads: two threads per coarse cell,
 // each with the four children of one z layer, combined by a shuffle.
 template <class T>
-__device__ __forceinline__ void restrict_brick(const DevMeta &M, int b, const T *e, const T *r, T *rc, double *tile,
-                                               double *alpha)
+__device__ __forceinline__ void restrict_brick(const DevMeta &M, int b, const T *e, const T *r, T *rc, T *tile,
+                                               T *alpha)
 {
     LevelConst L = M.lc[M.org[b].w];
+    const T ih2[3] = {(T)L.ih2[0], (T)L.ih2[1], (T)L.ih2[2]};
     const int cc = threadIdx.x >> 1, h = threadIdx.x & 1;
     const int cx = cc & 3, cy = (cc >> 2) & 3, cz = cc >> 4;
     const int z = 2 * cz + h;
-    double rv[4];
+    T rv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-        rv[q] = (double)r[(size_t)b * BRICK_CELLS + (2 * cx + (q & 1)) + 8 * (2 * cy + (q >> 1)) + 64 * z];
-    stage_tile<SrcB<T>, false, CpNone, RT>(M, b, SrcB<T>{e}, CpNone{}, false, tile, alpha);
-    double sum = 0.0;
+        rv[q] = r[(size_t)b * BRICK_CELLS + (2 * cx + (q & 1)) + 8 * (2 * cy + (q >> 1)) + 64 * z];
+    stage_tile<SrcB<T>, false, CpNone, RT, T>(M, b, SrcB<T>{e}, CpNone{}, false, tile, alpha);
+    T sum = (T)0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int x = 2 * cx + (q & 1), y = 2 * cy + (q >> 1);
-        double uc = tile[tix(x, y, z)], Au = 0.0;
+        T uc = tile[tix(x, y, z)], Au = (T)0;
 #pragma unroll
         for (int d = 0; d < 3; ++d)
 #pragma unroll
             for (int s = -1; s <= 1; s += 2) {
-                double a, bv;
+                T a, bv;
                 tile_ab(tile, alpha, x, y, z, d, s, a, bv);
-                Au += L.ih2[d] * ((1.0 - a) * uc - bv);
+                Au += ih2[d] * (((T)1 - a) * uc - bv);
             }
         sum += rv[q] - Au;
     }
@@ -752,7 +753,7 @@ __device__ __forceinline__ void restrict_brick(const DevMeta &M, int b, const T 
         int par = M.par[b];
         int pb = par >> 3, oc = par & 7;
         int X = (oc & 1) * 4 + cx, Y = ((oc >> 1) & 1) * 4 + cy, Z = (oc >> 2) * 4 + cz;
-        rc[(size_t)pb * BRICK_CELLS + X + 8 * Y + 64 * Z] = (T)(0.125 * sum);
+        rc[(size_t)pb * BRICK_CELLS + X + 8 * Y + 64 * Z] = (T)0.125 * sum;
     }
 }
 
@@ -800,8 +801,8 @@ template <class T>
 __global__ void __launch_bounds__(RT) k_restrict(DevMeta M, int b0, int nb, const int32_t *rlist, int nrf,
                                                  const T *e, T *r)
 {
-    __shared__ double tile[TE * TE * TE];
-    __shared__ double alpha[6];
+    __shared__ T tile[TE * TE * TE];
+    __shared__ T alpha[6];
     __shared__ int nbk[6];
     __shared__ uint8_t ncm[6];
     if ((int)blockIdx.x < nb)
