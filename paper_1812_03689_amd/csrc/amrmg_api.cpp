@@ -887,7 +887,14 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
     }
 
     Problem &pr = ctx->prob;
-    pr = Problem();
+    // the previous build's AMR levels lend their storage to the new ones
+    // (same level number), so that a regrid touches no fresh pages
+    std::vector<HostLevel> pool(P.max_level + 1);
+    for (auto &L : pr.lev)
+        if (L.amr >= 0 && L.amr <= P.max_level) pool[L.amr] = std::move(L);
+    pr.lev.clear();
+    pr.lev.reserve(P.max_level + 16);  // references into it stay valid while levels are added
+    pr.kg = 0;
     for (int d = 0; d < 3; ++d) {
         pr.lo[d] = P.lo[d];
         pr.hi[d] = P.hi[d];
@@ -895,12 +902,12 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
     pr.eps0 = P.eps0;
     pr.mono = ctx->mono;
     {
-        HostLevel L0;
+        HostLevel L0 = std::move(pool[0]);
         level_init(L0, P.n0, P.lo, P.hi);
         L0.amr = 0;
         Box B{{0, 0, 0}, {P.n0[0], P.n0[1], P.n0[2]}};
         level_set_boxes(L0, {B});
-        pr.lev.push_back(L0);
+        pr.lev.push_back(std::move(L0));
     }
     for (int l = 0; l < P.max_level; ++l) {
         std::vector<Box> boxes;
@@ -914,12 +921,12 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
         if (boxes.empty()) break;
         std::string msg = check_nesting(L, boxes, P.n_proper);
         if (!msg.empty()) return fail(AMRMG_E_NESTING, "level " + std::to_string(l + 1) + ": " + msg);
-        HostLevel F;
+        HostLevel F = std::move(pool[l + 1]);
         int nf[3] = {2 * L.n[0], 2 * L.n[1], 2 * L.n[2]};
         level_init(F, nf, P.lo, P.hi);
         F.amr = l + 1;
         level_set_boxes(F, boxes);
-        pr.lev.push_back(F);
+        pr.lev.push_back(std::move(F));
     }
     add_levels_below(pr);
     build_meta({&pr}, ctx->ds.meta, false);

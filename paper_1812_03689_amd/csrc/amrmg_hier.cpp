@@ -16,6 +16,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <iterator>
 
 namespace amrmg {
 
@@ -335,7 +336,7 @@ void add_levels_below(Problem &P)
         below.insert(below.begin(), L);
     }
     P.kg = (int)below.size();
-    below.insert(below.end(), P.lev.begin(), P.lev.end());
+    below.insert(below.end(), std::make_move_iterator(P.lev.begin()), std::make_move_iterator(P.lev.end()));
     P.lev.swap(below);
 }
 
@@ -360,7 +361,22 @@ static inline void tdirs(int d, int &du, int &dv)
 
 void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_data)
 {
-    M = Meta();
+    // start over, keeping the vectors' storage (a regrid reuses it without
+    // fresh page faults)
+    M.ent.clear();
+    M.step_ent0.clear();
+    M.K = 0;
+    M.nbrick = 0;
+    M.nbc = M.ncf = 0;
+    M.gf_owner.clear();
+    M.gbc.clear();
+    M.cf_pat.clear();
+    M.cf_idx.clear();
+    M.reflux.clear();
+    M.amr_bricks.clear();
+    M.prob_ent.clear();
+    M.dof.clear();
+    M.error.clear();
     const int np = (int)probs.size();
     M.K = 0;
     for (auto *p : probs) M.K = std::max(M.K, (int)p->lev.size());
@@ -405,14 +421,24 @@ void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_da
         Meta::Entry &e = M.ent[ei];
         const Problem &P = *probs[e.prob];
         const HostLevel &L = P.lev[e.k];
-        const HostLevel *F = (e.k + 1 < (int)P.lev.size()) ? &P.lev[e.k + 1] : nullptr;
         const HostLevel *Cc = (e.k > 0) ? &P.lev[e.k - 1] : nullptr;
-        int efine = F ? M.prob_ent[e.prob][e.k + 1] : -1;
         int ecrse = Cc ? M.prob_ent[e.prob][e.k - 1] : -1;
         e.cf0 = (int)cff.size();
+        // bricks are numbered box by box, x fastest inside a box: a face
+        // neighbour inside the same box is found without the brick map
+        int bcur = -1, bfirst = 0, blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0};
         for (int lb = 0; lb < L.nbrick(); ++lb) {
             int g = e.b0 + lb;
             int Pb[3] = {L.bpos[3 * lb], L.bpos[3 * lb + 1], L.bpos[3 * lb + 2]};
+            if (L.bbox[lb] != bcur) {
+                bcur = L.bbox[lb];
+                bfirst = lb;
+                for (int d = 0; d < 3; ++d) {
+                    blo[d] = L.boxes[bcur].lo[d] / 8;
+                    bhi[d] = L.boxes[bcur].hi[d] / 8;
+                }
+            }
+            const int ex = bhi[0] - blo[0], ey = bhi[1] - blo[1];
             for (int d = 0; d < 3; ++d) M.org[(size_t)g * 4 + d] = 8 * Pb[d];
             M.org[(size_t)g * 4 + 3] = (int32_t)ei;
             for (int d = 0; d < 3; ++d)
@@ -425,7 +451,11 @@ void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_da
                         v = -1 - (int32_t)bcf.size();
                         bcf.push_back({g, dir, (int)ei});
                     } else {
-                        int q = L.brick_at(Q[0], Q[1], Q[2]);
+                        int q;
+                        if (Q[d] >= blo[d] && Q[d] < bhi[d])
+                            q = bfirst + (Q[0] - blo[0]) + ex * ((Q[1] - blo[1]) + ey * (Q[2] - blo[2]));
+                        else
+                            q = L.brick_at(Q[0], Q[1], Q[2]);
                         if (q >= 0) {
                             v = e.b0 + q;
                         } else {
@@ -435,17 +465,8 @@ void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_da
                     }
                     M.nbr[(size_t)g * 6 + dir] = v;
                 }
-            if (F) {
-                uint8_t cm = 0;
-                for (int o = 0; o < 8; ++o) {
-                    int q = F->brick_at(2 * Pb[0] + (o & 1), 2 * Pb[1] + ((o >> 1) & 1), 2 * Pb[2] + (o >> 2));
-                    if (q >= 0) {
-                        M.child[(size_t)g * 8 + o] = M.ent[efine].b0 + q;
-                        cm |= (uint8_t)(1u << o);
-                    }
-                }
-                M.cmask[g] = L.amr >= 0 ? cm : 0;
-            }
+            // parent and octant; the parent's child table and covered mask
+            // are filled from here (levels are visited coarse to fine)
             if (Cc) {
                 int q = Cc->brick_at(Pb[0] >> 1, Pb[1] >> 1, Pb[2] >> 1);
                 int oc = (Pb[0] & 1) | ((Pb[1] & 1) << 1) | ((Pb[2] & 1) << 2);
@@ -453,7 +474,10 @@ void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_da
                     M.error = "a brick has no parent on the coarser level (nesting violated)";
                     q = 0;
                 }
-                M.par[g] = ((M.ent[ecrse].b0 + q) << 3) | oc;
+                const int pg = M.ent[ecrse].b0 + q;
+                M.par[g] = (pg << 3) | oc;
+                M.child[(size_t)pg * 8 + oc] = g;
+                if (Cc->amr >= 0) M.cmask[pg] |= (uint8_t)(1u << oc);
             }
             if (L.amr >= 0) {
                 const Box &B = L.boxes[L.bbox[lb]];
@@ -566,8 +590,15 @@ void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_da
                 M.amr_bricks.push_back(g);
                 uint8_t cm = M.cmask[g];
                 dof += 64 * (8 - __builtin_popcount(cm));
+                // a brick needs the update only next to a covered cell: in
+                // itself or in a face neighbour
+                bool near = cm != 0;
+                for (int f = 0; f < 6 && !near; ++f) {
+                    int nb = M.nbr[(size_t)g * 6 + f];
+                    near = nb >= 0 && M.cmask[nb] != 0;
+                }
                 bool want = false;
-                for (int o = 0; o < 8 && !want && cm != 0xFF; ++o) {
+                for (int o = 0; o < 8 && near && !want && cm != 0xFF; ++o) {
                     if ((cm >> o) & 1) continue;
                     for (int d = 0; d < 3 && !want; ++d)
                         for (int s = -1; s <= 1 && !want; s += 2) {
