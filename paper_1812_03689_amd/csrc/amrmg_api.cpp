@@ -193,6 +193,7 @@ struct DevState {
     int ws_prec = -1;
     void *e = nullptr, *r = nullptr, *et = nullptr, *cpe = nullptr;
     double *cpphi = nullptr, *part = nullptr, *dnorm = nullptr;
+    double *ffs = nullptr;  // fine sums of coarse-fine faces, 96 per brick
     double *phib = nullptr, *rhob = nullptr;  // FP64 phi and rho in brick layout during a solve
     double *cgw = nullptr;
     int *cgit = nullptr;
@@ -256,6 +257,30 @@ static const std::vector<double> &cached_direct_tables(const int n[3], const dou
         it = cache.emplace(k, direct_tables(n, h)).first;
     }
     return it->second;
+}
+
+// the direct_tables layout with every matrix zero-padded to P x P, P = n
+// rounded up to a multiple of 16 (the matrix-core tile), and stored in the
+// order the matrix cores take it: for row block rb and step s, 64 values,
+// value l = M[16 rb + l % 16][4 s + l / 16]; eigenvalues as they are
+static void append_padded_tables(std::vector<double> &out, const int n[3], const std::vector<double> &t)
+{
+    size_t off = 0;
+    for (int d = 0; d < 3; ++d) {
+        const int N = n[d], P = (N + 15) & ~15;
+        for (int m = 0; m < 2; ++m, off += (size_t)N * N) {
+            const size_t base = out.size();
+            out.resize(base + (size_t)P * P, 0.0);
+            for (int rb = 0; rb < P / 16; ++rb)
+                for (int s = 0; s < P / 4; ++s)
+                    for (int l = 0; l < 64; ++l) {
+                        const int a = 16 * rb + l % 16, b = 4 * s + l / 16;
+                        if (a < N && b < N)
+                            out[base + ((size_t)rb * (P / 4) + s) * 64 + l] = t[off + (size_t)a * N + b];
+                    }
+        }
+    }
+    out.insert(out.end(), t.begin() + off, t.end());
 }
 
 // Upload D.meta (built without face data) in one copy, then generate the
@@ -406,11 +431,13 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
         J.w = (int)D.dw_doubles;
         J.amr = L.amr >= 0 ? 1 : 0;
         const std::vector<double> &t = cached_direct_tables(L.n, L.h);
-        dtab.insert(dtab.end(), t.begin(), t.end());
+        append_padded_tables(dtab, L.n, t);
         D.dw_doubles += (size_t)L.n[0] * L.n[1] * L.n[2];
         const int jid = (int)djl.size();
         djl.push_back(J);
-        for (int z = 0; z < L.n[2]; ++z) planes.push_back(make_int2(jid, z));
+        // one workgroup per (z plane, block of 16 x frequencies)
+        for (int z = 0; z < L.n[2]; ++z)
+            for (int kb = 0; kb < (L.n[0] + 15) / 16; ++kb) planes.push_back(make_int2(jid, z | kb << 8));
         for (int c = 0; c < L.n[0] * L.n[1]; c += DIRECT_COLS) groups.push_back(make_int2(jid, c));
     }
     D.n_planes = (int)planes.size();
@@ -520,6 +547,7 @@ static size_t ws_need(const DevState &D, int prec)
     s += align256((size_t)m.ncf * 64 * w + 8);         // coarse parts of the cycle
     s += align256((size_t)m.ncf * 64 * 8 + 8);         // coarse parts of phi
     s += align256((size_t)m.nbrick * 16);              // per-wavefront partial norms (two per brick)
+    s += align256((size_t)m.nbrick * 96 * 8);          // fine sums of the coarse-fine faces
     s += align256(sizeof(double) * 2 * (D.range_prob.size() + 1));
     s += align256(D.cg_doubles * 8);
     s += align256(D.dw_doubles * 8 + 8);             // direct-solve scratch
@@ -559,6 +587,7 @@ static amrmg_status ensure_ws(DevState &D, int prec, void *user, size_t user_byt
     D.cpe = take((size_t)m.ncf * 64 * w + 8);
     D.cpphi = (double *)take((size_t)m.ncf * 64 * 8 + 8);
     D.part = (double *)take((size_t)m.nbrick * 16);
+    D.ffs = (double *)take((size_t)m.nbrick * 96 * 8);
     D.dnorm = (double *)take(sizeof(double) * 2 * (D.range_prob.size() + 1));
     D.cgw = (double *)take(D.cg_doubles * 8);
     D.dw = (double *)take(D.dw_doubles * 8 + 8);
@@ -1172,7 +1201,7 @@ struct Driver {
         amr_range(b0, nb, list);
         if (!zero_phi) {
             pb(AMRMG_K_CPART);
-            launch_cpart_brick<double>(st, D.M, 0, m.ncf, D.phib, D.cpphi);
+            launch_cpart_brick<double>(st, D.M, 0, m.ncf, D.phib, D.cpphi, D.phib, D.ffs);
             pe(AMRMG_K_CPART, (double)m.ncf * 16 * (9 + 4) * 8);
         }
         // (a last-workgroup reduction inside the residual kernel would need a
@@ -1180,7 +1209,7 @@ struct Driver {
         // extra launch on a chip whose XCDs have separate L2 caches)
         pb(AMRMG_K_RESIDUAL);
         launch_outer_residual<T>(st, D.M, b0, nb, list, D.phib, D.rhob, o.inv_eps0, zero_phi ? nullptr : D.cpphi,
-                                 (zero_phi || rout_user) ? nullptr : r, D.part, o.norm_p, zero_phi, rout_user);
+                                 (zero_phi || rout_user) ? nullptr : r, D.part, o.norm_p, zero_phi, rout_user, D.ffs);
         pe(AMRMG_K_RESIDUAL, (double)nb * BRICK_CELLS * (zero_phi ? 8.0 : 16.0 + W));
         launch_level_norms(st, D.d_ranges, (int)D.range_prob.size(), D.part, D.dnorm + noff, o.norm_p,
                            publish ? D.h_pub : nullptr, D.h_seq, D.d_seqc);
@@ -1232,14 +1261,16 @@ struct Driver {
         int b0 = step_b0(k), nb = step_nb(k);
         const double n = (double)nb * BRICK_CELLS;
         T *out = (o.nu1 % 2 == 1) ? e : et;
+        // the last pre-smoothing sweep also writes the fine sums of e that the
+        // restriction's coarse-fine update reads
         pb(AMRMG_K_GSRB);
-        launch_hgs<T>(st, D.M, b0, nb, nullptr, out, r, nullptr, D.phib, 1);
+        launch_hgs<T>(st, D.M, b0, nb, nullptr, out, r, nullptr, D.phib, D.ffs, o.nu1 <= 1 ? 1 | 16 : 1);
         pe(AMRMG_K_GSRB, 2.0 * n * W);
         T *src = out;
         for (int i = 1; i < o.nu1; ++i) {
             T *dst = (src == e) ? et : e;
             pb(AMRMG_K_GSRB);
-            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, nullptr, D.phib, 0);
+            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, nullptr, D.phib, D.ffs, i == o.nu1 - 1 ? 16 : 0);
             pe(AMRMG_K_GSRB, 3.0 * n * W);
             src = dst;
         }
@@ -1254,7 +1285,7 @@ struct Driver {
             T *dst = (src == e) ? et : e;
             int mode = (i == 0 ? 2 | 4 : 0) | (i == o.nu2 - 1 ? 8 : 0);
             pb(AMRMG_K_GSRB);
-            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, cpe, D.phib, mode);
+            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, cpe, D.phib, D.ffs, mode);
             // e, r in; e out; the parent value with the fused prolongation;
             // phi read and written on AMR bricks with the fused update
             pe(AMRMG_K_GSRB, (3.0 + (i == 0 ? 0.125 : 0.0)) * n * W + ((mode & 8) ? 16.0 * step_amr_cells(k) : 0.0));
@@ -1277,8 +1308,13 @@ struct Driver {
             const auto &e0 = m.ent[m.step_ent0[k - 1]];
             const auto &e1 = m.ent[m.step_ent0[k] - 1];
             int rf0 = e0.rf0, nrf = e1.rf0 + e1.nrf - e0.rf0;
+            if (!hybrid()) {  // the hybrid sweep writes the fine sums itself
+                const auto &f0 = m.ent[m.step_ent0[k]];
+                const auto &f1 = m.ent[m.step_ent0[k + 1] - 1];
+                launch_face_sums<T>(st, D.M, f0.cf0, f1.cf0 + f1.ncf - f0.cf0, e, D.ffs);
+            }
             pb(AMRMG_K_RESTRICT);
-            launch_restrict<T>(st, D.M, step_b0(k), step_nb(k), D.d_reflux + rf0, nrf, e, r);
+            launch_restrict<T>(st, D.M, step_b0(k), step_nb(k), D.d_reflux + rf0, nrf, e, r, D.ffs);
             pe(AMRMG_K_RESTRICT, (2.0 + 0.125) * n * W + 2.0 * nrf * BRICK_CELLS * W);
         }
         pb(AMRMG_K_BOTTOM);

@@ -14,6 +14,8 @@
 // stored in T (float in mixed precision, double otherwise).
 #include <hip/hip_ext.h>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <hip/hip_runtime.h>
 
 #include "amrmg_internal.hpp"
@@ -306,35 +308,63 @@ __device__ __forceinline__ void tile_ab(const V *tile, const V *alpha, int x, in
 // FP64 composite residual (Alg. 1) on a range of bricks of the AMR levels
 // ---------------------------------------------------------------------------
 
-// Fine part of the flux through the coarse face (d, s) of a coarse cell whose
-// neighbour nl (local cell of coarse brick nb) is covered: the four fine cells
-// next to the face and their inner neighbours, and the coarse parts of their
-// ghosts.  Returns sum over the 4 fine faces of (u_f/3 + u_in/5 - cpart);
-// the coarse operator gets -1/(2 h_d^2) times it.
-template <class UF>
-__device__ double fine_face_sum(const DevMeta &M, int nb, const int *nl, int d, int s, const UF &uf,
-                                const double *cp)
+// Fine part of the flux through a coarse-fine face, per coarse cell of the
+// face: over the four fine cells next to the face, sum (u_f/3 + u_in/5 -
+// cpart) with u_in the fine cell further inside and cpart the coarse part of
+// the fine cell's ghost; the coarse operator gets -1/(2 h_d^2) times it (the
+// flux through the coarse face is the mean of the four fine fluxes).  The
+// fine side computes these sums (it holds the fine values) into
+// ffs[(F * 6 + face) * 16 + m], F the fine brick, face its face towards the
+// coarse cell, m = mu + 4 mv the coarse cell's position on that face; the
+// coarse side reads them through the children of its brick and of its face
+// neighbours, staged in LDS.
+
+// kids[8 f + o]: child o of face neighbour f of brick b, kids[48 + o]: child
+// o of b (-1 where none).  Threads 0..55 load; a barrier must follow.
+__device__ __forceinline__ void stage_kids(const DevMeta &M, int b, int *kids)
 {
-    int F = M.child[nb * 8 + oct_of(nl[0], nl[1], nl[2])];
-    int4 co = M.org[nb], fo = M.org[F];
-    // the fine cell at twice the coarse cell's index, relative to F
-    const int bx = 2 * (co.x + nl[0]) - fo.x, by = 2 * (co.y + nl[1]) - fo.y, bz = 2 * (co.z + nl[2]) - fo.z;
-    const int gfc = -1 - M.nbr[F * 6 + 2 * d + (s < 0)];  // F's face towards the coarse cell
-    const size_t cf = (size_t)(gfc - M.nbc);
-    const int nd = (s > 0) ? 0 : 1;  // the fine layer next to the face along d
+    const int t = threadIdx.x;
+    if (t < 48) {
+        const int nb = M.nbr[b * 6 + (t >> 3)];
+        kids[t] = nb >= 0 ? M.child[nb * 8 + (t & 7)] : -1;
+    } else if (t < 56) {
+        kids[t] = M.child[b * 8 + (t - 48)];
+    }
+}
+
+// the fine sum of the face (d, s) of a coarse cell whose neighbour nl (local
+// cell of the brick inside, or of face neighbour f) is covered
+__device__ __forceinline__ double ffs_at(const double *ffs, const int *kids, bool inside, int f, const int *nl, int d,
+                                         int s)
+{
+    const int o = oct_of(nl[0], nl[1], nl[2]);
+    const int F = kids[inside ? 48 + o : 8 * f + o];
+    int du, dv;
+    transverse(d, du, dv);
+    const int m = (nl[du] & 3) + 4 * (nl[dv] & 3);
+    return ffs[((size_t)F * 6 + 2 * d + (s < 0)) * 16 + m];
+}
+
+// the sum of coarse cell m of face dir of fine brick F from fine values u
+// (brick layout) and the coarse parts c[q] of its four fine ghosts (q = the
+// fine cell's offsets along the two face axes, first axis fastest)
+template <class U>
+__device__ __forceinline__ double face_sum(const U &u, int F, int dir, int m, const double *c)
+{
+    const int d = dir >> 1;
+    const bool plus = dir & 1;
+    int du, dv;
+    transverse(d, du, dv);
+    int l[3], li[3];
+    l[d] = plus ? 7 : 0;
+    li[d] = plus ? 6 : 1;
     double sum = 0.0;
-    for (int bb = 0; bb < 2; ++bb)
-        for (int aa = 0; aa < 2; ++aa) {
-            // offsets along (d, du, dv) = (nd, aa, bb) with du < dv the other two axes
-            int ox = d == 0 ? nd : aa;
-            int oy = d == 1 ? nd : (d == 0 ? aa : bb);
-            int oz = d == 2 ? nd : bb;
-            int fl[3] = {bx + ox, by + oy, bz + oz};
-            int f2[3] = {fl[0] + (d == 0 ? s : 0), fl[1] + (d == 1 ? s : 0), fl[2] + (d == 2 ? s : 0)};
-            int tu = d == 0 ? fl[1] : fl[0], tv = d == 2 ? fl[1] : fl[2];
-            double c = cp ? cp[cf * 64 + tu + 8 * tv] : 0.0;
-            sum += (1.0 / 3.0) * uf(F, fl) + 0.2 * uf(F, f2) - c;
-        }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        l[du] = li[du] = 2 * (m & 3) + (q & 1);
+        l[dv] = li[dv] = 2 * (m >> 2) + (q >> 1);
+        sum += (1.0 / 3.0) * u(F, l[0] + 8 * l[1] + 64 * l[2]) + 0.2 * u(F, li[0] + 8 * li[1] + 64 * li[2]) - c[q];
+    }
     return sum;
 }
 
@@ -343,7 +373,7 @@ __device__ double fine_face_sum(const DevMeta &M, int nb, const int *nl, int d, 
 // brick layout, written as T in brick layout (r_out) and/or FP64 in the
 // caller's layout (r_user), with one partial norm per wavefront (part[2 b],
 // part[2 b + 1]).  A face towards a covered cell takes the mean of the four
-// fine fluxes through it (flux matching).  Bricks with no covered cell and no
+// fine fluxes through it (flux matching), from the fine sums ffs of phi.  Bricks with no covered cell and no
 // covered face neighbour (every brick of the finest level) take the plain
 // 7-point stencil on the tile, corrected on brick faces whose halo is a
 // boundary or coarse-fine ghost.  Two wavefronts per brick, one barrier.
@@ -360,11 +390,12 @@ template <class T, bool ZERO>
 __global__ void __launch_bounds__(RT) k_outer_residual(DevMeta M, int b0, int nb, const double *phib,
                                                        const double *rhob, double inv_eps0, const double *cp_phi,
                                                        T *r_out, double *part, int norm_p, const int32_t *list,
-                                                       double *const *r_user)
+                                                       double *const *r_user, const double *ffs)
 {
     __shared__ double tile[TE * TE * TE];
     __shared__ double alpha[6];
     __shared__ int nbk[6];
+    __shared__ int kids[56];
     __shared__ uint8_t ncm[6];
     constexpr int PER = BRICK_CELLS / RT;
     const int b = pick_brick(b0, nb, list, blockIdx.x);
@@ -375,6 +406,7 @@ __global__ void __launch_bounds__(RT) k_outer_residual(DevMeta M, int b0, int nb
         nbk[threadIdx.x] = f;
         ncm[threadIdx.x] = f >= 0 ? M.cmask[f] : 0;
     }
+    if (!ZERO) stage_kids(M, b, kids);
     double rv[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) rv[k] = rhob[(size_t)b * BRICK_CELLS + threadIdx.x + RT * k] * inv_eps0;
@@ -413,9 +445,8 @@ __global__ void __launch_bounds__(RT) k_outer_residual(DevMeta M, int b0, int nb
                         tile_ab(tile, alpha, x, y, z, d, s, a, bv);
                         Au += L.ih2[d] * ((1.0 - a) * uc - bv);
                     } else if (!ZERO) {
-                        int nl[3] = {qx & 7, qy & 7, qz & 7};
-                        Au += -0.5 * L.ih2[d] *
-                              fine_face_sum(M, inside ? b : nbk[f], nl, d, s, BrickAcc<double>{phib}, cp_phi);
+                        const int nl[3] = {qx & 7, qy & 7, qz & 7};
+                        Au += -0.5 * L.ih2[d] * ffs_at(ffs, kids, inside, f, nl, d, s);
                     }
                 }
             }
@@ -514,23 +545,40 @@ struct SrcBrick {
 };
 
 template <class T, class S>
-__global__ void __launch_bounds__(256) k_cpart(DevMeta M, int cf0, int ncf, S src, T *cp)
+__global__ void __launch_bounds__(256) k_cpart(DevMeta M, int cf0, int ncf, S src, T *cp, const T *fine,
+                                               double *ffs)
 {
     int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= ncf * 16) return;
     int cf = cf0 + (i >> 4), m = i & 15;
     size_t e = (size_t)cf * 16 + m;
+    const int ow = ffs ? M.gf_owner[M.nbc + cf] : 0;
     int pat = M.cf_pat[e];
     double v[9];
     for (int w = 0; w < 9; ++w) v[w] = src(M.cf_idx[e * 9 + w]);
     int mu = m & 3, mv = m >> 2;
+    double c[4];
     for (int q = 0; q < 4; ++q) {
         const double *W = c_cfw + (pat * 4 + q) * 9;
         double s = 0.0;
         for (int w = 0; w < 9; ++w) s += W[w] * v[w];
         int t = (2 * mu + (q & 1)) + 8 * (2 * mv + (q >> 1));
         cp[(size_t)cf * 64 + t] = (T)s;
+        c[q] = (double)(T)s;
     }
+    // with ffs: the fine sum of this coarse cell from the fine values and these coarse parts
+    if (ffs) ffs[((size_t)(ow >> 3) * 6 + (ow & 7)) * 16 + m] = face_sum(SrcB<T>{fine}, ow >> 3, ow & 7, m, c);
+}
+
+// fine sums (zero coarse parts) of the coarse-fine faces [cf0, cf0 + ncf) from e
+template <class T>
+__global__ void __launch_bounds__(256) k_face_sums(DevMeta M, int cf0, int ncf, const T *e, double *ffs)
+{
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= ncf * 16) return;
+    const int ow = M.gf_owner[M.nbc + cf0 + (i >> 4)], m = i & 15;
+    const double c[4] = {0.0, 0.0, 0.0, 0.0};
+    ffs[((size_t)(ow >> 3) * 6 + (ow & 7)) * 16 + m] = face_sum(SrcB<T>{e}, ow >> 3, ow & 7, m, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -617,6 +665,13 @@ struct SrcProl {
     }
 };
 
+// a brick's cells in its LDS tile, as face_sum reads them
+template <class T>
+struct TileAcc {
+    const T *tile;
+    __device__ double operator()(int, int c) const { return (double)tile[tix(c & 7, (c >> 3) & 7, c >> 6)]; }
+};
+
 // Brick-hybrid Gauss-Seidel sweep: red then black over the cells of one
 // brick in LDS, with the halo taken from the previous sweep (Gauss-Seidel
 // inside a brick, Jacobi between bricks, as a parallel Gauss-Seidel works
@@ -624,8 +679,9 @@ struct SrcProl {
 // MODE bits: 1 input is zero; 2 input plus the parent correction (fused
 // prolongation); 4 coarse parts of the coarse-fine ghosts computed from the
 // coarse level's values in ein and stored into cp (else read from cp);
-// 8 phi += result on AMR bricks (fused phi update; phi in brick layout).
-enum { HG_ZERO = 1, HG_PROL = 2, HG_CPIN = 4, HG_PHI = 8 };
+// 8 phi += result on AMR bricks (fused phi update; phi in brick layout);
+// 16 the fine sums of the result on the brick's coarse-fine faces into ffs.
+enum { HG_ZERO = 1, HG_PROL = 2, HG_CPIN = 4, HG_PHI = 8, HG_FFS = 16 };
 
 // threads per brick of the stencil kernels: two wavefronts, so that 16
 // bricks' workgroups fit a CU at once and more loads are in flight
@@ -633,7 +689,7 @@ constexpr int BT = 128;
 
 template <class T, int MODE>
 __global__ void __launch_bounds__(BT) k_hgs(DevMeta M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
-                                            double *phib)
+                                            double *phib, double *ffs)
 {
     __shared__ T tile[TE * TE * TE];  // arithmetic in the cycle's precision T
     __shared__ T alpha[6];
@@ -697,6 +753,17 @@ __global__ void __launch_bounds__(BT) k_hgs(DevMeta M, int b0, int nb, const T *
 #pragma unroll
             for (int k = 0; k < 2; ++k) phib[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]] += (double)v[k][j];
     }
+    // fine sums of the new e on the brick's coarse-fine faces (the coarse
+    // correction, and so the ghosts' coarse parts, are zero at the
+    // restriction that reads them)
+    if ((MODE & HG_FFS) && threadIdx.x < 96) {
+        const int f = threadIdx.x >> 4;
+        if (alpha[f] > (T)0) {
+            const double c[4] = {0.0, 0.0, 0.0, 0.0};
+            const int m = threadIdx.x & 15;
+            ffs[((size_t)b * 6 + f) * 16 + m] = face_sum(TileAcc<T>{tile}, b, f, m, c);
+        }
+    }
 }
 
 // residual of the homogeneous problem at one cell: r - A e (zero coarse data)
@@ -759,17 +826,19 @@ __device__ __forceinline__ void restrict_brick(const DevMeta &M, int b, const T 
 
 // Uncovered coarse cells next to covered ones: r -= B_fine e^l, i.e. add
 // 1/(2 h_d^2) * sum over the 4 fine faces of (e_f/3 + e_in/5) per coarse-fine
-// face (the coarse correction is still zero).  FP64 arithmetic.
+// face (the coarse correction is still zero), from the fine sums ffs of e.
+// FP64 arithmetic.
 template <class T>
-__device__ __forceinline__ void reflux_brick(const DevMeta &M, int b, const T *e, T *r, int *nbk, uint8_t *ncm)
+__device__ __forceinline__ void reflux_brick(const DevMeta &M, int b, const double *ffs, T *r, int *kids,
+                                             uint8_t *ncm)
 {
     const LevelConst L = M.lc[M.org[b].w];
     const uint8_t cm = M.cmask[b];
     if (threadIdx.x < 6) {
         int f = M.nbr[b * 6 + threadIdx.x];
-        nbk[threadIdx.x] = f;
         ncm[threadIdx.x] = f >= 0 ? M.cmask[f] : 0;
     }
+    stage_kids(M, b, kids);
     __syncthreads();
     for (int c = threadIdx.x; c < BRICK_CELLS; c += blockDim.x) {
         const int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
@@ -782,8 +851,8 @@ __device__ __forceinline__ void reflux_brick(const DevMeta &M, int b, const T *e
             bool inside = ((qx | qy | qz) & ~7) == 0;
             bool cov = ((inside ? cm : ncm[f]) >> oct_of(qx & 7, qy & 7, qz & 7)) & 1;
             if (cov) {
-                int nl[3] = {qx & 7, qy & 7, qz & 7};
-                add += 0.5 * L.ih2[d] * fine_face_sum(M, inside ? b : nbk[f], nl, d, s, BrickAcc<T>{e}, nullptr);
+                const int nl[3] = {qx & 7, qy & 7, qz & 7};
+                add += 0.5 * L.ih2[d] * ffs_at(ffs, kids, inside, f, nl, d, s);
             }
         }
         if (add != 0.0) {
@@ -799,16 +868,16 @@ __device__ __forceinline__ void reflux_brick(const DevMeta &M, int b, const T *e
 // two kinds of workgroups run together.
 template <class T>
 __global__ void __launch_bounds__(RT) k_restrict(DevMeta M, int b0, int nb, const int32_t *rlist, int nrf,
-                                                 const T *e, T *r)
+                                                 const T *e, T *r, const double *ffs)
 {
     __shared__ T tile[TE * TE * TE];
     __shared__ T alpha[6];
-    __shared__ int nbk[6];
+    __shared__ int kids[56];
     __shared__ uint8_t ncm[6];
     if ((int)blockIdx.x < nb)
         restrict_brick<T>(M, b0 + xcd_remap(blockIdx.x, nb), e, r, r, tile, alpha);
     else
-        reflux_brick<T>(M, rlist[xcd_remap(blockIdx.x - nb, nrf)], e, r, nbk, ncm);
+        reflux_brick<T>(M, rlist[xcd_remap(blockIdx.x - nb, nrf)], ffs, r, kids, ncm);
 }
 
 // e^l += I e^{l-1}: piecewise-constant injection of the parent value
@@ -1077,10 +1146,12 @@ __device__ int cg_solve_lds(const DevMeta &M, int b0, int nb, const T *rhs, T *e
 // Exact solve of the coarsest grid (one box, homogeneous Dirichlet ghosts) by
 // its separable eigendecomposition: e = Q diag(1/lambda) Q^T r with Q the
 // tensor product of the per-axis orthonormal eigenvector matrices.  Three
-// launches over all jobs: forward transforms along x and y per z plane; along
-// z per group of columns (forward, division by the eigenvalue sum, inverse);
-// inverse along x and y per plane.  FP64 arithmetic, FP64 scratch in natural
-// order (x fastest).
+// launches over all jobs: forward transforms along x and y per (z plane, block
+// of 16 x frequencies); along z per group of 16 columns (forward, division by
+// the eigenvalue sum, inverse); inverse along x and y per (plane, block).  The
+// work is dense FP64 products, bound by the matrix-core rate, so it is cut
+// into 16-wide blocks to occupy every CU (a 64^3 grid gives 256 workgroups per
+// launch).  FP64 scratch in natural order (x fastest).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ size_t direct_cell(const DirectJob &J, int x, int y, int z)
 {
@@ -1091,110 +1162,163 @@ __device__ __forceinline__ size_t direct_cell(const DirectJob &J, int x, int y, 
 
 __device__ __forceinline__ int pad16(int n) { return (n + 15) & ~15; }
 
-// copy an n x n table (row-major) into LDS with row stride ld, zero up to
-// the padded size pad16(n)
-__device__ __forceinline__ void stage_table(double *dst, int ld, const double *src, int n)
-{
-    const int p = pad16(n);
-    for (int t = threadIdx.x; t < p * p; t += blockDim.x) {
-        const int a = t / p, b = t - a * p;
-        dst[a * ld + b] = (a < n && b < n) ? src[a * n + b] : 0.0;
-    }
-}
-
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// C[r][k] = sum_i A[r][i] M[k][i] for r < R, k < N (both multiples of 16),
-// i < K (multiple of 4); A and M in LDS with row stride ld.  On the FP64
-// matrix cores, one 16 x 16 output tile per wavefront at a time:
-// v_mfma_f64 16x16x4 takes A[r0 + l%16][i0 + l/16] and M[k0 + l%16][i0 + l/16]
-// from lane l and returns C[r0 + l/16 + 4j][k0 + l%16] in element j.
-// out(r, k, v) is called for every output.
-template <class F>
-__device__ __forceinline__ void mfma_nt(const double *A, const double *M, int ld, int R, int N, int K, F out)
+// Products on the FP64 matrix cores, one 16 x 16 output tile per wavefront:
+// C[r][k] = sum_i Tb[r][i] D[k][i] with the table Tb (K x K, zero-padded, in
+// global memory in operand order) and the data D (rows of K values in LDS,
+// row stride ld).  v_mfma_f64 16x16x4 takes Tb[r0 + l%16][i0 + l/16] and
+// D[k0 + l%16][i0 + l/16] from lane l and returns C[r0 + l/16 + 4j][k0 + l%16]
+// in element j, so consecutive lanes hold consecutive k.
+struct DTile {
+    int r0, k0;
+    bool on;
+};
+// tile of this wavefront among (R/16) x (N/16) tiles (at most 16: R, N <= 64)
+__device__ __forceinline__ DTile dst_tile(int R, int N)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int tn = N >> 4, tiles = (R >> 4) * tn;
-    for (int u = wave; u < tiles; u += nw) {
-        const int r0 = (u / tn) << 4, k0 = (u % tn) << 4;
-        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-        const double *a = A + (r0 + lr) * ld + lk, *m = M + (k0 + lr) * ld + lk;
-        for (int i0 = 0; i0 < K; i0 += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i0], m[i0], acc, 0, 0, 0);
+    const int u = threadIdx.x >> 6, tr = R >> 4;
+    DTile t;
+    t.on = u < tr * (N >> 4);
+    t.r0 = (u % tr) << 4;
+    t.k0 = (u / tr) << 4;
+    return t;
+}
+// this lane's operands of the table rows of tile t: tb[s] = Tb[r0 + l%16][4s + l/16],
+// from the table stored in that order (64 consecutive values per row block and step)
+__device__ __forceinline__ void dst_rows(const double *Tb, int K, const DTile &t, double (&tb)[16])
+{
+    const double *p = Tb + (size_t)(t.r0 >> 4) * (K >> 2) * 64 + (threadIdx.x & 63);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) out(r0 + lk + 4 * j, k0 + lr, acc[j]);
+    for (int s = 0; s < 16; ++s) tb[s] = (t.on && 4 * s < K) ? p[64 * s] : 0.0;
+}
+template <class F>
+__device__ __forceinline__ void dst_mfma(const double (&tb)[16], const double *D, int ld, int K, const DTile &t, F out)
+{
+    if (!t.on) return;
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const double *d = D + (t.k0 + lr) * ld + lk;
+    dbl4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};  // two chains (even and odd steps)
+#pragma unroll
+    for (int s = 0; s < 16; s += 2) {
+        if (4 * s < K) a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[s], d[4 * s], a0, 0, 0, 0);
+        if (4 * s + 4 < K) a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[s + 1], d[4 * s + 4], a1, 0, 0, 0);
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out(t.r0 + lk + 4 * j, t.k0 + lr, j, a0[j] + a1[j]);
 }
 
-// transforms along x and y of one z plane; forward (r -> W) or inverse
-// (W -> e, phi += e).  Dynamic LDS: four ld x ld arrays, ld = padded
-// largest edge + 1.
+// table pool layout per job: forward and inverse matrices of x, y, z, each
+// P_d x P_d with P_d = pad16(n_d), zero-padded, in matrix-core operand order
+// (dst_rows); then the eigenvalues of x, y, z (n_d each)
+__device__ __forceinline__ const double *dst_table(const DirectJob &J, const double *tab, int d, bool inv)
+{
+    const int px = pad16(J.dn[0]), py = pad16(J.dn[1]), pz = pad16(J.dn[2]);
+    int off = J.tab;
+    if (d >= 1) off += 2 * px * px;
+    if (d >= 2) off += 2 * py * py;
+    const int p = d == 0 ? px : (d == 1 ? py : pz);
+    return tab + off + (inv ? p * p : 0);
+}
+
+// transforms along x and y of one z plane for one block of 16 x-frequencies
+// kx (x positions on the inverse), forward (r -> W) or inverse (W -> e,
+// phi += e): the x transform of the whole plane restricted to the block,
+// then the y transform of the block.  planes[i] = (job, z | block << 8).
+// Dynamic LDS: rows + 16 rows of ld doubles, rows = pad16(largest edge).
 template <class T, bool INV>
-__global__ void __launch_bounds__(1024) k_dst_plane(const DirectJob *jobs, const int2 *planes, const double *tab,
-                                                   double *W, const T *r, T *e, double *phib, int phi_update, int ld)
+__global__ void __launch_bounds__(256) k_dst_plane(const DirectJob *jobs, const int2 *planes, const double *tab,
+                                                  double *W, const T *r, T *e, double *phib, int phi_update, int ld,
+                                                  int rows)
 {
     extern __shared__ double sm[];
-    double *A = sm, *Bt = A + ld * ld, *Mx = Bt + ld * ld, *My = Mx + ld * ld;  // plane [y][x], [kx][y], tables
     const int2 pl = planes[blockIdx.x];
     const DirectJob J = jobs[pl.x];
-    const int nx = J.dn[0], ny = J.dn[1], z = pl.y, np = nx * ny;
+    const int nx = J.dn[0], ny = J.dn[1], z = pl.y & 255, kx0 = (pl.y >> 8) << 4, np = nx * ny;
     const int px = pad16(nx), py = pad16(ny);
-    const double *tx = tab + J.tab, *ty = tx + 2 * nx * nx;
+    double *A = sm, *Bt = sm + rows * ld;  // plane [y][x]; x-transformed block [kx - kx0][y]
     double *w = W + J.w + (size_t)np * z;
-    stage_table(Mx, ld, INV ? tx + nx * nx : tx, nx);
-    stage_table(My, ld, INV ? ty + ny * ny : ty, ny);
-    for (int i = threadIdx.x; i < px * py; i += blockDim.x) {
-        const int y = i / px, x = i - y * px;
-        double v = 0.0;
-        if (x < nx && y < ny) v = INV ? w[y * nx + x] : (double)r[direct_cell(J, x, y, z)];
-        A[y * ld + x] = v;
+    // table rows of both transforms first, then the plane: all loads in flight together
+    const DTile t1 = dst_tile(16, py), t2 = dst_tile(py, 16);
+    double m1[16], m2[16];
+    dst_rows(dst_table(J, tab, 0, INV) + (size_t)(kx0 >> 4) * (px >> 2) * 64, px, t1, m1);
+    dst_rows(dst_table(J, tab, 1, INV), py, t2, m2);
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = threadIdx.x + 256 * q, y = i / px, x = i - y * px;
+        v[q] = 0.0;
+        if (y < ny && x < nx) v[q] = INV ? w[y * nx + x] : (double)r[direct_cell(J, x, y, z)];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = threadIdx.x + 256 * q, y = i / px, x = i - y * px;
+        if (y < py) A[y * ld + x] = v[q];
     }
     __syncthreads();
-    // along x: out[y][kx] = sum_x A[y][x] Mx[kx][x], stored as Bt[kx][y]
-    mfma_nt(A, Mx, ld, py, px, px, [&](int y, int kx, double v) { Bt[kx * ld + y] = v; });
+    // along x: Bt[kx - kx0][y] = sum_x Mx[kx][x] A[y][x]
+    dst_mfma(m1, A, ld, px, t1, [&](int kx, int y, int, double s) { Bt[kx * ld + y] = s; });
     __syncthreads();
-    // along y: out[kx][ky] = sum_y Bt[kx][y] My[ky][y]
-    mfma_nt(Bt, My, ld, px, py, py, [&](int x, int y, double v) {
+    // along y: out[ky][kx] = sum_y My[ky][y] Bt[kx - kx0][y]
+    dst_mfma(m2, Bt, ld, py, t2, [&](int y, int xl, int, double s) {
+        const int x = kx0 + xl;
         if (x >= nx || y >= ny) return;
         if (!INV) {
-            w[y * nx + x] = v;
+            w[y * nx + x] = s;
         } else {
-            size_t bi = direct_cell(J, x, y, z);
-            e[bi] = (T)v;
-            if (phi_update && J.amr) phib[bi] += v;
+            const size_t bi = direct_cell(J, x, y, z);
+            e[bi] = (T)s;
+            if (phi_update && J.amr) phib[bi] += s;
         }
     });
 }
 
 // transform along z of a group of DIRECT_COLS columns: forward, division by
-// the eigenvalue sum, inverse.  Dynamic LDS: two DIRECT_COLS x ld arrays and
-// two ld x ld tables.
-__global__ void __launch_bounds__(1024) k_dst_column(const DirectJob *jobs, const int2 *groups, const double *tab,
-                                                    double *W, int ld)
+// the eigenvalue sum, inverse.  groups[i] = (job, first column).  Dynamic
+// LDS: two arrays of DIRECT_COLS rows of ld doubles.
+__global__ void __launch_bounds__(256) k_dst_column(const DirectJob *jobs, const int2 *groups, const double *tab,
+                                                   double *W, int ld)
 {
     extern __shared__ double sm[];
-    double *A = sm, *C = A + DIRECT_COLS * ld, *Fz = C + DIRECT_COLS * ld, *Bz = Fz + ld * ld;  // [col][z], [col][kz]
+    double *A = sm, *C = sm + DIRECT_COLS * ld;  // [col][z], [col][kz]
     const int2 gr = groups[blockIdx.x];
     const DirectJob J = jobs[gr.x];
     const int nx = J.dn[0], ny = J.dn[1], nz = J.dn[2], np = nx * ny, pz = pad16(nz);
     const int c0 = gr.y;  // np is a multiple of DIRECT_COLS
-    const double *tz = tab + J.tab + 2 * (nx * nx + ny * ny);
-    const double *mux = tz + 2 * nz * nz, *muy = mux + nx, *muz = muy + ny;
+    const double *mux = dst_table(J, tab, 2, false) + 2 * pz * pz, *muy = mux + nx, *muz = muy + ny;
     double *w = W + J.w;
-    stage_table(Fz, ld, tz, nz);
-    stage_table(Bz, ld, tz + nz * nz, nz);
-    for (int i = threadIdx.x; i < pz * DIRECT_COLS; i += blockDim.x) {
-        const int zz = i / DIRECT_COLS, c = i % DIRECT_COLS;
-        A[c * ld + zz] = zz < nz ? w[(size_t)np * zz + c0 + c] : 0.0;
+    const DTile t = dst_tile(pz, DIRECT_COLS);
+    double mf[16], mb[16];
+    dst_rows(dst_table(J, tab, 2, false), pz, t, mf);
+    dst_rows(dst_table(J, tab, 2, true), pz, t, mb);
+    // eigenvalue sums of this lane's outputs: column k0 + l%16, kz = r0 + l/16 + 4j
+    const int lane = threadIdx.x & 63, col = c0 + t.k0 + (lane & 15);
+    double muc = 0.0, mz[4] = {1.0, 1.0, 1.0, 1.0};
+    if (t.on) {
+        muc = mux[col % nx] + muy[col / nx];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int kz = t.r0 + (lane >> 4) + 4 * j;
+            if (kz < nz) mz[j] = muz[kz];
+        }
+    }
+    constexpr int NV = DIRECT_DIM * DIRECT_COLS / 256;
+    double v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const int i = threadIdx.x + 256 * q, zz = i / DIRECT_COLS, c = i % DIRECT_COLS;
+        v[q] = zz < nz ? w[(size_t)np * zz + c0 + c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const int i = threadIdx.x + 256 * q, zz = i / DIRECT_COLS, c = i % DIRECT_COLS;
+        if (zz < pz) A[c * ld + zz] = v[q];
     }
     __syncthreads();
-    mfma_nt(A, Fz, ld, DIRECT_COLS, pz, pz, [&](int c, int kz, double v) {
-        const int idx = c0 + c;
-        C[c * ld + kz] = kz < nz ? v / (mux[idx % nx] + muy[idx / nx] + muz[kz]) : 0.0;
-    });
+    dst_mfma(mf, A, ld, pz, t, [&](int kz, int c, int j, double s) { C[c * ld + kz] = kz < nz ? s / (muc + mz[j]) : 0.0; });
     __syncthreads();
-    mfma_nt(C, Bz, ld, DIRECT_COLS, pz, pz, [&](int c, int zz, double v) {
-        if (zz < nz) w[(size_t)np * zz + c0 + c] = v;
+    dst_mfma(mb, C, ld, pz, t, [&](int zz, int c, int, double s) {
+        if (zz < nz) w[(size_t)np * zz + c0 + c] = s;
     });
 }
 
@@ -1591,15 +1715,15 @@ static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + p
 template <class T>
 void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, const double *phib,
                            const double *rhob, double inv_eps0, const double *cp_phi, T *r_out, double *part,
-                           int norm_p, bool zero_phi, double *const *r_user)
+                           int norm_p, bool zero_phi, double *const *r_user, const double *ffs)
 {
     if (nb <= 0) return;
     if (zero_phi)
         AMRMG_LAUNCH((k_outer_residual<T, true>), dim3(nb), dim3(RT), 0, st, M, b0, nb, phib, rhob, inv_eps0,
-                     cp_phi, r_out, part, norm_p, list, r_user);
+                     cp_phi, r_out, part, norm_p, list, r_user, ffs);
     else
         AMRMG_LAUNCH((k_outer_residual<T, false>), dim3(nb), dim3(RT), 0, st, M, b0, nb, phib, rhob, inv_eps0,
-                     cp_phi, r_out, part, norm_p, list, r_user);
+                     cp_phi, r_out, part, norm_p, list, r_user, ffs);
 }
 
 void launch_user_brick(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, bool to_brick,
@@ -1617,12 +1741,21 @@ void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double 
 }
 
 template <class T>
-void launch_cpart_brick(hipStream_t st, const DevMeta &M, int cf0, int ncf, const T *src, T *cp)
+void launch_cpart_brick(hipStream_t st, const DevMeta &M, int cf0, int ncf, const T *src, T *cp, const T *fine,
+                        double *ffs)
 {
     if (ncf <= 0) return;
     SrcBrick<T> s{src};
     AMRMG_LAUNCH((k_cpart<T, SrcBrick<T>>), dim3(blocks_for((int64_t)ncf * 16, 256)), dim3(256), 0, st, M,
-                       cf0, ncf, s, cp);
+                       cf0, ncf, s, cp, fine, ffs);
+}
+
+template <class T>
+void launch_face_sums(hipStream_t st, const DevMeta &M, int cf0, int ncf, const T *e, double *ffs)
+{
+    if (ncf <= 0) return;
+    AMRMG_LAUNCH((k_face_sums<T>), dim3(blocks_for((int64_t)ncf * 16, 256)), dim3(256), 0, st, M, cf0, ncf, e,
+                 ffs);
 }
 
 template <class T>
@@ -1643,10 +1776,10 @@ void launch_jacobi(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ei
 
 template <class T>
 void launch_restrict(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *rlist, int nrf, const T *e,
-                     T *r)
+                     T *r, const double *ffs)
 {
     if (nb + nrf <= 0) return;
-    AMRMG_LAUNCH((k_restrict<T>), dim3(nb + nrf), dim3(RT), 0, st, M, b0, nb, rlist, nrf, e, r);
+    AMRMG_LAUNCH((k_restrict<T>), dim3(nb + nrf), dim3(RT), 0, st, M, b0, nb, rlist, nrf, e, r, ffs);
 }
 
 template <class T>
@@ -1737,22 +1870,25 @@ void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, doubl
 
 template <class T>
 void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
-                double *phib, int mode)
+                double *phib, double *ffs, int mode)
 {
     if (nb <= 0) return;
     dim3 g(nb), blk(BT);
+#define AMRMG_HGS(MD)                                                                                        \
+    case MD: AMRMG_LAUNCH((k_hgs<T, MD>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib, ffs); return;
     switch (mode) {
-    case HG_ZERO: AMRMG_LAUNCH((k_hgs<T, HG_ZERO>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib); break;
-    case 0: AMRMG_LAUNCH((k_hgs<T, 0>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib); break;
-    case HG_PHI: AMRMG_LAUNCH((k_hgs<T, HG_PHI>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib); break;
-    case HG_PROL | HG_CPIN:
-        AMRMG_LAUNCH((k_hgs<T, HG_PROL | HG_CPIN>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib);
-        break;
-    case HG_PROL | HG_CPIN | HG_PHI:
-        AMRMG_LAUNCH((k_hgs<T, HG_PROL | HG_CPIN | HG_PHI>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib);
-        break;
+        AMRMG_HGS(0)
+        AMRMG_HGS(HG_ZERO)
+        AMRMG_HGS(HG_FFS)
+        AMRMG_HGS(HG_ZERO | HG_FFS)
+        AMRMG_HGS(HG_PHI)
+        AMRMG_HGS(HG_PROL | HG_CPIN)
+        AMRMG_HGS(HG_PROL | HG_CPIN | HG_PHI)
     default: break;
     }
+#undef AMRMG_HGS
+    fprintf(stderr, "libamrmg: no sweep kernel for mode %d\n", mode);
+    abort();
 }
 
 template <class T>
@@ -1772,21 +1908,20 @@ void launch_direct(hipStream_t st, const DirectJob *jobs, const int2 *planes, in
                    int maxdim)
 {
     if (nplanes <= 0) return;
-    const int ld = ((maxdim + 15) & ~15) + 1;
-    const size_t sp = sizeof(double) * 4 * ld * ld, sc = sizeof(double) * (2 * DIRECT_COLS * ld + 2 * ld * ld);
-    static bool attr = false;  // allow more than 64 KiB of dynamic LDS (up to 4 x 65^2 doubles)
+    const int rows = (maxdim + 15) & ~15, ld = rows + 1;
+    const size_t sp = sizeof(double) * (rows + 16) * ld, sc = sizeof(double) * 2 * DIRECT_COLS * ld;
+    static bool attr = false;  // allow more than 64 KiB of dynamic LDS
     if (!attr) {
-        const int lim = (int)(sizeof(double) * 4 * 65 * 65);
+        const int lim = (int)(sizeof(double) * (DIRECT_DIM + 16) * (DIRECT_DIM + 1));
         (void)hipFuncSetAttribute((const void *)k_dst_plane<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         (void)hipFuncSetAttribute((const void *)k_dst_plane<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        (void)hipFuncSetAttribute((const void *)k_dst_column, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         attr = true;
     }
-    AMRMG_LAUNCH((k_dst_plane<T, false>), dim3(nplanes), dim3(1024), sp, st, jobs, planes, tab, W, r, e, phib,
-                 (int)phi_update, ld);
-    AMRMG_LAUNCH(k_dst_column, dim3(ngroups), dim3(1024), sc, st, jobs, groups, tab, W, ld);
-    AMRMG_LAUNCH((k_dst_plane<T, true>), dim3(nplanes), dim3(1024), sp, st, jobs, planes, tab, W, r, e, phib,
-                 (int)phi_update, ld);
+    AMRMG_LAUNCH((k_dst_plane<T, false>), dim3(nplanes), dim3(256), sp, st, jobs, planes, tab, W, r, e, phib,
+                 (int)phi_update, ld, rows);
+    AMRMG_LAUNCH(k_dst_column, dim3(ngroups), dim3(256), sc, st, jobs, groups, tab, W, ld);
+    AMRMG_LAUNCH((k_dst_plane<T, true>), dim3(nplanes), dim3(256), sp, st, jobs, planes, tab, W, r, e, phib,
+                 (int)phi_update, ld, rows);
 }
 
 template <class T>
@@ -1826,13 +1961,15 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val)
 #define AMRMG_INST(T)                                                                                            \
     template void launch_outer_residual<T>(hipStream_t, const DevMeta &, int, int, const int32_t *,               \
                                            const double *, const double *, double, const double *, T *, double *, \
-                                           int, bool, double *const *);                                           \
-    template void launch_cpart_brick<T>(hipStream_t, const DevMeta &, int, int, const T *, T *);                \
+                                           int, bool, double *const *, const double *);                           \
+    template void launch_cpart_brick<T>(hipStream_t, const DevMeta &, int, int, const T *, T *, const T *,      \
+                                        double *);                                                              \
+    template void launch_face_sums<T>(hipStream_t, const DevMeta &, int, int, const T *, double *);             \
     template void launch_gsrb<T>(hipStream_t, const DevMeta &, int, int, T *, const T *, const T *, int, bool);  \
     template void launch_jacobi<T>(hipStream_t, const DevMeta &, int, int, const T *, T *, const T *, const T *, \
                                    double, bool);                                                                \
     template void launch_restrict<T>(hipStream_t, const DevMeta &, int, int, const int32_t *, int, const T *,   \
-                                     T *);                                                                      \
+                                     T *, const double *);                                                      \
     template void launch_prolong<T>(hipStream_t, const DevMeta &, int, int, T *);                                \
     template void launch_phi_update<T>(hipStream_t, const DevMeta &, int, int, const int32_t *, double *,         \
                                        const T *);                                                               \
@@ -1840,7 +1977,7 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val)
                                       double, int, int *);                                                      \
     template void launch_copy<T>(hipStream_t, const T *, T *, int64_t);                                         \
     template void launch_hgs<T>(hipStream_t, const DevMeta &, int, int, const T *, T *, const T *, T *,         \
-                                double *, int);                                                                 \
+                                double *, double *, int);                                                       \
     template void launch_coarse_cycle<T>(hipStream_t, const DevMeta &, const CoarseJob *, int, T *, T *,        \
                                          double *, int, int, double, int, int *, double *, bool, int);          \
     template void launch_direct<T>(hipStream_t, const DirectJob *, const int2 *, int, const int2 *, int,         \

@@ -52,7 +52,7 @@ struct DirectJob {
 };
 constexpr int DIRECT_DIM = 64;
 // columns per workgroup of the transform along z
-constexpr int DIRECT_COLS = 64;
+constexpr int DIRECT_COLS = 16;
 
 hipError_t upload_cf_weights(const double *w);
 // window masks of patterns 0..12 and (u0, v0, nodes) of patterns 0..13
@@ -67,11 +67,15 @@ void launch_face_data(hipStream_t st, const DevMeta &M, const EntryDev *ent, con
 void set_launch_timing(hipEvent_t start, hipEvent_t stop);
 bool launch_timing_pending();
 
-// phib, rhob: FP64 phi and rho in brick layout
+// Fine sums ffs: per fine brick F, face f and coarse cell m of that face,
+// ffs[(F * 6 + f) * 16 + m] = sum over the four fine cells next to the face of
+// (u_f/3 + u_in/5 - coarse part of the ghost), written for coarse-fine faces.
+
+// phib, rhob: FP64 phi and rho in brick layout; ffs: fine sums of phib
 template <class T>
 void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, const double *phib,
                            const double *rhob, double inv_eps0, const double *cp_phi, T *r_out, double *part,
-                           int norm_p, bool zero_phi, double *const *r_user);
+                           int norm_p, bool zero_phi, double *const *r_user, const double *ffs);
 // caller's layout (per-level pointer tables a, bu) <-> brick layout (ab, bb)
 void launch_user_brick(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, bool to_brick,
                        double *const *a, double *ab, double *const *bu, double *bb);
@@ -79,8 +83,14 @@ void launch_user_brick(hipStream_t st, const DevMeta &M, int b0, int nb, const i
 // memory followed by the sequence number *counter + 1 at hseq
 void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double *part, double *out, int norm_p,
                         double *hout = nullptr, unsigned *hseq = nullptr, unsigned *counter = nullptr);
+// coarse parts cp of the ghosts of coarse-fine faces [cf0, cf0 + ncf) from
+// the coarse values src; with ffs, also the fine sums from the fine values
 template <class T>
-void launch_cpart_brick(hipStream_t st, const DevMeta &M, int cf0, int ncf, const T *src, T *cp);
+void launch_cpart_brick(hipStream_t st, const DevMeta &M, int cf0, int ncf, const T *src, T *cp,
+                        const T *fine = nullptr, double *ffs = nullptr);
+// fine sums of e (zero coarse parts) of coarse-fine faces [cf0, cf0 + ncf)
+template <class T>
+void launch_face_sums(hipStream_t st, const DevMeta &M, int cf0, int ncf, const T *e, double *ffs);
 template <class T>
 void launch_gsrb(hipStream_t st, const DevMeta &M, int b0, int nb, T *e, const T *r, const T *cp, int colour,
                  bool init);
@@ -88,10 +98,11 @@ template <class T>
 void launch_jacobi(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, const T *cp,
                    double omega, bool init);
 // restriction of nb fine bricks from b0 (r -> parents' covered cells) and the
-// coarse-fine update of the nrf listed coarse bricks, in one launch
+// coarse-fine update of the nrf listed coarse bricks (from the fine sums of
+// e), in one launch
 template <class T>
 void launch_restrict(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *rlist, int nrf, const T *e,
-                     T *r);
+                     T *r, const double *ffs);
 template <class T>
 void launch_prolong(hipStream_t st, const DevMeta &M, int b0, int nb, T *e);
 template <class T>
@@ -105,10 +116,11 @@ void launch_bottom_cg(hipStream_t st, const DevMeta &M, const int4 *jobs, int nj
                       double *work, double rtol, int maxit, int *iters);
 template <class T>
 void launch_copy(hipStream_t st, const T *a, T *b, int64_t n);
-// brick-hybrid Gauss-Seidel sweep; mode = bits of HG_ZERO 1, HG_PROL 2, HG_CPIN 4, HG_PHI 8
+// brick-hybrid Gauss-Seidel sweep; mode = bits of HG_ZERO 1, HG_PROL 2, HG_CPIN 4, HG_PHI 8,
+// HG_FFS 16 (fine sums of the result into ffs)
 template <class T>
 void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
-                double *phib, int mode);
+                double *phib, double *ffs, int mode);
 // direct solve e = A^-1 r of the coarsest grids of the listed jobs: planes
 // (job, z) for the x/y transforms, column groups (job, first column) for the
 // z transform; FP64 scratch W; phi += e on AMR grids when phi_update
