@@ -178,6 +178,8 @@ struct DevState {
     DirectJob *d_djobs = nullptr;
     int2 *d_planes = nullptr, *d_groups = nullptr;
     int n_planes = 0, n_groups = 0, direct_maxdim = 0;
+    int n_djobs = 0;
+    DirectJob djob0{};  // host copy of the job when there is one
     size_t dw_doubles = 0;
     double *dw = nullptr;
     int kc = 0;  // levels 0..kc of every problem run in the one-workgroup coarse cycle
@@ -442,6 +444,8 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
     }
     D.n_planes = (int)planes.size();
     D.n_groups = (int)groups.size();
+    D.n_djobs = (int)djl.size();
+    if (D.n_djobs == 1) D.djob0 = djl[0];
     if (dtab.empty()) dtab.push_back(0.0);
     if (djl.empty()) djl.push_back(DirectJob{});
     if (planes.empty()) planes.push_back(make_int2(0, 0));
@@ -1319,7 +1323,7 @@ struct Driver {
         }
         pb(AMRMG_K_BOTTOM);
         launch_direct<T>(st, D.d_djobs, D.d_planes, D.n_planes, D.d_groups, D.n_groups, D.d_dtab, D.dw, r, e, D.phib,
-                         hybrid(), D.direct_maxdim);
+                         hybrid(), D.direct_maxdim, D.n_djobs == 1 ? &D.djob0 : nullptr);
         if (D.n_cg > 0)
             launch_coarse_cycle<T>(st, D.M, D.d_cjobs, D.njobs, e, r, D.cgw, o.nu1, o.nu2, o.bottom_rtol, 10000,
                                    D.cgit, D.phib, hybrid(), D.cg_threads);

@@ -1224,17 +1224,30 @@ __device__ __forceinline__ const double *dst_table(const DirectJob &J, const dou
 // transforms along x and y of one z plane for one block of 16 x-frequencies
 // kx (x positions on the inverse), forward (r -> W) or inverse (W -> e,
 // phi += e): the x transform of the whole plane restricted to the block,
-// then the y transform of the block.  planes[i] = (job, z | block << 8).
+// then the y transform of the block.  planes[i] = (job, z | block << 8), or
+// with jobs == nullptr the one job J1 and workgroup z * blocks + block.
 // Dynamic LDS: rows + 16 rows of ld doubles, rows = pad16(largest edge).
 template <class T, bool INV>
-__global__ void __launch_bounds__(256) k_dst_plane(const DirectJob *jobs, const int2 *planes, const double *tab,
-                                                  double *W, const T *r, T *e, double *phib, int phi_update, int ld,
-                                                  int rows)
+__global__ void __launch_bounds__(256) k_dst_plane(const DirectJob *jobs, const int2 *planes, DirectJob J1,
+                                                  const double *tab, double *W, const T *r, T *e, double *phib,
+                                                  int phi_update, int ld, int rows)
 {
     extern __shared__ double sm[];
-    const int2 pl = planes[blockIdx.x];
-    const DirectJob J = jobs[pl.x];
-    const int nx = J.dn[0], ny = J.dn[1], z = pl.y & 255, kx0 = (pl.y >> 8) << 4, np = nx * ny;
+    // one job (jobs == nullptr): J1, workgroup = z * blocks + block; else from the lists
+    int z, kb;
+    DirectJob J;
+    if (!jobs) {
+        J = J1;
+        const int nkb = pad16(J.dn[0]) >> 4;
+        z = blockIdx.x / nkb;
+        kb = blockIdx.x - z * nkb;
+    } else {
+        const int2 pl = planes[blockIdx.x];
+        J = jobs[pl.x];
+        z = pl.y & 255;
+        kb = pl.y >> 8;
+    }
+    const int nx = J.dn[0], ny = J.dn[1], kx0 = kb << 4, np = nx * ny;
     const int px = pad16(nx), py = pad16(ny);
     double *A = sm, *Bt = sm + rows * ld;  // plane [y][x]; x-transformed block [kx - kx0][y]
     double *w = W + J.w + (size_t)np * z;
@@ -1243,17 +1256,19 @@ __global__ void __launch_bounds__(256) k_dst_plane(const DirectJob *jobs, const 
     double m1[16], m2[16];
     dst_rows(dst_table(J, tab, 0, INV) + (size_t)(kx0 >> 4) * (px >> 2) * 64, px, t1, m1);
     dst_rows(dst_table(J, tab, 1, INV), py, t2, m2);
+    // the plane in rows of 64: x = thread % 64, y = thread / 64 + 4 q
+    const int x = threadIdx.x & 63, y0 = threadIdx.x >> 6;
     double v[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        const int i = threadIdx.x + 256 * q, y = i / px, x = i - y * px;
+        const int y = y0 + 4 * q;
         v[q] = 0.0;
         if (y < ny && x < nx) v[q] = INV ? w[y * nx + x] : (double)r[direct_cell(J, x, y, z)];
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        const int i = threadIdx.x + 256 * q, y = i / px, x = i - y * px;
-        if (y < py) A[y * ld + x] = v[q];
+        const int y = y0 + 4 * q;
+        if (y < py && x < px) A[y * ld + x] = v[q];
     }
     __syncthreads();
     // along x: Bt[kx - kx0][y] = sum_x Mx[kx][x] A[y][x]
@@ -1274,17 +1289,25 @@ __global__ void __launch_bounds__(256) k_dst_plane(const DirectJob *jobs, const 
 }
 
 // transform along z of a group of DIRECT_COLS columns: forward, division by
-// the eigenvalue sum, inverse.  groups[i] = (job, first column).  Dynamic
+// the eigenvalue sum, inverse.  groups[i] = (job, first column), or with
+// jobs == nullptr the one job J1 and columns from DIRECT_COLS * workgroup.  Dynamic
 // LDS: two arrays of DIRECT_COLS rows of ld doubles.
-__global__ void __launch_bounds__(256) k_dst_column(const DirectJob *jobs, const int2 *groups, const double *tab,
-                                                   double *W, int ld)
+__global__ void __launch_bounds__(256) k_dst_column(const DirectJob *jobs, const int2 *groups, DirectJob J1,
+                                                   const double *tab, double *W, int ld)
 {
     extern __shared__ double sm[];
     double *A = sm, *C = sm + DIRECT_COLS * ld;  // [col][z], [col][kz]
-    const int2 gr = groups[blockIdx.x];
-    const DirectJob J = jobs[gr.x];
+    DirectJob J;
+    int c0;  // np is a multiple of DIRECT_COLS
+    if (!jobs) {  // one job: J1, workgroup = column group
+        J = J1;
+        c0 = blockIdx.x * DIRECT_COLS;
+    } else {
+        const int2 gr = groups[blockIdx.x];
+        J = jobs[gr.x];
+        c0 = gr.y;
+    }
     const int nx = J.dn[0], ny = J.dn[1], nz = J.dn[2], np = nx * ny, pz = pad16(nz);
-    const int c0 = gr.y;  // np is a multiple of DIRECT_COLS
     const double *mux = dst_table(J, tab, 2, false) + 2 * pz * pz, *muy = mux + nx, *muz = muy + ny;
     double *w = W + J.w;
     const DTile t = dst_tile(pz, DIRECT_COLS);
@@ -1905,7 +1928,7 @@ void launch_coarse_cycle(hipStream_t st, const DevMeta &M, const CoarseJob *jobs
 template <class T>
 void launch_direct(hipStream_t st, const DirectJob *jobs, const int2 *planes, int nplanes, const int2 *groups,
                    int ngroups, const double *tab, double *W, const T *r, T *e, double *phib, bool phi_update,
-                   int maxdim)
+                   int maxdim, const DirectJob *one)
 {
     if (nplanes <= 0) return;
     const int rows = (maxdim + 15) & ~15, ld = rows + 1;
@@ -1917,10 +1940,13 @@ void launch_direct(hipStream_t st, const DirectJob *jobs, const int2 *planes, in
         (void)hipFuncSetAttribute((const void *)k_dst_plane<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         attr = true;
     }
-    AMRMG_LAUNCH((k_dst_plane<T, false>), dim3(nplanes), dim3(256), sp, st, jobs, planes, tab, W, r, e, phib,
+    // one job: its record goes by value and the workgroups' lists are not read
+    const DirectJob J1 = one ? *one : DirectJob{};
+    const DirectJob *jl = one ? nullptr : jobs;
+    AMRMG_LAUNCH((k_dst_plane<T, false>), dim3(nplanes), dim3(256), sp, st, jl, planes, J1, tab, W, r, e, phib,
                  (int)phi_update, ld, rows);
-    AMRMG_LAUNCH(k_dst_column, dim3(ngroups), dim3(256), sc, st, jobs, groups, tab, W, ld);
-    AMRMG_LAUNCH((k_dst_plane<T, true>), dim3(nplanes), dim3(256), sp, st, jobs, planes, tab, W, r, e, phib,
+    AMRMG_LAUNCH(k_dst_column, dim3(ngroups), dim3(256), sc, st, jl, groups, J1, tab, W, ld);
+    AMRMG_LAUNCH((k_dst_plane<T, true>), dim3(nplanes), dim3(256), sp, st, jl, planes, J1, tab, W, r, e, phib,
                  (int)phi_update, ld, rows);
 }
 
@@ -1981,7 +2007,7 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val)
     template void launch_coarse_cycle<T>(hipStream_t, const DevMeta &, const CoarseJob *, int, T *, T *,        \
                                          double *, int, int, double, int, int *, double *, bool, int);          \
     template void launch_direct<T>(hipStream_t, const DirectJob *, const int2 *, int, const int2 *, int,         \
-                                   const double *, double *, const T *, T *, double *, bool, int);
+                                   const double *, double *, const T *, T *, double *, bool, int, const DirectJob *);
 AMRMG_INST(float)
 AMRMG_INST(double)
 #undef AMRMG_INST

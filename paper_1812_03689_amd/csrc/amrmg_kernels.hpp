@@ -122,12 +122,14 @@ template <class T>
 void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
                 double *phib, double *ffs, int mode);
 // direct solve e = A^-1 r of the coarsest grids of the listed jobs: planes
-// (job, z) for the x/y transforms, column groups (job, first column) for the
-// z transform; FP64 scratch W; phi += e on AMR grids when phi_update
+// (job, z | x-block << 8) for the x/y transforms, column groups (job, first
+// column) for the z transform; FP64 scratch W; phi += e on AMR grids when
+// phi_update.  one: the only job (host copy), when there is one; the lists
+// are then implied by the launch shape.
 template <class T>
 void launch_direct(hipStream_t st, const DirectJob *jobs, const int2 *planes, int nplanes, const int2 *groups,
                    int ngroups, const double *tab, double *W, const T *r, T *e, double *phib, bool phi_update,
-                   int maxdim);
+                   int maxdim, const DirectJob *one);
 template <class T>
 void launch_coarse_cycle(hipStream_t st, const DevMeta &M, const CoarseJob *jobs, int njobs, T *e, T *r,
                          double *work, int nu1, int nu2, double rtol, int maxit, int *iters, double *phib,
