@@ -531,7 +531,7 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
     D.d_E = D.d_rout + ne;
     HIP_TRY(D.h_normbuf.ensure(sizeof(double) * 2 * (D.range_prob.size() + 1)));
     D.h_norm = (double *)D.h_normbuf.p;
-    HIP_TRY(D.pubbuf.ensure(sizeof(double) * (D.range_prob.size() + 8)));
+    HIP_TRY(D.pubbuf.ensure(sizeof(double) * (2 * D.range_prob.size() + 8)));
     D.h_seq = (unsigned *)D.pubbuf.p;
     D.h_pub = (double *)D.pubbuf.p + 1;
     D.ws_prec = -1;  // carve the workspace again for the new hierarchy
@@ -1197,8 +1197,8 @@ struct Driver {
     }
 
     // outer FP64 residual of every AMR level; norms into dnorm[off ..] (and
-    // published to the host when publish is set)
-    void outer(bool zero_phi, int noff, double *const *rout_user, bool publish = false)
+    // published to the host at h_pub[pub_off ..] when publish is set)
+    void outer(bool zero_phi, int noff, double *const *rout_user, bool publish = false, int pub_off = 0)
     {
         int b0, nb;
         const int32_t *list;
@@ -1216,7 +1216,7 @@ struct Driver {
                                  (zero_phi || rout_user) ? nullptr : r, D.part, o.norm_p, zero_phi, rout_user, D.ffs);
         pe(AMRMG_K_RESIDUAL, (double)nb * BRICK_CELLS * (zero_phi ? 8.0 : 16.0 + W));
         launch_level_norms(st, D.d_ranges, (int)D.range_prob.size(), D.part, D.dnorm + noff, o.norm_p,
-                           publish ? D.h_pub : nullptr, D.h_seq, D.d_seqc);
+                           publish ? D.h_pub + pub_off : nullptr, D.h_seq, D.d_seqc);
     }
 
     void smooth(int k, int nu, bool pre)
@@ -1428,13 +1428,35 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
     D.seq = 0;
     *(volatile unsigned *)D.h_seq = 0;
     HIP_TRY(hipEventRecord(ev0, st));
+    // norms of b (zero phi) to h_pub[nr ..], of the initial residual to
+    // h_pub[0 ..]; each publication bumps the sequence number
     drv.to_bricks(true);
-    drv.outer(true, 0, nullptr);
-    drv.outer(false, nr, nullptr);
-    HIP_TRY(hipMemcpyAsync(D.h_norm, D.dnorm, sizeof(double) * 2 * nr, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    drv.outer(true, 0, nullptr, true, nr);
+    drv.outer(false, nr, nullptr, true, 0);
     HIP_TRY(hipGetLastError());
-    std::vector<double> bn(D.h_norm, D.h_norm + nr), rn(D.h_norm + nr, D.h_norm + 2 * nr);
+    // the first iteration is queued before the initial norms are read; when
+    // the initial guess already meets the tolerance it only refines phi, and
+    // the norms reported are those after it
+    const bool first_queued = o.max_iters > 0;
+    if (first_queued) ST_TRY(iterate<T>(D, drv, st, nr, o, g_use_graphs));
+    // wait for publication number want in host memory (no stream
+    // synchronisation); after a second without it, synchronise and look again
+    auto wait_pub = [&](unsigned want) -> amrmg_status {
+        auto t0 = std::chrono::steady_clock::now();
+        for (unsigned spin = 0; *(volatile unsigned *)D.h_seq < want; ++spin) {
+            if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) {
+                HIP_TRY(hipStreamSynchronize(st));
+                if (*(volatile unsigned *)D.h_seq < want)
+                    return fail(AMRMG_E_HIP, "the iteration's norms did not reach the host");
+                break;
+            }
+        }
+        HIP_TRY(hipGetLastError());
+        return AMRMG_OK;
+    };
+    D.seq = 2;
+    ST_TRY(wait_pub(D.seq));
+    std::vector<double> bn(D.h_pub + nr, D.h_pub + 2 * nr), rn(D.h_pub, D.h_pub + nr);
     // a level without right-hand side uses its problem's composite norm
     std::vector<double> tot(np, 0.0);
     for (int i = 0; i < nr; ++i) {
@@ -1461,21 +1483,15 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
     };
     int it = 0;
     bool all = check(0);
+    if (first_queued) {
+        ST_TRY(wait_pub(++D.seq));
+        rn.assign(D.h_pub, D.h_pub + nr);
+        it = 1;
+        if (!all) all = check(1);
+    }
     while (!all && it < o.max_iters) {
         ST_TRY(iterate<T>(D, drv, st, nr, o, g_use_graphs));
-        // wait for the iteration's norms in host memory (no stream synchronisation);
-        // after a second without them, synchronise and look again
-        const unsigned want = ++D.seq;
-        auto t0 = std::chrono::steady_clock::now();
-        for (unsigned spin = 0; *(volatile unsigned *)D.h_seq != want; ++spin) {
-            if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) {
-                HIP_TRY(hipStreamSynchronize(st));
-                if (*(volatile unsigned *)D.h_seq != want)
-                    return fail(AMRMG_E_HIP, "the iteration's norms did not reach the host");
-                break;
-            }
-        }
-        HIP_TRY(hipGetLastError());
+        ST_TRY(wait_pub(++D.seq));
         rn.assign(D.h_pub, D.h_pub + nr);
         ++it;
         all = check(it);
