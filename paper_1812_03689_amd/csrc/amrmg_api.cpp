@@ -689,7 +689,7 @@ struct amrmg_ctx {
     PBuf tag_stage, tag_host;
     // spatial visiting order of the particles (a performance hint for the
     // deposit; any order gives the same sums up to rounding)
-    DBuf sort_keys, sort_vals, sort_tmp;
+    DBuf sort_keys, sort_vals, sort_cnt, sort_tmp;
     DBuf sorted;  // the particles in visiting order, for the tagging passes of one build
     uint32_t *perm = nullptr;
     int64_t perm_n = -1;
@@ -792,26 +792,45 @@ static DepLevel dep_level(const Problem &P, const HostLevel &L, const int32_t *b
     return D;
 }
 
-// Morton order of the particles at the resolution of the finest allowed level
+// Visiting order of the particles (Morton-ordered buckets of the level-0
+// grid); with copy, also the particles in that order in ctx->sorted
+// (charges first, then x, y, z), returned through xs, ys, zs, qs
 static amrmg_status compute_order(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y, const void *z,
-                                  int64_t n)
+                                  const double *q, int64_t n, bool copy, const void **xs, const void **ys,
+                                  const void **zs, const double **qs)
 {
     ctx->perm = nullptr;
     ctx->perm_n = -1;
     if (n <= 0 || n > (int64_t)0x7fffffff) return AMRMG_OK;
     const amrmg_params &P = ctx->P;
-    int nf[3];
-    for (int d = 0; d < 3; ++d) nf[d] = P.n0[d] << P.max_level;
-    size_t tb = sort_temp_bytes(n);
-    HIP_TRY(ctx->sort_keys.ensure(sizeof(uint64_t) * 2 * n));
-    HIP_TRY(ctx->sort_vals.ensure(sizeof(uint32_t) * 2 * n));
-    HIP_TRY(ctx->sort_tmp.ensure(tb));
-    uint32_t *perm = nullptr;
-    HIP_TRY(particle_order(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, P.lo, P.hi, nf,
-                           (uint64_t *)ctx->sort_keys.p, (uint32_t *)ctx->sort_vals.p, ctx->sort_tmp.p,
-                           ctx->sort_tmp.cap, &perm));
-    ctx->perm = perm;
+    const size_t entries = order_count_entries(P.lo, P.hi, P.n0);
+    HIP_TRY(ctx->sort_keys.ensure(sizeof(uint32_t) * 2 * (size_t)n));
+    HIP_TRY(ctx->sort_vals.ensure(sizeof(uint32_t) * (size_t)n));
+    HIP_TRY(ctx->sort_cnt.ensure(sizeof(uint32_t) * 2 * entries));
+    HIP_TRY(ctx->sort_tmp.ensure(order_temp_bytes(entries) + 256));
+    char *cx = nullptr, *cy = nullptr, *cz = nullptr;
+    double *cq = nullptr;
+    if (copy) {
+        const size_t ps = pos_dtype == AMRMG_POS_F32 ? 4 : 8;
+        HIP_TRY(ctx->sorted.ensure((size_t)n * (3 * ps + 8) + 1024));
+        char *base = (char *)ctx->sorted.p;
+        cq = (double *)base;
+        cx = base + align256((size_t)n * 8);
+        cy = cx + align256((size_t)n * ps);
+        cz = cy + align256((size_t)n * ps);
+    }
+    uint32_t *key = (uint32_t *)ctx->sort_keys.p, *cnt = (uint32_t *)ctx->sort_cnt.p;
+    HIP_TRY(particle_order(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, P.lo, P.hi, P.n0, key, key + n, cnt,
+                           cnt + entries, (uint32_t *)ctx->sort_vals.p, ctx->sort_tmp.p, ctx->sort_tmp.cap, cx, cy,
+                           cz, cq));
+    ctx->perm = (uint32_t *)ctx->sort_vals.p;
     ctx->perm_n = n;
+    if (copy) {
+        *xs = cx;
+        *ys = cy;
+        *zs = cz;
+        *qs = cq;
+    }
     return AMRMG_OK;
 }
 
@@ -898,26 +917,14 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
     }
     ctx->built = false;
     ++ctx->generation;
-    ST_TRY(compute_order(ctx, pos_dtype, x, y, z, n));
     // the tagging passes read the particles in visiting order from a copy
-    const void *tx = x, *ty = y, *tz = z;
-    const double *tq = q;
-    const uint32_t *tperm = ctx->perm_n == n ? ctx->perm : nullptr;
+    // made with the order
     bool need_tags = false;
     for (int l = 1; l <= P.max_level; ++l) need_tags = need_tags || !expl.count(l);
-    if (tperm && need_tags) {
-        const size_t ps = pos_dtype == AMRMG_POS_F32 ? 4 : 8;
-        HIP_TRY(ctx->sorted.ensure((size_t)n * (3 * ps + 8) + 1024));
-        char *base = (char *)ctx->sorted.p;
-        double *qs = (double *)base;
-        char *xs = base + align256((size_t)n * 8), *ys = xs + align256((size_t)n * ps), *zs = ys + align256((size_t)n * ps);
-        launch_permute(ctx->st, pos_dtype == AMRMG_POS_F32, n, tperm, x, y, z, q, xs, ys, zs, qs);
-        tx = xs;
-        ty = ys;
-        tz = zs;
-        tq = qs;
-        tperm = nullptr;
-    }
+    const void *tx = x, *ty = y, *tz = z;
+    const double *tq = q;
+    ST_TRY(compute_order(ctx, pos_dtype, x, y, z, q, n, need_tags, &tx, &ty, &tz, &tq));
+    const uint32_t *tperm = ctx->perm_n == n && !need_tags ? ctx->perm : nullptr;
 
     Problem &pr = ctx->prob;
     // the previous build's AMR levels lend their storage to the new ones

@@ -143,15 +143,17 @@ void launch_gather(hipStream_t st, int pos_f32, int64_t n, const void *x, const 
                    double *Ey, double *Ez);
 void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, double *scratch, uint8_t *tags);
 void launch_fill(hipStream_t st, double *v, int64_t n, double val);
-// spatial (Morton) visiting order of particles: keys [2n], vals [2n]; on
-// success *perm_out points at the sorted indices (vals + n)
-size_t sort_temp_bytes(int64_t n);
+// spatial visiting order of particles (counting sort into Morton-ordered
+// buckets of the level-0 grid n0, at most 128 per axis): perm [n]; with xs,
+// also the particles in that order (xs, ys, zs in the position type, qs).
+// key, slot: [n] each; count, start: [order_count_entries] each; temp:
+// order_temp_bytes(order_count_entries) bytes
+size_t order_count_entries(const double *lo, const double *hi, const int *n0);
+size_t order_temp_bytes(size_t entries);
 hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
-                          const double *lo, const double *hi, const int *nf, uint64_t *keys, uint32_t *vals,
-                          void *temp, size_t temp_bytes, uint32_t **perm_out);
-// particles in the visiting order perm (xs[i] = x[perm[i]], ...)
-void launch_permute(hipStream_t st, int pos_f32, int64_t n, const uint32_t *perm, const void *x, const void *y,
-                    const void *z, const double *q, void *xs, void *ys, void *zs, double *qs);
+                          const double *q, const double *lo, const double *hi, const int *n0, uint32_t *key,
+                          uint32_t *slot, uint32_t *count, uint32_t *start, uint32_t *perm, void *temp,
+                          size_t temp_bytes, void *xs, void *ys, void *zs, double *qs);
 void launch_mark_blocks(hipStream_t st, const double *rho, int64_t ncell, const int4 *borg, const int64_t *ubase,
                         const int2 *ustr, int nb, double lambda, int nbuf, int half, int3 n, int3 g, double *scratch,
                         uint8_t *marks);

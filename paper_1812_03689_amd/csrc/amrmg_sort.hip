@@ -1,9 +1,13 @@
-// amrmg_sort.hip -- spatial visiting order of the particles for the deposit:
-// a Morton (Z-order) key of each particle's cell at a fine resolution, sorted
-// with the rocPRIM radix sort (through hipCUB).  In Z-order every cell of
-// every coarser level is a contiguous key range, so after the sort the
-// particles that a workgroup deposits or gathers fall into a few cells and
-// the deposit of a workgroup stays inside a small LDS tile on every level.
+// amrmg_sort.hip -- spatial visiting order of the particles for the deposit,
+// the gather and the tagging passes: a counting sort of the particles into
+// buckets, the cells of a grid of at most 128 cells per axis (the level-0
+// cells, merged 2^3 at a time while an axis has more), numbered in Morton
+// (Z) order.  In Z-order the buckets of any aligned block are contiguous, so
+// consecutive particles fall into a few neighbouring buckets and the
+// deposit of a workgroup stays inside a small LDS tile on every level; the
+// order inside a bucket does not matter (it is the order in which the
+// particles claimed their slots).  Three passes: count with slot claims,
+// exclusive scan of the counts (hipCUB), scatter.
 #include <hip/hip_runtime.h>
 
 #include <hipcub/hipcub.hpp>
@@ -12,117 +16,125 @@
 
 namespace amrmg {
 
-__device__ __forceinline__ uint64_t spread3(uint32_t v)
+__device__ __forceinline__ uint32_t spread3_10(uint32_t v)
 {
-    uint64_t x = v & 0x1fffff;  // 21 bits
-    x = (x | (x << 32)) & 0x1f00000000ffffull;
-    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
-    x = (x | (x << 8)) & 0x100f00f00f00f00full;
-    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
-    x = (x | (x << 2)) & 0x1249249249249249ull;
+    uint32_t x = v & 0x3ff;  // 10 bits
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
     return x;
 }
 
-template <class P, class K>
-__global__ void __launch_bounds__(256) k_morton_keys(int64_t n, const P *x, const P *y, const P *z, double lo0,
-                                                     double lo1, double lo2, double hi0, double hi1, double hi2,
-                                                     int3 nf, K *keys, uint32_t *vals)
+struct BucketGrid {
+    double lo[3], scale[3];  // cell = floor((x - lo) * scale) on the level-0 grid
+    int n[3];                // level-0 cells per axis
+    int shift;               // bucket = cell >> shift
+    uint32_t nbkt;           // Morton space of the buckets; bucket nbkt holds the particles outside
+};
+
+template <class P>
+__global__ void __launch_bounds__(256) k_bucket_count(int64_t n, const P *x, const P *y, const P *z, BucketGrid G,
+                                                      uint32_t *count, uint32_t *key, uint32_t *slot)
 {
-    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
-    double X[3] = {(double)x[p], (double)y[p], (double)z[p]};
-    double lo[3] = {lo0, lo1, lo2}, hi[3] = {hi0, hi1, hi2};
-    int nn[3] = {nf.x, nf.y, nf.z};
-    uint64_t key = 0;
+    const double X[3] = {(double)x[p], (double)y[p], (double)z[p]};
+    uint32_t k = 0;
     bool inside = true;
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-        if (!(X[d] >= lo[d] && X[d] < hi[d])) inside = false;
-        double s = (X[d] - lo[d]) / (hi[d] - lo[d]) * nn[d];
+        const double s = (X[d] - G.lo[d]) * G.scale[d];
+        if (!(s >= 0.0 && s < (double)G.n[d])) inside = false;
         int c = (int)floor(s);
-        c = c < 0 ? 0 : (c >= nn[d] ? nn[d] - 1 : c);
-        key |= spread3((uint32_t)c) << d;
+        c = c < 0 ? 0 : (c >= G.n[d] ? G.n[d] - 1 : c);
+        k |= spread3_10((uint32_t)(c >> G.shift)) << d;
     }
-    keys[p] = inside ? (K)key : ~(K)0;  // particles outside the domain go last
-    vals[p] = (uint32_t)p;
+    if (!inside) k = G.nbkt;
+    key[p] = k;
+    slot[p] = atomicAdd(&count[k], 1u);
 }
 
-// Keys are 32-bit when the Morton code of the grid fits (up to 1024 cells per
-// axis), 64-bit beyond.
-size_t sort_temp_bytes(int64_t n)
+// perm[dst] = p at dst = start of p's bucket + p's slot; with xs, also the
+// particle itself (positions and charge) at dst
+template <class P>
+__global__ void __launch_bounds__(256) k_bucket_scatter(int64_t n, const uint32_t *key, const uint32_t *slot,
+                                                        const uint32_t *start, uint32_t *perm, const P *x,
+                                                        const P *y, const P *z, const double *q, P *xs, P *ys, P *zs,
+                                                        double *qs)
 {
-    size_t b32 = 0, b64 = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b32, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                             (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n, 0, 32);
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b64, (const uint64_t *)nullptr, (uint64_t *)nullptr,
-                                             (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n, 0, 63);
-    return b32 > b64 ? b32 : b64;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t dst = start[key[p]] + slot[p];
+    perm[dst] = (uint32_t)p;
+    if (xs) {
+        xs[dst] = x[p];
+        ys[dst] = y[p];
+        zs[dst] = z[p];
+        qs[dst] = q[p];
+    }
 }
 
-template <class K>
-static hipError_t order_with(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
-                             const double *lo, const double *hi, int3 nn, int end_bit, K *keys, uint32_t *vals,
-                             void *temp, size_t temp_bytes)
+static BucketGrid bucket_grid(const double *lo, const double *hi, const int *n0)
 {
-    unsigned g = (unsigned)((n + 255) / 256);
-    if (pos_f32)
-        hipLaunchKernelGGL((k_morton_keys<float, K>), dim3(g), dim3(256), 0, st, n, (const float *)x,
-                           (const float *)y, (const float *)z, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], nn, keys,
-                           vals);
-    else
-        hipLaunchKernelGGL((k_morton_keys<double, K>), dim3(g), dim3(256), 0, st, n, (const double *)x,
-                           (const double *)y, (const double *)z, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], nn, keys,
-                           vals);
-    size_t tb = temp_bytes;
-    return hipcub::DeviceRadixSort::SortPairs(temp, tb, keys, keys + n, vals, vals + n, (int)n, 0, end_bit, st);
+    BucketGrid G{};
+    int m = 1;
+    for (int d = 0; d < 3; ++d) {
+        G.lo[d] = lo[d];
+        G.scale[d] = (double)n0[d] / (hi[d] - lo[d]);
+        G.n[d] = n0[d];
+        m = n0[d] > m ? n0[d] : m;
+    }
+    int bits = 0;
+    while ((1 << bits) < m) ++bits;
+    G.shift = bits > 7 ? bits - 7 : 0;
+    bits -= G.shift;
+    G.nbkt = 1u << (3 * bits);
+    return G;
+}
+
+size_t order_count_entries(const double *lo, const double *hi, const int *n0)
+{
+    return (size_t)bucket_grid(lo, hi, n0).nbkt + 1;
+}
+
+size_t order_temp_bytes(size_t entries)
+{
+    size_t b = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                           (int)entries);
+    return b;
 }
 
 hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
-                          const double *lo, const double *hi, const int *nf, uint64_t *keys, uint32_t *vals,
-                          void *temp, size_t temp_bytes, uint32_t **perm_out)
+                          const double *q, const double *lo, const double *hi, const int *n0, uint32_t *key,
+                          uint32_t *slot, uint32_t *count, uint32_t *start, uint32_t *perm, void *temp,
+                          size_t temp_bytes, void *xs, void *ys, void *zs, double *qs)
 {
-    *perm_out = nullptr;
     if (n <= 0) return hipSuccess;
-    int3 nn = make_int3(nf[0], nf[1], nf[2]);
-    int bits = 0;
-    int m = nf[0] > nf[1] ? nf[0] : nf[1];
-    m = m > nf[2] ? m : nf[2];
-    while ((1 << bits) < m) ++bits;
-    hipError_t e;
-    if (3 * bits <= 32)
-        e = order_with<uint32_t>(st, pos_f32, n, x, y, z, lo, hi, nn, 3 * bits, (uint32_t *)keys, vals, temp,
-                                 temp_bytes);
-    else
-        e = order_with<uint64_t>(st, pos_f32, n, x, y, z, lo, hi, nn, 3 * bits < 63 ? 3 * bits : 63, keys, vals,
-                                 temp, temp_bytes);
+    const BucketGrid G = bucket_grid(lo, hi, n0);
+    const int entries = (int)G.nbkt + 1;
+    hipError_t e = hipMemsetAsync(count, 0, sizeof(uint32_t) * entries, st);
     if (e != hipSuccess) return e;
-    *perm_out = vals + n;
-    return hipGetLastError();
-}
-
-template <class P>
-__global__ void __launch_bounds__(256) k_permute(int64_t n, const uint32_t *perm, const P *x, const P *y, const P *z,
-                                                 const double *q, P *xs, P *ys, P *zs, double *qs)
-{
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    int64_t p = perm[i];
-    xs[i] = x[p];
-    ys[i] = y[p];
-    zs[i] = z[p];
-    qs[i] = q[p];
-}
-
-void launch_permute(hipStream_t st, int pos_f32, int64_t n, const uint32_t *perm, const void *x, const void *y,
-                    const void *z, const double *q, void *xs, void *ys, void *zs, double *qs)
-{
-    if (n <= 0) return;
-    unsigned g = (unsigned)((n + 255) / 256);
+    const unsigned g = (unsigned)((n + 255) / 256);
     if (pos_f32)
-        hipLaunchKernelGGL((k_permute<float>), dim3(g), dim3(256), 0, st, n, perm, (const float *)x,
-                           (const float *)y, (const float *)z, q, (float *)xs, (float *)ys, (float *)zs, qs);
+        hipLaunchKernelGGL((k_bucket_count<float>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
+                           (const float *)z, G, count, key, slot);
     else
-        hipLaunchKernelGGL((k_permute<double>), dim3(g), dim3(256), 0, st, n, perm, (const double *)x,
-                           (const double *)y, (const double *)z, q, (double *)xs, (double *)ys, (double *)zs, qs);
+        hipLaunchKernelGGL((k_bucket_count<double>), dim3(g), dim3(256), 0, st, n, (const double *)x,
+                           (const double *)y, (const double *)z, G, count, key, slot);
+    size_t tb = temp_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(temp, tb, count, start, entries, st);
+    if (e != hipSuccess) return e;
+    if (pos_f32)
+        hipLaunchKernelGGL((k_bucket_scatter<float>), dim3(g), dim3(256), 0, st, n, key, slot, start, perm,
+                           (const float *)x, (const float *)y, (const float *)z, q, (float *)xs, (float *)ys,
+                           (float *)zs, qs);
+    else
+        hipLaunchKernelGGL((k_bucket_scatter<double>), dim3(g), dim3(256), 0, st, n, key, slot, start, perm,
+                           (const double *)x, (const double *)y, (const double *)z, q, (double *)xs, (double *)ys,
+                           (double *)zs, qs);
+    return hipGetLastError();
 }
 
 }  // namespace amrmg
