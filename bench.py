@@ -2,8 +2,10 @@
 
 One step = the whole path on one batch of particles: build the hierarchy
 (deposit, tag, box generation on every level), deposit the charge on every
-level, solve to the relative residual tolerance with the mixed-precision
-cycle, compute E, gather E to the particles.  Inputs are resident in device
+level (amrmg_deposit_built: the levels the build deposited are copied, the
+finest is deposited from the build's ordered particle copy), solve to the
+relative residual tolerance with the mixed-precision cycle, compute E,
+gather E to the particles.  Inputs are resident in device
 memory before the timed region.
 
 Default workload: 1e6 particles of a Gaussian bunch with sigma (0.05, 0.05,
@@ -146,7 +148,7 @@ def bench_batch(args):
     def step():
         for c, w, (x, y, z, q), r in zip(cm, ws, data, rho):
             c.build_hierarchy(x, y, z, q, tag_rel=w.tag_rel)
-            amrmg.amrmg_deposit(c.h, x, y, z, q, r)
+            amrmg.amrmg_deposit_built(c.h, r)
         for ph in phi:
             for t in ph:
                 t.zero_()
@@ -196,7 +198,7 @@ def bench_batch(args):
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "64 independent problems: base 16/24/32/48, 1-2 refined levels (ratio 2, tag "
                                "1e-3 x max|rho|), 1e4-1e5 Gaussian particles each, monopole Dirichlet, tol 1e-8",
-                   "dof": dof, "step": "64 x (build_hierarchy + deposit) + one batched mixed solve"},
+                   "dof": dof, "step": "64 x (build_hierarchy + deposit_built) + one batched mixed solve"},
         "batch": {"batch_mixed_solve_ms": batch_ms, "sequential_fp64_solves_ms": seq["fp64"],
                   "sequential_mixed_solves_ms": seq["mixed"], "batch_dof_per_s": dof / (batch_ms * 1e-3),
                   "speedup_vs_sequential_fp64": seq["fp64"] / batch_ms,
@@ -270,7 +272,7 @@ def main():
 
     def step():
         cm.build_hierarchy(x, y, z, q, tag_rel=w.tag_rel, explicit_boxes=w.explicit_boxes)
-        amrmg.amrmg_deposit(cm.h, x, y, z, q, rho)
+        amrmg.amrmg_deposit_built(cm.h, rho)
         for t in phi:
             t.zero_()
         st = amrmg.amrmg_solve(cm.h, rho, phi, E, tol)
@@ -324,7 +326,7 @@ def main():
         cm.build_hierarchy(x, y, z, q, tag_rel=w.tag_rel, explicit_boxes=w.explicit_boxes)
         torch.cuda.synchronize()
         b = time.perf_counter()
-        amrmg.amrmg_deposit(cm.h, x, y, z, q, rho)
+        amrmg.amrmg_deposit_built(cm.h, rho)
         torch.cuda.synchronize()
         c = time.perf_counter()
         for t in phi:
@@ -377,7 +379,7 @@ def main():
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": describe(w), "dof": dof, "ncells": info["ncells"], "nboxes": info["nboxes"],
                    "precision": "mixed", "smoother": args.smoother, "tol": tol,
-                   "step": "build_hierarchy + deposit + solve + E + gather"},
+                   "step": "build_hierarchy + deposit_built + solve + E + gather"},
         "roofline": roofline,
         "solve": solve,
         "iters": iters[-1],

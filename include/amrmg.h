@@ -173,6 +173,20 @@ amrmg_status amrmg_deposit(amrmg_ctx *ctx, int pos_dtype, const void *x, const v
                            const void *z, const double *q, int64_t n, double *const *rho,
                            int64_t *n_outside);
 
+/* The same cloud-in-cell deposit (same weights, clamping, skipped particles
+ * and count) of the particles given to the last amrmg_build_hierarchy,
+ * without reading them again: the build keeps the charge of every level it
+ * deposited for its tagging passes (each level below the last tagged one)
+ * and a copy of the particles in spatial order, from which the other levels
+ * (the finest, and levels whose next level was given explicitly) are
+ * deposited here.  The deposit a PIC step does anyway after a regrid
+ * (Sec. 1's particle-mesh cycle: deposit, solve, gather) then costs little
+ * more than copies.  rho and n_outside as in amrmg_deposit.
+ * AMRMG_E_STATE when no hierarchy is built, or when the build kept no copy
+ * (more than 2^31 - 1 particles).  The particle arrays given to the build
+ * may have changed since: the result is that of the build's particles. */
+amrmg_status amrmg_deposit_built(amrmg_ctx *ctx, double *const *rho, int64_t *n_outside);
+
 /* Solve the composite problem (Alg. 2 of the paper): A_comp phi = rho/eps0
  * with A = -Laplacian discretised by flux differencing with flux matching at
  * coarse-fine faces (Eqs. lap_flux_differencing, coarse_fluxes,

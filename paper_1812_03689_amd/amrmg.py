@@ -32,7 +32,7 @@ AMRMG_MAX_LEVELS = 8
 
 EXPORTED = ["amrmg_default_params", "amrmg_create", "amrmg_destroy", "amrmg_last_error",
             "amrmg_build_hierarchy", "amrmg_hierarchy_info", "amrmg_get_boxes", "amrmg_cf_faces",
-            "amrmg_workspace_size", "amrmg_set_workspace", "amrmg_deposit", "amrmg_solve",
+            "amrmg_workspace_size", "amrmg_set_workspace", "amrmg_deposit", "amrmg_deposit_built", "amrmg_solve",
             "amrmg_gather", "amrmg_residual", "amrmg_solve_batch", "amrmg_profile_enable",
             "amrmg_profile_read"]
 KCLASS = ["gsrb", "jacobi", "restrict", "prolong", "reflux", "cpart", "residual", "phi_update", "bottom",
@@ -91,6 +91,7 @@ def lib():
         L.amrmg_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.amrmg_set_workspace.argtypes = [vp, vp, C.c_size_t]
         L.amrmg_deposit.argtypes = [vp, C.c_int, vp, vp, vp, vp, i64, vp, vp]
+        L.amrmg_deposit_built.argtypes = [vp, vp, vp]
         L.amrmg_solve.argtypes = [vp, vp, vp, vp, dbl, C.POINTER(amrmg_solve_stats)]
         L.amrmg_gather.argtypes = [vp, C.c_int, vp, vp, vp, i64, vp, vp, vp, vp]
         L.amrmg_residual.argtypes = [vp, vp, vp, vp]
@@ -211,6 +212,12 @@ def amrmg_deposit(h, x, y, z, q, rho: Sequence) -> int:
     return nout.value
 
 
+def amrmg_deposit_built(h, rho: Sequence) -> int:
+    nout = C.c_int64()
+    _check(lib().amrmg_deposit_built(h, _ptrs(rho), C.byref(nout)))
+    return nout.value
+
+
 def amrmg_solve(h, rho: Sequence, phi: Sequence, E: Optional[Sequence], tol: float, allow_not_converged=True):
     st = amrmg_solve_stats()
     allow = (AMRMG_E_NOT_CONVERGED,) if allow_not_converged else ()
@@ -323,6 +330,12 @@ class Context:
     def deposit(self, x, y, z, q, rho=None):
         rho = rho if rho is not None else self.level_arrays()
         nout = amrmg_deposit(self.h, x, y, z, q, rho)
+        return rho, nout
+
+    def deposit_built(self, rho=None):
+        """Charge of the particles of the last build_hierarchy (amrmg_deposit_built)."""
+        rho = rho if rho is not None else self.level_arrays()
+        nout = amrmg_deposit_built(self.h, rho)
         return rho, nout
 
     def solve(self, rho, phi=None, E=None, tol=1e-8, want_E=True):

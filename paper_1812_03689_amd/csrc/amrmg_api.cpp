@@ -685,15 +685,24 @@ struct amrmg_ctx {
     bool built = false;
     DevState ds;
     // scratch of the tagging passes of build_hierarchy
-    DBuf tag_rho, tag_marks, tag_scratch, tag_geom;
+    DBuf tag_marks, tag_scratch, tag_geom;
     PBuf tag_stage, tag_host;
     // spatial visiting order of the particles (a performance hint for the
     // deposit; any order gives the same sums up to rounding)
     DBuf sort_keys, sort_vals, sort_cnt, sort_tmp;
-    DBuf sorted;  // the particles in visiting order, for the tagging passes of one build
+    DBuf sorted;  // the particles of the last build in visiting order (charges, x, y, z)
     uint32_t *perm = nullptr;
     int64_t perm_n = -1;
     DBuf dep_count;
+    // what the last build keeps for amrmg_deposit_built: the charge of each
+    // level it deposited for tagging (caller's layout), the particle count
+    // and position type of the ordered copy, and its count of particles
+    // outside the domain (device, valid when level 0 was deposited)
+    std::vector<DBuf> lev_rho;
+    std::vector<char> lev_rho_ok;
+    int64_t built_n = -1;
+    int built_pos = -1;
+    DBuf built_nout;
     void *user_ws = nullptr;
     size_t user_ws_bytes = 0;
     int generation = 0;
@@ -838,7 +847,7 @@ static amrmg_status compute_order(amrmg_ctx *ctx, int pos_dtype, const void *x, 
 // l+1 on the device; the host then applies nesting and the greedy merge.
 static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype, const void *x, const void *y,
                               const void *z, const double *q, int64_t n, double lambda, std::vector<Box> &boxes,
-                              const uint32_t *perm)
+                              const uint32_t *perm, unsigned long long *nout)
 {
     const amrmg_params &P = ctx->P;
     hipStream_t st = ctx->st;
@@ -872,11 +881,12 @@ static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype,
     int3 nn = make_int3(L.n[0], L.n[1], L.n[2]);
     int3 g = make_int3(2 * L.n[0] / P.blocking_factor, 2 * L.n[1] / P.blocking_factor, 2 * L.n[2] / P.blocking_factor);
     size_t ng = (size_t)g.x * g.y * g.z;
-    HIP_TRY(ctx->tag_rho.ensure(sizeof(double) * nc));
+    // the level's charge is kept for amrmg_deposit_built
+    HIP_TRY(ctx->lev_rho[L.amr].ensure(sizeof(double) * nc));
     HIP_TRY(ctx->tag_scratch.ensure(sizeof(double) * 1040));
     HIP_TRY(ctx->tag_marks.ensure(ng));
     HIP_TRY(ctx->tag_host.ensure(ng));
-    double *rho = (double *)ctx->tag_rho.p;
+    double *rho = (double *)ctx->lev_rho[L.amr].p;
     launch_fill(st, rho, nc, 0.0);
     Problem &pr = ctx->prob;
     DepArgs A{};
@@ -884,7 +894,7 @@ static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype,
     A.lev[0] = dep_level(pr, L, d_bmap);
     A.rho[0] = rho;
     A.ncell[0] = nc;
-    launch_deposit(st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, perm, A, d_ub, (const int2 *)d_us, nullptr);
+    launch_deposit(st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, perm, A, d_ub, (const int2 *)d_us, nout);
     HIP_TRY(hipMemsetAsync(ctx->tag_marks.p, 0, ng, st));
     launch_mark_blocks(st, rho, nc, (const int4 *)d_borg, d_ub, (const int2 *)d_us, nb, lambda, P.n_buffer, half, nn,
                        g, (double *)ctx->tag_scratch.p, (uint8_t *)ctx->tag_marks.p);
@@ -917,14 +927,18 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
     }
     ctx->built = false;
     ++ctx->generation;
-    // the tagging passes read the particles in visiting order from a copy
-    // made with the order
-    bool need_tags = false;
-    for (int l = 1; l <= P.max_level; ++l) need_tags = need_tags || !expl.count(l);
+    // the tagging passes (and amrmg_deposit_built) read the particles in
+    // visiting order from a copy made with the order
     const void *tx = x, *ty = y, *tz = z;
     const double *tq = q;
-    ST_TRY(compute_order(ctx, pos_dtype, x, y, z, q, n, need_tags, &tx, &ty, &tz, &tq));
-    const uint32_t *tperm = ctx->perm_n == n && !need_tags ? ctx->perm : nullptr;
+    ctx->built_n = -1;
+    ctx->lev_rho.resize(P.max_level + 1);
+    ctx->lev_rho_ok.assign(P.max_level + 1, 0);
+    ST_TRY(compute_order(ctx, pos_dtype, x, y, z, q, n, true, &tx, &ty, &tz, &tq));
+    const bool copied = ctx->perm_n == n && n > 0;
+    HIP_TRY(ctx->built_nout.ensure(sizeof(unsigned long long)));
+    HIP_TRY(hipMemsetAsync(ctx->built_nout.p, 0, sizeof(unsigned long long), ctx->st));
+    const uint32_t *tperm = nullptr;
 
     Problem &pr = ctx->prob;
     // the previous build's AMR levels lend their storage to the new ones
@@ -956,7 +970,9 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
             boxes = expl[l + 1];
         } else {
             if (!tag_rel) return fail(AMRMG_E_INVALID, "tag_rel is NULL but a level needs tagging");
-            ST_TRY(tag_level(ctx, L, pos_dtype, tx, ty, tz, tq, n, tag_rel[l], boxes, tperm));
+            ST_TRY(tag_level(ctx, L, pos_dtype, tx, ty, tz, tq, n, tag_rel[l], boxes, tperm,
+                             l == 0 ? (unsigned long long *)ctx->built_nout.p : nullptr));
+            ctx->lev_rho_ok[l] = 1;
         }
         if (boxes.empty()) break;
         std::string msg = check_nesting(L, boxes, P.n_proper);
@@ -976,6 +992,10 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
     if (*(int *)ctx->ds.h_face_err.p)
         return fail(AMRMG_E_NESTING, "coarse-fine window leaves the coarser level (nesting violated)");
     ctx->built = true;
+    if (copied || n == 0) {
+        ctx->built_n = n;
+        ctx->built_pos = pos_dtype;
+    }
     return AMRMG_OK;
 }
 
@@ -1111,6 +1131,63 @@ extern "C" amrmg_status amrmg_deposit(amrmg_ctx *ctx, int pos_dtype, const void 
     if (n_outside) {
         unsigned long long h = 0;
         HIP_TRY(hipMemcpyAsync(&h, dout, sizeof(h), hipMemcpyDeviceToHost, ctx->st));
+        HIP_TRY(hipStreamSynchronize(ctx->st));
+        *n_outside = (int64_t)h;
+    }
+    return AMRMG_OK;
+}
+
+extern "C" amrmg_status amrmg_deposit_built(amrmg_ctx *ctx, double *const *rho, int64_t *n_outside)
+{
+    if (!ctx) return fail(AMRMG_E_INVALID, "ctx is NULL");
+    if (!ctx->built) return fail(AMRMG_E_STATE, "hierarchy not built");
+    if (ctx->built_n < 0) return fail(AMRMG_E_STATE, "the last build kept no ordered copy of its particles");
+    if (!rho) return fail(AMRMG_E_INVALID, "rho is NULL");
+    const Problem &pr = ctx->prob;
+    const int64_t n = ctx->built_n;
+    const int pos = ctx->built_pos;
+    // levels deposited by the build are copied; the others are deposited
+    // together from the ordered copy (positions after the charges)
+    DepArgs A{};
+    for (int l = 0; l < pr.namr(); ++l) {
+        if (!rho[l]) return fail(AMRMG_E_INVALID, "rho[l] is NULL");
+        const HostLevel &L = pr.lev[pr.kg + l];
+        if (l < (int)ctx->lev_rho_ok.size() && ctx->lev_rho_ok[l]) {
+            HIP_TRY(hipMemcpyAsync(rho[l], ctx->lev_rho[l].p, sizeof(double) * L.ncells(), hipMemcpyDeviceToDevice,
+                                   ctx->st));
+            continue;
+        }
+        A.lev[A.nlev] = dep_level(pr, L, ctx->ds.d_bmap[l]);
+        A.rho[A.nlev] = rho[l];
+        A.ncell[A.nlev] = L.ncells();
+        ++A.nlev;
+    }
+    unsigned long long *dout = nullptr;
+    const bool level0_kept = !ctx->lev_rho_ok.empty() && ctx->lev_rho_ok[0];
+    if (A.nlev > 0) {
+        launch_zero_levels(ctx->st, A);
+        if (n_outside && !level0_kept) {
+            HIP_TRY(ctx->dep_count.ensure(sizeof(unsigned long long)));
+            dout = (unsigned long long *)ctx->dep_count.p;
+            HIP_TRY(hipMemsetAsync(dout, 0, sizeof(unsigned long long), ctx->st));
+        }
+        const size_t ps = pos == AMRMG_POS_F32 ? 4 : 8;
+        const char *base = (const char *)ctx->sorted.p;
+        const double *qs = (const double *)base;
+        const char *xs = base + align256((size_t)n * 8), *ys = xs + align256((size_t)n * ps),
+                   *zs = ys + align256((size_t)n * ps);
+        int64_t cells = 0;
+        for (int l = 0; l < A.nlev; ++l) cells += A.ncell[l];
+        ctx->prof.begin(AMRMG_K_DEPOSIT);
+        launch_deposit(ctx->st, pos == AMRMG_POS_F32, n, xs, ys, zs, qs, nullptr, A, ctx->ds.M.ubase, ctx->ds.M.ustr,
+                       dout);
+        ctx->prof.end(AMRMG_K_DEPOSIT, (double)n * (3.0 * ps + 8.0) + 8.0 * (double)cells);
+    }
+    HIP_TRY(hipGetLastError());
+    if (n_outside) {
+        unsigned long long h = 0;
+        if (level0_kept) dout = (unsigned long long *)ctx->built_nout.p;
+        if (dout) HIP_TRY(hipMemcpyAsync(&h, dout, sizeof(h), hipMemcpyDeviceToHost, ctx->st));
         HIP_TRY(hipStreamSynchronize(ctx->st));
         *n_outside = (int64_t)h;
     }

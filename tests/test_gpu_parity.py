@@ -105,6 +105,43 @@ def test_deposit(case):
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
+def test_deposit_built(case):
+    """amrmg_deposit_built (levels kept from the build's tagging deposits,
+    the rest deposited from its ordered copy) equals the oracle's deposit of
+    the build's particles, also after the caller's arrays have changed."""
+    print("case", case, flush=True)
+    w = CASES[case]()
+    H = O.hierarchy_from_workload(w)
+    ctx, (x, y, z, q) = make_ctx(w)
+    x.fill_(0.5)  # the caller reuses its arrays: the build's particles count
+    q.mul_(3.0)
+    rho, nout = ctx.deposit_built()
+    assert nout == 0
+    orho = H.deposit_all(w.particles)
+    for l, (g, o) in enumerate(zip(np_list(rho), orho)):
+        assert np.linalg.norm(g - o) <= 1e-12 * np.linalg.norm(o), l
+
+
+def test_deposit_built_counts_outside_particles():
+    """Particles outside [lo, hi) are skipped and counted as amrmg_deposit
+    does, whether level 0 was deposited by the build (tagging) or not."""
+    base = small_c2(20000)
+    p = base.particles
+    rng = np.random.default_rng(11)
+    out = rng.choice(p.x.size, 37, replace=False)
+    p.x[out[:20]] = 1.0 + 0.25 * rng.random(20)
+    p.z[out[20:]] = -0.5 * rng.random(17)
+    for w in (base, W.Workload("explicit", p, (32, 32, 32), 1, [], base.monopoles, 1e-8,
+                               explicit_boxes=[(1, 16, 16, 16, 48, 48, 48)])):
+        ctx, (x, y, z, q) = make_ctx(w)
+        ref, nref = ctx.deposit(x, y, z, q)
+        got, nout = ctx.deposit_built()
+        assert nref == 37 and nout == 37, (w.name, nref, nout)
+        for l, (g, o) in enumerate(zip(np_list(got), np_list(ref))):
+            assert np.linalg.norm(g - o) <= 1e-12 * np.linalg.norm(o), (w.name, l)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
 def test_composite_residual_operator(case):
     """amrmg_residual (the FP64 outer-residual kernels) equals the oracle's
     Alg. 1 residual for arbitrary phi, element by element."""
@@ -207,6 +244,9 @@ def test_status_codes():
     fresh = A.Context(prm)
     with pytest.raises(A.AmrmgError) as ei:
         A.amrmg_solve(fresh.h, [rho[0]], [phi[0]], None, 1e-8)
+    assert ei.value.status == A.AMRMG_E_STATE
+    with pytest.raises(A.AmrmgError) as ei:
+        A.amrmg_deposit_built(fresh.h, [rho[0]])
     assert ei.value.status == A.AMRMG_E_STATE
     # particles outside the domain are counted and skipped
     xo = x.clone()

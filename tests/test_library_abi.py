@@ -1,0 +1,53 @@
+"""The C-ABI boundary (include/amrmg.h) on the CPU: libamrmg.so loads, exports
+every function the header declares, the Python binding names exactly those,
+and the pure host entry points answer without a GPU.  No kernel is launched."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "amrmg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)  # comments out
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z_0-9]*\s*\**\s*(amrmg_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1812_03689_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    return C.CDLL(build.LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("amrmg_create", "amrmg_build_hierarchy", "amrmg_deposit", "amrmg_deposit_built", "amrmg_solve",
+                 "amrmg_gather", "amrmg_solve_batch"):
+        assert must in names
+    assert len(names) >= 17
+
+
+def test_library_exports_every_declared_function(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_names_the_same_functions():
+    from paper_1812_03689_amd import amrmg
+    assert sorted(amrmg.EXPORTED) == declared_functions()
+
+
+def test_default_params_without_gpu(lib):
+    from paper_1812_03689_amd import amrmg
+    p = amrmg.amrmg_params()
+    lib.amrmg_default_params(C.byref(p))
+    assert list(p.n0) == [32, 32, 32]
+    assert p.max_level == 2 and p.ref_ratio == 2 and p.blocking_factor == 8
+    assert (p.nu1, p.nu2) == (amrmg.make_params((32, 32, 32)).nu1, amrmg.make_params((32, 32, 32)).nu2)
