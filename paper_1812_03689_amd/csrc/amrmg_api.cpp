@@ -815,7 +815,7 @@ static amrmg_status compute_order(amrmg_ctx *ctx, int pos_dtype, const void *x, 
     const size_t entries = order_count_entries(P.lo, P.hi, P.n0);
     HIP_TRY(ctx->sort_keys.ensure(sizeof(uint32_t) * 2 * (size_t)n));
     HIP_TRY(ctx->sort_vals.ensure(sizeof(uint32_t) * (size_t)n));
-    HIP_TRY(ctx->sort_cnt.ensure(sizeof(uint32_t) * 2 * entries));
+    HIP_TRY(ctx->sort_cnt.ensure(sizeof(uint32_t) * 3 * entries));
     HIP_TRY(ctx->sort_tmp.ensure(order_temp_bytes(entries) + 256));
     char *cx = nullptr, *cy = nullptr, *cz = nullptr;
     double *cq = nullptr;
@@ -830,7 +830,7 @@ static amrmg_status compute_order(amrmg_ctx *ctx, int pos_dtype, const void *x, 
     }
     uint32_t *key = (uint32_t *)ctx->sort_keys.p, *cnt = (uint32_t *)ctx->sort_cnt.p;
     HIP_TRY(particle_order(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, P.lo, P.hi, P.n0, key, key + n, cnt,
-                           cnt + entries, (uint32_t *)ctx->sort_vals.p, ctx->sort_tmp.p, ctx->sort_tmp.cap, cx, cy,
+                           cnt + 2 * entries, (uint32_t *)ctx->sort_vals.p, ctx->sort_tmp.p, ctx->sort_tmp.cap, cx, cy,
                            cz, cq));
     ctx->perm = (uint32_t *)ctx->sort_vals.p;
     ctx->perm_n = n;

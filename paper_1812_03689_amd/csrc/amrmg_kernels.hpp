@@ -146,8 +146,8 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val);
 // spatial visiting order of particles (counting sort into Morton-ordered
 // buckets of the level-0 grid n0, at most 128 per axis): perm [n]; with xs,
 // also the particles in that order (xs, ys, zs in the position type, qs).
-// key, slot: [n] each; count, start: [order_count_entries] each; temp:
-// order_temp_bytes(order_count_entries) bytes
+// key, slot: [n] each; count: [2 order_count_entries], start:
+// [order_count_entries]; temp: order_temp_bytes(order_count_entries) bytes
 size_t order_count_entries(const double *lo, const double *hi, const int *n0);
 size_t order_temp_bytes(size_t entries);
 hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,

@@ -6,8 +6,8 @@
 // consecutive particles fall into a few neighbouring buckets and the
 // deposit of a workgroup stays inside a small LDS tile on every level; the
 // order inside a bucket does not matter (it is the order in which the
-// particles claimed their slots).  Three passes: count with slot claims,
-// exclusive scan of the counts (hipCUB), scatter.
+// particles claimed their slots).  Passes: count with slot claims, the
+// counts in bucket order, exclusive scan (hipCUB), scatter.
 #include <hip/hip_runtime.h>
 
 #include <hipcub/hipcub.hpp>
@@ -31,7 +31,19 @@ struct BucketGrid {
     int n[3];                // level-0 cells per axis
     int shift;               // bucket = cell >> shift
     uint32_t nbkt;           // Morton space of the buckets; bucket nbkt holds the particles outside
+    int sbits;               // counters of 2^sbits consecutive buckets lie on different cache lines
 };
+
+// Counter of bucket k: consecutive buckets are spread over distant counters
+// (a transpose of nbkt / 2^sbits rows of 2^sbits), so that the slot claims
+// of a dense region, many buckets with consecutive Morton codes, do not
+// queue on a few cache lines.  A bijection on [0, nbkt); nbkt maps to itself.
+__host__ __device__ __forceinline__ uint32_t counter_of(const BucketGrid &G, uint32_t k)
+{
+    if (k >= G.nbkt) return k;
+    const uint32_t S = 1u << G.sbits;
+    return (k & (S - 1)) * (G.nbkt >> G.sbits) + (k >> G.sbits);
+}
 
 template <class P>
 __global__ void __launch_bounds__(256) k_bucket_count(int64_t n, const P *x, const P *y, const P *z, BucketGrid G,
@@ -52,7 +64,14 @@ __global__ void __launch_bounds__(256) k_bucket_count(int64_t n, const P *x, con
     }
     if (!inside) k = G.nbkt;
     key[p] = k;
-    slot[p] = atomicAdd(&count[k], 1u);
+    slot[p] = atomicAdd(&count[counter_of(G, k)], 1u);
+}
+
+// the counts in bucket order, for the scan
+__global__ void __launch_bounds__(256) k_bucket_gather(BucketGrid G, const uint32_t *count, uint32_t *ordered)
+{
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k <= G.nbkt) ordered[k] = count[counter_of(G, k)];
 }
 
 // perm[dst] = p at dst = start of p's bucket + p's slot; with xs, also the
@@ -90,6 +109,7 @@ static BucketGrid bucket_grid(const double *lo, const double *hi, const int *n0)
     G.shift = bits > 7 ? bits - 7 : 0;
     bits -= G.shift;
     G.nbkt = 1u << (3 * bits);
+    G.sbits = 3 * bits < 10 ? 3 * bits : 10;
     return G;
 }
 
@@ -123,8 +143,10 @@ hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x,
     else
         hipLaunchKernelGGL((k_bucket_count<double>), dim3(g), dim3(256), 0, st, n, (const double *)x,
                            (const double *)y, (const double *)z, G, count, key, slot);
+    uint32_t *ordered = count + entries;
+    hipLaunchKernelGGL(k_bucket_gather, dim3((entries + 255) / 256), dim3(256), 0, st, G, count, ordered);
     size_t tb = temp_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(temp, tb, count, start, entries, st);
+    e = hipcub::DeviceScan::ExclusiveSum(temp, tb, ordered, start, entries, st);
     if (e != hipSuccess) return e;
     if (pos_f32)
         hipLaunchKernelGGL((k_bucket_scatter<float>), dim3(g), dim3(256), 0, st, n, key, slot, start, perm,
