@@ -7,7 +7,8 @@
 // deposit of a workgroup stays inside a small LDS tile on every level; the
 // order inside a bucket does not matter (it is the order in which the
 // particles claimed their slots).  Passes: count with slot claims, the
-// counts in bucket order, exclusive scan (hipCUB), scatter.
+// counts in bucket order, exclusive scan (hipCUB), scatter of the order,
+// ordered copy.
 #include <hip/hip_runtime.h>
 
 #include <hipcub/hipcub.hpp>
@@ -74,24 +75,29 @@ __global__ void __launch_bounds__(256) k_bucket_gather(BucketGrid G, const uint3
     if (k <= G.nbkt) ordered[k] = count[counter_of(G, k)];
 }
 
-// perm[dst] = p at dst = start of p's bucket + p's slot; with xs, also the
-// particle itself (positions and charge) at dst
-template <class P>
+// perm[dst] = p at dst = start of p's bucket + p's slot
 __global__ void __launch_bounds__(256) k_bucket_scatter(int64_t n, const uint32_t *key, const uint32_t *slot,
-                                                        const uint32_t *start, uint32_t *perm, const P *x,
-                                                        const P *y, const P *z, const double *q, P *xs, P *ys, P *zs,
-                                                        double *qs)
+                                                        const uint32_t *start, uint32_t *perm)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
     const uint32_t dst = start[key[p]] + slot[p];
     perm[dst] = (uint32_t)p;
-    if (xs) {
-        xs[dst] = x[p];
-        ys[dst] = y[p];
-        zs[dst] = z[p];
-        qs[dst] = q[p];
-    }
+}
+
+// the particles in visiting order (random reads, coalesced writes: faster
+// than scattering them with perm)
+template <class P>
+__global__ void __launch_bounds__(256) k_copy_ordered(int64_t n, const uint32_t *perm, const P *x, const P *y,
+                                                      const P *z, const double *q, P *xs, P *ys, P *zs, double *qs)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t p = perm[i];
+    xs[i] = x[p];
+    ys[i] = y[p];
+    zs[i] = z[p];
+    qs[i] = q[p];
 }
 
 static BucketGrid bucket_grid(const double *lo, const double *hi, const int *n0)
@@ -148,14 +154,15 @@ hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x,
     size_t tb = temp_bytes;
     e = hipcub::DeviceScan::ExclusiveSum(temp, tb, ordered, start, entries, st);
     if (e != hipSuccess) return e;
-    if (pos_f32)
-        hipLaunchKernelGGL((k_bucket_scatter<float>), dim3(g), dim3(256), 0, st, n, key, slot, start, perm,
-                           (const float *)x, (const float *)y, (const float *)z, q, (float *)xs, (float *)ys,
-                           (float *)zs, qs);
-    else
-        hipLaunchKernelGGL((k_bucket_scatter<double>), dim3(g), dim3(256), 0, st, n, key, slot, start, perm,
-                           (const double *)x, (const double *)y, (const double *)z, q, (double *)xs, (double *)ys,
-                           (double *)zs, qs);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(g), dim3(256), 0, st, n, key, slot, start, perm);
+    if (xs) {
+        if (pos_f32)
+            hipLaunchKernelGGL((k_copy_ordered<float>), dim3(g), dim3(256), 0, st, n, perm, (const float *)x,
+                               (const float *)y, (const float *)z, q, (float *)xs, (float *)ys, (float *)zs, qs);
+        else
+            hipLaunchKernelGGL((k_copy_ordered<double>), dim3(g), dim3(256), 0, st, n, perm, (const double *)x,
+                               (const double *)y, (const double *)z, q, (double *)xs, (double *)ys, (double *)zs, qs);
+    }
     return hipGetLastError();
 }
 
