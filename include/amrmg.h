@@ -154,6 +154,29 @@ amrmg_status amrmg_get_boxes(const amrmg_ctx *ctx, int32_t level, int32_t *boxes
 amrmg_status amrmg_cf_faces(const amrmg_ctx *ctx, int32_t level, int32_t *out, int64_t cap,
                             int64_t *count);
 
+/* The brick tables of the built hierarchy, copied to the host for inspection
+ * and tests.  Every level (levels below level 0 first, then the AMR levels)
+ * is cut into 8^3-cell bricks numbered level by level, box by box, x fastest
+ * inside a box.  counts (host [4], required): bricks, boundary faces,
+ * coarse-fine faces, bricks with coarse-fine coarse cells (the update list).
+ * Each array may be NULL; sizes follow the counts:
+ *   org    [bricks][4]: origin (cells, level index space) and level (0 = the
+ *          coarsest grid, AMR level l = l + levels below level 0)
+ *   nbr    [bricks][6]: per face 2d + (s > 0) the neighbour brick, or
+ *          -1 - face id (boundary faces first, then coarse-fine faces, both
+ *          in brick and face order)
+ *   child  [bricks][8]: child brick per octant (x bit 0, y bit 1, z bit 2) or -1
+ *   parent [bricks]: parent << 3 | octant, or -1
+ *   cmask  [bricks]: covered octants (AMR levels)
+ *   ubase  [bricks], ustr [bricks][2]: caller's-layout index of the brick's
+ *          first cell and the y, z strides (AMR levels; 0 below level 0)
+ *   owner  [faces]: brick << 3 | face
+ *   update [update count]: the bricks with coarse-fine coarse cells
+ * Synchronises. */
+amrmg_status amrmg_brick_tables(const amrmg_ctx *ctx, int64_t *counts, int32_t *org, int32_t *nbr,
+                                int32_t *child, int32_t *parent, uint8_t *cmask, int64_t *ubase,
+                                int32_t *ustr, int32_t *owner, int32_t *update);
+
 /* Device workspace for solve: the size needed for the current hierarchy and
  * precision, and an optional caller-owned buffer (device, >= that size,
  * 256-byte aligned) that the context then uses instead of allocating its own.

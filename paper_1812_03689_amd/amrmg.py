@@ -31,7 +31,7 @@ AMRMG_BOTTOM_AUTO, AMRMG_BOTTOM_CG = 0, 1
 AMRMG_MAX_LEVELS = 8
 
 EXPORTED = ["amrmg_default_params", "amrmg_create", "amrmg_destroy", "amrmg_last_error",
-            "amrmg_build_hierarchy", "amrmg_hierarchy_info", "amrmg_get_boxes", "amrmg_cf_faces",
+            "amrmg_build_hierarchy", "amrmg_hierarchy_info", "amrmg_get_boxes", "amrmg_cf_faces", "amrmg_brick_tables",
             "amrmg_workspace_size", "amrmg_set_workspace", "amrmg_deposit", "amrmg_deposit_built", "amrmg_solve",
             "amrmg_gather", "amrmg_residual", "amrmg_solve_batch", "amrmg_profile_enable",
             "amrmg_profile_read"]
@@ -88,6 +88,7 @@ def lib():
         L.amrmg_hierarchy_info.argtypes = [vp, vp, vp, vp, vp]
         L.amrmg_get_boxes.argtypes = [vp, i32, vp, vp]
         L.amrmg_cf_faces.argtypes = [vp, i32, vp, i64, vp]
+        L.amrmg_brick_tables.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.amrmg_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.amrmg_set_workspace.argtypes = [vp, vp, C.c_size_t]
         L.amrmg_deposit.argtypes = [vp, C.c_int, vp, vp, vp, vp, i64, vp, vp]
@@ -190,6 +191,22 @@ def amrmg_cf_faces(h, level: int):
     out = np.zeros((max(1, cnt.value), 6), dtype=np.int32)
     _check(lib().amrmg_cf_faces(h, level, out.ctypes.data, cnt.value, C.byref(cnt)))
     return out[:cnt.value]
+
+
+def amrmg_brick_tables(h) -> dict:
+    """Host copies of the brick tables (include/amrmg.h, amrmg_brick_tables)."""
+    import numpy as np
+    cnt = np.zeros(4, dtype=np.int64)
+    _check(lib().amrmg_brick_tables(h, cnt.ctypes.data, *([None] * 9)))
+    nb, nbc, ncf, nup = (int(v) for v in cnt)
+    t = {"org": np.zeros((nb, 4), np.int32), "nbr": np.zeros((nb, 6), np.int32), "child": np.zeros((nb, 8), np.int32),
+         "parent": np.zeros(nb, np.int32), "cmask": np.zeros(nb, np.uint8), "ubase": np.zeros(nb, np.int64),
+         "ustr": np.zeros((nb, 2), np.int32), "owner": np.zeros(nbc + ncf, np.int32),
+         "update": np.zeros(nup, np.int32)}
+    keys = ["org", "nbr", "child", "parent", "cmask", "ubase", "ustr", "owner", "update"]
+    _check(lib().amrmg_brick_tables(h, cnt.ctypes.data, *[t[k].ctypes.data if t[k].size else None for k in keys]))
+    t.update(nbrick=nb, nbc=nbc, ncf=ncf)
+    return t
 
 
 def amrmg_workspace_size(h) -> int:
@@ -321,6 +338,9 @@ class Context:
 
     def cf_faces(self, level):
         return amrmg_cf_faces(self.h, level)
+
+    def brick_tables(self):
+        return amrmg_brick_tables(self.h)
 
     def level_arrays(self, ncomp=1):
         import torch

@@ -47,6 +47,7 @@ static amrmg_status fail(amrmg_status s, const std::string &m)
     } while (0)
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
 
 // ---------------------------------------------------------------------------
 // grow-only device and pinned host buffers (allocation happens only when a
@@ -165,6 +166,12 @@ struct DevState {
     DevMeta M{};
     DBuf metabuf;
     PBuf stage;
+    // brick tables built on the device (org, nbr, child, ... and the scan
+    // scratch); per-level counts come back through bsum
+    DBuf brickbuf;
+    CBuf bsum;
+    unsigned bseq = 0;
+    int n_amr = 0, amr_first = 0, n_reflux = 0;  // AMR bricks (list d_amr), update list length
     int32_t *d_reflux = nullptr, *d_amr = nullptr;
     int2 *d_ranges = nullptr;  // brick range of each AMR level of each problem
     std::vector<int> range_prob, range_amr;
@@ -290,7 +297,8 @@ static void append_padded_tables(std::vector<double> &out, const int n[3], const
 static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<const Problem *> &probs,
                                 bool direct)
 {
-    const Meta &m = D.meta;
+    Meta &m = D.meta;
+    meta_entries(probs, m);
     if (!g_weights_ok) {
         std::vector<double> W = cf_weight_table();
         HIP_TRY(upload_cf_weights(W.data()));
@@ -300,20 +308,23 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
         HIP_TRY(upload_pattern_tables(masks, org));
         g_weights_ok = true;
     }
-    // level table, brick maps of the AMR levels (global ids) and monopoles
+    // level table, box table, monopoles; the brick maps of every level are
+    // built on the device into the map pool
     static thread_local std::vector<EntryDev> ed;
-    static thread_local std::vector<int32_t> pool;
+    static thread_local std::vector<BoxDev> bx;
     static thread_local std::vector<double> mono;
     static thread_local std::vector<int> mono_off;
     ed.assign(m.ent.size(), EntryDev{});
-    pool.clear();
+    bx.clear();
     mono.clear();
     mono_off.assign(probs.size(), 0);
     for (size_t i = 0; i < probs.size(); ++i) {
         mono_off[i] = (int)(mono.size() / 4);
         mono.insert(mono.end(), probs[i]->mono.begin(), probs[i]->mono.begin() + (probs[i]->mono.size() / 4) * 4);
     }
-    std::vector<int> amr_off;  // pool offset of AMR level l of problem 0
+    std::vector<int64_t> amr_off;  // pool offset of AMR level l of problem 0
+    int64_t npool = 0;
+    int n_amr = 0;
     for (size_t ei = 0; ei < m.ent.size(); ++ei) {
         const Meta::Entry &e = m.ent[ei];
         const Problem &P = *probs[e.prob];
@@ -330,13 +341,38 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
         E.crse = e.k > 0 ? m.prob_ent[e.prob][e.k - 1] : -1;
         E.mono_off = mono_off[e.prob];
         E.mono_n = (int)(P.mono.size() / 4);
-        E.bmap_off = -1;
-        if (L.amr >= 0) {
-            E.bmap_off = (int)pool.size();
-            if (e.prob == 0) amr_off.push_back(E.bmap_off);
-            for (int32_t v : L.bmap) pool.push_back(v >= 0 ? v + e.b0 : -1);
+        E.b0 = e.b0;
+        E.nb = e.nb;
+        E.bmap_off = (int)npool;
+        if (L.amr >= 0 && e.prob == 0) amr_off.push_back(npool);
+        npool += (int64_t)L.nbk[0] * L.nbk[1] * L.nbk[2];
+        E.amr_pos = L.amr >= 0 ? n_amr : 0;
+        if (L.amr >= 0) n_amr += e.nb;
+        int g0 = e.b0;
+        for (size_t b = 0; b < L.boxes.size(); ++b) {
+            const Box &B = L.boxes[b];
+            BoxDev t{};
+            for (int d = 0; d < 3; ++d) {
+                t.lo[d] = B.lo[d] / 8;
+                t.ext[d] = (B.hi[d] - B.lo[d]) / 8;
+            }
+            t.g0 = g0;
+            t.ent = (int)ei;
+            t.uoff = L.off.size() > b ? L.off[b] : 0;
+            t.nx = B.hi[0] - B.lo[0];
+            t.ny = B.hi[1] - B.lo[1];
+            g0 += t.ext[0] * t.ext[1] * t.ext[2];
+            bx.push_back(t);
         }
     }
+    if (npool > (int64_t)INT32_MAX) return fail(AMRMG_E_INVALID, "brick maps exceed 2^31 entries");
+    D.n_amr = n_amr;
+    D.amr_first = 0;
+    for (const auto &e : m.ent)
+        if (e.amr >= 0) {
+            D.amr_first = e.b0;
+            break;
+        }
     if (mono.empty()) mono.push_back(0.0);
     static thread_local std::vector<LevelConst> lc;
     lc.assign(m.ent.size(), LevelConst{});
@@ -452,39 +488,111 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
     if (groups.empty()) groups.push_back(make_int2(0, 0));
 
     Packer P;
-    int32_t *org = nullptr, *nbr = nullptr, *child = nullptr, *par = nullptr, *ustr = nullptr, *gfo = nullptr,
-            *cfi = nullptr, *drg = nullptr, *dj = nullptr;
-    uint8_t *cm = nullptr, *cfp = nullptr;
-    int64_t *ub = nullptr;
+    int32_t *drg = nullptr, *dj = nullptr, *cfi = nullptr;
+    uint8_t *cfp = nullptr;
     double *gbc = nullptr;
     LevelConst *dlc = nullptr;
-    P.add(m.org, &org);
-    P.add(m.nbr, &nbr);
-    P.add(m.child, &child);
-    P.add(m.par, &par);
-    P.add(m.cmask, &cm);
-    P.add(m.ubase, &ub);
-    P.add(m.ustr, &ustr);
-    P.add(m.gf_owner, &gfo);
-    P.add(m.reflux, &D.d_reflux);
-    P.add(m.amr_bricks, &D.d_amr);
     P.add(lc, &dlc);
     P.add(rg, &drg);
     P.add(jobs, &dj);
     P.add(cj, &D.d_cjobs);
     EntryDev *dent = nullptr;
-    int32_t *dpool = nullptr;
+    BoxDev *dbox = nullptr;
     double *dmono = nullptr;
     P.add(dtab, &D.d_dtab);
     P.add(djl, &D.d_djobs);
     P.add(planes, &D.d_planes);
     P.add(groups, &D.d_groups);
     P.add(ed, &dent);
-    P.add(pool, &dpool);
+    P.add(bx, &dbox);
     P.add(mono, &dmono);
     ST_TRY(P.run(D.metabuf, D.stage, st));
+
+    // brick tables on the device
+    const int nbr_ = m.nbrick, nent = (int)m.ent.size();
+    const size_t nbp = (size_t)nbr_ + 1;
+    MetaBuild B{};
+    B.nbrick = nbr_;
+    B.nbox = (int)bx.size();
+    B.nent = nent;
+    B.npool = npool;
+    B.boxes = dbox;
+    B.ent = dent;
+    B.temp_bytes = meta_scan_temp_bytes(nbr_);
+    {
+        size_t o = 0;
+        auto at = [&](size_t bytes) {
+            size_t p = o;
+            o += align256(bytes + 8);
+            return p;
+        };
+        const size_t o_pool = at(4 * (size_t)npool), o_org = at(16 * nbp), o_ub = at(8 * nbp), o_us = at(8 * nbp),
+                     o_ch = at(32 * nbp), o_par = at(4 * nbp), o_nbr = at(24 * nbp), o_gfo = at(24 * nbp),
+                     o_rf = at(4 * nbp), o_amr = at(4 * nbp), o_cm = at(nbp), o_cnt = at(8 * nbp),
+                     o_off = at(8 * nbp), o_flag = at(4 * nbp), o_roff = at(4 * nbp), o_dof = at(8 * (size_t)nent),
+                     o_err = at(4), o_tmp = at(B.temp_bytes);
+        HIP_TRY(D.brickbuf.ensure(o));
+        char *p = (char *)D.brickbuf.p;
+        B.pool = (int32_t *)(p + o_pool);
+        B.org = (int4 *)(p + o_org);
+        B.ubase = (int64_t *)(p + o_ub);
+        B.ustr = (int2 *)(p + o_us);
+        B.child = (int32_t *)(p + o_ch);
+        B.par = (int32_t *)(p + o_par);
+        B.nbr = (int32_t *)(p + o_nbr);
+        B.gf_owner = (int32_t *)(p + o_gfo);
+        B.reflux = (int32_t *)(p + o_rf);
+        B.amr_list = (int32_t *)(p + o_amr);
+        B.cmask = (uint8_t *)(p + o_cm);
+        B.cnt = (uint64_t *)(p + o_cnt);
+        B.off = (uint64_t *)(p + o_off);
+        B.flag = (uint32_t *)(p + o_flag);
+        B.roff = (uint32_t *)(p + o_roff);
+        B.dof = (unsigned long long *)(p + o_dof);
+        B.err = (int *)(p + o_err);
+        B.temp = p + o_tmp;
+    }
+    HIP_TRY(D.bsum.ensure(sizeof(int32_t) * (4 * (size_t)nent + 8) + sizeof(int64_t) * ((size_t)nent + 1) + 64));
+    unsigned *hseq = (unsigned *)D.bsum.p;
+    B.hout = (int32_t *)((char *)D.bsum.p + 64);
+    B.hdof = (int64_t *)((char *)D.bsum.p + 64 + align8(sizeof(int32_t) * (4 * (size_t)nent + 8)));
+    B.hseq = hseq;
+    B.seq = ++D.bseq;
+    HIP_TRY(launch_meta_build(st, B));
+    // the per-level counts, by polling host memory (no stream synchronisation)
+    {
+        auto t0 = std::chrono::steady_clock::now();
+        for (unsigned spin = 0; *(volatile unsigned *)hseq != B.seq; ++spin) {
+            if ((spin & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) {
+                HIP_TRY(hipStreamSynchronize(st));
+                if (*(volatile unsigned *)hseq != B.seq)
+                    return fail(AMRMG_E_HIP, "the brick-table build did not report to the host");
+                break;
+            }
+        }
+    }
+    const int32_t *h = B.hout;
+    m.nbc = h[4 * nent];
+    m.ncf = h[4 * nent + 1];
+    D.n_reflux = h[4 * nent + 2];
+    if (h[4 * nent + 3]) m.error = "a brick has no parent on the coarser level (nesting violated)";
+    m.dof.assign(probs.size(), std::vector<int64_t>());
+    for (int ei = 0; ei < nent; ++ei) {
+        Meta::Entry &e = m.ent[ei];
+        e.cf0 = h[4 * ei];
+        e.ncf = h[4 * ei + 1];
+        e.rf0 = h[4 * ei + 2];
+        e.nrf = h[4 * ei + 3];
+        if (e.amr >= 0) {
+            auto &dv = m.dof[e.prob];
+            if ((int)dv.size() <= e.amr) dv.resize(e.amr + 1, 0);
+            dv[e.amr] = B.hdof[ei];
+        }
+    }
+    D.d_reflux = B.reflux;
+    D.d_amr = B.amr_list;
     D.d_bmap.assign(amr_off.size(), nullptr);
-    for (size_t l = 0; l < amr_off.size(); ++l) D.d_bmap[l] = dpool + amr_off[l];
+    for (size_t l = 0; l < amr_off.size(); ++l) D.d_bmap[l] = B.pool + amr_off[l];
     // face data buffers: gbc [nbc*64], cf_idx [ncf*144], cf_pat [ncf*16], error flag
     size_t o_gbc = 0, o_idx = align256((size_t)m.nbc * 64 * 8 + 8);
     size_t o_pat = o_idx + align256((size_t)m.ncf * 144 * 4 + 4);
@@ -496,14 +604,14 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
     cfi = (int32_t *)(fb + o_idx);
     cfp = (uint8_t *)(fb + o_pat);
     D.d_face_err = (int *)(fb + o_err);
-    D.M.org = (const int4 *)org;
-    D.M.nbr = nbr;
-    D.M.child = child;
-    D.M.par = par;
-    D.M.cmask = cm;
-    D.M.ubase = ub;
-    D.M.ustr = (const int2 *)ustr;
-    D.M.gf_owner = gfo;
+    D.M.org = B.org;
+    D.M.nbr = B.nbr;
+    D.M.child = B.child;
+    D.M.par = B.par;
+    D.M.cmask = B.cmask;
+    D.M.ubase = B.ubase;
+    D.M.ustr = B.ustr;
+    D.M.gf_owner = B.gf_owner;
     D.M.gbc = gbc;
     D.M.cf_pat = cfp;
     D.M.cf_idx = cfi;
@@ -512,6 +620,7 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
     D.M.ncf = m.ncf;
     D.d_ranges = (int2 *)drg;
     D.d_jobs = (int4 *)dj;
+    int32_t *dpool = B.pool;
     HIP_TRY(hipMemsetAsync(D.d_face_err, 0, sizeof(int), st));
     launch_face_data(st, D.M, dent, dpool, dmono, gbc, cfp, cfi, D.d_face_err);
     HIP_TRY(hipGetLastError());
@@ -985,10 +1094,9 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
         pr.lev.push_back(std::move(F));
     }
     add_levels_below(pr);
-    build_meta({&pr}, ctx->ds.meta, false);
-    if (!ctx->ds.meta.error.empty()) return fail(AMRMG_E_NESTING, ctx->ds.meta.error);
     ST_TRY(upload_meta(ctx->ds, ctx->st, {&pr}, P.bottom == AMRMG_BOTTOM_AUTO));
     HIP_TRY(hipStreamSynchronize(ctx->st));
+    if (!ctx->ds.meta.error.empty()) return fail(AMRMG_E_NESTING, ctx->ds.meta.error);
     if (*(int *)ctx->ds.h_face_err.p)
         return fail(AMRMG_E_NESTING, "coarse-fine window leaves the coarser level (nesting violated)");
     ctx->built = true;
@@ -1045,14 +1153,21 @@ extern "C" amrmg_status amrmg_cf_faces(const amrmg_ctx *ctx, int32_t level, int3
     if (level < 0 || level >= pr.namr()) return fail(AMRMG_E_INVALID, "level out of range");
     const Meta &m = ctx->ds.meta;
     const Meta::Entry &e = m.ent[m.prob_ent[0][pr.kg + level]];
+    // the level's faces (owners, their origins, patterns) from the device tables
     std::vector<uint8_t> pat((size_t)e.ncf * 16);
+    std::vector<int32_t> owner(e.ncf);
+    std::vector<int4> org((size_t)e.nb);
+    HIP_TRY(hipStreamSynchronize(ctx->st));
     if (e.ncf > 0) {
-        HIP_TRY(hipStreamSynchronize(ctx->st));
         HIP_TRY(hipMemcpy(pat.data(), ctx->ds.M.cf_pat + (size_t)e.cf0 * 16, pat.size(), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(owner.data(), ctx->ds.M.gf_owner + m.nbc + e.cf0, sizeof(int32_t) * e.ncf,
+                          hipMemcpyDeviceToHost));
     }
+    if (e.nb > 0)
+        HIP_TRY(hipMemcpy(org.data(), ctx->ds.M.org + e.b0, sizeof(int4) * e.nb, hipMemcpyDeviceToHost));
     int64_t k = 0;
     for (int c = e.cf0; c < e.cf0 + e.ncf; ++c) {
-        int32_t ow = m.gf_owner[m.nbc + c];
+        int32_t ow = owner[c - e.cf0];
         int g = ow >> 3, dir = ow & 7, d = dir >> 1, s = (dir & 1) ? 1 : -1;
         int du = (d == 0) ? 1 : 0, dv = (d == 2) ? 1 : 2;
         for (int t = 0; t < 64; ++t, ++k) {
@@ -1062,7 +1177,9 @@ extern "C" amrmg_status amrmg_cf_faces(const amrmg_ctx *ctx, int32_t level, int3
             l[du] = t & 7;
             l[dv] = t >> 3;
             int32_t *o = out + 6 * k;
-            for (int a = 0; a < 3; ++a) o[a] = m.org[(size_t)g * 4 + a] + l[a];
+            const int4 og = org[g - e.b0];
+            const int O[3] = {og.x, og.y, og.z};
+            for (int a = 0; a < 3; ++a) o[a] = O[a] + l[a];
             o[3] = d;
             o[4] = s;
             int mm = ((t & 7) >> 1) + 4 * ((t >> 3) >> 1);
@@ -1070,6 +1187,36 @@ extern "C" amrmg_status amrmg_cf_faces(const amrmg_ctx *ctx, int32_t level, int3
         }
     }
     if (count) *count = k;
+    return AMRMG_OK;
+}
+
+extern "C" amrmg_status amrmg_brick_tables(const amrmg_ctx *ctx, int64_t *counts, int32_t *org, int32_t *nbr,
+                                           int32_t *child, int32_t *parent, uint8_t *cmask, int64_t *ubase,
+                                           int32_t *ustr, int32_t *owner, int32_t *update)
+{
+    if (!ctx || !counts) return fail(AMRMG_E_INVALID, "NULL argument");
+    if (!ctx->built) return fail(AMRMG_E_STATE, "hierarchy not built");
+    const DevState &D = ctx->ds;
+    const Meta &m = D.meta;
+    const size_t nb = (size_t)m.nbrick;
+    counts[0] = m.nbrick;
+    counts[1] = m.nbc;
+    counts[2] = m.ncf;
+    counts[3] = D.n_reflux;
+    HIP_TRY(hipStreamSynchronize(ctx->st));
+    auto get = [&](void *dst, const void *src, size_t bytes) -> amrmg_status {
+        if (dst && bytes) HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+        return AMRMG_OK;
+    };
+    ST_TRY(get(org, D.M.org, 16 * nb));
+    ST_TRY(get(nbr, D.M.nbr, 24 * nb));
+    ST_TRY(get(child, D.M.child, 32 * nb));
+    ST_TRY(get(parent, D.M.par, 4 * nb));
+    ST_TRY(get(cmask, D.M.cmask, nb));
+    ST_TRY(get(ubase, D.M.ubase, 8 * nb));
+    ST_TRY(get(ustr, D.M.ustr, 8 * nb));
+    ST_TRY(get(owner, D.M.gf_owner, 4 * (size_t)(m.nbc + m.ncf)));
+    ST_TRY(get(update, D.d_reflux, 4 * (size_t)D.n_reflux));
     return AMRMG_OK;
 }
 
@@ -1257,9 +1404,9 @@ struct Driver {
     // all AMR bricks: a contiguous range for one problem, a list otherwise
     void amr_range(int &b0, int &nb, const int32_t *&list) const
     {
-        nb = (int)m.amr_bricks.size();
+        nb = D.n_amr;
         if (single()) {
-            b0 = nb ? m.amr_bricks[0] : 0;
+            b0 = D.amr_first;
             list = nullptr;
         } else {
             b0 = 0;
@@ -1747,10 +1894,9 @@ extern "C" amrmg_status amrmg_solve_batch(amrmg_ctx *const *ctxs, int32_t nb, do
         c0->batch_ctx.clear();
         std::vector<const Problem *> probs;
         for (int i = 0; i < nb; ++i) probs.push_back(&ctxs[i]->prob);
-        build_meta(probs, c0->batch->meta, false);
-        if (!c0->batch->meta.error.empty()) return fail(AMRMG_E_NESTING, c0->batch->meta.error);
         ST_TRY(upload_meta(*c0->batch, c0->st, probs, c0->P.bottom == AMRMG_BOTTOM_AUTO));
         HIP_TRY(hipStreamSynchronize(c0->st));
+        if (!c0->batch->meta.error.empty()) return fail(AMRMG_E_NESTING, c0->batch->meta.error);
         if (*(int *)c0->batch->h_face_err.p)
             return fail(AMRMG_E_NESTING, "coarse-fine window leaves the coarser level (nesting violated)");
         c0->batch_ctx = key;

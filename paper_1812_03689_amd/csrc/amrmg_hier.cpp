@@ -359,7 +359,16 @@ static inline void tdirs(int d, int &du, int &dv)
     dv = (d == 2) ? 1 : 2;
 }
 
-void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_data)
+// bricks of a level from its box list alone
+static int level_bricks(const HostLevel &L)
+{
+    int64_t nb = 0;
+    for (const Box &B : L.boxes)
+        nb += (int64_t)((B.hi[0] - B.lo[0]) / 8) * ((B.hi[1] - B.lo[1]) / 8) * ((B.hi[2] - B.lo[2]) / 8);
+    return (int)nb;
+}
+
+void meta_entries(const std::vector<const Problem *> &probs, Meta &M)
 {
     // start over, keeping the vectors' storage (a regrid reuses it without
     // fresh page faults)
@@ -395,7 +404,7 @@ void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_da
             e.k = k;
             e.amr = L.amr;
             e.b0 = nb;
-            e.nb = L.nbrick();
+            e.nb = level_bricks(L);
             for (int d = 0; d < 3; ++d) e.h[d] = L.h[d];
             nb += e.nb;
             M.prob_ent[i][k] = (int)M.ent.size();
@@ -404,6 +413,20 @@ void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_da
     }
     M.step_ent0.push_back((int)M.ent.size());
     M.nbrick = nb;
+    M.org.clear();
+    M.nbr.clear();
+    M.child.clear();
+    M.par.clear();
+    M.cmask.clear();
+    M.ubase.clear();
+    M.ustr.clear();
+}
+
+void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_data)
+{
+    meta_entries(probs, M);
+    const int np = (int)probs.size();
+    const int nb = M.nbrick;
     M.org.assign((size_t)nb * 4, 0);
     M.nbr.assign((size_t)nb * 6, 0);
     M.child.assign((size_t)nb * 8, -1);
@@ -594,8 +617,8 @@ void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_da
                 // itself or in a face neighbour
                 bool near = cm != 0;
                 for (int f = 0; f < 6 && !near; ++f) {
-                    int nb = M.nbr[(size_t)g * 6 + f];
-                    near = nb >= 0 && M.cmask[nb] != 0;
+                    int q = M.nbr[(size_t)g * 6 + f];
+                    near = q >= 0 && M.cmask[q] != 0;
                 }
                 bool want = false;
                 for (int o = 0; o < 8 && near && !want && cm != 0xFF; ++o) {

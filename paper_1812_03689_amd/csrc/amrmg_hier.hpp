@@ -131,8 +131,14 @@ struct Meta {
     std::string error;                       // non-empty when the hierarchy is inconsistent
 };
 
-// face_data: also compute gbc, cf_pat and cf_idx on the host (the library
-// generates them on the device instead, from the same pattern tables)
+// The level table only (ent with b0/nb, step_ent0, K, nbrick, prob_ent);
+// every other field of M is cleared.  The library builds the brick tables
+// from it on the device.
+void meta_entries(const std::vector<const Problem *> &probs, Meta &M);
+// The whole metadata on the host (meta_entries, then the brick tables, face
+// lists, reflux list and composite cell counts).  face_data: also compute
+// gbc, cf_pat and cf_idx (the library generates them on the device from
+// the same pattern tables).
 void build_meta(const std::vector<const Problem *> &probs, Meta &M, bool face_data = true);
 
 }  // namespace amrmg

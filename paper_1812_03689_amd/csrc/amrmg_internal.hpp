@@ -48,8 +48,9 @@ struct DevMeta {
     int32_t ncf;              // coarse-fine faces are gface [nbc, nbc+ncf)
 };
 
-// per level id: what the kernels that generate face data (Dirichlet values
-// of boundary faces, coarse-fine windows) need to know about its level
+// per level id: what the kernels that build the brick tables and generate
+// face data (Dirichlet values of boundary faces, coarse-fine windows) need
+// to know about its level
 struct EntryDev {
     double lo[3];    // problem domain lower corner
     double h[3];     // cell size
@@ -58,9 +59,23 @@ struct EntryDev {
     int nbk[3];      // brick grid extent
     int amr;         // AMR level number, -1 below level 0
     int crse;        // level id of the next coarser level of the problem, -1 if none
-    int bmap_off;    // offset of the brick map (global brick ids, -1 = no brick) in the map pool, -1 if none
+    int bmap_off;    // offset of the brick map (global brick ids, -1 = no brick) in the map pool
     int mono_off;    // first monopole (q, x, y, z) of the problem in the monopole pool
     int mono_n;      // number of monopoles
+    int b0, nb;      // its bricks [b0, b0 + nb)
+    int amr_pos;     // position of its first brick in the list of AMR bricks (AMR levels)
+    int pad;
+};
+
+// one box of a level, in bricks: the level's bricks are numbered box by box,
+// x fastest inside a box, from g0
+struct BoxDev {
+    int lo[3];      // first brick (brick index space of the level)
+    int ext[3];     // bricks per axis
+    int g0;         // global id of its first brick
+    int ent;        // level id
+    int64_t uoff;   // caller's-layout offset of the box on its level (cells)
+    int nx, ny;     // box extent in cells along x and y (caller's-layout strides)
 };
 
 }  // namespace amrmg

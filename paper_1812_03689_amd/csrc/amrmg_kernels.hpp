@@ -57,6 +57,35 @@ constexpr int DIRECT_COLS = 16;
 hipError_t upload_cf_weights(const double *w);
 // window masks of patterns 0..12 and (u0, v0, nodes) of patterns 0..13
 hipError_t upload_pattern_tables(const uint32_t *masks13, const int *org14x3);
+// Device build of the brick tables (org, nbr, child, par, cmask, ubase, ustr,
+// gf_owner, reflux list, AMR brick list) from the box table; the per-level
+// counts (cf0, ncf, rf0, nrf), composite cell counts and totals (nbc, ncf,
+// reflux length, nesting error) reach the host through hout / hdof
+// (host-visible), followed by seq at hseq.
+struct MetaBuild {
+    int nbrick, nbox, nent;
+    int64_t npool;
+    const BoxDev *boxes;
+    const EntryDev *ent;
+    int32_t *pool;  // [npool] brick maps of all levels
+    int4 *org;
+    int64_t *ubase;
+    int2 *ustr;
+    int32_t *child, *par, *nbr, *gf_owner, *reflux, *amr_list;
+    uint8_t *cmask;
+    uint64_t *cnt, *off;      // [nbrick + 1]
+    uint32_t *flag, *roff;    // [nbrick + 1]
+    unsigned long long *dof;  // [nent]
+    int *err;
+    void *temp;
+    size_t temp_bytes;
+    int32_t *hout;  // [4 nent + 4]
+    int64_t *hdof;  // [nent]
+    unsigned *hseq;
+    unsigned seq;
+};
+size_t meta_scan_temp_bytes(int nbrick);
+hipError_t launch_meta_build(hipStream_t st, const MetaBuild &B);
 // Dirichlet values of the boundary faces (gbc) and the coarse-fine windows
 // (cf_pat, cf_idx) of the hierarchy in M; *err is set when a window leaves
 // the coarser level

@@ -1,5 +1,5 @@
-// amrmg_meta.hip -- face data of a new hierarchy generated on the device:
-// the Dirichlet values at the centres of the physical-boundary faces of the
+// amrmg_meta.hip -- brick tables and face data of a new hierarchy, built on
+// the device.  Face data: the Dirichlet values at the centres of the physical-boundary faces of the
 // AMR levels, and for every coarse-fine face the interpolation pattern and
 // window cells of each of its 16 coarse cells (Sec. 5.1 of arXiv:1812.03689,
 // Tab. bit_pattern and the bilinear table after it).
@@ -12,6 +12,8 @@
 // (pattern 13).  Window masks and origins come from the host tables, so host
 // and device select from one definition.
 #include <hip/hip_runtime.h>
+
+#include <hipcub/hipcub.hpp>
 
 #include "amrmg_internal.hpp"
 #include "amrmg_kernels.hpp"
@@ -130,6 +132,239 @@ __global__ void __launch_bounds__(256) k_bc_values(DevMeta M, const EntryDev *en
         }
     }
     gbc[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Brick tables of a new hierarchy, built on the device from the box lists
+// (the same tables, bit for bit, as the host reference build_meta):
+// 1. per brick: origin, level id, caller's-layout base and strides, brick
+//    map entry; children and parent cleared;
+// 2. per brick: face neighbours (or boundary / coarse-fine markers, counted),
+//    parent and octant, the parent's child slot;
+// 3. scan of the (boundary, coarse-fine) face counts in brick order;
+// 4. per brick: face ids (boundary faces first, then coarse-fine faces, both
+//    in brick and face order) with their owners; covered-octant mask;
+// 5. per AMR brick: coarse-fine update flag (an uncovered cell next to a
+//    covered one), composite cell count per level, the list of AMR bricks;
+// 6. scan of the flags and the update list; per-level summary to the host.
+// ---------------------------------------------------------------------------
+constexpr int32_t NBR_BND = -1, NBR_CF = -2;  // markers between steps 2 and 4
+
+__device__ __forceinline__ int pool_at(const EntryDev &E, const int32_t *pool, int bx, int by, int bz)
+{
+    return pool[E.bmap_off + bx + E.nbk[0] * (by + E.nbk[1] * bz)];
+}
+
+__global__ void __launch_bounds__(256) k_meta_bricks(int nbrick, int nbox, const BoxDev *boxes, const EntryDev *ent,
+                                                     int32_t *pool, int4 *org, int64_t *ubase, int2 *ustr,
+                                                     int32_t *child, int32_t *par)
+{
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= nbrick) return;
+    int lo = 0, hi = nbox - 1;  // the last box starting at or before g
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (boxes[mid].g0 <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const BoxDev B = boxes[lo];
+    const int li = g - B.g0, ix = li % B.ext[0], r = li / B.ext[0], iy = r % B.ext[1], iz = r / B.ext[1];
+    const int P[3] = {B.lo[0] + ix, B.lo[1] + iy, B.lo[2] + iz};
+    const EntryDev &E = ent[B.ent];
+    org[g] = make_int4(8 * P[0], 8 * P[1], 8 * P[2], B.ent);
+    pool[E.bmap_off + P[0] + E.nbk[0] * (P[1] + E.nbk[1] * P[2])] = g;
+    if (E.amr >= 0) {
+        ubase[g] = B.uoff + 8 * ix + (int64_t)B.nx * (8 * iy + (int64_t)B.ny * 8 * iz);
+        ustr[g] = make_int2(B.nx, B.nx * B.ny);
+    } else {
+        ubase[g] = 0;
+        ustr[g] = make_int2(0, 0);
+    }
+    par[g] = -1;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) child[(size_t)g * 8 + o] = -1;
+}
+
+__global__ void __launch_bounds__(256) k_meta_links(int nbrick, const EntryDev *ent, const int32_t *pool,
+                                                    const int4 *org, int32_t *nbr, int32_t *child, int32_t *par,
+                                                    uint64_t *cnt, int *err)
+{
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= nbrick) {
+        if (g == nbrick) cnt[g] = 0;
+        return;
+    }
+    const int4 o = org[g];
+    const EntryDev &E = ent[o.w];
+    const int P[3] = {o.x >> 3, o.y >> 3, o.z >> 3};
+    uint32_t nbnd = 0, ncf = 0;
+#pragma unroll
+    for (int dir = 0; dir < 6; ++dir) {
+        const int d = dir >> 1;
+        int Q[3] = {P[0], P[1], P[2]};
+        Q[d] += (dir & 1) ? 1 : -1;
+        int32_t v;
+        if (Q[d] < 0 || Q[d] >= E.nbk[d]) {
+            v = NBR_BND;
+            ++nbnd;
+        } else {
+            v = pool_at(E, pool, Q[0], Q[1], Q[2]);
+            if (v < 0) {
+                v = NBR_CF;
+                ++ncf;
+            }
+        }
+        nbr[(size_t)g * 6 + dir] = v;
+    }
+    cnt[g] = (uint64_t)nbnd | ((uint64_t)ncf << 32);
+    if (E.crse >= 0) {
+        const EntryDev &C = ent[E.crse];
+        int q = pool_at(C, pool, P[0] >> 1, P[1] >> 1, P[2] >> 1);
+        const int oc = (P[0] & 1) | ((P[1] & 1) << 1) | ((P[2] & 1) << 2);
+        if (q < 0) {  // no parent: nesting is violated
+            *err = 1;
+            q = C.b0;
+        }
+        par[g] = (q << 3) | oc;
+        child[(size_t)q * 8 + oc] = g;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_meta_faces(int nbrick, const EntryDev *ent, const int4 *org,
+                                                    const uint64_t *off, int32_t *nbr, int32_t *gf_owner,
+                                                    const int32_t *child, uint8_t *cmask)
+{
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= nbrick) return;
+    const uint64_t of = off[g], tot = off[nbrick];
+    uint32_t jb = (uint32_t)of, jc = (uint32_t)(of >> 32);
+    const uint32_t nbc = (uint32_t)tot;
+#pragma unroll
+    for (int dir = 0; dir < 6; ++dir) {
+        const int32_t v = nbr[(size_t)g * 6 + dir];
+        if (v >= 0) continue;
+        const uint32_t gf = v == NBR_BND ? jb++ : nbc + jc++;
+        nbr[(size_t)g * 6 + dir] = -1 - (int32_t)gf;
+        gf_owner[gf] = (g << 3) | dir;
+    }
+    uint32_t cm = 0;
+    if (ent[org[g].w].amr >= 0)
+#pragma unroll
+        for (int o = 0; o < 8; ++o) cm |= (child[(size_t)g * 8 + o] >= 0 ? 1u : 0u) << o;
+    cmask[g] = (uint8_t)cm;
+}
+
+__global__ void __launch_bounds__(256) k_meta_reflux(int nbrick, const EntryDev *ent, const int4 *org,
+                                                     const int32_t *nbr, const uint8_t *cmask, uint32_t *flag,
+                                                     unsigned long long *dof, int32_t *amr_list)
+{
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= nbrick) {
+        if (g == nbrick) flag[g] = 0;
+        return;
+    }
+    const int w = org[g].w;
+    const EntryDev &E = ent[w];
+    uint32_t want = 0;
+    if (E.amr >= 0) {
+        const uint32_t cm = cmask[g];
+        atomicAdd(&dof[w], (unsigned long long)(64 * (8 - __popc(cm))));
+        amr_list[E.amr_pos + (g - E.b0)] = g;
+        int32_t nb[6];
+        uint32_t ncm[6];
+        bool near = cm != 0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            nb[f] = nbr[(size_t)g * 6 + f];
+            ncm[f] = nb[f] >= 0 ? cmask[nb[f]] : 0;
+            near = near || ncm[f] != 0;
+        }
+        // an uncovered octant with a covered face neighbour (in the brick or across a face)
+        for (int o = 0; o < 8 && near && !want && cm != 0xFF; ++o) {
+            if ((cm >> o) & 1) continue;
+            for (int d = 0; d < 3 && !want; ++d) {
+                const int od = (o >> d) & 1, on = o ^ (1 << d);
+                // the face neighbour inside the brick, then the one across the brick face
+                if ((cm >> on) & 1) want = 1;
+                const uint32_t across = ncm[2 * d + (od ? 1 : 0)];
+                if ((across >> on) & 1) want = 1;
+            }
+        }
+    }
+    flag[g] = want;
+}
+
+__global__ void __launch_bounds__(256) k_meta_list(int nbrick, const uint32_t *flag, const uint32_t *roff,
+                                                   int32_t *reflux)
+{
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g < nbrick && flag[g]) reflux[roff[g]] = g;
+}
+
+// per level id: (cf0, ncf, rf0, nrf) and the composite cell count; then the
+// totals (boundary faces, coarse-fine faces, update list length, nesting
+// error) and, last, the sequence number seq, all in host-visible memory
+__global__ void __launch_bounds__(1024) k_meta_summary(int nent, int nbrick, const EntryDev *ent, const uint64_t *off,
+                                                       const uint32_t *roff, const unsigned long long *dof,
+                                                       const int *err, int32_t *hout, int64_t *hdof,
+                                                       unsigned *hseq, unsigned seq)
+{
+    for (int e = threadIdx.x; e < nent; e += blockDim.x) {
+        const EntryDev &E = ent[e];
+        const uint32_t c0 = (uint32_t)(off[E.b0] >> 32), c1 = (uint32_t)(off[E.b0 + E.nb] >> 32);
+        hout[4 * e] = (int32_t)c0;
+        hout[4 * e + 1] = (int32_t)(c1 - c0);
+        hout[4 * e + 2] = (int32_t)roff[E.b0];
+        hout[4 * e + 3] = (int32_t)(roff[E.b0 + E.nb] - roff[E.b0]);
+        hdof[e] = (int64_t)dof[e];
+    }
+    if (threadIdx.x == 0) {
+        const uint64_t tot = off[nbrick];
+        hout[4 * nent] = (int32_t)(uint32_t)tot;
+        hout[4 * nent + 1] = (int32_t)(tot >> 32);
+        hout[4 * nent + 2] = (int32_t)roff[nbrick];
+        hout[4 * nent + 3] = *err;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence_system();
+        *(volatile unsigned *)hseq = seq;
+    }
+}
+
+size_t meta_scan_temp_bytes(int nbrick)
+{
+    size_t a = 0, b = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, a, (const uint64_t *)nullptr, (uint64_t *)nullptr, nbrick + 1);
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const uint32_t *)nullptr, (uint32_t *)nullptr, nbrick + 1);
+    return a > b ? a : b;
+}
+
+hipError_t launch_meta_build(hipStream_t st, const MetaBuild &B)
+{
+    const unsigned g1 = (unsigned)((B.nbrick + 256) / 256);  // one thread more than bricks
+    hipError_t e = hipMemsetAsync(B.pool, 0xFF, sizeof(int32_t) * B.npool, st);
+    if (e == hipSuccess) e = hipMemsetAsync(B.dof, 0, sizeof(unsigned long long) * B.nent, st);
+    if (e == hipSuccess) e = hipMemsetAsync(B.err, 0, sizeof(int), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_meta_bricks, dim3(g1), dim3(256), 0, st, B.nbrick, B.nbox, B.boxes, B.ent, B.pool, B.org,
+                       B.ubase, B.ustr, B.child, B.par);
+    hipLaunchKernelGGL(k_meta_links, dim3(g1), dim3(256), 0, st, B.nbrick, B.ent, B.pool, B.org, B.nbr, B.child,
+                       B.par, B.cnt, B.err);
+    size_t tb = B.temp_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(B.temp, tb, B.cnt, B.off, B.nbrick + 1, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_meta_faces, dim3(g1), dim3(256), 0, st, B.nbrick, B.ent, B.org, B.off, B.nbr, B.gf_owner,
+                       B.child, B.cmask);
+    hipLaunchKernelGGL(k_meta_reflux, dim3(g1), dim3(256), 0, st, B.nbrick, B.ent, B.org, B.nbr, B.cmask, B.flag,
+                       B.dof, B.amr_list);
+    tb = B.temp_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(B.temp, tb, B.flag, B.roff, B.nbrick + 1, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_meta_list, dim3(g1), dim3(256), 0, st, B.nbrick, B.flag, B.roff, B.reflux);
+    hipLaunchKernelGGL(k_meta_summary, dim3(1), dim3(1024), 0, st, B.nent, B.nbrick, B.ent, B.off, B.roff, B.dof,
+                       B.err, B.hout, B.hdof, B.hseq, B.seq);
+    return hipGetLastError();
 }
 
 void launch_face_data(hipStream_t st, const DevMeta &M, const EntryDev *ent, const int32_t *pool,

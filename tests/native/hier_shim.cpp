@@ -80,6 +80,63 @@ extern "C" long hs_cf_patterns(const int32_t *n0, int nlev, const int32_t *nbox,
     return k;
 }
 
+// the brick tables of the host reference build_meta for the same box lists
+// (counts[4] = bricks, boundary faces, coarse-fine faces, update list length;
+// arrays sized as amrmg_brick_tables documents; call with NULL arrays for
+// the counts first)
+extern "C" void hs_brick_tables(const int32_t *n0, int nlev, const int32_t *nbox, const int32_t *boxes,
+                                int64_t *counts, int32_t *org, int32_t *nbr, int32_t *child, int32_t *par,
+                                uint8_t *cmask, int64_t *ubase, int32_t *ustr, int32_t *owner, int32_t *update,
+                                int32_t *lev_counts)
+{
+    Problem P;
+    for (int d = 0; d < 3; ++d) {
+        P.lo[d] = 0;
+        P.hi[d] = 1;
+    }
+    const int32_t *bp = boxes;
+    for (int l = 0; l < nlev; ++l) {
+        HostLevel L;
+        int n[3] = {n0[0] << l, n0[1] << l, n0[2] << l};
+        level_init(L, n, P.lo, P.hi);
+        L.amr = l;
+        std::vector<Box> bx(nbox[l]);
+        for (int b = 0; b < nbox[l]; ++b, bp += 6)
+            for (int d = 0; d < 3; ++d) {
+                bx[b].lo[d] = bp[d];
+                bx[b].hi[d] = bp[3 + d];
+            }
+        level_set_boxes(L, bx);
+        P.lev.push_back(L);
+    }
+    add_levels_below(P);
+    Meta M;
+    build_meta({&P}, M, false);
+    counts[0] = M.nbrick;
+    counts[1] = M.nbc;
+    counts[2] = M.ncf;
+    counts[3] = (int64_t)M.reflux.size();
+    if (!org) return;
+    std::memcpy(org, M.org.data(), 4 * M.org.size());
+    std::memcpy(nbr, M.nbr.data(), 4 * M.nbr.size());
+    std::memcpy(child, M.child.data(), 4 * M.child.size());
+    std::memcpy(par, M.par.data(), 4 * M.par.size());
+    std::memcpy(cmask, M.cmask.data(), M.cmask.size());
+    std::memcpy(ubase, M.ubase.data(), 8 * M.ubase.size());
+    std::memcpy(ustr, M.ustr.data(), 4 * M.ustr.size());
+    std::memcpy(owner, M.gf_owner.data(), 4 * M.gf_owner.size());
+    std::memcpy(update, M.reflux.data(), 4 * M.reflux.size());
+    // per level (coarsest first): cf0, ncf, rf0, nrf, composite cells (AMR levels, else -1)
+    for (size_t e = 0; e < M.ent.size(); ++e) {
+        int32_t *o = lev_counts + 5 * e;
+        o[0] = M.ent[e].cf0;
+        o[1] = M.ent[e].ncf;
+        o[2] = M.ent[e].rf0;
+        o[3] = M.ent[e].nrf;
+        o[4] = M.ent[e].amr >= 0 ? (int32_t)M.dof[0][M.ent[e].amr] : -1;
+    }
+}
+
 // the weight table and quadratic masks, for checks against the printed table
 extern "C" void hs_tables(double *w, uint32_t *qmask)
 {
