@@ -258,17 +258,29 @@ __global__ void __launch_bounds__(256) k_meta_reflux(int nbrick, const EntryDev 
                                                      const int32_t *nbr, const uint8_t *cmask, uint32_t *flag,
                                                      unsigned long long *dof, int32_t *amr_list)
 {
-    const int g = blockIdx.x * 256 + threadIdx.x;
-    if (g >= nbrick) {
-        if (g == nbrick) flag[g] = 0;
-        return;
-    }
+    const int gi = blockIdx.x * 256 + threadIdx.x;
+    if (gi == nbrick) flag[gi] = 0;
+    if (nbrick <= 0) return;
+    // lanes past the last brick take its level and count nothing
+    const bool live = gi < nbrick;
+    const int g = live ? gi : nbrick - 1;
     const int w = org[g].w;
     const EntryDev &E = ent[w];
     uint32_t want = 0;
+    // composite cells: one atomic per wavefront when its bricks share a level
+    // (the usual case; per-brick atomics on a few counters would queue)
+    const uint32_t cells = live && E.amr >= 0 ? 64 * (8 - __popc((uint32_t)cmask[g])) : 0;
+    const int w0 = __shfl(w, 0, 64);
+    if (__all(w == w0)) {
+        unsigned long long sum = cells;
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if ((threadIdx.x & 63) == 0 && sum) atomicAdd(&dof[w0], sum);
+    } else if (cells) {
+        atomicAdd(&dof[w], (unsigned long long)cells);
+    }
+    if (!live) return;
     if (E.amr >= 0) {
         const uint32_t cm = cmask[g];
-        atomicAdd(&dof[w], (unsigned long long)(64 * (8 - __popc(cm))));
         amr_list[E.amr_pos + (g - E.b0)] = g;
         int32_t nb[6];
         uint32_t ncm[6];
