@@ -1170,42 +1170,54 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // row stride ld).  v_mfma_f64 16x16x4 takes Tb[r0 + l%16][i0 + l/16] and
 // D[k0 + l%16][i0 + l/16] from lane l and returns C[r0 + l/16 + 4j][k0 + l%16]
 // in element j, so consecutive lanes hold consecutive k.
-struct DTile {
-    int r0, k0;
-    bool on;
+// The wavefronts of a workgroup take the (R/16) x (N/16) output tiles in
+// turn; the K columns go in chunks of 64 (16 matrix-core steps, two
+// accumulation chains).  A wavefront can take its first tile's first chunk
+// of table rows early (dst_pre), so that those loads overlap the data loads.
+struct DPre {
+    double tb[16];
 };
-// tile of this wavefront among (R/16) x (N/16) tiles (at most 16: R, N <= 64)
-__device__ __forceinline__ DTile dst_tile(int R, int N)
+// this lane's operands of table rows r0.. for columns kc..kc+63:
+// tb[s] = Tb[r0 + l%16][kc + 4s + l/16], from the table stored in that order
+// (64 consecutive values per row block and step)
+__device__ __forceinline__ void dst_rows(const double *Tb, int K, int r0, int kc, double (&tb)[16])
+{
+    const double *p = Tb + ((size_t)(r0 >> 4) * (K >> 2) + (kc >> 2)) * 64 + (threadIdx.x & 63);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) tb[s] = kc + 4 * s < K ? p[64 * s] : 0.0;
+}
+__device__ __forceinline__ void dst_pre(const double *Tb, int R, int N, int K, DPre &pre)
 {
     const int u = threadIdx.x >> 6, tr = R >> 4;
-    DTile t;
-    t.on = u < tr * (N >> 4);
-    t.r0 = (u % tr) << 4;
-    t.k0 = (u / tr) << 4;
-    return t;
-}
-// this lane's operands of the table rows of tile t: tb[s] = Tb[r0 + l%16][4s + l/16],
-// from the table stored in that order (64 consecutive values per row block and step)
-__device__ __forceinline__ void dst_rows(const double *Tb, int K, const DTile &t, double (&tb)[16])
-{
-    const double *p = Tb + (size_t)(t.r0 >> 4) * (K >> 2) * 64 + (threadIdx.x & 63);
-#pragma unroll
-    for (int s = 0; s < 16; ++s) tb[s] = (t.on && 4 * s < K) ? p[64 * s] : 0.0;
+    if (u < tr * (N >> 4)) dst_rows(Tb, K, (u % tr) << 4, 0, pre.tb);
 }
 template <class F>
-__device__ __forceinline__ void dst_mfma(const double (&tb)[16], const double *D, int ld, int K, const DTile &t, F out)
+__device__ __forceinline__ void dst_product(const DPre &pre, const double *Tb, int R, int N, int K, const double *D,
+                                            int ld, F out)
 {
-    if (!t.on) return;
     const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-    const double *d = D + (t.k0 + lr) * ld + lk;
-    dbl4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};  // two chains (even and odd steps)
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, tr = R >> 4, tiles = tr * (N >> 4);
+    for (int u = wave; u < tiles; u += nw) {
+        const int r0 = (u % tr) << 4, k0 = (u / tr) << 4;
+        dbl4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};  // two chains (even and odd steps)
+        for (int kc = 0; kc < K; kc += 64) {
+            double tb[16];
+            if (u == wave && kc == 0) {
 #pragma unroll
-    for (int s = 0; s < 16; s += 2) {
-        if (4 * s < K) a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[s], d[4 * s], a0, 0, 0, 0);
-        if (4 * s + 4 < K) a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[s + 1], d[4 * s + 4], a1, 0, 0, 0);
+                for (int q = 0; q < 16; ++q) tb[q] = pre.tb[q];
+            } else {
+                dst_rows(Tb, K, r0, kc, tb);
+            }
+            const double *d = D + (k0 + lr) * ld + lk + kc;
+#pragma unroll
+            for (int q = 0; q < 16; q += 2) {
+                if (kc + 4 * q < K) a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[q], d[4 * q], a0, 0, 0, 0);
+                if (kc + 4 * q + 4 < K) a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[q + 1], d[4 * q + 4], a1, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out(r0 + lk + 4 * j, k0 + lr, j, a0[j] + a1[j]);
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) out(t.r0 + lk + 4 * j, t.k0 + lr, j, a0[j] + a1[j]);
 }
 
 // table pool layout per job: forward and inverse matrices of x, y, z, each
@@ -1251,31 +1263,35 @@ __global__ void __launch_bounds__(256) k_dst_plane(const DirectJob *jobs, const 
     const int px = pad16(nx), py = pad16(ny);
     double *A = sm, *Bt = sm + rows * ld;  // plane [y][x]; x-transformed block [kx - kx0][y]
     double *w = W + J.w + (size_t)np * z;
-    // table rows of both transforms first, then the plane: all loads in flight together
-    const DTile t1 = dst_tile(16, py), t2 = dst_tile(py, 16);
-    double m1[16], m2[16];
-    dst_rows(dst_table(J, tab, 0, INV) + (size_t)(kx0 >> 4) * (px >> 2) * 64, px, t1, m1);
-    dst_rows(dst_table(J, tab, 1, INV), py, t2, m2);
-    // the plane in rows of 64: x = thread % 64, y = thread / 64 + 4 q
-    const int x = threadIdx.x & 63, y0 = threadIdx.x >> 6;
-    double v[16];
+    // the x table's first rows first, then the plane: those loads in flight together
+    const double *Mx = dst_table(J, tab, 0, INV) + (size_t)(kx0 >> 4) * (px >> 2) * 64, *My = dst_table(J, tab, 1, INV);
+    DPre p1;
+    dst_pre(Mx, 16, py, px, p1);
+    // the plane in rows of 64: x = xb + thread % 64, y = yb + thread / 64 + 4 q
+    for (int xb = 0; xb < px; xb += 64)
+        for (int yb = 0; yb < py; yb += 64) {
+            const int x = xb + (threadIdx.x & 63), y0 = yb + (threadIdx.x >> 6);
+            double v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int y = y0 + 4 * q;
-        v[q] = 0.0;
-        if (y < ny && x < nx) v[q] = INV ? w[y * nx + x] : (double)r[direct_cell(J, x, y, z)];
-    }
+            for (int q = 0; q < 16; ++q) {
+                const int y = y0 + 4 * q;
+                v[q] = 0.0;
+                if (y < ny && x < nx) v[q] = INV ? w[y * nx + x] : (double)r[direct_cell(J, x, y, z)];
+            }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int y = y0 + 4 * q;
-        if (y < py && x < px) A[y * ld + x] = v[q];
-    }
+            for (int q = 0; q < 16; ++q) {
+                const int y = y0 + 4 * q;
+                if (y < py && x < px) A[y * ld + x] = v[q];
+            }
+        }
+    DPre p2;
+    dst_pre(My, py, 16, py, p2);
     __syncthreads();
     // along x: Bt[kx - kx0][y] = sum_x Mx[kx][x] A[y][x]
-    dst_mfma(m1, A, ld, px, t1, [&](int kx, int y, int, double s) { Bt[kx * ld + y] = s; });
+    dst_product(p1, Mx, 16, py, px, A, ld, [&](int kx, int y, int, double s) { Bt[kx * ld + y] = s; });
     __syncthreads();
     // along y: out[ky][kx] = sum_y My[ky][y] Bt[kx - kx0][y]
-    dst_mfma(m2, Bt, ld, py, t2, [&](int y, int xl, int, double s) {
+    dst_product(p2, My, py, 16, py, Bt, ld, [&](int y, int xl, int, double s) {
         const int x = kx0 + xl;
         if (x >= nx || y >= ny) return;
         if (!INV) {
@@ -1309,22 +1325,10 @@ __global__ void __launch_bounds__(256) k_dst_column(const DirectJob *jobs, const
     }
     const int nx = J.dn[0], ny = J.dn[1], nz = J.dn[2], np = nx * ny, pz = pad16(nz);
     const double *mux = dst_table(J, tab, 2, false) + 2 * pz * pz, *muy = mux + nx, *muz = muy + ny;
+    const double *Fz = dst_table(J, tab, 2, false), *Bz = dst_table(J, tab, 2, true);
     double *w = W + J.w;
-    const DTile t = dst_tile(pz, DIRECT_COLS);
-    double mf[16], mb[16];
-    dst_rows(dst_table(J, tab, 2, false), pz, t, mf);
-    dst_rows(dst_table(J, tab, 2, true), pz, t, mb);
-    // eigenvalue sums of this lane's outputs: column k0 + l%16, kz = r0 + l/16 + 4j
-    const int lane = threadIdx.x & 63, col = c0 + t.k0 + (lane & 15);
-    double muc = 0.0, mz[4] = {1.0, 1.0, 1.0, 1.0};
-    if (t.on) {
-        muc = mux[col % nx] + muy[col / nx];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int kz = t.r0 + (lane >> 4) + 4 * j;
-            if (kz < nz) mz[j] = muz[kz];
-        }
-    }
+    DPre pf;
+    dst_pre(Fz, pz, DIRECT_COLS, pz, pf);
     constexpr int NV = DIRECT_DIM * DIRECT_COLS / 256;
     double v[NV];
 #pragma unroll
@@ -1337,10 +1341,16 @@ __global__ void __launch_bounds__(256) k_dst_column(const DirectJob *jobs, const
         const int i = threadIdx.x + 256 * q, zz = i / DIRECT_COLS, c = i % DIRECT_COLS;
         if (zz < pz) A[c * ld + zz] = v[q];
     }
+    DPre pb;
+    dst_pre(Bz, pz, DIRECT_COLS, pz, pb);
     __syncthreads();
-    dst_mfma(mf, A, ld, pz, t, [&](int kz, int c, int j, double s) { C[c * ld + kz] = kz < nz ? s / (muc + mz[j]) : 0.0; });
+    // forward, then the division by the eigenvalue sum of (column, kz)
+    dst_product(pf, Fz, pz, DIRECT_COLS, pz, A, ld, [&](int kz, int c, int, double s) {
+        const int col = c0 + c;
+        C[c * ld + kz] = kz < nz ? s / (mux[col % nx] + muy[col / nx] + muz[kz]) : 0.0;
+    });
     __syncthreads();
-    dst_mfma(mb, C, ld, pz, t, [&](int zz, int c, int, double s) {
+    dst_product(pb, Bz, pz, DIRECT_COLS, pz, C, ld, [&](int zz, int c, int, double s) {
         if (zz < nz) w[(size_t)np * zz + c0 + c] = s;
     });
 }

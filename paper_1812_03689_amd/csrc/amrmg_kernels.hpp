@@ -50,7 +50,7 @@ struct DirectJob {
     int amr;  // 1 when the grid is an AMR level (phi += e after the solve)
     int pad;
 };
-constexpr int DIRECT_DIM = 64;
+constexpr int DIRECT_DIM = 128;
 // columns per workgroup of the transform along z
 constexpr int DIRECT_COLS = 16;
 

@@ -205,10 +205,13 @@ def test_other_smoothers_converge_to_same(smoother, nu):
 @pytest.mark.parametrize("n0,levels", [((16, 16, 16), []), ((24, 24, 24), [(1, 16, 16, 16, 32, 32, 32)]),
                                        ((16, 24, 32), [(1, 8, 16, 24, 24, 32, 40)]),
                                        ((8, 8, 8), [(1, 0, 0, 0, 8, 8, 8), (2, 0, 0, 0, 8, 8, 8)]),
-                                       ((32, 32, 24), [(1, 8, 8, 8, 40, 40, 32)])])
+                                       ((32, 32, 24), [(1, 8, 8, 8, 40, 40, 32)]),
+                                       ((72, 72, 72), []), ((72, 120, 88), [])])
 def test_small_and_ragged_hierarchies(n0, levels):
     """Single level; bases solved directly without multigrid levels below them
-    (24^3, 32 x 32 x 24); unequal edges (anisotropic spacing); a corner box
+    (24^3, 32 x 32 x 24, and coarsest grids above 64 cells per edge whose
+    transforms take several tiles per wavefront and several column chunks:
+    72^3, 72 x 120 x 88); unequal edges (anisotropic spacing); a corner box
     touching the boundary on two refined levels over an 8^3 base.  Each with
     the automatic bottom solver (direct) and with CG forced."""
     print("case", n0, levels, flush=True)
