@@ -315,4 +315,5 @@ def build_hierarchy(n0, particles, max_level: int, tag_rel: Sequence[float],
 
 def hierarchy_from_workload(w) -> OracleHierarchy:
     return build_hierarchy(w.n0, w.particles, w.max_level, w.tag_rel, w.monopoles,
-                           w.explicit_boxes, mgs=w.max_grid_size, bf=w.blocking_factor)
+                           w.explicit_boxes, mgs=w.max_grid_size, bf=w.blocking_factor,
+                           lo=getattr(w, "lo", (0.0, 0.0, 0.0)), hi=getattr(w, "hi", (1.0, 1.0, 1.0)))

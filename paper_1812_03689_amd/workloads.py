@@ -8,8 +8,10 @@ without sharing any part of the computation.
 Workloads follow the paper's own synthetic test problems: a uniformly charged
 sphere (Sec. 6.2, "Uniformly Charged Sphere in Free Space") and Gaussian
 bunches, alone or placed side by side (Sec. 6.3 and Sec. 7, neighbouring
-bunches in a cyclotron).  The domain is the unit cube, eps0 = 1, and the total
-charge of every bunch is 1 split evenly over its macro particles.
+bunches in a cyclotron), and the paper's benchmark chain of 11 bunches.  The
+domain is the unit cube (the chain: a computation cube around the
+particles), eps0 = 1, and the total charge is 1 split evenly over the macro
+particles.
 
 Random numbers: NumPy PCG64 seeded with ``1812000 + 100*config + instance``.
 Particles that fall outside [0, 1)^3 are redrawn.
@@ -147,6 +149,8 @@ class Workload:
     max_grid_size: int = 32
     blocking_factor: int = 8
     precision: str = "mixed"
+    lo: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # the domain [lo, hi)
+    hi: Tuple[float, float, float] = (1.0, 1.0, 1.0)
 
 
 def config1(n_particles: int = 10**4) -> Workload:
@@ -196,4 +200,58 @@ def config5_instances(count: int = 64, scale: float = 1.0) -> List[Workload]:
     return out
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
+def chain_bunches(n_per: int = 10**6, nb: int = 11, sigma=(1.5e-3, 5e-3, 5e-3), spacing: float = 0.04,
+                  seed: int = seed_for(6)) -> Particles:
+    """The paper's benchmark source (Sec. 6.3 and the strong-scaling test of
+    Sec. 6.4): ``nb`` Gaussian bunches of ``n_per`` particles in metres, sigma
+    (1.5 mm, 5 mm, 5 mm), centres 4 cm apart along x around the origin.  Unit
+    total charge split evenly (the paper's 0.1 fC per particle only scales
+    phi)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = np.asarray(sigma, dtype=np.float64)
+    pts = []
+    for k in range(nb):
+        c = np.array([(k - (nb - 1) / 2.0) * spacing, 0.0, 0.0])
+        pts.append(c + rng.standard_normal((n_per, 3)) * s)
+    p = np.concatenate(pts)
+    q = np.full(p.shape[0], 1.0 / p.shape[0], dtype=np.float64)
+    return Particles(np.ascontiguousarray(p[:, 0]), np.ascontiguousarray(p[:, 1]),
+                     np.ascontiguousarray(p[:, 2]), q)
+
+
+def isotropic_domain(p: Particles, margin: float = 0.1):
+    """The computation cube around the particles (the paper's S_c with a
+    box increment delta = 10 %): centred on their bounding box, edge
+    (1 + margin) times its longest side, so that cells are cubes."""
+    lo = np.array([p.x.min(), p.y.min(), p.z.min()], dtype=np.float64)
+    hi = np.array([p.x.max(), p.y.max(), p.z.max()], dtype=np.float64)
+    c, hw = 0.5 * (lo + hi), 0.5 * (1.0 + margin) * float(np.max(hi - lo))
+    return tuple(float(v) for v in c - hw), tuple(float(v) for v in c + hw)
+
+
+def config6(n_per: int = 10**6, n0: int = 576, lam: float = 1e-3, nb: int = 11) -> Workload:
+    """The paper's strong-scaling benchmark on one GPU: 11 Gaussian bunches of
+    1e6 particles, 576^3 base cells on the computation cube, 2 refined levels
+    tagged at lam x max|rho| (the paper does not state its threshold),
+    homogeneous Dirichlet boundary, tol 1e-8."""
+    p = chain_bunches(n_per, nb)
+    lo, hi = isotropic_domain(p)
+    return Workload(f"chain{nb}_{n0}c_2lev", p, (n0, n0, n0), 2, [lam, lam], [], 1e-8, max_grid_size=32,
+                    lo=lo, hi=hi)
+
+
+def jitter(x, y, z, lo, hi, amp: float = 1e-3, gen=None):
+    """One step of the benchmark's particle motion: every coordinate moves by a
+    uniform random amount in [-amp, amp] times the half-edge of the
+    computation cube (the paper's displacement within [-1e-3, 1e-3] in
+    computation-space units).  Works on torch tensors (any device); gen is a
+    torch.Generator of that device."""
+    import torch
+    out = []
+    for a, l, h in zip((x, y, z), lo, hi):
+        d = torch.rand(a.shape, generator=gen, device=a.device, dtype=torch.float64) * 2.0 - 1.0
+        out.append(a + (d * (amp * 0.5 * (h - l))).to(a.dtype))
+    return out
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 6: config6}

@@ -40,7 +40,7 @@ def rel_l2_composite(H, a, b):
 def make_ctx(w, precision="fp64", smoother="gsrb", **kw):
     A = amr()
     prm = A.make_params(w.n0, max_level=w.max_level, monopoles=w.monopoles, precision=precision,
-                        smoother=smoother, max_grid_size=w.max_grid_size, **kw)
+                        smoother=smoother, max_grid_size=w.max_grid_size, lo=w.lo, hi=w.hi, **kw)
     ctx = A.Context(prm)
     x, y, z, q = dev(w.particles)
     ctx.build_hierarchy(x, y, z, q, tag_rel=w.tag_rel, explicit_boxes=w.explicit_boxes)
@@ -66,7 +66,17 @@ def oracle_solution(w, key):
     return _cache[key]
 
 
-CASES = {"c1": lambda: W.config1(), "c2s": small_c2}
+def small_chain():
+    """The paper's benchmark shape (11 bunches 4 cm apart, sigma 1.5 / 5 / 5 mm,
+    homogeneous Dirichlet on the computation cube around them, which is not
+    the unit cube) with 2e3 particles per bunch on a 32^3 base: all charge
+    lies on level 2, so levels 0 and 1 use the composite norm."""
+    p = W.chain_bunches(2000, seed=W.seed_for(6, 1))
+    lo, hi = W.isotropic_domain(p)
+    return W.Workload("chain11_32c_2lev", p, (32, 32, 32), 2, [1e-3, 1e-3], [], 1e-8, lo=lo, hi=hi)
+
+
+CASES = {"c1": lambda: W.config1(), "c2s": small_c2, "chain": small_chain}
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
