@@ -292,6 +292,20 @@ def bench_paper(args):
     value = float(np.sum(dofs)) / (ms_step * 1e-3 * args.steps)
     info = state["info"]
 
+    # every kernel class timed over one more step (kernel-execution events on
+    # the library's stream): algorithmic GB/s per class against the HBM peak
+    amrmg.amrmg_profile_enable(cm.h, list(range(len(amrmg.KCLASS))))
+    step(nsets - 1)
+    torch.cuda.synchronize()
+    classes = {}
+    for c in amrmg.KCLASS:
+        v = amrmg.amrmg_profile_read(cm.h, c)
+        if v["launches"]:
+            gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else 0.0
+            classes[c] = {"ms": round(v["ms"], 4), "launches": v["launches"], "achieved_gbs": round(gbs, 1),
+                          "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 3)}
+    amrmg.amrmg_profile_enable(cm.h, [])
+
     # the solve alone on the last hierarchy: mixed and plain FP64
     cf = ctx_for("fp64")
     cf.build_hierarchy(*sets[-1], q, tag_rel=w.tag_rel)
@@ -318,7 +332,7 @@ def bench_paper(args):
                    "regrid_every": args.regrid_every, "jitter": "uniform +-1e-3 x half-edge per step",
                    "step": "jitter (pre-drawn) + [build_hierarchy + deposit_built every regrid_every steps, else "
                            "deposit] + solve + E + gather"},
-        "iters": iters, "solve": solve, "paper_context": PAPER_CONTEXT,
+        "iters": iters, "solve": solve, "kernel_classes_one_step": classes, "paper_context": PAPER_CONTEXT,
     }
     print(json.dumps(out), flush=True)
 
