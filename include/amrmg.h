@@ -235,6 +235,34 @@ amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *x, const vo
                           const void *z, int64_t n, double *const *E, double *Ex, double *Ey,
                           double *Ez);
 
+/* Domain transform (Sec. 4.2 of the paper): map particles from particle
+ * space S_p into the computation space S_c = [-l0,l0] x [-l1,l1] x [-l2,l2]
+ * around the reference position c.  With Gamma(x, l) = max_d |x_d - c_d| /
+ * l_d, the scale is s = max over the n particles of Gamma (the particle
+ * farthest out in units of l lands on the boundary of S_c) and
+ * x* = (x - c) / s, computed in FP64 (FP32 positions are promoted, the
+ * result rounded back).  The mesh domain (lo, hi of the parameters) is then
+ * S_c enlarged by the margin the caller chooses.  Solving in S_c with the
+ * same charges gives phi* and E*; amrmg_rescale_fields turns them into the
+ * particle-space fields.
+ *   x, y, z     device [n] (pos_dtype); xs, ys, zs device [n] outputs of the
+ *               same type, which may alias x, y, z
+ *   center, l   host [3]; l > 0
+ *   s           host output; 0 when n == 0 (nothing is written)
+ * AMRMG_E_INVALID for a non-finite coordinate or when every particle sits
+ * at c (s = 0); then xs, ys, zs are not written.  Synchronises (s is read
+ * back); the map itself is enqueued after that. */
+amrmg_status amrmg_transform_particles(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y,
+                                       const void *z, int64_t n, const double *center, const double *l,
+                                       void *xs, void *ys, void *zs, double *s);
+
+/* Rescale the fields of a solve in computation space to particle space, on
+ * the grid (Eqs. potential_transform and efield_transform, three
+ * dimensions): phi[l] /= s and E[3l+d] /= s^2 on every level of the built
+ * hierarchy (device, user layout; phi or E may be NULL).  s > 0 as returned
+ * by amrmg_transform_particles.  Asynchronous. */
+amrmg_status amrmg_rescale_fields(amrmg_ctx *ctx, double s, double *const *phi, double *const *E);
+
 /* The FP64 composite residual of Alg. 1 on every level for given rho and phi:
  * r[l] = U^l (rho^l/eps0 - A_comp phi) (user layout, device, zero on covered
  * cells).  Diagnostic entry point; it runs the same kernels as the solve's

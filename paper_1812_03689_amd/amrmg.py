@@ -34,7 +34,7 @@ EXPORTED = ["amrmg_default_params", "amrmg_create", "amrmg_destroy", "amrmg_last
             "amrmg_build_hierarchy", "amrmg_hierarchy_info", "amrmg_get_boxes", "amrmg_cf_faces", "amrmg_brick_tables",
             "amrmg_workspace_size", "amrmg_set_workspace", "amrmg_deposit", "amrmg_deposit_built", "amrmg_solve",
             "amrmg_gather", "amrmg_residual", "amrmg_solve_batch", "amrmg_profile_enable",
-            "amrmg_profile_read"]
+            "amrmg_profile_read", "amrmg_transform_particles", "amrmg_rescale_fields"]
 KCLASS = ["gsrb", "jacobi", "restrict", "prolong", "reflux", "cpart", "residual", "phi_update", "bottom",
           "efield", "avgdown", "deposit", "gather"]
 
@@ -99,6 +99,8 @@ def lib():
         L.amrmg_solve_batch.argtypes = [vp, i32, vp, vp, dbl, C.POINTER(amrmg_solve_stats)]
         L.amrmg_profile_enable.argtypes = [vp, C.c_uint32]
         L.amrmg_profile_read.argtypes = [vp, i32, vp, vp, vp]
+        L.amrmg_transform_particles.argtypes = [vp, C.c_int, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.amrmg_rescale_fields.argtypes = [vp, dbl, vp, vp]
         _lib = L
     return _lib
 
@@ -269,6 +271,21 @@ def amrmg_solve_batch(handles: Sequence, rho: Sequence[Sequence], phi: Sequence[
     return out
 
 
+def amrmg_transform_particles(h, x, y, z, center, l, xs, ys, zs) -> float:
+    c = (C.c_double * 3)(*[float(v) for v in center])
+    ll = (C.c_double * 3)(*[float(v) for v in l])
+    s = C.c_double()
+    _check(lib().amrmg_transform_particles(h, _pos_dtype(x), x.data_ptr(), y.data_ptr(), z.data_ptr(),
+                                           int(x.numel()), c, ll, xs.data_ptr(), ys.data_ptr(), zs.data_ptr(),
+                                           C.byref(s)))
+    return s.value
+
+
+def amrmg_rescale_fields(h, s: float, phi: Optional[Sequence], E: Optional[Sequence]) -> None:
+    _check(lib().amrmg_rescale_fields(h, float(s), _ptrs(phi) if phi is not None else None,
+                                      _ptrs(E) if E is not None else None))
+
+
 def amrmg_profile_enable(h, classes) -> None:
     mask = 0
     for c in classes:
@@ -376,3 +393,14 @@ class Context:
         Ex, Ey, Ez = (torch.empty(n, dtype=torch.float64, device=x.device) for _ in range(3))
         amrmg_gather(self.h, x, y, z, E, Ex, Ey, Ez)
         return Ex, Ey, Ez
+
+    def transform_particles(self, x, y, z, center, l, out=None):
+        """Map particles into computation space (amrmg_transform_particles):
+        returns (xs, ys, zs, s); out=(x, y, z) transforms in place."""
+        import torch
+        xs, ys, zs = out if out is not None else (torch.empty_like(x), torch.empty_like(y), torch.empty_like(z))
+        s = amrmg_transform_particles(self.h, x, y, z, center, l, xs, ys, zs)
+        return xs, ys, zs, s
+
+    def rescale_fields(self, s, phi=None, E=None):
+        amrmg_rescale_fields(self.h, s, phi, E)

@@ -1367,6 +1367,61 @@ extern "C" amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *
 }
 
 // ---------------------------------------------------------------------------
+// domain transform (Sec. 4.2)
+// ---------------------------------------------------------------------------
+extern "C" amrmg_status amrmg_transform_particles(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y,
+                                                  const void *z, int64_t n, const double *center, const double *l,
+                                                  void *xs, void *ys, void *zs, double *s)
+{
+    if (!ctx) return fail(AMRMG_E_INVALID, "ctx is NULL");
+    if (pos_dtype != AMRMG_POS_F64 && pos_dtype != AMRMG_POS_F32) return fail(AMRMG_E_INVALID, "bad pos_dtype");
+    if (!center || !l || !s) return fail(AMRMG_E_INVALID, "center, l and s must not be NULL");
+    if (n < 0 || (n > 0 && (!x || !y || !z || !xs || !ys || !zs))) return fail(AMRMG_E_INVALID, "bad particle arrays");
+    for (int d = 0; d < 3; ++d) {
+        if (!(l[d] > 0.0) || !std::isfinite(l[d])) return fail(AMRMG_E_INVALID, "l must be positive and finite");
+        if (!std::isfinite(center[d])) return fail(AMRMG_E_INVALID, "center must be finite");
+    }
+    *s = 0.0;
+    if (n == 0) return AMRMG_OK;
+    HIP_TRY(ctx->tag_scratch.ensure(sizeof(double) * 1040));
+    unsigned long long *d_bits = (unsigned long long *)ctx->tag_scratch.p;
+    HIP_TRY(hipMemsetAsync(d_bits, 0, sizeof(unsigned long long), ctx->st));
+    launch_domain_scale(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, center, l, d_bits);
+    HIP_TRY(hipGetLastError());
+    double v = 0.0;
+    HIP_TRY(hipMemcpyAsync(&v, d_bits, sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+    HIP_TRY(hipStreamSynchronize(ctx->st));
+    if (!std::isfinite(v)) return fail(AMRMG_E_INVALID, "a particle coordinate is not finite");
+    if (!(v > 0.0)) return fail(AMRMG_E_INVALID, "every particle sits at the centre: the scale is zero");
+    launch_to_computation(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, center, v, xs, ys, zs);
+    HIP_TRY(hipGetLastError());
+    *s = v;
+    return AMRMG_OK;
+}
+
+extern "C" amrmg_status amrmg_rescale_fields(amrmg_ctx *ctx, double s, double *const *phi, double *const *E)
+{
+    if (!ctx) return fail(AMRMG_E_INVALID, "ctx is NULL");
+    if (!ctx->built) return fail(AMRMG_E_STATE, "hierarchy not built");
+    if (!(s > 0.0) || !std::isfinite(s)) return fail(AMRMG_E_INVALID, "s must be positive and finite");
+    const Problem &pr = ctx->prob;
+    const int L = pr.namr();
+    for (int l = 0; l < L; ++l) {
+        if ((phi && !phi[l]) || (E && (!E[3 * l] || !E[3 * l + 1] || !E[3 * l + 2])))
+            return fail(AMRMG_E_INVALID, "a level array is NULL");
+    }
+    const double s2 = s * s;
+    for (int l = 0; l < L; ++l) {
+        const int64_t nc = pr.lev[pr.kg + l].ncells();
+        if (phi) launch_divide(ctx->st, phi[l], nc, s);
+        if (E)
+            for (int d = 0; d < 3; ++d) launch_divide(ctx->st, E[3 * l + d], nc, s2);
+    }
+    HIP_TRY(hipGetLastError());
+    return AMRMG_OK;
+}
+
+// ---------------------------------------------------------------------------
 // the solve
 // ---------------------------------------------------------------------------
 // replay the outer iteration as a hipGraph (AMRMG_NO_GRAPH=1 disables)

@@ -186,5 +186,13 @@ hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x,
 void launch_mark_blocks(hipStream_t st, const double *rho, int64_t ncell, const int4 *borg, const int64_t *ubase,
                         const int2 *ustr, int nb, double lambda, int nbuf, int half, int3 n, int3 g, double *scratch,
                         uint8_t *marks);
+// domain transform (amrmg_transform.hip): out (one word, zeroed by the
+// caller) receives the bits of max_i max_d |x_d - c_d| / l_d (+inf for a NaN
+// coordinate); xs = (x - c) / s (may alias x); v[i] = v[i] / div
+void launch_domain_scale(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
+                         const double *c, const double *l, unsigned long long *out);
+void launch_to_computation(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
+                           const double *c, double s, void *xs, void *ys, void *zs);
+void launch_divide(hipStream_t st, double *v, int64_t n, double div);
 
 }  // namespace amrmg
