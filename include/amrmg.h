@@ -68,6 +68,14 @@ enum { AMRMG_GSRB = 0, AMRMG_JACOBI = 1, AMRMG_GSRB_GLOBAL = 2 };
  * AMRMG_BOTTOM_CG always uses CG. */
 enum { AMRMG_BOTTOM_AUTO = 0, AMRMG_BOTTOM_CG = 1 };
 enum { AMRMG_MAX_LEVELS = 8 };
+/* Refinement criteria of amrmg_build_hierarchy (Sec. 4.1): tag a cell of
+ * level l when |rho| > lambda max|rho| (AMRMG_TAG_CHARGE), |phi| > lambda
+ * max|phi| (AMRMG_TAG_POTENTIAL), or |E_w| > lambda max|E_w| for some
+ * component w (AMRMG_TAG_EFIELD), each maximum taken over level l.  phi and
+ * E come from solving the composite problem on the levels built so far
+ * (0..l) to a relative residual of AMRMG_TAG_SOLVE_TOL. */
+enum { AMRMG_TAG_CHARGE = 0, AMRMG_TAG_POTENTIAL = 1, AMRMG_TAG_EFIELD = 2 };
+#define AMRMG_TAG_SOLVE_TOL 1e-10
 
 /* Solver and hierarchy parameters.  amrmg_default_params fills the defaults
  * named in brackets. */
@@ -93,6 +101,7 @@ typedef struct amrmg_params {
                                    side; it bounds only how well each cycle treats the smoothest
                                    modes, not the accuracy of the result [1e-2] */
     int32_t bottom;             /* AMRMG_BOTTOM_AUTO or AMRMG_BOTTOM_CG [AUTO] */
+    int32_t tag_policy;         /* AMRMG_TAG_CHARGE, AMRMG_TAG_POTENTIAL or AMRMG_TAG_EFIELD [CHARGE] */
 } amrmg_params;
 
 /* Per-solve statistics. */
@@ -116,7 +125,10 @@ const char *amrmg_last_error(void);
 
 /* Build the level hierarchy (Sec. 3 and Sec. 4.1 of the paper).  For each
  * level l < max_level in turn: deposit the particles on level l, tag the
- * cells with |rho^l| > tag_rel[l] * max|rho^l|, dilate the tags by n_buffer
+ * cells with |rho^l| > tag_rel[l] * max|rho^l| (or, with the potential and
+ * field criteria of tag_policy, solve on levels 0..l and tag by |phi^l| or
+ * the components of E^l; the solve's status is returned if it fails, with
+ * the context left unbuilt), dilate the tags by n_buffer
  * cells, group them into 8-cell blocks of level l+1, drop blocks that break
  * proper nesting, and merge the blocks greedily (x, then y, then z, at most
  * max_grid_size cells per edge) into the boxes of level l+1.  The procedure is

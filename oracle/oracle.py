@@ -291,10 +291,32 @@ def step1_layer(mask5: int, layer: np.ndarray, tu: float, tv: float):
     return float(v), int(pat.value)
 
 
+TAG_SOLVE_TOL = 1e-13
+
+
+def field_tags(H: OracleHierarchy, l: int, particles, policy: str, lam: float) -> np.ndarray:
+    """Tags of level l, the finest level of H, by the potential or the
+    electric field (Sec. 4.1): the composite problem on H's levels is solved
+    with every particle deposited, then a cell is tagged when |phi| exceeds
+    lam times the level's max |phi| ("potential"), or when some component
+    |E_w| exceeds lam times that component's max over the level ("efield")."""
+    assert H.nlev == l + 1
+    phi, E, st = H.solve(H.deposit_all(particles), tol=TAG_SOLVE_TOL, max_iters=80, bottom_rtol=1e-14)
+    if policy == "potential":
+        return H.tag(l, phi[l], lam)
+    if policy == "efield":
+        tags = np.zeros(H.ncells(l), dtype=np.uint8)
+        for d in range(3):
+            tags |= H.tag(l, E[3 * l + d], lam)
+        return tags
+    raise ValueError(policy)
+
+
 def build_hierarchy(n0, particles, max_level: int, tag_rel: Sequence[float],
                     monopoles=(), explicit_boxes=None, n_buffer=1, n_proper=2, bf=8, mgs=32,
-                    lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), eps0=1.0) -> OracleHierarchy:
-    """Regrid loop: deposit level l, tag it, generate level l+1 boxes; explicit
+                    lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), eps0=1.0, tag_policy="charge") -> OracleHierarchy:
+    """Regrid loop: tag level l (by its own deposit, or by the potential or
+    field of a solve on levels 0..l), generate level l+1 boxes; explicit
     boxes ``(level, lo3, hi3)`` replace the tagging for their level."""
     H = OracleHierarchy(n0, lo, hi, eps0, monopoles)
     explicit = {}
@@ -304,8 +326,11 @@ def build_hierarchy(n0, particles, max_level: int, tag_rel: Sequence[float],
         if (l + 1) in explicit:
             boxes = np.asarray(explicit[l + 1], dtype=np.int32)
         else:
-            rho, _ = H.deposit(l, particles)
-            tags = H.tag(l, rho, tag_rel[l])
+            if tag_policy == "charge":
+                rho, _ = H.deposit(l, particles)
+                tags = H.tag(l, rho, tag_rel[l])
+            else:
+                tags = field_tags(H, l, particles, tag_policy, tag_rel[l])
             boxes = H.cluster(l, tags, n_buffer, n_proper, bf, mgs)
         if boxes.shape[0] == 0:
             break
@@ -316,4 +341,5 @@ def build_hierarchy(n0, particles, max_level: int, tag_rel: Sequence[float],
 def hierarchy_from_workload(w) -> OracleHierarchy:
     return build_hierarchy(w.n0, w.particles, w.max_level, w.tag_rel, w.monopoles,
                            w.explicit_boxes, mgs=w.max_grid_size, bf=w.blocking_factor,
-                           lo=getattr(w, "lo", (0.0, 0.0, 0.0)), hi=getattr(w, "hi", (1.0, 1.0, 1.0)))
+                           lo=getattr(w, "lo", (0.0, 0.0, 0.0)), hi=getattr(w, "hi", (1.0, 1.0, 1.0)),
+                           tag_policy=getattr(w, "tag_policy", "charge"))

@@ -794,7 +794,7 @@ struct amrmg_ctx {
     bool built = false;
     DevState ds;
     // scratch of the tagging passes of build_hierarchy
-    DBuf tag_marks, tag_scratch, tag_geom;
+    DBuf tag_marks, tag_scratch, tag_geom, tag_fields;
     PBuf tag_stage, tag_host;
     // spatial visiting order of the particles (a performance hint for the
     // deposit; any order gives the same sums up to rounding)
@@ -849,6 +849,7 @@ extern "C" void amrmg_default_params(amrmg_params *p)
     p->max_iters = 50;
     p->bottom_rtol = 1e-2;
     p->bottom = AMRMG_BOTTOM_AUTO;
+    p->tag_policy = AMRMG_TAG_CHARGE;
 }
 
 extern "C" const char *amrmg_last_error(void) { return g_err.c_str(); }
@@ -876,6 +877,8 @@ static amrmg_status check_params(const amrmg_params *p)
     if (!(p->bottom_rtol > 0 && p->bottom_rtol < 1)) return fail(AMRMG_E_INVALID, "bottom_rtol in (0, 1)");
     if (p->bottom != AMRMG_BOTTOM_AUTO && p->bottom != AMRMG_BOTTOM_CG) return fail(AMRMG_E_INVALID, "bad bottom");
     if (!(p->omega > 0 && p->omega <= 1)) return fail(AMRMG_E_INVALID, "omega in (0, 1]");
+    if (p->tag_policy != AMRMG_TAG_CHARGE && p->tag_policy != AMRMG_TAG_POTENTIAL && p->tag_policy != AMRMG_TAG_EFIELD)
+        return fail(AMRMG_E_INVALID, "bad tag_policy");
     return AMRMG_OK;
 }
 
@@ -952,16 +955,23 @@ static amrmg_status compute_order(amrmg_ctx *ctx, int pos_dtype, const void *x, 
     return AMRMG_OK;
 }
 
-// Tagging pass on level l: deposit, tag, dilate and mark the blocks of level
-// l+1 on the device; the host then applies nesting and the greedy merge.
-static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype, const void *x, const void *y,
-                              const void *z, const double *q, int64_t n, double lambda, std::vector<Box> &boxes,
-                              const uint32_t *perm, unsigned long long *nout)
+// Geometry of the tagging passes on level L: per brick its origin, its
+// caller's-layout base and strides, and the level's brick map, uploaded to
+// the device; the block marks of level l+1 cleared.
+struct TagGeom {
+    int32_t *borg = nullptr, *us = nullptr, *bmap = nullptr;
+    int64_t *ub = nullptr;
+    int nb = 0;
+    int64_t nc = 0;
+    int3 nn{}, g{};
+    size_t ng = 0;
+};
+
+static amrmg_status tag_geometry(amrmg_ctx *ctx, const HostLevel &L, TagGeom &G)
 {
     const amrmg_params &P = ctx->P;
     hipStream_t st = ctx->st;
     int nb = L.nbrick();
-    int64_t nc = L.ncells();
     static thread_local std::vector<int32_t> borg;
     static thread_local std::vector<int64_t> ub;
     static thread_local std::vector<int32_t> us;
@@ -979,39 +989,134 @@ static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype,
         us[2 * b + 1] = (int32_t)(nx * ny);
     }
     Packer pk;
-    int32_t *d_borg = nullptr, *d_us = nullptr, *d_bmap = nullptr;
-    int64_t *d_ub = nullptr;
-    pk.add(borg, &d_borg);
-    pk.add(ub, &d_ub);
-    pk.add(us, &d_us);
-    pk.add(L.bmap, &d_bmap);
+    pk.add(borg, &G.borg);
+    pk.add(ub, &G.ub);
+    pk.add(us, &G.us);
+    pk.add(L.bmap, &G.bmap);
     ST_TRY(pk.run(ctx->tag_geom, ctx->tag_stage, st));
-    const int half = P.blocking_factor / 2;
-    int3 nn = make_int3(L.n[0], L.n[1], L.n[2]);
-    int3 g = make_int3(2 * L.n[0] / P.blocking_factor, 2 * L.n[1] / P.blocking_factor, 2 * L.n[2] / P.blocking_factor);
-    size_t ng = (size_t)g.x * g.y * g.z;
-    // the level's charge is kept for amrmg_deposit_built
-    HIP_TRY(ctx->lev_rho[L.amr].ensure(sizeof(double) * nc));
+    G.nb = nb;
+    G.nc = L.ncells();
+    G.nn = make_int3(L.n[0], L.n[1], L.n[2]);
+    G.g = make_int3(2 * L.n[0] / P.blocking_factor, 2 * L.n[1] / P.blocking_factor, 2 * L.n[2] / P.blocking_factor);
+    G.ng = (size_t)G.g.x * G.g.y * G.g.z;
     HIP_TRY(ctx->tag_scratch.ensure(sizeof(double) * 1040));
-    HIP_TRY(ctx->tag_marks.ensure(ng));
-    HIP_TRY(ctx->tag_host.ensure(ng));
-    double *rho = (double *)ctx->lev_rho[L.amr].p;
-    launch_fill(st, rho, nc, 0.0);
-    Problem &pr = ctx->prob;
-    DepArgs A{};
-    A.nlev = 1;
-    A.lev[0] = dep_level(pr, L, d_bmap);
-    A.rho[0] = rho;
-    A.ncell[0] = nc;
-    launch_deposit(st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, perm, A, d_ub, (const int2 *)d_us, nout);
-    HIP_TRY(hipMemsetAsync(ctx->tag_marks.p, 0, ng, st));
-    launch_mark_blocks(st, rho, nc, (const int4 *)d_borg, d_ub, (const int2 *)d_us, nb, lambda, P.n_buffer, half, nn,
-                       g, (double *)ctx->tag_scratch.p, (uint8_t *)ctx->tag_marks.p);
-    HIP_TRY(hipMemcpyAsync(ctx->tag_host.p, ctx->tag_marks.p, ng, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(ctx->tag_marks.ensure(G.ng));
+    HIP_TRY(ctx->tag_host.ensure(G.ng));
+    HIP_TRY(hipMemsetAsync(ctx->tag_marks.p, 0, G.ng, st));
+    return AMRMG_OK;
+}
+
+// mark the blocks of level l+1 reached by the (dilated) cells of level L
+// with |v| > lambda * max |v|; the marks of several arrays accumulate
+static void tag_mark(amrmg_ctx *ctx, const TagGeom &G, const double *v, double lambda)
+{
+    launch_mark_blocks(ctx->st, v, G.nc, (const int4 *)G.borg, G.ub, (const int2 *)G.us, G.nb, lambda, ctx->P.n_buffer,
+                       ctx->P.blocking_factor / 2, G.nn, G.g, (double *)ctx->tag_scratch.p,
+                       (uint8_t *)ctx->tag_marks.p);
+}
+
+// the marks to the host, then proper nesting and the greedy merge
+static amrmg_status tag_boxes(amrmg_ctx *ctx, const HostLevel &L, const TagGeom &G, std::vector<Box> &boxes)
+{
+    const amrmg_params &P = ctx->P;
+    HIP_TRY(hipMemcpyAsync(ctx->tag_host.p, ctx->tag_marks.p, G.ng, hipMemcpyDeviceToHost, ctx->st));
+    HIP_TRY(hipStreamSynchronize(ctx->st));
     HIP_TRY(hipGetLastError());
     boxes = merge_blocks(L, (uint8_t *)ctx->tag_host.p, P.n_proper, P.blocking_factor, P.max_grid_size);
     return AMRMG_OK;
+}
+
+// Charge tagging of level l (Sec. 4.1, Eq. tag_charge in relative form):
+// deposit level l alone, tag, dilate and mark the blocks of level l+1 on the
+// device; the host then applies nesting and the greedy merge.
+static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype, const void *x, const void *y,
+                              const void *z, const double *q, int64_t n, double lambda, std::vector<Box> &boxes,
+                              const uint32_t *perm, unsigned long long *nout)
+{
+    hipStream_t st = ctx->st;
+    TagGeom G;
+    ST_TRY(tag_geometry(ctx, L, G));
+    // the level's charge is kept for amrmg_deposit_built
+    HIP_TRY(ctx->lev_rho[L.amr].ensure(sizeof(double) * G.nc));
+    double *rho = (double *)ctx->lev_rho[L.amr].p;
+    launch_fill(st, rho, G.nc, 0.0);
+    Problem &pr = ctx->prob;
+    DepArgs A{};
+    A.nlev = 1;
+    A.lev[0] = dep_level(pr, L, G.bmap);
+    A.rho[0] = rho;
+    A.ncell[0] = G.nc;
+    launch_deposit(st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, perm, A, G.ub, (const int2 *)G.us, nout);
+    tag_mark(ctx, G, rho, lambda);
+    return tag_boxes(ctx, L, G, boxes);
+}
+
+// Potential or field tagging of level l (Sec. 4.1, the relative criteria on
+// phi and on each component E_w): the hierarchy built so far (levels 0..l)
+// is finished, every particle deposited on it and the composite problem
+// solved to a relative residual of AMRMG_TAG_SOLVE_TOL; a cell of level l is
+// tagged when |phi| > lambda max|phi| over the level, or (field) when
+// |E_w| > lambda max|E_w| for some component w.  The levels below level 0
+// are removed again afterwards.
+static amrmg_status tag_level_field(amrmg_ctx *ctx, int l, int pos_dtype, const void *x, const void *y,
+                                    const void *z, const double *q, int64_t n, double lambda,
+                                    std::vector<Box> &boxes)
+{
+    const amrmg_params &P = ctx->P;
+    hipStream_t st = ctx->st;
+    Problem &pr = ctx->prob;
+    add_levels_below(pr);
+    auto restore = [&]() {
+        pr.lev.erase(pr.lev.begin(), pr.lev.begin() + pr.kg);
+        pr.kg = 0;
+        pr.lev.reserve(P.max_level + 16);
+        ctx->built = false;
+    };
+    amrmg_status rc = upload_meta(ctx->ds, st, {&pr}, P.bottom == AMRMG_BOTTOM_AUTO);
+    if (rc == AMRMG_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(AMRMG_E_HIP, "hipStreamSynchronize failed");
+    if (rc == AMRMG_OK && !ctx->ds.meta.error.empty()) rc = fail(AMRMG_E_NESTING, ctx->ds.meta.error);
+    if (rc == AMRMG_OK && *(int *)ctx->ds.h_face_err.p)
+        rc = fail(AMRMG_E_NESTING, "coarse-fine window leaves the coarser level (nesting violated)");
+    if (rc != AMRMG_OK) {
+        restore();
+        return rc;
+    }
+    ctx->built = true;
+    const bool field = P.tag_policy == AMRMG_TAG_EFIELD;
+    const int nv = field ? 5 : 2;  // rho, phi (, E)
+    int64_t total = 0;
+    for (int k = 0; k <= l; ++k) total += pr.lev[pr.kg + k].ncells();
+    std::vector<double *> rho(l + 1), phi(l + 1), E(3 * (l + 1));
+    if (ctx->tag_fields.ensure(sizeof(double) * (size_t)(nv * total + 1)) != hipSuccess) {
+        restore();
+        return fail(AMRMG_E_OOM, "tagging fields");
+    }
+    double *cur = (double *)ctx->tag_fields.p;
+    for (int k = 0; k <= l; ++k) {
+        const int64_t nc = pr.lev[pr.kg + k].ncells();
+        rho[k] = cur;
+        phi[k] = cur + nc;
+        cur += 2 * nc;
+        if (field)
+            for (int d = 0; d < 3; ++d, cur += nc) E[3 * k + d] = cur;
+    }
+    launch_fill(st, (double *)ctx->tag_fields.p, nv * total, 0.0);
+    rc = amrmg_deposit(ctx, pos_dtype, x, y, z, q, n, rho.data(), nullptr);
+    if (rc == AMRMG_OK)
+        rc = amrmg_solve(ctx, rho.data(), phi.data(), field ? E.data() : nullptr, AMRMG_TAG_SOLVE_TOL, nullptr);
+    if (rc == AMRMG_E_NOT_CONVERGED)
+        rc = fail(AMRMG_E_NOT_CONVERGED, "the solve for tagging level " + std::to_string(l) + " did not converge");
+    TagGeom G;
+    if (rc == AMRMG_OK) rc = tag_geometry(ctx, pr.lev[pr.kg + l], G);
+    if (rc == AMRMG_OK) {
+        if (field)
+            for (int d = 0; d < 3; ++d) tag_mark(ctx, G, E[3 * l + d], lambda);
+        else
+            tag_mark(ctx, G, phi[l], lambda);
+        rc = tag_boxes(ctx, pr.lev[pr.kg + l], G, boxes);
+    }
+    restore();
+    return rc;
 }
 
 extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y,
@@ -1074,15 +1179,20 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
     }
     for (int l = 0; l < P.max_level; ++l) {
         std::vector<Box> boxes;
-        const HostLevel &L = pr.lev[l];
         if (expl.count(l + 1)) {
             boxes = expl[l + 1];
         } else {
             if (!tag_rel) return fail(AMRMG_E_INVALID, "tag_rel is NULL but a level needs tagging");
-            ST_TRY(tag_level(ctx, L, pos_dtype, tx, ty, tz, tq, n, tag_rel[l], boxes, tperm,
-                             l == 0 ? (unsigned long long *)ctx->built_nout.p : nullptr));
-            ctx->lev_rho_ok[l] = 1;
+            if (P.tag_policy == AMRMG_TAG_CHARGE) {
+                ST_TRY(tag_level(ctx, pr.lev[l], pos_dtype, tx, ty, tz, tq, n, tag_rel[l], boxes, tperm,
+                                 l == 0 ? (unsigned long long *)ctx->built_nout.p : nullptr));
+                ctx->lev_rho_ok[l] = 1;
+            } else {
+                // moves the levels (the reference below is taken afterwards)
+                ST_TRY(tag_level_field(ctx, l, pos_dtype, x, y, z, q, n, tag_rel[l], boxes));
+            }
         }
+        const HostLevel &L = pr.lev[l];
         if (boxes.empty()) break;
         std::string msg = check_nesting(L, boxes, P.n_proper);
         if (!msg.empty()) return fail(AMRMG_E_NESTING, "level " + std::to_string(l + 1) + ": " + msg);

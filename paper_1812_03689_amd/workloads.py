@@ -151,6 +151,7 @@ class Workload:
     precision: str = "mixed"
     lo: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # the domain [lo, hi)
     hi: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    tag_policy: str = "charge"                          # "charge", "potential" or "efield"
 
 
 def config1(n_particles: int = 10**4) -> Workload:

@@ -51,3 +51,25 @@ def test_default_params_without_gpu(lib):
     assert list(p.n0) == [32, 32, 32]
     assert p.max_level == 2 and p.ref_ratio == 2 and p.blocking_factor == 8
     assert (p.nu1, p.nu2) == (amrmg.make_params((32, 32, 32)).nu1, amrmg.make_params((32, 32, 32)).nu2)
+
+
+def test_params_struct_matches_the_header(lib):
+    """amrmg_default_params writes exactly the binding's structure: bytes
+    past its end stay untouched and its last field is written."""
+    from paper_1812_03689_amd import amrmg
+    size = C.sizeof(amrmg.amrmg_params)
+    buf = (C.c_uint8 * (size + 64))(*([0xAB] * (size + 64)))
+    lib.amrmg_default_params(C.cast(buf, C.POINTER(amrmg.amrmg_params)))
+    assert all(b == 0xAB for b in bytes(buf)[size:])
+    p = amrmg.amrmg_params.from_buffer(buf)
+    assert p.tag_policy == amrmg.AMRMG_TAG_CHARGE and p.bottom == amrmg.AMRMG_BOTTOM_AUTO
+
+
+def test_bad_tag_policy_rejected_without_gpu(lib):
+    from paper_1812_03689_amd import amrmg
+    p = amrmg.make_params((16, 16, 16))
+    p.tag_policy = 7
+    h = C.c_void_p()
+    lib.amrmg_create.argtypes = [C.POINTER(amrmg.amrmg_params), C.c_void_p, C.POINTER(C.c_void_p)]
+    assert lib.amrmg_create(C.byref(p), None, C.byref(h)) == amrmg.AMRMG_E_INVALID
+    assert not h.value
