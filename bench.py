@@ -214,7 +214,7 @@ def bench_batch(args):
 PAPER_CONTEXT = {"cores": 14400, "hardware": "400 nodes of 2 x Xeon E5-2695 v4",
                  "seconds_per_solve_regrid_every_solve": 3.78715,
                  "seconds_per_solve_regrid_every_10th": 3.4366,
-                 "source": "strong-scaling table of Sec. 6.4 (totals of 100 solves / 100)"}
+                 "source": "strong-scaling table of Sec. 8 (totals of 100 solves / 100)"}
 
 
 def bench_paper(args):

@@ -6,8 +6,8 @@
  *
  * The path (the space-charge workflow of Fig. 2 of the paper, without the
  * frame transforms): cloud-in-cell charge deposition -> charge tagging and
- * box generation (Sec. 4.1) -> composite AMR multigrid solve of
- * L_comp phi = -rho / eps0 (Sec. 5.4, Alg. 1-3) -> E = -grad phi (Alg. 2) ->
+ * box generation (Sec. 4.2) -> composite AMR multigrid solve of
+ * L_comp phi = -rho / eps0 (Sec. 5.3, Alg. 1-3) -> E = -grad phi (Alg. 2) ->
  * interpolation of E to the particles.
  *
  * Conventions shared by every call:
@@ -68,7 +68,7 @@ enum { AMRMG_GSRB = 0, AMRMG_JACOBI = 1, AMRMG_GSRB_GLOBAL = 2 };
  * AMRMG_BOTTOM_CG always uses CG. */
 enum { AMRMG_BOTTOM_AUTO = 0, AMRMG_BOTTOM_CG = 1 };
 enum { AMRMG_MAX_LEVELS = 8 };
-/* Refinement criteria of amrmg_build_hierarchy (Sec. 4.1): tag a cell of
+/* Refinement criteria of amrmg_build_hierarchy (Sec. 4.2): tag a cell of
  * level l when |rho| > lambda max|rho| (AMRMG_TAG_CHARGE), |phi| > lambda
  * max|phi| (AMRMG_TAG_POTENTIAL), or |E_w| > lambda max|E_w| for some
  * component w (AMRMG_TAG_EFIELD), each maximum taken over level l.  phi and
@@ -102,6 +102,10 @@ typedef struct amrmg_params {
                                    modes, not the accuracy of the result [1e-2] */
     int32_t bottom;             /* AMRMG_BOTTOM_AUTO or AMRMG_BOTTOM_CG [AUTO] */
     int32_t tag_policy;         /* AMRMG_TAG_CHARGE, AMRMG_TAG_POTENTIAL or AMRMG_TAG_EFIELD [CHARGE] */
+    double robin_d;             /* > 0: open boundary by the Robin condition d phi/dn + phi/robin_d = 0
+                                   (Eq. robin_bc, central difference across the boundary face: ghost
+                                   (2 d - h)/(2 d + h) phi_in) on every face, with no monopoles;
+                                   0: Dirichlet data from the monopoles [0] */
 } amrmg_params;
 
 /* Per-solve statistics. */
@@ -123,7 +127,7 @@ amrmg_status amrmg_create(const amrmg_params *p, void *hip_stream, amrmg_ctx **o
 void amrmg_destroy(amrmg_ctx *ctx);
 const char *amrmg_last_error(void);
 
-/* Build the level hierarchy (Sec. 3 and Sec. 4.1 of the paper).  For each
+/* Build the level hierarchy (Sec. 3 and Sec. 4.2 of the paper).  For each
  * level l < max_level in turn: deposit the particles on level l, tag the
  * cells with |rho^l| > tag_rel[l] * max|rho^l| (or, with the potential and
  * field criteria of tag_policy, solve on levels 0..l and tag by |phi^l| or
@@ -227,7 +231,7 @@ amrmg_status amrmg_deposit_built(amrmg_ctx *ctx, double *const *rho, int64_t *n_
  * coarse-fine faces (Eqs. lap_flux_differencing, coarse_fluxes,
  * flux_differencing), quadratic two-step Lagrange ghosts (Eq. 2d_lagrange,
  * Tab. bit_pattern) and the Dirichlet data through a linear ghost
- * 2 g - phi_in.  V-cycles (Alg. 3) run until ||r^l||_p <= tol ||b^l||_p on
+ * 2 g - phi_in (or, with robin_d > 0, the Robin ghost of robin_d).  V-cycles (Alg. 3) run until ||r^l||_p <= tol ||b^l||_p on
  * every level, b^l being the uncovered right-hand side including the
  * Dirichlet data, or until max_iters.  In AMRMG_MIXED the cycle works in
  * FP32 on the correction equation of an FP64 outer residual (iterative
@@ -247,7 +251,7 @@ amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *x, const vo
                           const void *z, int64_t n, double *const *E, double *Ex, double *Ey,
                           double *Ez);
 
-/* Domain transform (Sec. 4.2 of the paper): map particles from particle
+/* Domain transform (Sec. 4.1 of the paper): map particles from particle
  * space S_p into the computation space S_c = [-l0,l0] x [-l1,l1] x [-l2,l2]
  * around the reference position c.  With Gamma(x, l) = max_d |x_d - c_d| /
  * l_d, the scale is s = max over the n particles of Gamma (the particle

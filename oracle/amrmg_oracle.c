@@ -18,9 +18,12 @@
  *     space; its arrays concatenate the boxes in list order, each box stored
  *     x-fastest;
  *   - A := -L_h (the negative discrete Laplacian), b := rho / eps0, residual
- *     r = b - A phi (Sec. 5.4, Alg. 1 writes r = rho - A phi);
+ *     r = b - A phi (Sec. 5.3, Alg. 1 writes r = rho - A phi);
  *   - Dirichlet data g on the physical boundary enters through the linear
- *     ghost phi_g = 2 g - phi_in at the boundary face.
+ *     ghost phi_g = 2 g - phi_in at the boundary face; with an artificial
+ *     distance d > 0 the boundary is instead the open (Robin) condition
+ *     d phi / dn + phi / d = 0 of Sec. 5.2 (Eq. robin_bc), discretised by
+ *     central difference across the boundary face.
  */
 #include <math.h>
 #include <stdint.h>
@@ -45,6 +48,7 @@ typedef struct {
     int nlev;
     double lo[3], hi[3];
     double eps0;
+    double robin; /* artificial distance d of the Robin boundary; 0 = Dirichlet */
     int nmono;
     double *mono; /* [nmono][4] q, x, y, z */
     OLev L[OR_MAXL];
@@ -157,6 +161,10 @@ static int64_t cidx(const OLev *L, int i, int j, int k)
 }
 
 int64_t or_cell_index(const OHier *H, int l, int i, int j, int k) { return cidx(&H->L[l], i, j, k); }
+
+/* switch the physical boundary to the Robin condition with distance d (d <= 0:
+ * back to Dirichlet) */
+void or_set_robin(OHier *H, double d) { H->robin = d > 0.0 ? d : 0.0; }
 
 /* cell (i,j,k) of level l is covered when level l+1 holds its children */
 static int covered(const OHier *H, int l, int i, int j, int k)
@@ -334,7 +342,9 @@ static double cf_step1(const OHier *H, int lc, const int C[3], int d, double tu,
 }
 
 /* Value that cell (i,j,k) of level l sees across its face (d, s):
- *   - outside the domain: linear Dirichlet ghost 2 g - u_c (g = 0 unless inhom);
+ *   - outside the domain: linear Dirichlet ghost 2 g - u_c (g = 0 unless inhom),
+ *     or for the Robin condition the ghost u_g that makes the central
+ *     difference (u_g - u_c)/h + (u_g + u_c)/(2 dist) vanish;
  *   - a cell of the same level: its value (covered or not);
  *   - otherwise (l > 0) a coarse-fine ghost: step 1 in the coarse layer
  *     (uc == NULL means the coarse values are zero), step 2 a quadratic along
@@ -350,6 +360,11 @@ static double nbval(const OHier *H, int l, int i, int j, int k, int d, int s,
     p[d] += s;
     int64_t ic = cidx(L, i, j, k);
     if (p[d] < 0 || p[d] >= L->n[d]) {
+        if (H->robin > 0.0) {
+            double h = L->h[d], dist = H->robin;
+            /* u_g (1/h + 1/(2 dist)) = u_c (1/h - 1/(2 dist)) */
+            return ul[ic] * (1.0 / h - 1.0 / (2.0 * dist)) / (1.0 / h + 1.0 / (2.0 * dist));
+        }
         double g = inhom ? bc_face(H, l, i, j, k, d, s) : 0.0;
         return 2.0 * g - ul[ic];
     }
@@ -914,7 +929,7 @@ int64_t or_gather(const OHier *H, int64_t n, const double *x, const double *y, c
     return outside;
 }
 
-/* charge tagging (Sec. 4.1, Eq. tag_charge, in the relative form of the
+/* charge tagging (Sec. 4.2, Eq. tag_charge, in the relative form of the
  * potential and field policies): tag when |rho| > lambda * max |rho^l| */
 void or_tag(const OHier *H, int l, const double *rho, double lambda, uint8_t *tags)
 {

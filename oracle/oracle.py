@@ -52,6 +52,8 @@ def lib():
         L.or_new.restype = vp
         L.or_new.argtypes = [vp, vp, vp, dbl, C.c_int, vp]
         L.or_free.argtypes = [vp]
+        L.or_set_robin.argtypes = [vp, dbl]
+        L.or_set_robin.restype = None
         L.or_set_level.argtypes = [vp, C.c_int, C.c_int, vp]
         L.or_nlev.argtypes = [vp]
         L.or_nboxes.argtypes = [vp, C.c_int]
@@ -101,7 +103,7 @@ class OracleHierarchy:
     relations under Eq. mesh_spacing; refinement ratio 2)."""
 
     def __init__(self, n0, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), eps0: float = 1.0,
-                 monopoles: Sequence[Sequence[float]] = ()):
+                 monopoles: Sequence[Sequence[float]] = (), robin: float = 0.0):
         self.n0 = tuple(int(v) for v in n0)
         self.lo = np.asarray(lo, dtype=np.float64)
         self.hi = np.asarray(hi, dtype=np.float64)
@@ -112,6 +114,9 @@ class OracleHierarchy:
         self.h = lib().or_new(_ptr(self.lo), _ptr(self.hi), _ptr(n0a), self.eps0,
                               int(mono.shape[0]), _ptr(self._mono))
         self.set_level(0, [(0, 0, 0) + self.n0])
+        # open boundary d phi/dn + phi/robin = 0 (Sec. 5.2, Eq. robin_bc) instead of Dirichlet data
+        self.robin = float(robin)
+        lib().or_set_robin(self.h, self.robin)
 
     def __del__(self):
         try:
@@ -205,7 +210,7 @@ class OracleHierarchy:
         lib().or_gather(self.h, n, _ptr(x), _ptr(y), _ptr(z), _ptrs(Es), _ptr(Ex), _ptr(Ey), _ptr(Ez))
         return Ex, Ey, Ez
 
-    # -- tagging and box generation (Sec. 4.1; box generation see C) ------
+    # -- tagging and box generation (Sec. 4.2; box generation see C) ------
     def tag(self, l: int, rho: np.ndarray, lam: float) -> np.ndarray:
         tags = np.zeros(self.ncells(l), dtype=np.uint8)
         lib().or_tag(self.h, l, _ptr(_f64(rho)), float(lam), _ptr(tags))
@@ -296,7 +301,7 @@ TAG_SOLVE_TOL = 1e-13
 
 def field_tags(H: OracleHierarchy, l: int, particles, policy: str, lam: float) -> np.ndarray:
     """Tags of level l, the finest level of H, by the potential or the
-    electric field (Sec. 4.1): the composite problem on H's levels is solved
+    electric field (Sec. 4.2): the composite problem on H's levels is solved
     with every particle deposited, then a cell is tagged when |phi| exceeds
     lam times the level's max |phi| ("potential"), or when some component
     |E_w| exceeds lam times that component's max over the level ("efield")."""
@@ -314,11 +319,12 @@ def field_tags(H: OracleHierarchy, l: int, particles, policy: str, lam: float) -
 
 def build_hierarchy(n0, particles, max_level: int, tag_rel: Sequence[float],
                     monopoles=(), explicit_boxes=None, n_buffer=1, n_proper=2, bf=8, mgs=32,
-                    lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), eps0=1.0, tag_policy="charge") -> OracleHierarchy:
+                    lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), eps0=1.0, tag_policy="charge",
+                    robin=0.0) -> OracleHierarchy:
     """Regrid loop: tag level l (by its own deposit, or by the potential or
     field of a solve on levels 0..l), generate level l+1 boxes; explicit
     boxes ``(level, lo3, hi3)`` replace the tagging for their level."""
-    H = OracleHierarchy(n0, lo, hi, eps0, monopoles)
+    H = OracleHierarchy(n0, lo, hi, eps0, monopoles, robin)
     explicit = {}
     for e in (explicit_boxes or []):
         explicit.setdefault(int(e[0]), []).append(tuple(int(v) for v in e[1:7]))
@@ -342,4 +348,4 @@ def hierarchy_from_workload(w) -> OracleHierarchy:
     return build_hierarchy(w.n0, w.particles, w.max_level, w.tag_rel, w.monopoles,
                            w.explicit_boxes, mgs=w.max_grid_size, bf=w.blocking_factor,
                            lo=getattr(w, "lo", (0.0, 0.0, 0.0)), hi=getattr(w, "hi", (1.0, 1.0, 1.0)),
-                           tag_policy=getattr(w, "tag_policy", "charge"))
+                           tag_policy=getattr(w, "tag_policy", "charge"), robin=getattr(w, "robin", 0.0))

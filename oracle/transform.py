@@ -1,4 +1,4 @@
-"""FP64 oracle of the domain transform of arXiv:1812.03689, Sec. 4.2.
+"""FP64 oracle of the domain transform of arXiv:1812.03689, Sec. 4.1.
 
 TEST INFRASTRUCTURE ONLY: imported by ``tests/``.  Plain NumPy, no code
 shared with the product library.

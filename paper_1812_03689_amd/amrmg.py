@@ -48,7 +48,8 @@ class amrmg_params(C.Structure):
                 ("eps0", C.c_double), ("n_monopoles", C.c_int32), ("monopoles", C.POINTER(C.c_double)),
                 ("precision", C.c_int32), ("smoother", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("omega", C.c_double), ("norm_p", C.c_int32), ("max_iters", C.c_int32),
-                ("bottom_rtol", C.c_double), ("bottom", C.c_int32), ("tag_policy", C.c_int32)]
+                ("bottom_rtol", C.c_double), ("bottom", C.c_int32), ("tag_policy", C.c_int32),
+                ("robin_d", C.c_double)]
 
 
 class amrmg_solve_stats(C.Structure):
@@ -306,7 +307,8 @@ def amrmg_profile_read(h, kclass):
 
 def make_params(n0, max_level=2, monopoles=(), precision="mixed", smoother="gsrb", nu1=2, nu2=2,
                 max_grid_size=32, max_iters=50, norm_p=2, bottom_rtol=1e-2, lo=(0, 0, 0), hi=(1, 1, 1),
-                eps0=1.0, n_buffer=1, n_proper=2, omega=6.0 / 7.0, bottom="auto", tag_policy="charge"):
+                eps0=1.0, n_buffer=1, n_proper=2, omega=6.0 / 7.0, bottom="auto", tag_policy="charge",
+                robin_d=0.0):
     p = amrmg_default_params()
     for d in range(3):
         p.lo[d], p.hi[d], p.n0[d] = float(lo[d]), float(hi[d]), int(n0[d])
@@ -327,6 +329,7 @@ def make_params(n0, max_level=2, monopoles=(), precision="mixed", smoother="gsrb
     p.bottom_rtol = float(bottom_rtol)
     p.bottom = {"auto": AMRMG_BOTTOM_AUTO, "cg": AMRMG_BOTTOM_CG}[bottom]
     p.tag_policy = TAG_POLICIES[tag_policy]
+    p.robin_d = float(robin_d)
     return p
 
 

@@ -244,26 +244,27 @@ static bool g_weights_ok = false;
 
 // direct-solve tables by grid shape and spacing (they depend on nothing else;
 // a regrid keeps level 0 and so its coarsest grid)
-static const std::vector<double> &cached_direct_tables(const int n[3], const double h[3])
+static const std::vector<double> &cached_direct_tables(const int n[3], const double h[3], const double a[3])
 {
     struct Key {
         int n[3];
-        double h[3];
+        double h[3], a[3];
         bool operator<(const Key &o) const
         {
             for (int d = 0; d < 3; ++d) {
                 if (n[d] != o.n[d]) return n[d] < o.n[d];
                 if (h[d] != o.h[d]) return h[d] < o.h[d];
+                if (a[d] != o.a[d]) return a[d] < o.a[d];
             }
             return false;
         }
     };
     static thread_local std::map<Key, std::vector<double>> cache;
-    Key k{{n[0], n[1], n[2]}, {h[0], h[1], h[2]}};
+    Key k{{n[0], n[1], n[2]}, {h[0], h[1], h[2]}, {a[0], a[1], a[2]}};
     auto it = cache.find(k);
     if (it == cache.end()) {
         if (cache.size() > 64) cache.clear();
-        it = cache.emplace(k, direct_tables(n, h)).first;
+        it = cache.emplace(k, direct_tables(n, h, a)).first;
     }
     return it->second;
 }
@@ -381,6 +382,7 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
             lc[i].h[d] = m.ent[i].h[d];
             lc[i].ih2[d] = 1.0 / (m.ent[i].h[d] * m.ent[i].h[d]);
         }
+        boundary_ghost(*probs[m.ent[i].prob], m.ent[i].h, lc[i].abnd);
         lc[i].amr = m.ent[i].amr;
     }
     // norm ranges: every AMR level of every problem, entry order
@@ -468,7 +470,9 @@ static amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<c
         J.tab = (int)dtab.size();
         J.w = (int)D.dw_doubles;
         J.amr = L.amr >= 0 ? 1 : 0;
-        const std::vector<double> &t = cached_direct_tables(L.n, L.h);
+        double ab[3];
+        boundary_ghost(*probs[e0.prob], L.h, ab);
+        const std::vector<double> &t = cached_direct_tables(L.n, L.h, ab);
         append_padded_tables(dtab, L.n, t);
         D.dw_doubles += (size_t)L.n[0] * L.n[1] * L.n[2];
         const int jid = (int)djl.size();
@@ -850,6 +854,7 @@ extern "C" void amrmg_default_params(amrmg_params *p)
     p->bottom_rtol = 1e-2;
     p->bottom = AMRMG_BOTTOM_AUTO;
     p->tag_policy = AMRMG_TAG_CHARGE;
+    p->robin_d = 0.0;
 }
 
 extern "C" const char *amrmg_last_error(void) { return g_err.c_str(); }
@@ -879,6 +884,9 @@ static amrmg_status check_params(const amrmg_params *p)
     if (!(p->omega > 0 && p->omega <= 1)) return fail(AMRMG_E_INVALID, "omega in (0, 1]");
     if (p->tag_policy != AMRMG_TAG_CHARGE && p->tag_policy != AMRMG_TAG_POTENTIAL && p->tag_policy != AMRMG_TAG_EFIELD)
         return fail(AMRMG_E_INVALID, "bad tag_policy");
+    if (!(p->robin_d >= 0.0) || !std::isfinite(p->robin_d)) return fail(AMRMG_E_INVALID, "robin_d must be >= 0");
+    if (p->robin_d > 0.0 && p->n_monopoles > 0)
+        return fail(AMRMG_E_INVALID, "Robin boundaries are homogeneous: no Dirichlet monopoles");
     return AMRMG_OK;
 }
 
@@ -1026,7 +1034,7 @@ static amrmg_status tag_boxes(amrmg_ctx *ctx, const HostLevel &L, const TagGeom 
     return AMRMG_OK;
 }
 
-// Charge tagging of level l (Sec. 4.1, Eq. tag_charge in relative form):
+// Charge tagging of level l (Sec. 4.2, Eq. tag_charge in relative form):
 // deposit level l alone, tag, dilate and mark the blocks of level l+1 on the
 // device; the host then applies nesting and the greedy merge.
 static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype, const void *x, const void *y,
@@ -1051,7 +1059,7 @@ static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype,
     return tag_boxes(ctx, L, G, boxes);
 }
 
-// Potential or field tagging of level l (Sec. 4.1, the relative criteria on
+// Potential or field tagging of level l (Sec. 4.2, the relative criteria on
 // phi and on each component E_w): the hierarchy built so far (levels 0..l)
 // is finished, every particle deposited on it and the composite problem
 // solved to a relative residual of AMRMG_TAG_SOLVE_TOL; a cell of level l is
@@ -1168,6 +1176,7 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
         pr.hi[d] = P.hi[d];
     }
     pr.eps0 = P.eps0;
+    pr.robin = P.robin_d;
     pr.mono = ctx->mono;
     {
         HostLevel L0 = std::move(pool[0]);
@@ -1477,7 +1486,7 @@ extern "C" amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *
 }
 
 // ---------------------------------------------------------------------------
-// domain transform (Sec. 4.2)
+// domain transform (Sec. 4.1)
 // ---------------------------------------------------------------------------
 extern "C" amrmg_status amrmg_transform_particles(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y,
                                                   const void *z, int64_t n, const double *center, const double *l,

@@ -1,7 +1,7 @@
 // amrmg_hier.cpp -- host-side hierarchy construction of libamrmg.
 //
 // Box generation: the paper leaves box generation to its AMR library (Sec.
-// 3, Sec. 4.1).  Here it is a fixed integer procedure on 8-cell blocks of the
+// 3, Sec. 4.2).  Here it is a fixed integer procedure on 8-cell blocks of the
 // finer level: tag dilation, block marking, proper nesting, greedy merge.
 //
 // Coarse-fine metadata follows Sec. 5.1 of the paper: for each fine brick face
@@ -298,28 +298,89 @@ std::vector<double> cf_weight_table()
     return W;
 }
 
-std::vector<double> direct_tables(const int n[3], const double h[3])
+// Eigendecomposition of a symmetric matrix (row-major N x N, destroyed) by
+// cyclic Jacobi rotations: A = V diag(w) V^T, V column k the k-th
+// eigenvector.  Each rotation zeroes A[p][q] with t = tan(angle) the smaller
+// root of t^2 + 2 theta t - 1 = 0, theta = (A_qq - A_pp) / (2 A_pq); sweeps
+// over all p < q until the off-diagonal part is negligible.
+static void jacobi_eigen(std::vector<double> &A, int N, std::vector<double> &V, std::vector<double> &w)
 {
-    std::vector<double> t;
+    V.assign((size_t)N * N, 0.0);
+    for (int i = 0; i < N; ++i) V[(size_t)i * N + i] = 1.0;
+    auto at = [&](int i, int j) -> double & { return A[(size_t)i * N + j]; };
+    double scale = 0.0;
+    for (double v : A) scale += v * v;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < N; ++p)
+            for (int q = p + 1; q < N; ++q) off += at(p, q) * at(p, q);
+        if (off <= 1e-32 * scale) break;
+        for (int p = 0; p < N; ++p)
+            for (int q = p + 1; q < N; ++q) {
+                const double apq = at(p, q);
+                if (apq == 0.0) continue;
+                const double theta = (at(q, q) - at(p, p)) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < N; ++k) {  // columns p, q
+                    const double akp = at(k, p), akq = at(k, q);
+                    at(k, p) = c * akp - s * akq;
+                    at(k, q) = s * akp + c * akq;
+                }
+                for (int k = 0; k < N; ++k) {  // rows p, q
+                    const double apk = at(p, k), aqk = at(q, k);
+                    at(p, k) = c * apk - s * aqk;
+                    at(q, k) = s * apk + c * aqk;
+                }
+                for (int k = 0; k < N; ++k) {
+                    const double vkp = V[(size_t)k * N + p], vkq = V[(size_t)k * N + q];
+                    V[(size_t)k * N + p] = c * vkp - s * vkq;
+                    V[(size_t)k * N + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    w.resize(N);
+    for (int i = 0; i < N; ++i) w[i] = at(i, i);
+}
+
+std::vector<double> direct_tables(const int n[3], const double h[3], const double abnd[3])
+{
+    std::vector<double> t, lam;
     for (int d = 0; d < 3; ++d) {
         const int N = n[d];
-        std::vector<double> S((size_t)N * N);
-        for (int i = 0; i < N; ++i)
+        std::vector<double> S((size_t)N * N), w(N);
+        if (abnd[d] == -1.0) {
+            for (int i = 0; i < N; ++i)
+                for (int k = 0; k < N; ++k) {
+                    double c = (k == N - 1) ? std::sqrt(1.0 / N) : std::sqrt(2.0 / N);
+                    S[(size_t)i * N + k] = c * std::sin(kPi * (k + 1) * (i + 0.5) / N);
+                }
             for (int k = 0; k < N; ++k) {
-                double c = (k == N - 1) ? std::sqrt(1.0 / N) : std::sqrt(2.0 / N);
-                S[(size_t)i * N + k] = c * std::sin(kPi * (k + 1) * (i + 0.5) / N);
+                double s = std::sin(kPi * (k + 1) / (2.0 * N));
+                w[k] = 4.0 * s * s;
             }
+        } else {
+            // 2 on the diagonal, 2 - abnd at both ends, -1 off the diagonal
+            std::vector<double> A((size_t)N * N, 0.0);
+            for (int i = 0; i < N; ++i) {
+                A[(size_t)i * N + i] = 2.0 - ((i == 0) ? abnd[d] : 0.0) - ((i == N - 1) ? abnd[d] : 0.0);
+                if (i + 1 < N) A[(size_t)i * N + i + 1] = A[(size_t)(i + 1) * N + i] = -1.0;
+            }
+            jacobi_eigen(A, N, S, w);
+        }
         for (int k = 0; k < N; ++k)
             for (int i = 0; i < N; ++i) t.push_back(S[(size_t)i * N + k]);
         for (int i = 0; i < N; ++i)
             for (int k = 0; k < N; ++k) t.push_back(S[(size_t)i * N + k]);
+        for (int k = 0; k < N; ++k) lam.push_back(w[k] / (h[d] * h[d]));
     }
-    for (int d = 0; d < 3; ++d)
-        for (int k = 0; k < n[d]; ++k) {
-            double s = std::sin(kPi * (k + 1) / (2.0 * n[d]));
-            t.push_back(4.0 * s * s / (h[d] * h[d]));
-        }
+    t.insert(t.end(), lam.begin(), lam.end());
     return t;
+}
+
+void boundary_ghost(const Problem &P, const double h[3], double a[3])
+{
+    for (int d = 0; d < 3; ++d) a[d] = P.robin > 0.0 ? (2.0 * P.robin - h[d]) / (2.0 * P.robin + h[d]) : -1.0;
 }
 
 void add_levels_below(Problem &P)

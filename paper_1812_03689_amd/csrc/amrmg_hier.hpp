@@ -68,21 +68,24 @@ uint32_t quadratic_mask(int pat);
 void pattern_tables(uint32_t masks13[13], int org14x3[42]);
 
 // Direct solve of the coarsest grid: the cell-centred Laplacian with
-// homogeneous Dirichlet ghosts (-u_c) on a full box of n cells is separable;
-// along an axis of N cells its 1-D matrix (2 on the diagonal, 3 at both ends,
-// -1 off the diagonal, times 1/h^2) has the orthonormal eigenvectors
-// S[i][k] = c_k sin(pi (k+1) (i+1/2) / N), c_k = sqrt(2/N) (k < N-1) or
-// sqrt(1/N) (k = N-1), with eigenvalues 4 sin^2(pi (k+1) / (2N)) / h^2.
-// Layout per axis d (N = n[d]): the forward matrix F[k][i] = S[i][k] and the
-// inverse matrix B[i][k] = S[i][k], each N x N, output-major; then the three
-// eigenvalue vectors.  Size 2 (n0^2 + n1^2 + n2^2) + n0 + n1 + n2 doubles.
-std::vector<double> direct_tables(const int n[3], const double h[3]);
+// homogeneous boundary ghosts abnd u_c on a full box of n cells is separable;
+// along an axis of N cells its 1-D matrix is 2 on the diagonal, 2 - abnd at
+// both ends, -1 off the diagonal, times 1/h^2.  For Dirichlet (abnd = -1) it
+// has the orthonormal eigenvectors S[i][k] = c_k sin(pi (k+1) (i+1/2) / N),
+// c_k = sqrt(2/N) (k < N-1) or sqrt(1/N) (k = N-1), with eigenvalues
+// 4 sin^2(pi (k+1) / (2N)) / h^2; otherwise (Robin) they are computed by
+// Jacobi rotations.  Layout per axis d (N = n[d]): the forward matrix
+// F[k][i] = S[i][k] and the inverse matrix B[i][k] = S[i][k], each N x N,
+// output-major; then the three eigenvalue vectors.  Size
+// 2 (n0^2 + n1^2 + n2^2) + n0 + n1 + n2 doubles.
+std::vector<double> direct_tables(const int n[3], const double h[3], const double abnd[3]);
 
 // One problem (one context): its levels coarsest first; kg = index of AMR
 // level 0.
 struct Problem {
     double lo[3], hi[3];
     double eps0 = 1.0;
+    double robin = 0.0;        // > 0: Robin boundary d phi/dn + phi/robin = 0; 0: Dirichlet
     std::vector<double> mono;  // [n][4] q, x, y, z
     std::vector<HostLevel> lev;
     int kg = 0;
@@ -94,6 +97,12 @@ struct Problem {
 // is small enough for its direct solve); lev[0..] must hold the AMR levels on
 // entry
 void add_levels_below(Problem &P);
+
+// boundary ghost coefficient per axis of a level of spacing h: u_g = a u_c
+// (+ 2 g for Dirichlet data g).  Dirichlet: a = -1.  Robin (Eq. robin_bc,
+// central difference across the face): (u_g - u_c)/h + (u_g + u_c)/(2 d) = 0,
+// a = (2 d - h) / (2 d + h).
+void boundary_ghost(const Problem &P, const double h[3], double a[3]);
 
 // Merged metadata of one or more problems.  Levels are numbered coarsest
 // first across problems: level entry (k, i) = level k (counted from each

@@ -20,9 +20,10 @@ constexpr int BRICK_CELLS = 512;
 
 // per-level constants
 struct LevelConst {
-    double ih2[3];  // 1 / h_d^2
+    double ih2[3];   // 1 / h_d^2
     double h[3];
-    int amr;        // AMR level number, -1 below level 0
+    double abnd[3];  // boundary ghost u_g = abnd u_c (+ 2 g): -1 for Dirichlet, (2 d - h)/(2 d + h) for Robin
+    int amr;         // AMR level number, -1 below level 0
     int pad;
 };
 

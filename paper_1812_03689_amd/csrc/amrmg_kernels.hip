@@ -103,8 +103,9 @@ struct ZeroAcc {
 // The neighbour value that cell l of brick b sees across face (d, s), written
 // as a * u_c + bv:
 //   same level (in this brick or the face neighbour brick): a = 0, bv = u_nb
-//   physical boundary, Dirichlet ghost 2 g - u_c: a = -1, bv = 2 g (g = 0 when
-//     !inhom)
+//   physical boundary: Dirichlet ghost 2 g - u_c, a = -1, bv = 2 g (g = 0 when
+//     !inhom); Robin ghost (central difference of d phi/dn + phi/d = 0),
+//     a = (2 d - h)/(2 d + h), bv = 0 (the level's abnd)
 //   coarse-fine face, fine side: ghost = cpart + 2/3 u_c - 1/5 u_in, with
 //     cpart the coarse part precomputed per ghost (zero when cp == nullptr):
 //     a = 2/3, bv = cpart - u_in / 5.
@@ -132,7 +133,7 @@ __device__ __forceinline__ void face_nb(const DevMeta &M, int b, const int *lc, 
     transverse(d, du, dv);
     int t = l[du] + 8 * l[dv];
     if (g < M.nbc) {
-        a = -1.0;
+        a = M.lc[M.org[b].w].abnd[d];
         bv = inhom ? 2.0 * M.gbc[(size_t)g * 64 + t] : 0.0;
         return;
     }
@@ -179,7 +180,10 @@ __device__ double block_reduce(double v, int op)
 // (edges and corners are never read by the 7-point stencil).  A halo cell
 // across a same-level face holds the neighbour's value; across a boundary or
 // coarse-fine face it holds bv of the ghost a*u_c + bv, and alpha[face] holds
-// a.  All loads of a tile are independent and issued before one barrier.
+// a, stored as a - 2 on a boundary face so that its sign tells the kinds
+// apart (coarse-fine 2/3 > 0, same level 0, boundary a - 2 < -1 since
+// |a| < 1 or a = -1; tile_ab and ghost_shift take the 2 back).  All loads of
+// a tile are independent and issued before one barrier.
 // ---------------------------------------------------------------------------
 constexpr int TE = 10;
 __device__ __forceinline__ int tix(int x, int y, int z) { return (x + 1) + TE * ((y + 1) + TE * (z + 1)); }
@@ -254,7 +258,7 @@ __device__ void stage_tile(const DevMeta &M, int b, const S &src, const CP &cp, 
         } else {
             const int g = -1 - nb;
             if (g < M.nbc) {
-                ah[j] = -1.0;
+                ah[j] = M.lc[M.org[b].w].abnd[d] - 2.0;
                 vh[j] = inhom ? 2.0 * M.gbc[(size_t)g * 64 + fl] : 0.0;
             } else {
                 ah[j] = 2.0 / 3.0;
@@ -300,6 +304,8 @@ __device__ __forceinline__ void tile_ab(const V *tile, const V *alpha, int x, in
             int in[3] = {x, y, z};
             in[d] -= s;
             bv -= (V)0.2 * tile[tix(in[0], in[1], in[2])];
+        } else if (a < (V)0) {
+            a += (V)2;  // boundary
         }
     }
 }
@@ -380,10 +386,11 @@ __device__ __forceinline__ double face_sum(const U &u, int F, int dir, int m, co
 constexpr int RT = 128;
 
 // a u_c + bv - bv_halo for a ghost a u_c + bv whose halo slot holds bv_halo
-// (bv = bv_halo - u_in / 5 on a coarse-fine face)
+// (bv = bv_halo - u_in / 5 on a coarse-fine face), from the stored alpha
+// (a, or a - 2 on a boundary face)
 __device__ __forceinline__ double ghost_shift(double a, double uc, double uin)
 {
-    return a * uc - (a > 0.0 ? 0.2 * uin : 0.0);
+    return a > 0.0 ? a * uc - 0.2 * uin : (a < 0.0 ? (a + 2.0) * uc : 0.0);
 }
 
 template <class T, bool ZERO>
@@ -961,7 +968,7 @@ __global__ void __launch_bounds__(256) k_efield(DevMeta M, int b0, int nb, const
 
 // ---------------------------------------------------------------------------
 // CG on the coarsest grid, one workgroup of 1024 threads (FP64 vectors and
-// dot products).  Homogeneous Dirichlet data, no coarse-fine faces.
+// dot products).  Homogeneous boundary data, no coarse-fine faces.
 // ---------------------------------------------------------------------------
 __device__ double block_reduce_1024(double v)
 {
@@ -1057,8 +1064,8 @@ __device__ int cg_solve_lds(const DevMeta &M, int b0, int nb, const T *rhs, T *e
     const int n = nb * BRICK_CELLS;
     const LevelConst L = M.lc[M.org[b0].w];
     // neighbours of each owned cell (at most CG_PER per thread), resolved once: LDS index, or -1 for a
-    // homogeneous Dirichlet ghost (-p_c); the coarsest grid has no
-    // coarse-fine faces
+    // homogeneous boundary ghost (abnd p_c, in the diagonal); the coarsest
+    // grid has no coarse-fine faces
     int nbi[CG_PER][6];
     double diag[CG_PER];
     for (int k = 0; k < CG_PER; ++k) {
@@ -1081,7 +1088,7 @@ __device__ int cg_solve_lds(const DevMeta &M, int b0, int nb, const T *rhs, T *e
                 nbi[k][f] = (bb - b0) * BRICK_CELLS + m[0] + 8 * m[1] + 64 * m[2];
                 diag[k] += L.ih2[d];
             } else {
-                diag[k] += 2.0 * L.ih2[d];
+                diag[k] += (1.0 - L.abnd[d]) * L.ih2[d];
             }
         }
     }
@@ -1143,7 +1150,7 @@ __device__ int cg_solve_lds(const DevMeta &M, int b0, int nb, const T *rhs, T *e
 }
 
 // ---------------------------------------------------------------------------
-// Exact solve of the coarsest grid (one box, homogeneous Dirichlet ghosts) by
+// Exact solve of the coarsest grid (one box, homogeneous boundary ghosts) by
 // its separable eigendecomposition: e = Q diag(1/lambda) Q^T r with Q the
 // tensor product of the per-axis orthonormal eigenvector matrices.  Three
 // launches over all jobs: forward transforms along x and y per (z plane, block

@@ -1,4 +1,4 @@
-// amrmg_transform.hip -- the domain transform of Sec. 4.2 (arXiv:1812.03689)
+// amrmg_transform.hip -- the domain transform of Sec. 4.1 (arXiv:1812.03689)
 // between particle space S_p and computation space S_c = [-l0,l0] x [-l1,l1]
 // x [-l2,l2]: the scale s = max over the particles of
 // Gamma(x, l) = max_d |x_d - c_d| / l_d (c: the reference particle), the map

@@ -152,6 +152,7 @@ class Workload:
     lo: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # the domain [lo, hi)
     hi: Tuple[float, float, float] = (1.0, 1.0, 1.0)
     tag_policy: str = "charge"                          # "charge", "potential" or "efield"
+    robin: float = 0.0                                  # > 0: Robin open boundary with this distance
 
 
 def config1(n_particles: int = 10**4) -> Workload:
@@ -204,7 +205,7 @@ def config5_instances(count: int = 64, scale: float = 1.0) -> List[Workload]:
 def chain_bunches(n_per: int = 10**6, nb: int = 11, sigma=(1.5e-3, 5e-3, 5e-3), spacing: float = 0.04,
                   seed: int = seed_for(6)) -> Particles:
     """The paper's benchmark source (Sec. 6.3 and the strong-scaling test of
-    Sec. 6.4): ``nb`` Gaussian bunches of ``n_per`` particles in metres, sigma
+    Sec. 8): ``nb`` Gaussian bunches of ``n_per`` particles in metres, sigma
     (1.5 mm, 5 mm, 5 mm), centres 4 cm apart along x around the origin.  Unit
     total charge split evenly (the paper's 0.1 fC per particle only scales
     phi)."""

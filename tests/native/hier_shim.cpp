@@ -146,10 +146,11 @@ extern "C" void hs_tables(double *w, uint32_t *qmask)
 }
 
 // the direct-solve tables of an n[0] x n[1] x n[2] grid with spacing h
-extern "C" long hs_direct_tables(const int32_t *n, const double *h, double *out, long cap)
+extern "C" long hs_direct_tables(const int32_t *n, const double *h, const double *abnd, double *out, long cap)
 {
     int nn[3] = {n[0], n[1], n[2]};
-    std::vector<double> t = direct_tables(nn, h);
+    const double dir[3] = {-1.0, -1.0, -1.0};
+    std::vector<double> t = direct_tables(nn, h, abnd ? abnd : dir);
     if ((long)t.size() > cap) return -1;
     std::memcpy(out, t.data(), sizeof(double) * t.size());
     return (long)t.size();

@@ -1,4 +1,4 @@
-"""The potential and electric-field refinement criteria of Sec. 4.1 through
+"""The potential and electric-field refinement criteria of Sec. 4.2 through
 the C ABI (tag_policy AMRMG_TAG_POTENTIAL / AMRMG_TAG_EFIELD) against the
 oracle: box lists and offsets bit for bit on every level (each level tagged
 from a solve on the levels below it, in both precisions), the solve on the

@@ -1,4 +1,4 @@
-"""The domain transform of Sec. 4.2 through the C ABI against the oracle
+"""The domain transform of Sec. 4.1 through the C ABI against the oracle
 (oracle/transform.py): the scale s and the mapped coordinates bit for bit
 (FP64 and FP32 positions, in place and out of place), the grid rescale bit
 for bit, argument errors, and the whole space-charge workflow of the paper's

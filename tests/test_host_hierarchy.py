@@ -28,7 +28,7 @@ def shim(tmp_path_factory):
     L.hs_cf_patterns.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_long]
     L.hs_cf_patterns.restype = C.c_long
     L.hs_tables.argtypes = [C.c_void_p, C.c_void_p]
-    L.hs_direct_tables.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_long]
+    L.hs_direct_tables.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_long]
     L.hs_direct_tables.restype = C.c_long
     return L
 
@@ -136,9 +136,10 @@ def test_cf_patterns_match_oracle(oracle_lib, shim, name):
     assert seen
 
 
-def dirichlet_laplacian_dense(n, h):
+def dirichlet_laplacian_dense(n, h, abnd=(-1.0, -1.0, -1.0)):
     """-L_h of the 7-point cell-centred Laplacian on one box with homogeneous
-    Dirichlet ghosts (ghost = -u of the boundary cell), x fastest."""
+    boundary ghosts (ghost = abnd_d u of the boundary cell: -1 is Dirichlet),
+    x fastest."""
     nx, ny, nz = n
     N = nx * ny * nz
     A = np.zeros((N, N))
@@ -155,18 +156,22 @@ def dirichlet_laplacian_dense(n, h):
                         if 0 <= c[d] < m:
                             A[r, idx(*c)] -= 1.0 / hd ** 2
                         else:
-                            A[r, r] += 1.0 / hd ** 2
+                            A[r, r] -= abnd[d] / hd ** 2
     return A
 
 
+@pytest.mark.parametrize("robin", [None, 1.7, 0.03])
 @pytest.mark.parametrize("n,h", [((8, 8, 8), (1 / 8, 1 / 8, 1 / 8)), ((8, 16, 24), (0.1, 0.05, 0.02))])
-def test_direct_tables_diagonalise_the_dirichlet_laplacian(shim, n, h):
-    """The coarsest-grid direct solve: Q diag(lambda) Q^T reproduces the dense
-    operator and Q is orthonormal, so Q diag(1/lambda) Q^T r = A^-1 r."""
+def test_direct_tables_diagonalise_the_laplacian(shim, n, h, robin):
+    """The coarsest-grid direct solve, Dirichlet (sine tables) or Robin
+    (Jacobi eigenvectors; ghost (2d - h)/(2d + h) u, Eq. robin_bc by central
+    difference): Q diag(lambda) Q^T reproduces the dense operator and Q is
+    orthonormal, so Q diag(1/lambda) Q^T r = A^-1 r."""
     n32 = np.asarray(n, dtype=np.int32)
     hh = np.asarray(h, dtype=np.float64)
+    ab = np.array([-1.0] * 3 if robin is None else [(2 * robin - hd) / (2 * robin + hd) for hd in h])
     out = np.zeros(1 << 16)
-    k = shim.hs_direct_tables(n32.ctypes.data, hh.ctypes.data, out.ctypes.data, out.size)
+    k = shim.hs_direct_tables(n32.ctypes.data, hh.ctypes.data, ab.ctypes.data, out.ctypes.data, out.size)
     assert k == 2 * sum(m * m for m in n) + sum(n)
     off, F, B = 0, [], []
     for m in n:
@@ -180,7 +185,7 @@ def test_direct_tables_diagonalise_the_dirichlet_laplacian(shim, n, h):
     # Q = kron over axes with x fastest: index i + nx (j + ny k)
     Q = np.kron(B[2], np.kron(B[1], B[0]))
     lam = (mu[2][:, None, None] + mu[1][None, :, None] + mu[0][None, None, :]).ravel()
-    A = dirichlet_laplacian_dense(n, h)
+    A = dirichlet_laplacian_dense(n, h, ab)
     np.testing.assert_allclose(Q @ np.diag(lam) @ Q.T, A, atol=1e-9 * np.abs(A).max())
     rng = np.random.default_rng(3)
     r = rng.standard_normal(A.shape[0])

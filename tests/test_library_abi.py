@@ -73,3 +73,15 @@ def test_bad_tag_policy_rejected_without_gpu(lib):
     lib.amrmg_create.argtypes = [C.POINTER(amrmg.amrmg_params), C.c_void_p, C.POINTER(C.c_void_p)]
     assert lib.amrmg_create(C.byref(p), None, C.byref(h)) == amrmg.AMRMG_E_INVALID
     assert not h.value
+
+
+def test_robin_with_monopoles_rejected_without_gpu(lib):
+    """The Robin boundary is homogeneous: Dirichlet monopoles with it are an
+    argument error (checked before any device work)."""
+    from paper_1812_03689_amd import amrmg
+    h = C.c_void_p()
+    lib.amrmg_create.argtypes = [C.POINTER(amrmg.amrmg_params), C.c_void_p, C.POINTER(C.c_void_p)]
+    p = amrmg.make_params((16, 16, 16), monopoles=[(1.0, 0.5, 0.5, 0.5)], robin_d=1.7)
+    assert lib.amrmg_create(C.byref(p), None, C.byref(h)) == amrmg.AMRMG_E_INVALID
+    p = amrmg.make_params((16, 16, 16), robin_d=-1.0)
+    assert lib.amrmg_create(C.byref(p), None, C.byref(h)) == amrmg.AMRMG_E_INVALID

@@ -1,5 +1,5 @@
 """Pins of the oracle's potential and electric-field refinement criteria
-(Sec. 4.1; ``oracle.field_tags``) on the CPU, against the closed-form fields
+(Sec. 4.2; ``oracle.field_tags``) on the CPU, against the closed-form fields
 of a uniformly charged ball (charge Q, radius R, Dirichlet data from the
 exact exterior potential):
 

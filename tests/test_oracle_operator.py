@@ -1,5 +1,5 @@
 """Pins of the oracle's composite operator (arXiv:1812.03689 Sec. 5.1, Eqs.
-lap_flux_differencing, coarse_fluxes, flux_differencing; Sec. 5.4 composite
+lap_flux_differencing, coarse_fluxes, flux_differencing; Sec. 5.3 composite
 domain) by properties the mathematics fixes:
   * exactness on quadratics away from the physical boundary (flux matching
     plus second-order ghosts);

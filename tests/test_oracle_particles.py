@@ -1,6 +1,6 @@
 """Pins of the oracle's particle and regrid steps: CIC deposit and gather
 (cloud-in-cell of Hockney & Eastwood, the deposit/interpolate stages of the
-space-charge workflow, Fig. 2 of arXiv:1812.03689), charge tagging (Sec. 4.1)
+space-charge workflow, Fig. 2 of arXiv:1812.03689), charge tagging (Sec. 4.2)
 and the box generation used for the refined levels."""
 import numpy as np
 import pytest

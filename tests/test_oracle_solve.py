@@ -1,4 +1,4 @@
-"""Pins of the oracle's solver (arXiv:1812.03689 Sec. 5.4, Alg. 1-3) against
+"""Pins of the oracle's solver (arXiv:1812.03689 Sec. 5.3, Alg. 1-3) against
 results fixed independently of it:
   * a single level reduces to the cell-centred 7-point Dirichlet problem,
     solved exactly by a DST-II diagonalisation;

@@ -1,4 +1,4 @@
-"""Pins of the domain-transform oracle (oracle/transform.py, Sec. 4.2 of the
+"""Pins of the domain-transform oracle (oracle/transform.py, Sec. 4.1 of the
 paper) on the CPU: a hand-worked example of Gamma and s, the outermost
 particle landing on the boundary of the computation space, and the physics
 the transform must preserve: one problem solved by the composite oracle in
