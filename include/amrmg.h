@@ -4,11 +4,14 @@
  * Locans, "On Architecture and Performance of Adaptive Mesh Refinement in an
  * Electrostatics Particle-In-Cell Code" (arXiv:1812.03689).
  *
- * The path (the space-charge workflow of Fig. 2 of the paper, without the
- * frame transforms): cloud-in-cell charge deposition -> charge tagging and
- * box generation (Sec. 4.2) -> composite AMR multigrid solve of
- * L_comp phi = -rho / eps0 (Sec. 5.3, Alg. 1-3) -> E = -grad phi (Alg. 2) ->
- * interpolation of E to the particles.
+ * The path (the space-charge workflow of Fig. 2 of the paper):
+ * cloud-in-cell charge deposition -> tagging (charge, potential or field)
+ * and box generation (Sec. 4.2) -> composite AMR multigrid solve of
+ * L_comp phi = -rho / eps0 (Sec. 5.3, Alg. 1-3) with Dirichlet or Robin
+ * boundaries (Sec. 5.2) -> E = -grad phi (Alg. 2) -> interpolation of E to
+ * the particles; optionally wrapped in the domain transform of Sec. 4.1
+ * (particles into computation space, fields rescaled on the grid).  The
+ * Lorentz transform of the co-moving frame is the caller's.
  *
  * Conventions shared by every call:
  *   - Domain [lo, hi) with n0 cells per axis on level 0; refinement ratio 2
