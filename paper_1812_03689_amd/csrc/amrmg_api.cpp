@@ -922,8 +922,10 @@ static DepLevel dep_level(const Problem &P, const HostLevel &L, const int32_t *b
 }
 
 // Visiting order of the particles (Morton-ordered buckets of the level-0
-// grid); with copy, also the particles in that order in ctx->sorted
-// (charges first, then x, y, z), returned through xs, ys, zs, qs
+// grid); with copy, also room for the particles in that order in
+// ctx->sorted (charges first, then x, y, z), returned through xs, ys, zs,
+// qs: the caller writes the copy (the first tagging deposit does, while it
+// reads the particles anyway, or launch_copy_ordered)
 static amrmg_status compute_order(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y, const void *z,
                                   const double *q, int64_t n, bool copy, const void **xs, const void **ys,
                                   const void **zs, const double **qs)
@@ -950,8 +952,8 @@ static amrmg_status compute_order(amrmg_ctx *ctx, int pos_dtype, const void *x, 
     }
     uint32_t *key = (uint32_t *)ctx->sort_keys.p, *cnt = (uint32_t *)ctx->sort_cnt.p;
     HIP_TRY(particle_order(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, P.lo, P.hi, P.n0, key, key + n, cnt,
-                           cnt + 2 * entries, (uint32_t *)ctx->sort_vals.p, ctx->sort_tmp.p, ctx->sort_tmp.cap, cx, cy,
-                           cz, cq));
+                           cnt + 2 * entries, (uint32_t *)ctx->sort_vals.p, ctx->sort_tmp.p, ctx->sort_tmp.cap, nullptr,
+                           nullptr, nullptr, nullptr));
     ctx->perm = (uint32_t *)ctx->sort_vals.p;
     ctx->perm_n = n;
     if (copy) {
@@ -1039,7 +1041,8 @@ static amrmg_status tag_boxes(amrmg_ctx *ctx, const HostLevel &L, const TagGeom 
 // device; the host then applies nesting and the greedy merge.
 static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype, const void *x, const void *y,
                               const void *z, const double *q, int64_t n, double lambda, std::vector<Box> &boxes,
-                              const uint32_t *perm, unsigned long long *nout)
+                              const uint32_t *perm, unsigned long long *nout, void *cx = nullptr,
+                              void *cy = nullptr, void *cz = nullptr, double *cq = nullptr)
 {
     hipStream_t st = ctx->st;
     TagGeom G;
@@ -1054,7 +1057,8 @@ static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype,
     A.lev[0] = dep_level(pr, L, G.bmap);
     A.rho[0] = rho;
     A.ncell[0] = G.nc;
-    launch_deposit(st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, perm, A, G.ub, (const int2 *)G.us, nout);
+    launch_deposit(st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, perm, A, G.ub, (const int2 *)G.us, nout, cx, cy,
+                   cz, cq);
     tag_mark(ctx, G, rho, lambda);
     return tag_boxes(ctx, L, G, boxes);
 }
@@ -1158,6 +1162,15 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
     ctx->lev_rho_ok.assign(P.max_level + 1, 0);
     ST_TRY(compute_order(ctx, pos_dtype, x, y, z, q, n, true, &tx, &ty, &tz, &tq));
     const bool copied = ctx->perm_n == n && n > 0;
+    // the ordered copy: written by the first charge-tagging deposit of level
+    // 0, else by a copy before the first pass that reads it
+    bool copy_done = !copied;
+    auto ensure_copy = [&]() {
+        if (copy_done) return;
+        launch_copy_ordered(ctx->st, pos_dtype == AMRMG_POS_F32, n, ctx->perm, x, y, z, q, (void *)tx, (void *)ty,
+                            (void *)tz, (double *)tq);
+        copy_done = true;
+    };
     HIP_TRY(ctx->built_nout.ensure(sizeof(unsigned long long)));
     HIP_TRY(hipMemsetAsync(ctx->built_nout.p, 0, sizeof(unsigned long long), ctx->st));
     const uint32_t *tperm = nullptr;
@@ -1193,8 +1206,17 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
         } else {
             if (!tag_rel) return fail(AMRMG_E_INVALID, "tag_rel is NULL but a level needs tagging");
             if (P.tag_policy == AMRMG_TAG_CHARGE) {
-                ST_TRY(tag_level(ctx, pr.lev[l], pos_dtype, tx, ty, tz, tq, n, tag_rel[l], boxes, tperm,
-                                 l == 0 ? (unsigned long long *)ctx->built_nout.p : nullptr));
+                if (!copy_done && l == 0) {
+                    // read through the order, write the ordered copy on the way
+                    ST_TRY(tag_level(ctx, pr.lev[l], pos_dtype, x, y, z, q, n, tag_rel[l], boxes, ctx->perm,
+                                     (unsigned long long *)ctx->built_nout.p, (void *)tx, (void *)ty, (void *)tz,
+                                     (double *)tq));
+                    copy_done = true;
+                } else {
+                    ensure_copy();
+                    ST_TRY(tag_level(ctx, pr.lev[l], pos_dtype, tx, ty, tz, tq, n, tag_rel[l], boxes, tperm,
+                                     l == 0 ? (unsigned long long *)ctx->built_nout.p : nullptr));
+                }
                 ctx->lev_rho_ok[l] = 1;
             } else {
                 // moves the levels (the reference below is taken afterwards)
@@ -1212,6 +1234,7 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
         level_set_boxes(F, boxes);
         pr.lev.push_back(std::move(F));
     }
+    ensure_copy();
     add_levels_below(pr);
     ST_TRY(upload_meta(ctx->ds, ctx->st, {&pr}, P.bottom == AMRMG_BOTTOM_AUTO));
     HIP_TRY(hipStreamSynchronize(ctx->st));

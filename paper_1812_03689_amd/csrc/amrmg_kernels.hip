@@ -1548,7 +1548,8 @@ __device__ __forceinline__ void wg_minmax6(int *v, int *red)
 template <class P, int PPT>
 __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P *y, const P *z, const double *q,
                                                  const uint32_t *perm, DepArgs A, const int64_t *ubase,
-                                                 const int2 *ustr, unsigned long long *nout)
+                                                 const int2 *ustr, unsigned long long *nout, P *xs, P *ys, P *zs,
+                                                 double *qs)
 {
     __shared__ double acc[DEP_TILE];
     __shared__ int red[24];
@@ -1564,6 +1565,12 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
         Y[k] = valid[k] ? (double)y[p] : 0.0;
         Z[k] = valid[k] ? (double)z[p] : 0.0;
         Q[k] = valid[k] ? q[p] : 0.0;
+        if (xs && valid[k]) {  // the visiting-order copy (exact: P -> double -> P)
+            xs[i] = (P)X[k];
+            ys[i] = (P)Y[k];
+            zs[i] = (P)Z[k];
+            qs[i] = Q[k];
+        }
     }
     for (int l = 0; l < A.nlev; ++l) {
         const DepLevel &D = A.lev[l];
@@ -1860,7 +1867,7 @@ void launch_bottom_cg(hipStream_t st, const DevMeta &M, const int4 *jobs, int nj
 
 void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                     const double *q, const uint32_t *perm, const DepArgs &A, const int64_t *ubase, const int2 *ustr,
-                    unsigned long long *nout)
+                    unsigned long long *nout, void *xs, void *ys, void *zs, double *qs)
 {
     if (n <= 0 || A.nlev <= 0) return;
     // two particles per thread up to 4M particles (enough workgroups to fill
@@ -1869,18 +1876,20 @@ void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const
         unsigned g = blocks_for(n, 512);
         if (pos_f32)
             AMRMG_LAUNCH((k_deposit<float, 2>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
-                         (const float *)z, q, perm, A, ubase, ustr, nout);
+                         (const float *)z, q, perm, A, ubase, ustr, nout, (float *)xs, (float *)ys, (float *)zs, qs);
         else
             AMRMG_LAUNCH((k_deposit<double, 2>), dim3(g), dim3(256), 0, st, n, (const double *)x, (const double *)y,
-                         (const double *)z, q, perm, A, ubase, ustr, nout);
+                         (const double *)z, q, perm, A, ubase, ustr, nout, (double *)xs, (double *)ys, (double *)zs,
+                         qs);
     } else {
         unsigned g = blocks_for(n, 1024);
         if (pos_f32)
             AMRMG_LAUNCH((k_deposit<float, 4>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
-                         (const float *)z, q, perm, A, ubase, ustr, nout);
+                         (const float *)z, q, perm, A, ubase, ustr, nout, (float *)xs, (float *)ys, (float *)zs, qs);
         else
             AMRMG_LAUNCH((k_deposit<double, 4>), dim3(g), dim3(256), 0, st, n, (const double *)x, (const double *)y,
-                         (const double *)z, q, perm, A, ubase, ustr, nout);
+                         (const double *)z, q, perm, A, ubase, ustr, nout, (double *)xs, (double *)ys, (double *)zs,
+                         qs);
     }
 }
 

@@ -163,9 +163,13 @@ template <class T>
 void launch_coarse_cycle(hipStream_t st, const DevMeta &M, const CoarseJob *jobs, int njobs, T *e, T *r,
                          double *work, int nu1, int nu2, double rtol, int maxit, int *iters, double *phib,
                          bool phi_update, int threads_hint);
+// with xs != nullptr, also the particles in visiting order (the order perm
+// gives; perm required): xs[i] = x[perm[i]], ... (the copy the ordered
+// deposits read later, written while the particles pass anyway)
 void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                     const double *q, const uint32_t *perm, const DepArgs &A, const int64_t *ubase, const int2 *ustr,
-                    unsigned long long *nout);
+                    unsigned long long *nout,
+                    void *xs = nullptr, void *ys = nullptr, void *zs = nullptr, double *qs = nullptr);
 void launch_zero_levels(hipStream_t st, const DepArgs &A);
 void launch_gather(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                    const uint32_t *perm, const GatherArgs &G, const int64_t *ubase, const int2 *ustr, double *Ex,
@@ -178,6 +182,9 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val);
 // key, slot: [n] each; count: [2 order_count_entries], start:
 // [order_count_entries]; temp: order_temp_bytes(order_count_entries) bytes
 size_t order_count_entries(const double *lo, const double *hi, const int *n0);
+// the particles in the visiting order alone: xs[i] = x[perm[i]], ...
+void launch_copy_ordered(hipStream_t st, int pos_f32, int64_t n, const uint32_t *perm, const void *x, const void *y,
+                         const void *z, const double *q, void *xs, void *ys, void *zs, double *qs);
 size_t order_temp_bytes(size_t entries);
 hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                           const double *q, const double *lo, const double *hi, const int *n0, uint32_t *key,

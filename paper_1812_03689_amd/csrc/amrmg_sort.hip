@@ -155,15 +155,21 @@ hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x,
     e = hipcub::DeviceScan::ExclusiveSum(temp, tb, ordered, start, entries, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bucket_scatter, dim3(g), dim3(256), 0, st, n, key, slot, start, perm);
-    if (xs) {
-        if (pos_f32)
-            hipLaunchKernelGGL((k_copy_ordered<float>), dim3(g), dim3(256), 0, st, n, perm, (const float *)x,
-                               (const float *)y, (const float *)z, q, (float *)xs, (float *)ys, (float *)zs, qs);
-        else
-            hipLaunchKernelGGL((k_copy_ordered<double>), dim3(g), dim3(256), 0, st, n, perm, (const double *)x,
-                               (const double *)y, (const double *)z, q, (double *)xs, (double *)ys, (double *)zs, qs);
-    }
+    if (xs) launch_copy_ordered(st, pos_f32, n, perm, x, y, z, q, xs, ys, zs, qs);
     return hipGetLastError();
+}
+
+void launch_copy_ordered(hipStream_t st, int pos_f32, int64_t n, const uint32_t *perm, const void *x, const void *y,
+                         const void *z, const double *q, void *xs, void *ys, void *zs, double *qs)
+{
+    if (n <= 0) return;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (pos_f32)
+        hipLaunchKernelGGL((k_copy_ordered<float>), dim3(g), dim3(256), 0, st, n, perm, (const float *)x,
+                           (const float *)y, (const float *)z, q, (float *)xs, (float *)ys, (float *)zs, qs);
+    else
+        hipLaunchKernelGGL((k_copy_ordered<double>), dim3(g), dim3(256), 0, st, n, perm, (const double *)x,
+                           (const double *)y, (const double *)z, q, (double *)xs, (double *)ys, (double *)zs, qs);
 }
 
 }  // namespace amrmg
