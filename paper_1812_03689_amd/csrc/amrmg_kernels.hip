@@ -690,17 +690,22 @@ struct TileAcc {
 // 16 the fine sums of the result on the brick's coarse-fine faces into ffs.
 enum { HG_ZERO = 1, HG_PROL = 2, HG_CPIN = 4, HG_PHI = 8, HG_FFS = 16 };
 
-// threads per brick of the stencil kernels: two wavefronts, so that 16
-// bricks' workgroups fit a CU at once and more loads are in flight
+// threads per brick of the sweep: two wavefronts on large levels, so that 16
+// bricks' workgroups fit a CU at once and more loads are in flight (the
+// sweep is bandwidth-bound there); four on levels whose bricks all fit the
+// chip at once, where a workgroup's latency is the launch's (fewer cells
+// per thread, shorter chains)
 constexpr int BT = 128;
+constexpr int BT_SMALL = 256;
+constexpr int HGS_SMALL_LEVEL = 4096;  // bricks
 
-template <class T, int MODE>
-__global__ void __launch_bounds__(BT) k_hgs(DevMeta M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
+template <class T, int MODE, int NT>
+__global__ void __launch_bounds__(NT) k_hgs(DevMeta M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
                                             double *phib, double *ffs)
 {
     __shared__ T tile[TE * TE * TE];  // arithmetic in the cycle's precision T
     __shared__ T alpha[6];
-    constexpr int PER = 256 / BT;  // cells of each colour per thread
+    constexpr int PER = 256 / NT;  // cells of each colour per thread
     int b = b0 + xcd_remap(blockIdx.x, nb);
     int lev = M.org[b].w;
     LevelConst L = M.lc[lev];
@@ -709,7 +714,7 @@ __global__ void __launch_bounds__(BT) k_hgs(DevMeta M, int b0, int nb, const T *
     const T ih2[3] = {(T)L.ih2[0], (T)L.ih2[1], (T)L.ih2[2]};
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-        int t = threadIdx.x + BT * j;
+        int t = threadIdx.x + NT * j;
         int z = t >> 5, y = (t >> 2) & 7, xx = (t & 3) << 1;
         cyz[j] = y + 8 * z;
         cx[0][j] = xx + ((y + z) & 1);
@@ -718,16 +723,16 @@ __global__ void __launch_bounds__(BT) k_hgs(DevMeta M, int b0, int nb, const T *
         for (int k = 0; k < 2; ++k) rv[k][j] = r[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]];
     }
     if (MODE & HG_ZERO) {
-        stage_tile<SrcZ, true, CpNone, BT, T>(M, b, SrcZ{}, CpNone{}, false, tile, alpha);
+        stage_tile<SrcZ, true, CpNone, NT, T>(M, b, SrcZ{}, CpNone{}, false, tile, alpha);
     } else if (MODE & HG_PROL) {
         if (MODE & HG_CPIN)
-            stage_tile<SrcProl<T>, false, CpInline<T>, BT, T>(M, b, SrcProl<T>{ein, M.par},
+            stage_tile<SrcProl<T>, false, CpInline<T>, NT, T>(M, b, SrcProl<T>{ein, M.par},
                                                               CpInline<T>{&M, ein, cp}, false, tile, alpha);
         else
-            stage_tile<SrcProl<T>, false, CpArr<T>, BT, T>(M, b, SrcProl<T>{ein, M.par}, CpArr<T>{cp}, false, tile,
+            stage_tile<SrcProl<T>, false, CpArr<T>, NT, T>(M, b, SrcProl<T>{ein, M.par}, CpArr<T>{cp}, false, tile,
                                                            alpha);
     } else {
-        stage_tile<SrcB<T>, false, CpArr<T>, BT, T>(M, b, SrcB<T>{ein}, CpArr<T>{cp}, false, tile, alpha);
+        stage_tile<SrcB<T>, false, CpArr<T>, NT, T>(M, b, SrcB<T>{ein}, CpArr<T>{cp}, false, tile, alpha);
     }
     T v[2][PER];
 #pragma unroll
@@ -763,12 +768,14 @@ __global__ void __launch_bounds__(BT) k_hgs(DevMeta M, int b0, int nb, const T *
     // fine sums of the new e on the brick's coarse-fine faces (the coarse
     // correction, and so the ghosts' coarse parts, are zero at the
     // restriction that reads them)
-    if ((MODE & HG_FFS) && threadIdx.x < 96) {
-        const int f = threadIdx.x >> 4;
-        if (alpha[f] > (T)0) {
-            const double c[4] = {0.0, 0.0, 0.0, 0.0};
-            const int m = threadIdx.x & 15;
-            ffs[((size_t)b * 6 + f) * 16 + m] = face_sum(TileAcc<T>{tile}, b, f, m, c);
+    if (MODE & HG_FFS) {
+        for (int t = threadIdx.x; t < 96; t += NT) {
+            const int f = t >> 4;
+            if (alpha[f] > (T)0) {
+                const double c[4] = {0.0, 0.0, 0.0, 0.0};
+                const int m = t & 15;
+                ffs[((size_t)b * 6 + f) * 16 + m] = face_sum(TileAcc<T>{tile}, b, f, m, c);
+            }
         }
     }
 }
@@ -1922,9 +1929,15 @@ void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, 
                 double *phib, double *ffs, int mode)
 {
     if (nb <= 0) return;
-    dim3 g(nb), blk(BT);
+    const bool small = nb <= HGS_SMALL_LEVEL;
+    dim3 g(nb), blk(small ? BT_SMALL : BT);
 #define AMRMG_HGS(MD)                                                                                        \
-    case MD: AMRMG_LAUNCH((k_hgs<T, MD>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib, ffs); return;
+    case MD:                                                                                                 \
+        if (small)                                                                                           \
+            AMRMG_LAUNCH((k_hgs<T, MD, BT_SMALL>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib, ffs);    \
+        else                                                                                                 \
+            AMRMG_LAUNCH((k_hgs<T, MD, BT>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib, ffs);          \
+        return;
     switch (mode) {
         AMRMG_HGS(0)
         AMRMG_HGS(HG_ZERO)
