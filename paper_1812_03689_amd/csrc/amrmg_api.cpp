@@ -1225,8 +1225,10 @@ extern "C" amrmg_status amrmg_build_hierarchy(amrmg_ctx *ctx, int pos_dtype, con
         }
         const HostLevel &L = pr.lev[l];
         if (boxes.empty()) break;
-        std::string msg = check_nesting(L, boxes, P.n_proper);
-        if (!msg.empty()) return fail(AMRMG_E_NESTING, "level " + std::to_string(l + 1) + ": " + msg);
+        if (expl.count(l + 1)) {  // generated boxes are aligned, disjoint and nested by construction
+            std::string msg = check_nesting(L, boxes, P.n_proper);
+            if (!msg.empty()) return fail(AMRMG_E_NESTING, "level " + std::to_string(l + 1) + ": " + msg);
+        }
         HostLevel F = std::move(pool[l + 1]);
         int nf[3] = {2 * L.n[0], 2 * L.n[1], 2 * L.n[2]};
         level_init(F, nf, P.lo, P.hi);

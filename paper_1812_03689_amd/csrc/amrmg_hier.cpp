@@ -16,6 +16,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <iterator>
 
 namespace amrmg {
@@ -50,6 +51,10 @@ void level_set_boxes(HostLevel &L, const std::vector<Box> &boxes)
     L.bmap.assign((size_t)L.nbk[0] * L.nbk[1] * L.nbk[2], -1);
     L.bpos.clear();
     L.bbox.clear();
+    size_t nbr = 0;
+    for (const Box &B : boxes) nbr += (size_t)(B.volume() / 512);
+    L.bpos.reserve(3 * nbr);
+    L.bbox.reserve(nbr);
     for (size_t b = 0; b < boxes.size(); ++b) {
         const Box &B = boxes[b];
         L.off[b + 1] = L.off[b] + B.volume();
@@ -116,22 +121,33 @@ std::vector<Box> merge_blocks(const HostLevel &L, uint8_t *mark, int n_proper, i
     int g[3];
     for (int d = 0; d < 3; ++d) g[d] = 2 * L.n[d] / bf;
     auto at = [&](int x, int y, int z) { return (size_t)x + (size_t)g[0] * ((size_t)y + (size_t)g[1] * z); };
+    // the scans below visit blocks in linear order (z slowest, x fastest) and
+    // skip eight blocks at a time where a word of marks holds none they want
+    const size_t total = (size_t)g[0] * g[1] * g[2];
+    auto word = [&](size_t t) {
+        uint64_t w;
+        std::memcpy(&w, mark + t, 8);
+        return w;
+    };
     // 3: proper nesting
-    for (int z = 0; z < g[2]; ++z)
-        for (int y = 0; y < g[1]; ++y)
-            for (int x = 0; x < g[0]; ++x) {
-                if (!mark[at(x, y, z)]) continue;
-                int blk[3] = {x, y, z}, lo[3], hi[3];
-                grown_footprint(L, blk, half, n_proper, lo, hi);
-                if (!region_inside(L, lo, hi)) mark[at(x, y, z)] = 0;
-            }
+    for (size_t t0 = 0; t0 < total; t0 += 8) {
+        if (t0 + 8 <= total && word(t0) == 0) continue;
+        for (size_t t = t0; t < std::min(t0 + 8, total); ++t) {
+            if (!mark[t]) continue;
+            int blk[3] = {(int)(t % g[0]), (int)((t / g[0]) % g[1]), (int)(t / ((size_t)g[0] * g[1]))}, lo[3], hi[3];
+            grown_footprint(L, blk, half, n_proper, lo, hi);
+            if (!region_inside(L, lo, hi)) mark[t] = 0;
+        }
+    }
     // 4-5: greedy merge, z slowest, x fastest; mark value 2 = taken
     const int maxb = max_grid_size / bf;
     std::vector<Box> out;
     auto avail = [&](int x, int y, int z) { return mark[at(x, y, z)] == 1; };
-    for (int z = 0; z < g[2]; ++z)
-        for (int y = 0; y < g[1]; ++y)
-            for (int x = 0; x < g[0]; ++x) {
+    for (size_t t0 = 0; t0 < total; t0 += 8) {
+        if (t0 + 8 <= total && (word(t0) & 0x0101010101010101ull) == 0) continue;  // no mark 1 (marks are 0, 1, 2)
+        for (size_t t = t0; t < std::min(t0 + 8, total); ++t) {
+            const int x = (int)(t % g[0]), y = (int)((t / g[0]) % g[1]), z = (int)(t / ((size_t)g[0] * g[1]));
+            {
                 if (!avail(x, y, z)) continue;
                 int ex = 1, ey = 1, ez = 1;
                 while (x + ex < g[0] && ex < maxb && avail(x + ex, y, z)) ++ex;
@@ -160,6 +176,8 @@ std::vector<Box> merge_blocks(const HostLevel &L, uint8_t *mark, int n_proper, i
                 B.hi[2] = (z + ez) * bf;
                 out.push_back(B);
             }
+        }
+    }
     return out;
 }
 
