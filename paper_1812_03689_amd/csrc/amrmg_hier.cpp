@@ -48,7 +48,15 @@ void level_set_boxes(HostLevel &L, const std::vector<Box> &boxes)
 {
     L.boxes = boxes;
     L.off.assign(boxes.size() + 1, 0);
-    L.bmap.assign((size_t)L.nbk[0] * L.nbk[1] * L.nbk[2], -1);
+    const size_t nmap = (size_t)L.nbk[0] * L.nbk[1] * L.nbk[2];
+    if (L.bmap.size() == nmap && L.map_nbk[0] == L.nbk[0] && L.map_nbk[1] == L.nbk[1] && L.map_nbk[2] == L.nbk[2]) {
+        // the same brick grid as the previous box list (a regrid): clear only its bricks
+        for (size_t k = 0; k + 2 < L.bpos.size(); k += 3)
+            L.bmap[(size_t)L.bpos[k] + (size_t)L.nbk[0] * ((size_t)L.bpos[k + 1] + (size_t)L.nbk[1] * L.bpos[k + 2])] = -1;
+    } else {
+        L.bmap.assign(nmap, -1);
+        for (int d = 0; d < 3; ++d) L.map_nbk[d] = L.nbk[d];
+    }
     L.bpos.clear();
     L.bbox.clear();
     size_t nbr = 0;

@@ -26,6 +26,8 @@ struct HostLevel {
     std::vector<int64_t> off;   // user-layout offsets (nb + 1)
     int nbk[3] = {0, 0, 0};     // brick grid extent
     std::vector<int32_t> bmap;  // brick grid -> local brick or -1
+    int map_nbk[3] = {0, 0, 0}; // brick grid extent bmap was built for (its entries
+                                // other than those of bpos are -1)
     std::vector<int32_t> bpos;  // local brick -> brick grid position (3 each)
     std::vector<int32_t> bbox;  // local brick -> box
     int nbrick() const { return (int)bbox.size(); }
