@@ -1809,8 +1809,34 @@ struct Driver {
     }
 };
 
-// Run one outer iteration, through a captured graph when possible.  The
-// graph is instantiated once per hierarchy, workspace and option set.
+// The graph of one outer iteration, captured and instantiated once per
+// hierarchy, workspace and option set; iterate launches it (or the kernels
+// themselves when graphs are off or launches are being timed).
+template <class T>
+static amrmg_status ensure_graph(DevState &D, int nr, const SolveOpts &o)
+{
+    std::vector<int64_t> key = {D.meta_gen, (int64_t)(intptr_t)D.ws, (int64_t)sizeof(T), o.smoother, o.nu1, o.nu2,
+                                o.norm_p, (int64_t)(o.omega * 1e12), (int64_t)(o.bottom_rtol * 1e15),
+                                (int64_t)(o.inv_eps0 * 1e12)};
+    if (D.gexec && D.gkey == key) return AMRMG_OK;
+    D.drop_graph();
+    if (!D.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&D.cap_stream, hipStreamNonBlocking));
+    Driver<T> cap(D, D.cap_stream, o, nullptr);
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(D.cap_stream, hipStreamCaptureModeThreadLocal));
+    cap.iteration(nr);
+    hipError_t ec = hipStreamEndCapture(D.cap_stream, &g);
+    if (ec != hipSuccess) return fail(AMRMG_E_HIP, std::string("graph capture: ") + hipGetErrorString(ec));
+    hipError_t ei = hipGraphInstantiate(&D.gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        D.gexec = nullptr;
+        return fail(AMRMG_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    }
+    D.gkey = key;
+    return AMRMG_OK;
+}
+
 template <class T>
 static amrmg_status iterate(DevState &D, Driver<T> &drv, hipStream_t st, int nr, const SolveOpts &o, bool graphs)
 {
@@ -1818,26 +1844,7 @@ static amrmg_status iterate(DevState &D, Driver<T> &drv, hipStream_t st, int nr,
         drv.iteration(nr);
         return AMRMG_OK;
     }
-    std::vector<int64_t> key = {D.meta_gen, (int64_t)(intptr_t)D.ws, (int64_t)sizeof(T), o.smoother, o.nu1, o.nu2,
-                                o.norm_p, (int64_t)(o.omega * 1e12), (int64_t)(o.bottom_rtol * 1e15),
-                                (int64_t)(o.inv_eps0 * 1e12)};
-    if (!D.gexec || D.gkey != key) {
-        D.drop_graph();
-        if (!D.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&D.cap_stream, hipStreamNonBlocking));
-        Driver<T> cap(D, D.cap_stream, o, nullptr);
-        hipGraph_t g = nullptr;
-        HIP_TRY(hipStreamBeginCapture(D.cap_stream, hipStreamCaptureModeThreadLocal));
-        cap.iteration(nr);
-        hipError_t ec = hipStreamEndCapture(D.cap_stream, &g);
-        if (ec != hipSuccess) return fail(AMRMG_E_HIP, std::string("graph capture: ") + hipGetErrorString(ec));
-        hipError_t ei = hipGraphInstantiate(&D.gexec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ei != hipSuccess) {
-            D.gexec = nullptr;
-            return fail(AMRMG_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
-        }
-        D.gkey = key;
-    }
+    ST_TRY(ensure_graph<T>(D, nr, o));
     HIP_TRY(hipGraphLaunch(D.gexec, st));
     return AMRMG_OK;
 }
@@ -1854,6 +1861,9 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
     hipEvent_t ev0, ev1;
     HIP_TRY(hipEventCreate(&ev0));
     HIP_TRY(hipEventCreate(&ev1));
+    // the iteration's graph is captured and instantiated first, while the
+    // stream may still be busy with the caller's earlier work (the deposit)
+    if (g_use_graphs && !prof && o.max_iters > 0) ST_TRY(ensure_graph<T>(D, nr, o));
     HIP_TRY(hipMemsetAsync(D.cgit, 0, 64, st));  // CG iteration count and the norm sequence counter
     D.seq = 0;
     *(volatile unsigned *)D.h_seq = 0;
