@@ -542,10 +542,10 @@ def main():
         orho = H2.deposit_all(p)
         t_build = time.perf_counter() - t
         t = time.perf_counter()
-        _, oE, _ = H2.solve(orho, tol=tol, max_iters=0, bottom_rtol=1e-12)
+        _, oE, _ = H2.solve(orho, tol=tol, max_iters=0, bottom_rtol=1e-12, nu1=cm.params.nu1, nu2=cm.params.nu2)
         t_s0 = time.perf_counter() - t
         t = time.perf_counter()
-        H2.solve(orho, tol=tol, max_iters=1, bottom_rtol=1e-12)
+        H2.solve(orho, tol=tol, max_iters=1, bottom_rtol=1e-12, nu1=cm.params.nu1, nu2=cm.params.nu2)
         t_s1 = time.perf_counter() - t
         t = time.perf_counter()
         H2.gather(p, oE)

@@ -96,7 +96,7 @@ typedef struct amrmg_params {
     const double *monopoles;    /* host [n_monopoles][4] = q, x, y, z; copied by amrmg_create */
     int32_t precision;          /* AMRMG_FP64 or AMRMG_MIXED [MIXED] */
     int32_t smoother;           /* AMRMG_GSRB, AMRMG_JACOBI or AMRMG_GSRB_GLOBAL [GSRB] */
-    int32_t nu1, nu2;           /* pre / post smoothing sweeps [2, 2] */
+    int32_t nu1, nu2;           /* pre / post smoothing sweeps [2, 4] */
     double omega;               /* damped-Jacobi weight [6/7] */
     int32_t norm_p;             /* residual norm: 1, 2, or 0 for max-norm [2] */
     int32_t max_iters;          /* V-cycle cap i_max [50] */

@@ -305,7 +305,7 @@ def amrmg_profile_read(h, kclass):
 
 # --- convenience wrapper ----------------------------------------------------
 
-def make_params(n0, max_level=2, monopoles=(), precision="mixed", smoother="gsrb", nu1=2, nu2=2,
+def make_params(n0, max_level=2, monopoles=(), precision="mixed", smoother="gsrb", nu1=2, nu2=4,
                 max_grid_size=32, max_iters=50, norm_p=2, bottom_rtol=1e-2, lo=(0, 0, 0), hi=(1, 1, 1),
                 eps0=1.0, n_buffer=1, n_proper=2, omega=6.0 / 7.0, bottom="auto", tag_policy="charge",
                 robin_d=0.0):

@@ -847,7 +847,7 @@ extern "C" void amrmg_default_params(amrmg_params *p)
     p->precision = AMRMG_MIXED;
     p->smoother = AMRMG_GSRB;
     p->nu1 = 2;
-    p->nu2 = 2;
+    p->nu2 = 4;
     p->omega = 6.0 / 7.0;
     p->norm_p = 2;
     p->max_iters = 50;
