@@ -20,9 +20,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1576,6 +1578,31 @@ struct SolveOpts {
     double omega, bottom_rtol, inv_eps0;
 };
 
+// Threads per brick of the sweep kernel, tuned on the device: for each
+// launch size class (bricks per launch, rounded up to a power of two) and
+// cycle precision the first solve that meets it times a plain sweep with
+// 128 and with 256 threads per brick and keeps the faster; later solves and
+// captured graphs read the choice.  Process-wide (one GPU per process);
+// AMRMG_NO_TUNE=1 keeps the size rule instead.
+static std::mutex g_tune_mu;
+static std::map<std::pair<int, int>, int> g_hgs_nt;  // (sizeof(T), log2 bricks) -> threads
+static const bool g_tune = getenv("AMRMG_NO_TUNE") == nullptr;
+
+static int size_class(int nb)
+{
+    int c = 0;
+    while ((1 << c) < nb) ++c;
+    return c;
+}
+
+static int tuned_nt(int wbytes, int nb)
+{
+    if (!g_tune) return 0;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_hgs_nt.find({wbytes, size_class(nb)});
+    return it == g_hgs_nt.end() ? 0 : it->second;
+}
+
 template <class T>
 struct Driver {
     DevState &D;
@@ -1624,6 +1651,46 @@ struct Driver {
     {
         const auto &last = m.ent[m.step_ent0[k + 1] - 1];
         return last.b0 + last.nb - step_b0(k);
+    }
+    int hgs_nt(int k) const { return tuned_nt((int)sizeof(T), step_nb(k)); }
+
+    // time the sweep of every level with each block size not yet tuned for
+    // its size class (plain sweeps from e into et: both are scratch before
+    // the cycle starts)
+    amrmg_status tune()
+    {
+        if (!g_tune) return AMRMG_OK;
+        for (int k = D.kc + 1; k < m.K; ++k) {
+            const int b0 = step_b0(k), nb = step_nb(k);
+            if (nb <= 0 || tuned_nt((int)sizeof(T), nb)) continue;
+            hipEvent_t a, z;
+            HIP_TRY(hipEventCreate(&a));
+            HIP_TRY(hipEventCreate(&z));
+            constexpr int REPS = 5;
+            float each[2] = {0.f, 0.f};
+            const int cand[2] = {128, 256};
+            for (int i = 0; i < 2; ++i) {
+                launch_hgs<T>(st, D.M, b0, nb, e, et, r, cpe, D.phib, D.ffs, 0, cand[i]);  // warm
+                HIP_TRY(hipEventRecord(a, st));
+                for (int rep = 0; rep < REPS; ++rep)
+                    launch_hgs<T>(st, D.M, b0, nb, e, et, r, cpe, D.phib, D.ffs, 0, cand[i]);
+                HIP_TRY(hipEventRecord(z, st));
+                HIP_TRY(hipEventSynchronize(z));
+                HIP_TRY(hipEventElapsedTime(&each[i], a, z));
+            }
+            // the size rule's choice unless the other is clearly faster
+            const int rule = hgs_rule_threads(nb) == cand[1] ? 1 : 0, other = 1 - rule;
+            const int pick = each[other] < 0.97f * each[rule] ? cand[other] : cand[rule];
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(z);
+            HIP_TRY(hipGetLastError());
+            if (getenv("AMRMG_TUNE_LOG"))
+                fprintf(stderr, "libamrmg: sweep of %d bricks (%d-byte cycle): 128 threads %.4f ms, 256 threads %.4f ms -> %d\n",
+                        nb, (int)sizeof(T), each[0] / REPS, each[1] / REPS, pick);
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_hgs_nt.emplace(std::make_pair((int)sizeof(T), size_class(nb)), pick);
+        }
+        return AMRMG_OK;
     }
 
     // outer FP64 residual of every AMR level; norms into dnorm[off ..] (and
@@ -1698,13 +1765,13 @@ struct Driver {
         // the last pre-smoothing sweep also writes the fine sums of e that the
         // restriction's coarse-fine update reads
         pb(AMRMG_K_GSRB);
-        launch_hgs<T>(st, D.M, b0, nb, nullptr, out, r, nullptr, D.phib, D.ffs, o.nu1 <= 1 ? 1 | 16 : 1);
+        launch_hgs<T>(st, D.M, b0, nb, nullptr, out, r, nullptr, D.phib, D.ffs, o.nu1 <= 1 ? 1 | 16 : 1, hgs_nt(k));
         pe(AMRMG_K_GSRB, 2.0 * n * W);
         T *src = out;
         for (int i = 1; i < o.nu1; ++i) {
             T *dst = (src == e) ? et : e;
             pb(AMRMG_K_GSRB);
-            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, nullptr, D.phib, D.ffs, i == o.nu1 - 1 ? 16 : 0);
+            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, nullptr, D.phib, D.ffs, i == o.nu1 - 1 ? 16 : 0, hgs_nt(k));
             pe(AMRMG_K_GSRB, 3.0 * n * W);
             src = dst;
         }
@@ -1719,7 +1786,7 @@ struct Driver {
             T *dst = (src == e) ? et : e;
             int mode = (i == 0 ? 2 | 4 : 0) | (i == o.nu2 - 1 ? 8 : 0);
             pb(AMRMG_K_GSRB);
-            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, cpe, D.phib, D.ffs, mode);
+            launch_hgs<T>(st, D.M, b0, nb, src, dst, r, cpe, D.phib, D.ffs, mode, hgs_nt(k));
             // e, r in; e out; the parent value with the fused prolongation;
             // phi read and written on AMR bricks with the fused update
             pe(AMRMG_K_GSRB, (3.0 + (i == 0 ? 0.125 : 0.0)) * n * W + ((mode & 8) ? 16.0 * step_amr_cells(k) : 0.0));
@@ -1863,6 +1930,7 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
     HIP_TRY(hipEventCreate(&ev1));
     // the iteration's graph is captured and instantiated first, while the
     // stream may still be busy with the caller's earlier work (the deposit)
+    if (o.smoother == AMRMG_GSRB) ST_TRY(drv.tune());
     if (g_use_graphs && !prof && o.max_iters > 0) ST_TRY(ensure_graph<T>(D, nr, o));
     HIP_TRY(hipMemsetAsync(D.cgit, 0, 64, st));  // CG iteration count and the norm sequence counter
     D.seq = 0;

@@ -1924,12 +1924,14 @@ void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, doubl
     AMRMG_LAUNCH(k_tag, dim3(blocks_for(n, 256)), dim3(256), 0, st, v, n, scratch, lambda, tags);
 }
 
+int hgs_rule_threads(int nb) { return nb <= HGS_SMALL_LEVEL ? BT_SMALL : BT; }
+
 template <class T>
 void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
-                double *phib, double *ffs, int mode)
+                double *phib, double *ffs, int mode, int nt)
 {
     if (nb <= 0) return;
-    const bool small = nb <= HGS_SMALL_LEVEL;
+    const bool small = (nt ? nt : hgs_rule_threads(nb)) == BT_SMALL;
     dim3 g(nb), blk(small ? BT_SMALL : BT);
 #define AMRMG_HGS(MD)                                                                                        \
     case MD:                                                                                                 \
@@ -2042,7 +2044,7 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val)
                                       double, int, int *);                                                      \
     template void launch_copy<T>(hipStream_t, const T *, T *, int64_t);                                         \
     template void launch_hgs<T>(hipStream_t, const DevMeta &, int, int, const T *, T *, const T *, T *,         \
-                                double *, double *, int);                                                       \
+                                double *, double *, int, int);                                                       \
     template void launch_coarse_cycle<T>(hipStream_t, const DevMeta &, const CoarseJob *, int, T *, T *,        \
                                          double *, int, int, double, int, int *, double *, bool, int);          \
     template void launch_direct<T>(hipStream_t, const DirectJob *, const int2 *, int, const int2 *, int,         \

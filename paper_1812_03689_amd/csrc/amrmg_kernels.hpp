@@ -147,9 +147,12 @@ template <class T>
 void launch_copy(hipStream_t st, const T *a, T *b, int64_t n);
 // brick-hybrid Gauss-Seidel sweep; mode = bits of HG_ZERO 1, HG_PROL 2, HG_CPIN 4, HG_PHI 8,
 // HG_FFS 16 (fine sums of the result into ffs)
+// nt: threads per brick (128 or 256), or 0 for the size rule
+// hgs_rule_threads (256 up to 4096 bricks, else 128)
+int hgs_rule_threads(int nb);
 template <class T>
 void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
-                double *phib, double *ffs, int mode);
+                double *phib, double *ffs, int mode, int nt = 0);
 // direct solve e = A^-1 r of the coarsest grids of the listed jobs: planes
 // (job, z | x-block << 8) for the x/y transforms, column groups (job, first
 // column) for the z transform; FP64 scratch W; phi += e on AMR grids when
