@@ -908,6 +908,13 @@ extern "C" amrmg_status amrmg_create(const amrmg_params *p, void *hip_stream, am
 
 extern "C" void amrmg_destroy(amrmg_ctx *ctx) { delete ctx; }
 
+// the deposit's larger LDS tile on levels where a visiting-order bucket spans
+// 8 or more cells per axis
+static bool big_tile(const amrmg_ctx *ctx, int level)
+{
+    return order_bucket_shift(ctx->P.lo, ctx->P.hi, ctx->P.n0) + level >= 3;
+}
+
 static DepLevel dep_level(const Problem &P, const HostLevel &L, const int32_t *bmap)
 {
     DepLevel D{};
@@ -1060,7 +1067,7 @@ static amrmg_status tag_level(amrmg_ctx *ctx, const HostLevel &L, int pos_dtype,
     A.rho[0] = rho;
     A.ncell[0] = G.nc;
     launch_deposit(st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, perm, A, G.ub, (const int2 *)G.us, nout, cx, cy,
-                   cz, cq);
+                   cz, cq, big_tile(ctx, L.amr));
     tag_mark(ctx, G, rho, lambda);
     return tag_boxes(ctx, L, G, boxes);
 }
@@ -1418,7 +1425,8 @@ extern "C" amrmg_status amrmg_deposit(amrmg_ctx *ctx, int pos_dtype, const void 
     for (int l = 0; l < A.nlev; ++l) cells += A.ncell[l];
     ctx->prof.begin(AMRMG_K_DEPOSIT);
     launch_deposit(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, ctx->perm_n == n ? ctx->perm : nullptr, A,
-                   ctx->ds.M.ubase, ctx->ds.M.ustr, dout);
+                   ctx->ds.M.ubase, ctx->ds.M.ustr, dout, nullptr, nullptr, nullptr, nullptr,
+                   big_tile(ctx, pr.namr() - 1));
     ctx->prof.end(AMRMG_K_DEPOSIT, (double)n * (3.0 * (pos_dtype == AMRMG_POS_F32 ? 4 : 8) + 8.0) + 8.0 * (double)cells);
     HIP_TRY(hipGetLastError());
     if (n_outside) {
@@ -1442,6 +1450,7 @@ extern "C" amrmg_status amrmg_deposit_built(amrmg_ctx *ctx, double *const *rho, 
     // levels deposited by the build are copied; the others are deposited
     // together from the ordered copy (positions after the charges)
     DepArgs A{};
+    int finest = 0;
     for (int l = 0; l < pr.namr(); ++l) {
         if (!rho[l]) return fail(AMRMG_E_INVALID, "rho[l] is NULL");
         const HostLevel &L = pr.lev[pr.kg + l];
@@ -1450,6 +1459,7 @@ extern "C" amrmg_status amrmg_deposit_built(amrmg_ctx *ctx, double *const *rho, 
                                    ctx->st));
             continue;
         }
+        finest = l;
         A.lev[A.nlev] = dep_level(pr, L, ctx->ds.d_bmap[l]);
         A.rho[A.nlev] = rho[l];
         A.ncell[A.nlev] = L.ncells();
@@ -1473,7 +1483,7 @@ extern "C" amrmg_status amrmg_deposit_built(amrmg_ctx *ctx, double *const *rho, 
         for (int l = 0; l < A.nlev; ++l) cells += A.ncell[l];
         ctx->prof.begin(AMRMG_K_DEPOSIT);
         launch_deposit(ctx->st, pos == AMRMG_POS_F32, n, xs, ys, zs, qs, nullptr, A, ctx->ds.M.ubase, ctx->ds.M.ustr,
-                       dout);
+                       dout, nullptr, nullptr, nullptr, nullptr, big_tile(ctx, finest));
         ctx->prof.end(AMRMG_K_DEPOSIT, (double)n * (3.0 * ps + 8.0) + 8.0 * (double)cells);
     }
     HIP_TRY(hipGetLastError());

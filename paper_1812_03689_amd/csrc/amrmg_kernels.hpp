@@ -168,11 +168,14 @@ void launch_coarse_cycle(hipStream_t st, const DevMeta &M, const CoarseJob *jobs
                          bool phi_update, int threads_hint);
 // with xs != nullptr, also the particles in visiting order (the order perm
 // gives; perm required): xs[i] = x[perm[i]], ... (the copy the ordered
-// deposits read later, written while the particles pass anyway)
+// deposits read later, written while the particles pass anyway).
+// big_tile: the larger LDS tile, for levels on which a visiting-order
+// bucket spans 8 or more cells per axis
 void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                     const double *q, const uint32_t *perm, const DepArgs &A, const int64_t *ubase, const int2 *ustr,
                     unsigned long long *nout,
-                    void *xs = nullptr, void *ys = nullptr, void *zs = nullptr, double *qs = nullptr);
+                    void *xs = nullptr, void *ys = nullptr, void *zs = nullptr, double *qs = nullptr,
+                    bool big_tile = false);
 void launch_zero_levels(hipStream_t st, const DepArgs &A);
 void launch_gather(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                    const uint32_t *perm, const GatherArgs &G, const int64_t *ubase, const int2 *ustr, double *Ex,
@@ -185,6 +188,8 @@ void launch_fill(hipStream_t st, double *v, int64_t n, double val);
 // key, slot: [n] each; count: [2 order_count_entries], start:
 // [order_count_entries]; temp: order_temp_bytes(order_count_entries) bytes
 size_t order_count_entries(const double *lo, const double *hi, const int *n0);
+// log2 of the visiting-order bucket edge in level-0 cells
+int order_bucket_shift(const double *lo, const double *hi, const int *n0);
 // the particles in the visiting order alone: xs[i] = x[perm[i]], ...
 void launch_copy_ordered(hipStream_t st, int pos_f32, int64_t n, const uint32_t *perm, const void *x, const void *y,
                          const void *z, const double *q, void *xs, void *ys, void *zs, double *qs);

@@ -124,6 +124,8 @@ size_t order_count_entries(const double *lo, const double *hi, const int *n0)
     return (size_t)bucket_grid(lo, hi, n0).nbkt + 1;
 }
 
+int order_bucket_shift(const double *lo, const double *hi, const int *n0) { return bucket_grid(lo, hi, n0).shift; }
+
 size_t order_temp_bytes(size_t entries)
 {
     size_t b = 0;
