@@ -1,0 +1,89 @@
+"""The eager launch path: the outer iteration launched kernel by kernel instead
+of replayed from a captured hipGraph, with the sweep's threads per brick from
+the size rule instead of the autotuner (AMRMG_NO_GRAPH=1, AMRMG_NO_TUNE=1;
+both are read once when the library loads, so the solve runs in a child
+process).  Its phi matches the oracle to the solve's bar (1e-9 FP64 cycle,
+1e-8 mixed) and the graph-replayed phi of this process to a tenth of that
+(the tuned and the rule's threads per brick may order a brick's updates
+differently, so the two converged iterates agree to the solve tolerance,
+not bit for bit)."""
+import functools
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def workload():
+    from paper_1812_03689_amd import workloads as W
+    p = W.gaussian_bunch(100000, sigma=(0.05, 0.05, 0.1), seed=W.seed_for(2, 7))
+    return W.Workload("gauss_32c_2lev", p, (32, 32, 32), 2, [1e-3, 1e-3], [(1.0, 0.5, 0.5, 0.5)], 1e-8)
+
+
+def gpu_solve(precision):
+    import torch
+    from paper_1812_03689_amd import amrmg as A
+    w = workload()
+    prm = A.make_params(w.n0, max_level=w.max_level, monopoles=w.monopoles, precision=precision)
+    ctx = A.Context(prm)
+    x, y, z, q = (torch.as_tensor(a, device="cuda") for a in (w.particles.x, w.particles.y, w.particles.z,
+                                                                w.particles.q))
+    ctx.build_hierarchy(x, y, z, q, tag_rel=w.tag_rel)
+    rho, nout = ctx.deposit_built()
+    assert nout == 0
+    phi, E, st = ctx.solve(rho, tol=1e-11)
+    assert st["converged"], st
+    return [t.cpu().numpy() for t in phi], st
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_solution():
+    from oracle import oracle as O
+    w = workload()
+    H = O.hierarchy_from_workload(w)
+    orho = H.deposit_all(w.particles)
+    ophi, _, _ = H.solve(orho, tol=1e-13, max_iters=80, bottom_rtol=1e-14)
+    return H, ophi
+
+
+@pytest.mark.parametrize("precision,tol_err", [("fp64", 1e-9), ("mixed", 1e-8)])
+def test_eager_path_matches_oracle_and_graph_path(precision, tol_err, tmp_path):
+    print("eager child", precision, flush=True)
+    out = tmp_path / "phi.npz"
+    env = dict(os.environ, AMRMG_NO_GRAPH="1", AMRMG_NO_TUNE="1",
+               PYTHONPATH=ROOT + os.pathsep + os.environ.get("PYTHONPATH", ""))
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), precision, str(out)], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=240)
+    print(r.stdout[-2000:], r.stderr[-2000:], flush=True)
+    assert r.returncode == 0
+    z = np.load(out)
+    eager = [z["l%d" % l] for l in range(int(z["nlev"]))]
+
+    H, ophi = oracle_solution()
+    assert len(eager) == H.nlev
+    num = den = 0.0
+    for l in range(H.nlev):
+        unc = ~H.covered_mask(l)
+        num += np.sum((eager[l][unc] - ophi[l][unc]) ** 2)
+        den += np.sum(ophi[l][unc] ** 2)
+    err = float(np.sqrt(num / den))
+    print("rel L2 vs oracle", err, flush=True)
+    assert err <= tol_err
+
+    print("graph path", precision, flush=True)
+    graph, st = gpu_solve(precision)
+    d = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(eager, graph))
+    print("eager vs graph", d, st["iters"], flush=True)
+    assert d <= 0.1 * tol_err
+
+
+if __name__ == "__main__":
+    phi, st = gpu_solve(sys.argv[1])
+    print("child", st, flush=True)
+    np.savez(sys.argv[2], nlev=len(phi), **{"l%d" % l: a for l, a in enumerate(phi)})
