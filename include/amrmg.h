@@ -254,6 +254,18 @@ amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *x, const vo
                           const void *z, int64_t n, double *const *E, double *Ex, double *Ey,
                           double *Ez);
 
+/* The same gather (same weights, level choice and result, bit for bit) at
+ * the particles given to the last amrmg_build_hierarchy, read from the
+ * build's copy of them in spatial order instead of the caller's arrays: the
+ * gather of a PIC step at the positions it deposited (Sec. 1's particle-mesh
+ * cycle), with coalesced position reads; only the writes of E follow the
+ * caller's order.  Ex, Ey, Ez device [n], n the particle count of that
+ * build, in its order.  AMRMG_E_STATE when no hierarchy is built or the
+ * build kept no copy (as amrmg_deposit_built).  The particle arrays given to
+ * the build may have changed since: the result is that at the build's
+ * particles. */
+amrmg_status amrmg_gather_built(amrmg_ctx *ctx, double *const *E, double *Ex, double *Ey, double *Ez);
+
 /* Domain transform (Sec. 4.1 of the paper): map particles from particle
  * space S_p into the computation space S_c = [-l0,l0] x [-l1,l1] x [-l2,l2]
  * around the reference position c.  With Gamma(x, l) = max_d |x_d - c_d| /

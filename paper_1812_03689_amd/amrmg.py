@@ -35,7 +35,7 @@ AMRMG_MAX_LEVELS = 8
 EXPORTED = ["amrmg_default_params", "amrmg_create", "amrmg_destroy", "amrmg_last_error",
             "amrmg_build_hierarchy", "amrmg_hierarchy_info", "amrmg_get_boxes", "amrmg_cf_faces", "amrmg_brick_tables",
             "amrmg_workspace_size", "amrmg_set_workspace", "amrmg_deposit", "amrmg_deposit_built", "amrmg_solve",
-            "amrmg_gather", "amrmg_residual", "amrmg_solve_batch", "amrmg_profile_enable",
+            "amrmg_gather", "amrmg_gather_built", "amrmg_residual", "amrmg_solve_batch", "amrmg_profile_enable",
             "amrmg_profile_read", "amrmg_transform_particles", "amrmg_rescale_fields"]
 KCLASS = ["gsrb", "jacobi", "restrict", "prolong", "reflux", "cpart", "residual", "phi_update", "bottom",
           "efield", "avgdown", "deposit", "gather"]
@@ -98,6 +98,7 @@ def lib():
         L.amrmg_deposit_built.argtypes = [vp, vp, vp]
         L.amrmg_solve.argtypes = [vp, vp, vp, vp, dbl, C.POINTER(amrmg_solve_stats)]
         L.amrmg_gather.argtypes = [vp, C.c_int, vp, vp, vp, i64, vp, vp, vp, vp]
+        L.amrmg_gather_built.argtypes = [vp, vp, vp, vp, vp]
         L.amrmg_residual.argtypes = [vp, vp, vp, vp]
         L.amrmg_solve_batch.argtypes = [vp, i32, vp, vp, dbl, C.POINTER(amrmg_solve_stats)]
         L.amrmg_profile_enable.argtypes = [vp, C.c_uint32]
@@ -255,6 +256,10 @@ def amrmg_gather(h, x, y, z, E: Sequence, Ex, Ey, Ez) -> None:
                               _ptrs(E), Ex.data_ptr(), Ey.data_ptr(), Ez.data_ptr()))
 
 
+def amrmg_gather_built(h, E: Sequence, Ex, Ey, Ez) -> None:
+    _check(lib().amrmg_gather_built(h, _ptrs(E), Ex.data_ptr(), Ey.data_ptr(), Ez.data_ptr()))
+
+
 def amrmg_residual(h, rho: Sequence, phi: Sequence, r: Sequence) -> None:
     _check(lib().amrmg_residual(h, _ptrs(rho), _ptrs(phi), _ptrs(r)))
 
@@ -353,6 +358,7 @@ class Context:
 
     def build_hierarchy(self, x, y, z, q, tag_rel=None, explicit_boxes=None):
         amrmg_build_hierarchy(self.h, x, y, z, q, tag_rel, explicit_boxes)
+        self.built_n = x.numel()
         self.info = amrmg_hierarchy_info(self.h)
         return self.info
 
@@ -398,6 +404,14 @@ class Context:
         n = x.numel()
         Ex, Ey, Ez = (torch.empty(n, dtype=torch.float64, device=x.device) for _ in range(3))
         amrmg_gather(self.h, x, y, z, E, Ex, Ey, Ez)
+        return Ex, Ey, Ez
+
+    def gather_built(self, E):
+        """E at the particles of the last build_hierarchy, in their order
+        (amrmg_gather_built)."""
+        import torch
+        Ex, Ey, Ez = (torch.empty(self.built_n, dtype=torch.float64, device="cuda") for _ in range(3))
+        amrmg_gather_built(self.h, E, Ex, Ey, Ez)
         return Ex, Ey, Ez
 
     def transform_particles(self, x, y, z, center, l, out=None):

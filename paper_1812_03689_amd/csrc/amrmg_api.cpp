@@ -1497,15 +1497,11 @@ extern "C" amrmg_status amrmg_deposit_built(amrmg_ctx *ctx, double *const *rho, 
     return AMRMG_OK;
 }
 
-extern "C" amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y, const void *z,
-                                     int64_t n, double *const *E, double *Ex, double *Ey, double *Ez)
+// the levels and E pointers a gather reads
+static amrmg_status gather_args(const amrmg_ctx *ctx, double *const *E, GatherArgs &G)
 {
-    if (!ctx) return fail(AMRMG_E_INVALID, "ctx is NULL");
-    if (!ctx->built) return fail(AMRMG_E_STATE, "hierarchy not built");
-    if (pos_dtype != AMRMG_POS_F64 && pos_dtype != AMRMG_POS_F32) return fail(AMRMG_E_INVALID, "bad pos_dtype");
-    if (!E || n < 0 || (n > 0 && (!x || !y || !z || !Ex || !Ey || !Ez))) return fail(AMRMG_E_INVALID, "bad arguments");
     const Problem &pr = ctx->prob;
-    GatherArgs G{};
+    G = GatherArgs{};
     G.nlev = pr.namr();
     for (int l = 0; l < G.nlev; ++l) {
         G.lev[l] = dep_level(pr, pr.lev[pr.kg + l], ctx->ds.d_bmap[l]);
@@ -1514,10 +1510,45 @@ extern "C" amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *
             G.E[3 * l + d] = E[3 * l + d];
         }
     }
+    return AMRMG_OK;
+}
+
+extern "C" amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y, const void *z,
+                                     int64_t n, double *const *E, double *Ex, double *Ey, double *Ez)
+{
+    if (!ctx) return fail(AMRMG_E_INVALID, "ctx is NULL");
+    if (!ctx->built) return fail(AMRMG_E_STATE, "hierarchy not built");
+    if (pos_dtype != AMRMG_POS_F64 && pos_dtype != AMRMG_POS_F32) return fail(AMRMG_E_INVALID, "bad pos_dtype");
+    if (!E || n < 0 || (n > 0 && (!x || !y || !z || !Ex || !Ey || !Ez))) return fail(AMRMG_E_INVALID, "bad arguments");
+    GatherArgs G;
+    ST_TRY(gather_args(ctx, E, G));
     ctx->prof.begin(AMRMG_K_GATHER);
     launch_gather(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, ctx->perm_n == n ? ctx->perm : nullptr, G,
                   ctx->ds.M.ubase, ctx->ds.M.ustr, Ex, Ey, Ez);
     ctx->prof.end(AMRMG_K_GATHER, (double)n * (3.0 * (pos_dtype == AMRMG_POS_F32 ? 4 : 8) + 24.0));
+    HIP_TRY(hipGetLastError());
+    return AMRMG_OK;
+}
+
+extern "C" amrmg_status amrmg_gather_built(amrmg_ctx *ctx, double *const *E, double *Ex, double *Ey, double *Ez)
+{
+    if (!ctx) return fail(AMRMG_E_INVALID, "ctx is NULL");
+    if (!ctx->built) return fail(AMRMG_E_STATE, "hierarchy not built");
+    if (ctx->built_n < 0) return fail(AMRMG_E_STATE, "the last build kept no ordered copy of its particles");
+    const int64_t n = ctx->built_n;
+    if (!E || (n > 0 && (!Ex || !Ey || !Ez))) return fail(AMRMG_E_INVALID, "bad arguments");
+    if (n > 0 && (ctx->perm_n != n || !ctx->perm)) return fail(AMRMG_E_STATE, "visiting order of the build lost");
+    GatherArgs G;
+    ST_TRY(gather_args(ctx, E, G));
+    const int pos = ctx->built_pos;
+    const size_t ps = pos == AMRMG_POS_F32 ? 4 : 8;
+    const char *base = (const char *)ctx->sorted.p;
+    const char *xs = base + align256((size_t)n * 8), *ys = xs + align256((size_t)n * ps),
+               *zs = ys + align256((size_t)n * ps);
+    ctx->prof.begin(AMRMG_K_GATHER);
+    launch_gather(ctx->st, pos == AMRMG_POS_F32, n, xs, ys, zs, ctx->perm, G, ctx->ds.M.ubase, ctx->ds.M.ustr, Ex, Ey,
+                  Ez, true);
+    ctx->prof.end(AMRMG_K_GATHER, (double)n * (3.0 * ps + 4.0 + 24.0));
     HIP_TRY(hipGetLastError());
     return AMRMG_OK;
 }

@@ -1650,8 +1650,10 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
 
 // E at every particle from the finest level whose boxes hold all 8 cells of
 // its CIC stencil; particles are visited in the given (spatially sorted)
-// order so that neighbouring threads read neighbouring field cells.
-template <class P>
+// order so that neighbouring threads read neighbouring field cells.  ORD:
+// the positions are already in that order (x[i] is particle perm[i]), so
+// only the writes go through perm.
+template <class P, bool ORD>
 __global__ void __launch_bounds__(256) k_gather(int64_t n, const P *x, const P *y, const P *z, const uint32_t *perm,
                                                 GatherArgs G, const int64_t *ubase, const int2 *ustr, double *Ex,
                                                 double *Ey, double *Ez)
@@ -1659,7 +1661,8 @@ __global__ void __launch_bounds__(256) k_gather(int64_t n, const P *x, const P *
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     int64_t p = perm ? (int64_t)perm[i] : i;
-    double X = (double)x[p], Y = (double)y[p], Z = (double)z[p];
+    int64_t s = ORD ? i : p;
+    double X = (double)x[s], Y = (double)y[s], Z = (double)z[s];
     double e[3] = {0.0, 0.0, 0.0};
     for (int l = G.nlev - 1; l >= 0; --l) {
         const DepLevel &D = G.lev[l];
@@ -1913,18 +1916,31 @@ void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const
     }
 }
 
+template <class P, bool ORD>
+static void launch_gather_t(hipStream_t st, unsigned g, int64_t n, const void *x, const void *y, const void *z,
+                            const uint32_t *perm, const GatherArgs &G, const int64_t *ubase, const int2 *ustr,
+                            double *Ex, double *Ey, double *Ez)
+{
+    AMRMG_LAUNCH((k_gather<P, ORD>), dim3(g), dim3(256), 0, st, n, (const P *)x, (const P *)y, (const P *)z, perm, G,
+                 ubase, ustr, Ex, Ey, Ez);
+}
+
 void launch_gather(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                    const uint32_t *perm, const GatherArgs &G, const int64_t *ubase, const int2 *ustr, double *Ex,
-                   double *Ey, double *Ez)
+                   double *Ey, double *Ez, bool ordered)
 {
     if (n <= 0) return;
     unsigned g = blocks_for(n, 256);
-    if (pos_f32)
-        AMRMG_LAUNCH((k_gather<float>), dim3(g), dim3(256), 0, st, n, (const float *)x, (const float *)y,
-                     (const float *)z, perm, G, ubase, ustr, Ex, Ey, Ez);
-    else
-        AMRMG_LAUNCH((k_gather<double>), dim3(g), dim3(256), 0, st, n, (const double *)x, (const double *)y,
-                     (const double *)z, perm, G, ubase, ustr, Ex, Ey, Ez);
+    if (ordered && perm) {
+        if (pos_f32)
+            launch_gather_t<float, true>(st, g, n, x, y, z, perm, G, ubase, ustr, Ex, Ey, Ez);
+        else
+            launch_gather_t<double, true>(st, g, n, x, y, z, perm, G, ubase, ustr, Ex, Ey, Ez);
+    } else if (pos_f32) {
+        launch_gather_t<float, false>(st, g, n, x, y, z, perm, G, ubase, ustr, Ex, Ey, Ez);
+    } else {
+        launch_gather_t<double, false>(st, g, n, x, y, z, perm, G, ubase, ustr, Ex, Ey, Ez);
+    }
 }
 
 void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, double *scratch, uint8_t *tags)

@@ -177,9 +177,11 @@ void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const
                     void *xs = nullptr, void *ys = nullptr, void *zs = nullptr, double *qs = nullptr,
                     bool big_tile = false);
 void launch_zero_levels(hipStream_t st, const DepArgs &A);
+// ordered: x, y, z are already in the order perm gives (x[i] is particle
+// perm[i], the build's ordered copy); E is written at perm[i]
 void launch_gather(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                    const uint32_t *perm, const GatherArgs &G, const int64_t *ubase, const int2 *ustr, double *Ex,
-                   double *Ey, double *Ez);
+                   double *Ey, double *Ez, bool ordered = false);
 void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, double *scratch, uint8_t *tags);
 void launch_fill(hipStream_t st, double *v, int64_t n, double val);
 // spatial visiting order of particles (counting sort into Morton-ordered

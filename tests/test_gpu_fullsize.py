@@ -12,7 +12,8 @@ pass each:
     level relative to the right-hand side: at most the tolerance;
   * E against the oracle's E = -grad of the GPU's phi, and the gather against
     the oracle's interpolation of the GPU's E (both one pass of the same
-    data, so to round-off)."""
+    data, so to round-off); the gather from the build's ordered copy (the
+    bench's) equal to it bit for bit."""
 import numpy as np
 import pytest
 
@@ -43,6 +44,9 @@ def test_full_size_properties(case):
     print("  ", {k: st[k] for k in ("iters", "converged", "rel_residual", "dof")}, flush=True)
     assert st["converged"]
     Ex, Ey, Ez = ctx.gather(x, y, z, E)
+    # the bench's gather: from the build's ordered copy, equal bit for bit
+    for u, v in zip((Ex, Ey, Ez), ctx.gather_built(E)):
+        assert torch.equal(u, v)
     torch.cuda.synchronize()
 
     H = O.hierarchy_from_workload(w)

@@ -29,7 +29,7 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("amrmg_create", "amrmg_build_hierarchy", "amrmg_deposit", "amrmg_deposit_built", "amrmg_solve",
-                 "amrmg_gather", "amrmg_solve_batch"):
+                 "amrmg_gather", "amrmg_gather_built", "amrmg_solve_batch"):
         assert must in names
     assert len(names) >= 17
 
