@@ -1899,21 +1899,14 @@ void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const
                     unsigned long long *nout, void *xs, void *ys, void *zs, double *qs, bool big_tile)
 {
     if (n <= 0 || A.nlev <= 0) return;
-    // two particles per thread up to 4M particles (enough workgroups to fill
-    // the chip), four beyond
-    if (n <= (4 << 20)) {
-        const unsigned g = blocks_for(n, 512);
-        if (pos_f32)
-            launch_deposit_tile<float, 2>(st, g, big_tile, n, x, y, z, q, perm, A, ubase, ustr, nout, xs, ys, zs, qs);
-        else
-            launch_deposit_tile<double, 2>(st, g, big_tile, n, x, y, z, q, perm, A, ubase, ustr, nout, xs, ys, zs, qs);
-    } else {
-        const unsigned g = blocks_for(n, 1024);
-        if (pos_f32)
-            launch_deposit_tile<float, 4>(st, g, big_tile, n, x, y, z, q, perm, A, ubase, ustr, nout, xs, ys, zs, qs);
-        else
-            launch_deposit_tile<double, 4>(st, g, big_tile, n, x, y, z, q, perm, A, ubase, ustr, nout, xs, ys, zs, qs);
-    }
+    // one particle per thread: the most workgroups in flight measured fastest
+    // at 1e6 to 1e7 particles (ahead of two and four per thread, whose fewer
+    // tile flushes per particle do not make up for the lost parallelism)
+    const unsigned g = blocks_for(n, 256);
+    if (pos_f32)
+        launch_deposit_tile<float, 1>(st, g, big_tile, n, x, y, z, q, perm, A, ubase, ustr, nout, xs, ys, zs, qs);
+    else
+        launch_deposit_tile<double, 1>(st, g, big_tile, n, x, y, z, q, perm, A, ubase, ustr, nout, xs, ys, zs, qs);
 }
 
 template <class P, bool ORD>
