@@ -466,7 +466,12 @@ static double apply_cell(const OHier *H, int l, int i, int j, int k, double *con
 }
 
 /* diagonal of the no-finer-level operator with homogeneous data: the
- * coefficient of u_c in (A u)_c */
+ * coefficient of u_c in (A u)_c, face by face (1 - g)/h^2 where g u_c is the
+ * part of the value across the face that depends on u_c (nbval):
+ *   - a same-level neighbour: g = 0;
+ *   - a coarse-fine ghost: g = 2/3, the weight of the cell itself in step 2;
+ *   - the physical boundary: g = -1 for the Dirichlet ghost 2 g - u_c, or
+ *     g = (1/h - 1/(2 d)) / (1/h + 1/(2 d)) for the Robin ghost. */
 static double diag_nf(const OHier *H, int l, int i, int j, int k)
 {
     const OLev *L = &H->L[l];
@@ -475,10 +480,20 @@ static double diag_nf(const OHier *H, int l, int i, int j, int k)
         for (int s = -1; s <= 1; s += 2) {
             int p[3] = {i, j, k};
             p[d] += s;
-            double h2 = L->h[d] * L->h[d];
-            if (p[d] < 0 || p[d] >= L->n[d]) a += 2.0 / h2;      /* u_c - (-u_c) */
-            else if (cidx(L, p[0], p[1], p[2]) >= 0) a += 1.0 / h2;
-            else a += (1.0 - 2.0 / 3.0) / h2;                   /* u_c - (2/3 u_c + ...) */
+            double h = L->h[d], h2 = h * h, g;
+            if (p[d] < 0 || p[d] >= L->n[d]) {
+                if (H->robin > 0.0) {
+                    double dist = H->robin;
+                    g = (1.0 / h - 1.0 / (2.0 * dist)) / (1.0 / h + 1.0 / (2.0 * dist));
+                } else {
+                    g = -1.0;
+                }
+            } else if (cidx(L, p[0], p[1], p[2]) >= 0) {
+                g = 0.0;
+            } else {
+                g = 2.0 / 3.0;
+            }
+            a += (1.0 - g) / h2;
         }
     return a;
 }
@@ -533,20 +548,34 @@ static void residual(OCtx *X, int l)
     }
 }
 
+/* Gauss-Seidel update of one cell of A_nf^l e = r (zero coarse data,
+ * homogeneous boundary data): with every other value fixed, the cell's value
+ * that makes its own residual vanish (Sec. 5.3, the smoothing of Alg. 3) */
+static void relax_point(const OHier *H, int l, int i, int j, int k, double *e, const double *r)
+{
+    double *u[OR_MAXL] = {0};
+    u[l] = e;
+    int64_t c = cidx(&H->L[l], i, j, k);
+    double Ae = apply_cell(H, l, i, j, k, u, NULL, 0, 0);
+    e[c] += (r[c] - Ae) / diag_nf(H, l, i, j, k);
+}
+
+void or_relax_point(const OHier *H, int l, int i, int j, int k, double *e, const double *r)
+{
+    if (cidx(&H->L[l], i, j, k) >= 0) relax_point(H, l, i, j, k, e, r);
+}
+
 /* Gauss-Seidel red-black on A_nf^l e = r with zero coarse data and homogeneous
  * boundary data; colour (i+j+k) mod 2 in level indices, even colour first */
 static void smooth(OCtx *X, int l, double *e, const double *r, int sweeps)
 {
     OHier *H = X->H;
     const OLev *L = &H->L[l];
-    double *u[OR_MAXL] = {0};
-    u[l] = e;
     for (int it = 0; it < sweeps; ++it)
         for (int colour = 0; colour < 2; ++colour) {
             FOR_CELLS(L, b, i, j, k, c) {
                 if (((i + j + k) & 1) != colour) continue;
-                double Ae = apply_cell(H, l, i, j, k, u, NULL, 0, 0);
-                e[c] += (r[c] - Ae) / diag_nf(H, l, i, j, k);
+                relax_point(H, l, i, j, k, e, r);
             }
         }
 }

@@ -73,6 +73,8 @@ def lib():
         L.or_solve.argtypes = [vp, vp, vp, vp, dbl, C.c_int, C.c_int, C.c_int, C.c_int, dbl,
                                C.POINTER(OStats)]
         L.or_residual.argtypes = [vp, vp, vp, vp]
+        L.or_relax_point.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp]
+        L.or_relax_point.restype = None
         L.or_deposit.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp, vp]
         L.or_deposit.restype = i64
         L.or_gather.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
@@ -245,6 +247,14 @@ class OracleHierarchy:
         uc = None if ucoarse is None else _f64(ucoarse)
         out = np.zeros(self.ncells(l))
         lib().or_apply_nf(self.h, l, _ptrs(arrs), None if uc is None else _ptr(uc), _ptr(out), int(inhom))
+        return out
+
+    def relax_point(self, l: int, i: int, j: int, k: int, e: np.ndarray, r: np.ndarray) -> np.ndarray:
+        """One Gauss-Seidel update (the smoother of Alg. 3, Sec. 5.3) of cell
+        (i, j, k) of level l for A_nf e = r with zero coarse data and
+        homogeneous boundary data; returns the updated copy of e."""
+        out = np.array(e, dtype=np.float64, copy=True)
+        lib().or_relax_point(self.h, l, i, j, k, _ptr(out), _ptr(_f64(r)))
         return out
 
     def residual(self, rho: Sequence[np.ndarray], phi: Sequence[np.ndarray]) -> List[np.ndarray]:
