@@ -334,6 +334,16 @@ amrmg_status amrmg_profile_enable(amrmg_ctx *ctx, uint32_t mask);
 amrmg_status amrmg_profile_read(amrmg_ctx *ctx, int32_t kclass, double *ms, int64_t *launches,
                                 double *bytes);
 
+/* The individual launches behind amrmg_profile_read, in launch order: for
+ * each of the first min(cap, *count) recorded launches of class kclass since
+ * the last enable, its device milliseconds ms[i] and algorithmic bytes
+ * bytes[i] (host arrays of cap entries; NULL with cap = 0 to query the
+ * count).  *count receives the number recorded (at most 65536 are kept per
+ * class; the totals of amrmg_profile_read count every launch).  Synchronises
+ * the stream. */
+amrmg_status amrmg_profile_launches(amrmg_ctx *ctx, int32_t kclass, double *ms, double *bytes, int64_t cap,
+                                    int64_t *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -178,17 +178,45 @@ class OracleHierarchy:
         return np.concatenate(out).astype(np.int64)
 
     def covered_mask(self, l: int) -> np.ndarray:
-        """True on cells of level l whose children are in level l+1."""
+        """True on cells of level l whose children are in level l+1: per box
+        of level l, the coarse footprints [lo/2, hi/2) of the level-(l+1)
+        boxes that meet it (fine boxes are whole blocks, so even-aligned)."""
         n = self.ncells(l)
-        if l + 1 >= self.nlev:
-            return np.zeros(n, dtype=bool)
-        ijk = self.cell_indices(l)
-        fb, _ = self.boxes(l + 1)
         m = np.zeros(n, dtype=bool)
-        for B in fb:
-            inside = np.all((2 * ijk >= B[:3]) & (2 * ijk < B[3:]), axis=1)
-            m |= inside
+        if l + 1 >= self.nlev:
+            return m
+        cb, coff = self.boxes(l)
+        fb, _ = self.boxes(l + 1)
+        flo, fhi = fb[:, :3] // 2, fb[:, 3:] // 2
+        for bi, B in enumerate(cb):
+            lo = np.maximum(flo, B[:3])
+            hi = np.minimum(fhi, B[3:])
+            hit = np.all(hi > lo, axis=1)
+            if not hit.any():
+                continue
+            ext = B[3:] - B[:3]
+            blk = np.zeros((ext[2], ext[1], ext[0]), dtype=bool)
+            for a, b in zip(lo[hit] - B[:3], hi[hit] - B[:3]):
+                blk[a[2]:b[2], a[1]:b[1], a[0]:b[0]] = True
+            m[coff[bi]:coff[bi + 1]] = blk.ravel()
         return m
+
+    def composite_rel_l2(self, a: Sequence[np.ndarray], b: Sequence[np.ndarray], ncomp: int = 1) -> float:
+        """Relative L2 difference of a from the reference b over the composite
+        cells (the uncovered cells of every level, Sec. 5.3), each cell
+        weighted by its volume h_x h_y h_z.  With ncomp > 1 the arrays are
+        per level and component (E[ncomp * l + d]) and the components are
+        summed."""
+        num = den = 0.0
+        for l in range(self.nlev):
+            unc = ~self.covered_mask(l)
+            vol = float(np.prod(self.spacing(l)))
+            for d in range(ncomp):
+                x = np.asarray(a[ncomp * l + d])[unc]
+                y = np.asarray(b[ncomp * l + d])[unc]
+                num += vol * float(np.sum((x - y) ** 2))
+                den += vol * float(np.sum(y ** 2))
+        return float(np.sqrt(num / den)) if den > 0 else float(np.sqrt(num))
 
     def zeros(self) -> List[np.ndarray]:
         return [np.zeros(self.ncells(l)) for l in range(self.nlev)]

@@ -36,7 +36,7 @@ EXPORTED = ["amrmg_default_params", "amrmg_create", "amrmg_destroy", "amrmg_last
             "amrmg_build_hierarchy", "amrmg_hierarchy_info", "amrmg_get_boxes", "amrmg_cf_faces", "amrmg_brick_tables",
             "amrmg_workspace_size", "amrmg_set_workspace", "amrmg_deposit", "amrmg_deposit_built", "amrmg_solve",
             "amrmg_gather", "amrmg_gather_built", "amrmg_residual", "amrmg_solve_batch", "amrmg_profile_enable",
-            "amrmg_profile_read", "amrmg_transform_particles", "amrmg_rescale_fields"]
+            "amrmg_profile_read", "amrmg_profile_launches", "amrmg_transform_particles", "amrmg_rescale_fields"]
 KCLASS = ["gsrb", "jacobi", "restrict", "prolong", "reflux", "cpart", "residual", "phi_update", "bottom",
           "efield", "avgdown", "deposit", "gather"]
 
@@ -103,6 +103,7 @@ def lib():
         L.amrmg_solve_batch.argtypes = [vp, i32, vp, vp, dbl, C.POINTER(amrmg_solve_stats)]
         L.amrmg_profile_enable.argtypes = [vp, C.c_uint32]
         L.amrmg_profile_read.argtypes = [vp, i32, vp, vp, vp]
+        L.amrmg_profile_launches.argtypes = [vp, i32, vp, vp, i64, vp]
         L.amrmg_transform_particles.argtypes = [vp, C.c_int, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.amrmg_rescale_fields.argtypes = [vp, dbl, vp, vp]
         _lib = L
@@ -306,6 +307,18 @@ def amrmg_profile_read(h, kclass):
     ms, n, b = C.c_double(), C.c_int64(), C.c_double()
     _check(lib().amrmg_profile_read(h, k, C.byref(ms), C.byref(n), C.byref(b)))
     return dict(ms=ms.value, launches=n.value, bytes=b.value)
+
+
+def amrmg_profile_launches(h, kclass):
+    """Per-launch (ms, bytes) lists of one kernel class since the last enable."""
+    import numpy as np
+    k = KCLASS.index(kclass) if isinstance(kclass, str) else int(kclass)
+    cnt = C.c_int64()
+    _check(lib().amrmg_profile_launches(h, k, None, None, 0, C.byref(cnt)))
+    ms = np.zeros(max(1, cnt.value))
+    by = np.zeros(max(1, cnt.value))
+    _check(lib().amrmg_profile_launches(h, k, ms.ctypes.data, by.ctypes.data, cnt.value, C.byref(cnt)))
+    return ms[:cnt.value], by[:cnt.value]
 
 
 # --- convenience wrapper ----------------------------------------------------

@@ -731,6 +731,9 @@ struct Prof {
     std::vector<Rec> recs;
     double tot_ms[AMRMG_K_NCLASS] = {}, tot_bytes[AMRMG_K_NCLASS] = {};
     int64_t tot_n[AMRMG_K_NCLASS] = {};
+    // per-launch (ms, bytes) of each class, the first kMaxKept launches
+    static constexpr size_t kMaxKept = 65536;
+    std::vector<std::pair<double, double>> kept[AMRMG_K_NCLASS];
     size_t pending = (size_t)-1;
     int pending_cls = -1;
 
@@ -767,6 +770,7 @@ struct Prof {
                 tot_ms[r.cls] += e;
                 tot_bytes[r.cls] += r.bytes;
                 tot_n[r.cls] += 1;
+                if (kept[r.cls].size() < kMaxKept) kept[r.cls].emplace_back((double)e, r.bytes);
             }
         }
         recs.clear();
@@ -777,7 +781,7 @@ struct Prof {
         mask = m;
         used = 0;
         recs.clear();
-        for (int c = 0; c < AMRMG_K_NCLASS; ++c) tot_ms[c] = tot_bytes[c] = 0.0, tot_n[c] = 0;
+        for (int c = 0; c < AMRMG_K_NCLASS; ++c) tot_ms[c] = tot_bytes[c] = 0.0, tot_n[c] = 0, kept[c].clear();
         if (m && pool.empty()) {
             pool.resize(1 << 12);
             for (auto &e : pool) (void)hipEventCreate(&e);
@@ -2264,5 +2268,22 @@ extern "C" amrmg_status amrmg_profile_read(amrmg_ctx *ctx, int32_t kclass, doubl
     if (ms) *ms = ctx->prof.tot_ms[kclass];
     if (launches) *launches = ctx->prof.tot_n[kclass];
     if (bytes) *bytes = ctx->prof.tot_bytes[kclass];
+    return AMRMG_OK;
+}
+
+extern "C" amrmg_status amrmg_profile_launches(amrmg_ctx *ctx, int32_t kclass, double *ms, double *bytes,
+                                               int64_t cap, int64_t *count)
+{
+    if (!ctx || !count) return fail(AMRMG_E_INVALID, "ctx and count must be set");
+    if (kclass < 0 || kclass >= AMRMG_K_NCLASS) return fail(AMRMG_E_INVALID, "bad kernel class");
+    if (cap < 0 || (cap > 0 && (!ms || !bytes))) return fail(AMRMG_E_INVALID, "cap > 0 needs ms and bytes");
+    HIP_TRY(hipStreamSynchronize(ctx->st));
+    ctx->prof.flush();
+    const auto &k = ctx->prof.kept[kclass];
+    *count = (int64_t)k.size();
+    for (int64_t i = 0; i < cap && i < (int64_t)k.size(); ++i) {
+        ms[i] = k[i].first;
+        bytes[i] = k[i].second;
+    }
     return AMRMG_OK;
 }

@@ -67,12 +67,7 @@ def test_eager_path_matches_oracle_and_graph_path(precision, tol_err, tmp_path):
 
     H, ophi = oracle_solution()
     assert len(eager) == H.nlev
-    num = den = 0.0
-    for l in range(H.nlev):
-        unc = ~H.covered_mask(l)
-        num += np.sum((eager[l][unc] - ophi[l][unc]) ** 2)
-        den += np.sum(ophi[l][unc] ** 2)
-    err = float(np.sqrt(num / den))
+    err = H.composite_rel_l2(eager, ophi)
     print("rel L2 vs oracle", err, flush=True)
     assert err <= tol_err
 

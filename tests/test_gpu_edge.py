@@ -34,12 +34,9 @@ def run(w, precision="fp64"):
 
 
 def composite_err(H, a, b):
-    num = den = 0.0
-    for l in range(H.nlev):
-        unc = ~H.covered_mask(l)
-        num += np.sum((a[l][unc] - b[l][unc]) ** 2)
-        den += np.sum(b[l][unc] ** 2)
-    return float(np.sqrt(num / den)) if den > 0 else float(np.sqrt(num))
+    """Volume-weighted relative L2 over the composite cells (absolute when
+    the reference vanishes)."""
+    return H.composite_rel_l2(a, b)
 
 
 def test_no_particles_with_dirichlet_data():

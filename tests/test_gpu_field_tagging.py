@@ -88,13 +88,7 @@ def test_solve_on_field_tagged_hierarchy(policy):
     print(st, flush=True)
     assert st["converged"]
     ophi, _, _ = H.solve(orho, tol=1e-11, max_iters=80, bottom_rtol=1e-14)
-    num = den = 0.0
-    for l in range(H.nlev):
-        unc = ~H.covered_mask(l)
-        g = phi[l].cpu().numpy()
-        num += np.sum((g[unc] - ophi[l][unc]) ** 2)
-        den += np.sum(ophi[l][unc] ** 2)
-    assert np.sqrt(num / den) <= 1e-8
+    assert H.composite_rel_l2([t.cpu().numpy() for t in phi], ophi) <= 1e-8
 
 
 def test_tagging_solve_that_cannot_converge():

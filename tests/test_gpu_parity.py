@@ -29,12 +29,8 @@ def np_list(ts):
 
 
 def rel_l2_composite(H, a, b):
-    num = den = 0.0
-    for l in range(H.nlev):
-        unc = ~H.covered_mask(l)
-        num += np.sum((a[l][unc] - b[l][unc]) ** 2)
-        den += np.sum(b[l][unc] ** 2)
-    return float(np.sqrt(num / den))
+    """Volume-weighted relative L2 over the composite cells."""
+    return H.composite_rel_l2(a, b)
 
 
 def make_ctx(w, precision="fp64", smoother="gsrb", **kw):
@@ -170,15 +166,18 @@ def test_composite_residual_operator(case):
         assert np.abs(r_gpu[l] - r_or[l]).max() <= 1e-13 * scale, l
 
 
+@pytest.mark.parametrize("solve_tol", ["tight", "workload"])
 @pytest.mark.parametrize("precision,tol_err", [("fp64", 1e-9), ("mixed", 1e-8)])
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_solve_matches_oracle(case, precision, tol_err):
-    print("case", case, precision, flush=True)
+def test_solve_matches_oracle(case, precision, tol_err, solve_tol):
+    """Solved to 1e-12, and to the workload's own tolerance (1e-8, or 1e-10
+    for the sphere), which the error gates must also meet."""
+    print("case", case, precision, solve_tol, flush=True)
     w = CASES[case]()
     H, orho, ophi, oE, ost = oracle_solution(w, case)
     ctx, (x, y, z, q) = make_ctx(w, precision=precision)
     rho, _ = ctx.deposit(x, y, z, q)
-    phi, E, st = ctx.solve(rho, tol=1e-12)
+    phi, E, st = ctx.solve(rho, tol=1e-12 if solve_tol == "tight" else w.tol)
     print(st, flush=True)
     assert st["converged"]
     err = rel_l2_composite(H, np_list(phi), ophi)
