@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamrmg.so")
-SOURCES = ["amrmg_kernels.hip", "amrmg_meta.hip", "amrmg_sort.hip", "amrmg_transform.hip", "amrmg_hier.cpp", "amrmg_api.cpp"]
+SOURCES = ["amrmg_kernels.hip", "amrmg_meta.hip", "amrmg_sort.hip", "amrmg_transform.hip", "amrmg_hier.cpp",
+           "amrmg_api.cpp", "amrmg_build.cpp", "amrmg_particles.cpp", "amrmg_solver.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
