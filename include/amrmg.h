@@ -247,6 +247,28 @@ amrmg_status amrmg_deposit_built(amrmg_ctx *ctx, double *const *rho, int64_t *n_
 amrmg_status amrmg_solve(amrmg_ctx *ctx, double *const *rho, double *const *phi, double *const *E,
                          double tol, amrmg_solve_stats *stats);
 
+/* For callers that cannot allocate device memory (code that runs under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * solve of amrmg_solve, same arguments, same results, that allocates no
+ * device or pinned host memory and instantiates no graph.  Its workspace is
+ * carved from a file-scope device array of AMRMG_NOALLOC_SCRATCH_BYTES
+ * (128 MiB) that the library's code object holds on every GPU it runs on
+ * until the process ends; the array's address on a device is looked up once,
+ * when the first context on that device is created.  The cycle is launched
+ * kernel by kernel (no graph replay), with the sweep shapes amrmg_solve has
+ * tuned so far or the size rule.  The hierarchy must have been built
+ * (amrmg_build_hierarchy allocates); a hierarchy whose workspace
+ * (amrmg_workspace_size) exceeds the array gives AMRMG_E_OOM with phi, E
+ * and stats untouched.  Every call on a GPU shares that GPU's array and
+ * leaves its contents behind (nothing in it is read before the call writes
+ * it): calls that overlap in time on one GPU -- contexts on different
+ * streams driven from different threads -- race and must not be made.
+ * AMRMG_E_HIP when the array's address could not be looked up on the
+ * context's device.  Synchronises. */
+#define AMRMG_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+amrmg_status amrmg_solve_noalloc(amrmg_ctx *ctx, double *const *rho, double *const *phi, double *const *E,
+                                 double tol, amrmg_solve_stats *stats);
+
 /* Interpolate E to particles with the deposit's CIC weights, on the finest
  * level whose boxes hold all 8 stencil cells.  Ex, Ey, Ez device [n];
  * particles outside the domain get 0. */

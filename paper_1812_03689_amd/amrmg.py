@@ -31,10 +31,12 @@ AMRMG_BOTTOM_AUTO, AMRMG_BOTTOM_CG = 0, 1
 AMRMG_TAG_CHARGE, AMRMG_TAG_POTENTIAL, AMRMG_TAG_EFIELD = 0, 1, 2
 TAG_POLICIES = {"charge": AMRMG_TAG_CHARGE, "potential": AMRMG_TAG_POTENTIAL, "efield": AMRMG_TAG_EFIELD}
 AMRMG_MAX_LEVELS = 8
+AMRMG_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 EXPORTED = ["amrmg_default_params", "amrmg_create", "amrmg_destroy", "amrmg_last_error",
             "amrmg_build_hierarchy", "amrmg_hierarchy_info", "amrmg_get_boxes", "amrmg_cf_faces", "amrmg_brick_tables",
             "amrmg_workspace_size", "amrmg_set_workspace", "amrmg_deposit", "amrmg_deposit_built", "amrmg_solve",
+            "amrmg_solve_noalloc",
             "amrmg_gather", "amrmg_gather_built", "amrmg_residual", "amrmg_solve_batch", "amrmg_profile_enable",
             "amrmg_profile_read", "amrmg_profile_launches", "amrmg_transform_particles", "amrmg_rescale_fields"]
 KCLASS = ["gsrb", "jacobi", "restrict", "prolong", "reflux", "cpart", "residual", "phi_update", "bottom",
@@ -97,6 +99,7 @@ def lib():
         L.amrmg_deposit.argtypes = [vp, C.c_int, vp, vp, vp, vp, i64, vp, vp]
         L.amrmg_deposit_built.argtypes = [vp, vp, vp]
         L.amrmg_solve.argtypes = [vp, vp, vp, vp, dbl, C.POINTER(amrmg_solve_stats)]
+        L.amrmg_solve_noalloc.argtypes = [vp, vp, vp, vp, dbl, C.POINTER(amrmg_solve_stats)]
         L.amrmg_gather.argtypes = [vp, C.c_int, vp, vp, vp, i64, vp, vp, vp, vp]
         L.amrmg_gather_built.argtypes = [vp, vp, vp, vp, vp]
         L.amrmg_residual.argtypes = [vp, vp, vp, vp]
@@ -247,6 +250,19 @@ def amrmg_solve(h, rho: Sequence, phi: Sequence, E: Optional[Sequence], tol: flo
     allow = (AMRMG_E_NOT_CONVERGED,) if allow_not_converged else ()
     rc = _check(lib().amrmg_solve(h, _ptrs(rho), _ptrs(phi), _ptrs(E) if E is not None else None, float(tol),
                                   C.byref(st)), allow)
+    d = st.as_dict()
+    d["status"] = rc
+    return d
+
+
+def amrmg_solve_noalloc(h, rho: Sequence, phi: Sequence, E: Optional[Sequence], tol: float,
+                        allow_not_converged=True):
+    """amrmg_solve with its workspace in the library's static device array
+    (no device allocation)."""
+    st = amrmg_solve_stats()
+    allow = (AMRMG_E_NOT_CONVERGED,) if allow_not_converged else ()
+    rc = _check(lib().amrmg_solve_noalloc(h, _ptrs(rho), _ptrs(phi), _ptrs(E) if E is not None else None,
+                                          float(tol), C.byref(st)), allow)
     d = st.as_dict()
     d["status"] = rc
     return d

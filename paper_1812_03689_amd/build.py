@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamrmg.so")
 SOURCES = ["amrmg_kernels.hip", "amrmg_meta.hip", "amrmg_sort.hip", "amrmg_transform.hip", "amrmg_hier.cpp",
-           "amrmg_api.cpp", "amrmg_build.cpp", "amrmg_particles.cpp", "amrmg_solver.cpp"]
+           "amrmg_api.cpp", "amrmg_build.cpp", "amrmg_particles.cpp", "amrmg_solver.cpp",
+           "amrmg_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

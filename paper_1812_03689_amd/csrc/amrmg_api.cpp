@@ -98,6 +98,20 @@ extern "C" amrmg_status amrmg_create(const amrmg_params *p, void *hip_stream, am
     if (p->n_monopoles > 0) c->mono.assign(p->monopoles, p->monopoles + 4 * p->n_monopoles);
     c->P.monopoles = nullptr;
     c->st = (hipStream_t)hip_stream;
+    // the device of the stream: the no-allocation solve's scratch array is
+    // looked up there (once per device, with that device current) and its
+    // timing events are made there; a failure only disables that solve
+    int dev = -1, cur = -1;
+    hipError_t ed = c->st ? hipStreamGetDevice(c->st, &dev) : hipGetDevice(&dev);
+    if (ed == hipSuccess && dev >= 0 && hipGetDevice(&cur) == hipSuccess) {
+        c->device = dev;
+        (void)noalloc_setup(dev);
+        if (cur == dev || hipSetDevice(dev) == hipSuccess) {
+            for (auto &e : c->ev_solve)
+                if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+            if (cur != dev) (void)hipSetDevice(cur);
+        }
+    }
     *out = c;
     return AMRMG_OK;
 }

@@ -460,21 +460,47 @@ static amrmg_status iterate(DevState &D, Driver<T> &drv, hipStream_t st, int nr,
 }
 
 // run a solve on a DevState whose pointer tables are set; per-problem stats
+// Events that time a solve: two made for it (and destroyed with it), or the
+// caller's pair when it may make none.
+struct SolveTimers {
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool own = false;
+    ~SolveTimers()
+    {
+        if (own)
+            for (auto e : ev)
+                if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// noalloc: the solve may allocate nothing -- no sweep tuning (the tuned or
+// the size rule's threads per brick), no graph (eager launches), the events
+// of ev_fixed
 template <class T>
 static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, double tol,
-                              std::vector<amrmg_solve_stats> &stats, bool want_E, Prof *prof)
+                              std::vector<amrmg_solve_stats> &stats, bool want_E, Prof *prof,
+                              const hipEvent_t *ev_fixed = nullptr)
 {
     const Meta &m = D.meta;
     Driver<T> drv(D, st, o, prof);
     const int nr = (int)D.range_prob.size();
     const int np = (int)m.prob_ent.size();
-    hipEvent_t ev0, ev1;
-    HIP_TRY(hipEventCreate(&ev0));
-    HIP_TRY(hipEventCreate(&ev1));
+    const bool noalloc = ev_fixed != nullptr;
+    SolveTimers evs;
+    if (noalloc) {
+        evs.ev[0] = ev_fixed[0];
+        evs.ev[1] = ev_fixed[1];
+    } else {
+        evs.own = true;
+        HIP_TRY(hipEventCreate(&evs.ev[0]));
+        HIP_TRY(hipEventCreate(&evs.ev[1]));
+    }
+    hipEvent_t ev0 = evs.ev[0], ev1 = evs.ev[1];
+    const bool graphs = g_use_graphs && !noalloc;
     // the iteration's graph is captured and instantiated first, while the
     // stream may still be busy with the caller's earlier work (the deposit)
-    if (o.smoother == AMRMG_GSRB) ST_TRY(drv.tune());
-    if (g_use_graphs && !prof && o.max_iters > 0) ST_TRY(ensure_graph<T>(D, nr, o));
+    if (o.smoother == AMRMG_GSRB && !noalloc) ST_TRY(drv.tune());
+    if (graphs && !prof && o.max_iters > 0) ST_TRY(ensure_graph<T>(D, nr, o));
     HIP_TRY(hipMemsetAsync(D.cgit, 0, 64, st));  // CG iteration count and the norm sequence counter
     D.seq = 0;
     *(volatile unsigned *)D.h_seq = 0;
@@ -489,7 +515,7 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
     // the initial guess already meets the tolerance it only refines phi, and
     // the norms reported are those after it
     const bool first_queued = o.max_iters > 0;
-    if (first_queued) ST_TRY(iterate<T>(D, drv, st, nr, o, g_use_graphs));
+    if (first_queued) ST_TRY(iterate<T>(D, drv, st, nr, o, graphs));
     // wait for publication number want in host memory (no stream
     // synchronisation); after a second without it, synchronise and look again
     auto wait_pub = [&](unsigned want) -> amrmg_status {
@@ -541,7 +567,7 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
         if (!all) all = check(1);
     }
     while (!all && it < o.max_iters) {
-        ST_TRY(iterate<T>(D, drv, st, nr, o, g_use_graphs));
+        ST_TRY(iterate<T>(D, drv, st, nr, o, graphs));
         ST_TRY(wait_pub(++D.seq));
         rn.assign(D.h_pub, D.h_pub + nr);
         ++it;
@@ -569,8 +595,6 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
     HIP_TRY(hipGetLastError());
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
     int cgmax = 0;
     HIP_TRY(hipMemcpy(&cgmax, D.cgit, sizeof(int), hipMemcpyDeviceToHost));
     stats.assign(np, amrmg_solve_stats{});
@@ -619,8 +643,10 @@ static amrmg_status set_tables(DevState &D, hipStream_t st)
     return AMRMG_OK;
 }
 
-extern "C" amrmg_status amrmg_solve(amrmg_ctx *ctx, double *const *rho, double *const *phi, double *const *E,
-                                    double tol, amrmg_solve_stats *stats)
+// check the arguments of a solve and record the caller's level arrays in the
+// pointer tables of the context's DevState
+static amrmg_status bind_solve_levels(amrmg_ctx *ctx, double *const *rho, double *const *phi, double *const *E,
+                                      double tol)
 {
     if (!ctx) return fail(AMRMG_E_INVALID, "ctx is NULL");
     if (!ctx->built) return fail(AMRMG_E_STATE, "hierarchy not built");
@@ -642,16 +668,52 @@ extern "C" amrmg_status amrmg_solve(amrmg_ctx *ctx, double *const *rho, double *
             D.h_E[3 * ei + d] = E ? E[3 * l + d] : nullptr;
         }
     }
-    ST_TRY(ensure_ws(D, ctx->P.precision, ctx->user_ws, ctx->user_ws_bytes));
+    return AMRMG_OK;
+}
+
+static amrmg_status solve_bound(amrmg_ctx *ctx, bool want_E, double tol, amrmg_solve_stats *stats,
+                                const hipEvent_t *ev_fixed)
+{
+    DevState &D = ctx->ds;
     ST_TRY(set_tables(D, ctx->st));
     std::vector<amrmg_solve_stats> sv;
     SolveOpts o = opts_of(ctx->P);
     Prof *pf = ctx->prof.mask ? &ctx->prof : nullptr;
-    amrmg_status rc = ctx->P.precision == AMRMG_MIXED ? run_solve<float>(D, ctx->st, o, tol, sv, E != nullptr, pf)
-                                                      : run_solve<double>(D, ctx->st, o, tol, sv, E != nullptr, pf);
+    amrmg_status rc = ctx->P.precision == AMRMG_MIXED
+                          ? run_solve<float>(D, ctx->st, o, tol, sv, want_E, pf, ev_fixed)
+                          : run_solve<double>(D, ctx->st, o, tol, sv, want_E, pf, ev_fixed);
     if (stats && !sv.empty()) *stats = sv[0];
     if (rc == AMRMG_E_NOT_CONVERGED) (void)fail(rc, "not converged within max_iters");
     return rc;
+}
+
+extern "C" amrmg_status amrmg_solve(amrmg_ctx *ctx, double *const *rho, double *const *phi, double *const *E,
+                                    double tol, amrmg_solve_stats *stats)
+{
+    ST_TRY(bind_solve_levels(ctx, rho, phi, E, tol));
+    ST_TRY(ensure_ws(ctx->ds, ctx->P.precision, ctx->user_ws, ctx->user_ws_bytes));
+    return solve_bound(ctx, E != nullptr, tol, stats, nullptr);
+}
+
+static_assert(NOALLOC_SCRATCH_BYTES == AMRMG_NOALLOC_SCRATCH_BYTES, "header and array sizes differ");
+
+extern "C" amrmg_status amrmg_solve_noalloc(amrmg_ctx *ctx, double *const *rho, double *const *phi,
+                                            double *const *E, double tol, amrmg_solve_stats *stats)
+{
+    ST_TRY(bind_solve_levels(ctx, rho, phi, E, tol));
+    hipError_t se = hipSuccess;
+    void *scr = noalloc_scratch(ctx->device, &se);
+    if (!scr)
+        return fail(AMRMG_E_HIP, "the no-allocation scratch array has no address on device " +
+                                     std::to_string(ctx->device) + ": " + hipGetErrorString(se));
+    if (!ctx->ev_solve[0] || !ctx->ev_solve[1])
+        return fail(AMRMG_E_HIP, "the context's timing events were not created");
+    const size_t need = ws_need(ctx->ds, ctx->P.precision);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(AMRMG_E_OOM, "the hierarchy needs " + std::to_string(need) + " bytes of workspace; "
+                                 "amrmg_solve_noalloc has " + std::to_string(NOALLOC_SCRATCH_BYTES));
+    ST_TRY(ensure_ws(ctx->ds, ctx->P.precision, scr, NOALLOC_SCRATCH_BYTES));
+    return solve_bound(ctx, E != nullptr, tol, stats, ctx->ev_solve);
 }
 
 extern "C" amrmg_status amrmg_residual(amrmg_ctx *ctx, double *const *rho, double *const *phi, double *const *r)

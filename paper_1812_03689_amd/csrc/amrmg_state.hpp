@@ -16,6 +16,7 @@
 #include "amrmg.h"
 #include "amrmg_hier.hpp"
 #include "amrmg_kernels.hpp"
+#include "amrmg_noalloc.hpp"
 
 using namespace amrmg;
 
@@ -336,7 +337,16 @@ struct amrmg_ctx {
     std::vector<int> batch_gen;
     DevState *batch = nullptr;
     Prof prof;
-    ~amrmg_ctx() { delete batch; }
+    // the device of the context's stream, and two events made on it at
+    // creation for the timing of amrmg_solve_noalloc (which makes none)
+    int device = -1;
+    hipEvent_t ev_solve[2] = {nullptr, nullptr};
+    ~amrmg_ctx()
+    {
+        delete batch;
+        for (auto &e : ev_solve)
+            if (e) (void)hipEventDestroy(e);
+    }
 };
 
 struct SolveOpts {
