@@ -115,6 +115,48 @@ def write_traffic(args):
     print(open(out_md).read())
 
 
+def write_kernel_stats(args):
+    """Turn the kernel statistics of a rocprofv3 --kernel-trace --stats run of
+    this script into the summary of a workload: per-kernel totals, and the
+    kernel classes as bench.py times them."""
+    import csv
+    import re
+    tag, stats_csv, out_md = args.write_kernel_stats
+    if stats_csv.endswith(".db"):  # rocprofv3's default SQLite output: aggregate its kernels view (ns)
+        import sqlite3
+        con = sqlite3.connect(stats_csv)
+        rows = [{"Name": n, "Calls": str(c), "TotalDurationNs": str(t), "AverageNs": str(a)}
+                for n, c, t, a in con.execute("select name, count(*), sum(duration), avg(duration) from kernels "
+                                              "group by name")]
+        con.close()
+    else:
+        rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    with open(out_md, "w") as f:
+        f.write(f"# rocprofv3 kernel statistics: bench.py, workload {tag}\n\n")
+        f.write("Command (from the repository root on the GPU box, `cd /tmp && export TMPDIR=/tmp` first):\n\n")
+        f.write("```\n" + args.traffic_cmd.replace(";", "\n") + "\n```\n\n")
+        f.write(f"- kernel source sha256: `{kernel_source_hash()}`\n\n")
+        f.write("Per-kernel totals over the whole run (durations in microseconds):\n\n")
+        f.write("| kernel | calls | total us | avg us | % |\n|---|---|---|---|---|\n")
+        for r in rows[:30]:
+            name = r["Name"].replace("amrmg::", "")
+            name = re.sub(r"\(.*", "", name)[:70]
+            f.write(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
+                    f"{float(r['AverageNs']) / 1e3:.3f} | {100.0 * float(r['TotalDurationNs']) / tot:.2f} |\n")
+        f.write("\nKernel classes as bench.py times them (FP32 cycle kernels, all levels):\n\n")
+        f.write("| class | kernels | calls | total us | avg us per launch |\n|---|---|---|---|---|\n")
+        for kc, rx in CLASS_KERNELS.items():
+            pat = re.compile(rx)
+            sel = [r for r in rows if pat.search(r["Name"])]
+            n = sum(int(r["Calls"]) for r in sel)
+            t = sum(float(r["TotalDurationNs"]) for r in sel) / 1e3
+            if n:
+                f.write(f"| {kc} | `{rx}` | {n} | {t:.1f} | {t / n:.3f} |\n")
+    print(open(out_md).read())
+
+
 def workload_for(cfg):
     from paper_1812_03689_amd import workloads as W
     return {1: W.config1, 2: W.config2, 3: W.config3, 4: W.config4}[cfg]()
@@ -531,10 +573,15 @@ def main():
                     help="only warmup + steps of the workload (for profilers), then the calibration copy")
     ap.add_argument("--write-traffic", nargs=5, metavar=("CLASS", "TAG", "FETCH_CSV", "WRITE_CSV", "OUT_MD"),
                     help="write the traffic summary of a kernel class from two rocprofv3 counter CSVs")
+    ap.add_argument("--write-kernel-stats", nargs=3, metavar=("TAG", "STATS_CSV", "OUT_MD"),
+                    help="write the kernel statistics summary of a workload from a rocprofv3 --stats CSV")
     ap.add_argument("--traffic-cmd", default="", help="the profiling commands, recorded in the summary")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(args)
+        return
+    if args.write_kernel_stats:
+        write_kernel_stats(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is not built.",

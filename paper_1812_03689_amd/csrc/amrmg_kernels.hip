@@ -672,13 +672,6 @@ struct SrcProl {
     }
 };
 
-// a brick's cells in its LDS tile, as face_sum reads them
-template <class T>
-struct TileAcc {
-    const T *tile;
-    __device__ double operator()(int, int c) const { return (double)tile[tix(c & 7, (c >> 3) & 7, c >> 6)]; }
-};
-
 // Brick-hybrid Gauss-Seidel sweep: red then black over the cells of one
 // brick in LDS, with the halo taken from the previous sweep (Gauss-Seidel
 // inside a brick, Jacobi between bricks, as a parallel Gauss-Seidel works
@@ -690,92 +683,214 @@ struct TileAcc {
 // 16 the fine sums of the result on the brick's coarse-fine faces into ffs.
 enum { HG_ZERO = 1, HG_PROL = 2, HG_CPIN = 4, HG_PHI = 8, HG_FFS = 16 };
 
-// threads per brick of the sweep: two wavefronts on large levels, so that 16
-// bricks' workgroups fit a CU at once and more loads are in flight (the
-// sweep is bandwidth-bound there); four on levels whose bricks all fit the
-// chip at once, where a workgroup's latency is the launch's (fewer cells
-// per thread, shorter chains)
-constexpr int BT = 128;
-constexpr int BT_SMALL = 256;
-constexpr int HGS_SMALL_LEVEL = 4096;  // bricks
+// The sweep runs one wavefront per brick.  Lane (y, z) = (lane & 7, lane >> 3)
+// owns the brick's x-row (y, z): its 8 cells, their right-hand sides and, for
+// x = 0 and x = 7, the x halo slots stay in registers, so x-neighbours need no
+// LDS.  The rows of the brick and the y and z halo rows sit in LDS, row
+// (y', z') for y', z' in -1..8 at rows[((y' + 1) + 10 (z' + 1)) * 9]: rows are
+// 9 words apart, so the 64 lanes reading the same x of their neighbouring rows
+// fall in different banks.  Row r of the brick starts at cell 8 r of its slab,
+// so the global row loads and stores are whole coalesced vectors.  A
+// workgroup holds BPW bricks (one per wavefront); the bricks per workgroup are
+// tuned.
+constexpr int RW = 10, RS = 9;
+__device__ __forceinline__ int rrow(int y, int z) { return ((y + 1) + RW * (z + 1)) * RS; }
 
-template <class T, int MODE, int NT>
-__global__ void __launch_bounds__(NT) k_hgs(DevMeta M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
-                                            double *phib, double *ffs)
+template <class T>
+struct Row8;
+template <>
+struct Row8<float> {
+    static __device__ __forceinline__ void load(const float *p, float (&v)[8])
+    {
+        const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 4);
+        v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+    }
+    static __device__ __forceinline__ void store(float *p, const float (&v)[8])
+    {
+        *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
+        *(float4 *)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+    }
+};
+template <>
+struct Row8<double> {
+    static __device__ __forceinline__ void load(const double *p, double (&v)[8])
+    {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double2 a = *(const double2 *)(p + 2 * i);
+            v[2 * i] = a.x, v[2 * i + 1] = a.y;
+        }
+    }
+    static __device__ __forceinline__ void store(double *p, const double (&v)[8])
+    {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) *(double2 *)(p + 2 * i) = make_double2(v[2 * i], v[2 * i + 1]);
+    }
+};
+
+// face_sum of a brick held in the row layout with zero coarse parts: over the
+// four fine cells of coarse cell m of face f, u_f/3 + u_in/5 (u_in the cell
+// further inside along the face normal)
+template <class T>
+__device__ __forceinline__ double row_face_sum(const T *rows, int f, int m)
 {
-    __shared__ T tile[TE * TE * TE];  // arithmetic in the cycle's precision T
-    __shared__ T alpha[6];
-    constexpr int PER = 256 / NT;  // cells of each colour per thread
-    int b = b0 + xcd_remap(blockIdx.x, nb);
-    int lev = M.org[b].w;
-    LevelConst L = M.lc[lev];
-    int cyz[PER], cx[2][PER];  // y + 8 z, and x of the colour-0 / colour-1 cell (brick origins are even)
-    T rv[2][PER];
-    const T ih2[3] = {(T)L.ih2[0], (T)L.ih2[1], (T)L.ih2[2]};
+    const int d = f >> 1, at = (f & 1) ? 7 : 0, in = (f & 1) ? 6 : 1;
+    double sum = 0.0;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        int t = threadIdx.x + NT * j;
-        int z = t >> 5, y = (t >> 2) & 7, xx = (t & 3) << 1;
-        cyz[j] = y + 8 * z;
-        cx[0][j] = xx + ((y + z) & 1);
-        cx[1][j] = xx + (((y + z) & 1) ^ 1);
-#pragma unroll
-        for (int k = 0; k < 2; ++k) rv[k][j] = r[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]];
+    for (int q = 0; q < 4; ++q) {
+        const int u = 2 * (m & 3) + (q & 1), v = 2 * (m >> 2) + (q >> 1);
+        // (x, y, z) of the face cell and of the cell inside, for the normal d
+        // with u, v along the two other axes in x < y < z order
+        const int x0 = d == 0 ? at : u, y0 = d == 1 ? at : (d == 0 ? u : v), z0 = d == 2 ? at : v;
+        const int x1 = d == 0 ? in : u, y1 = d == 1 ? in : (d == 0 ? u : v), z1 = d == 2 ? in : v;
+        sum += (1.0 / 3.0) * (double)rows[rrow(y0, z0) + x0] + 0.2 * (double)rows[rrow(y1, z1) + x1];
     }
+    return sum;
+}
+
+// parent cell of local cell (x, y, z) of a brick whose parent entry is p
+// (parent brick << 3 | octant), as a cell index of the parent's slab
+__device__ __forceinline__ size_t parent_cell(int p, int x, int y, int z)
+{
+    const int oc = p & 7;
+    return (size_t)(p >> 3) * BRICK_CELLS + ((oc & 1) * 4 + (x >> 1)) + 8 * (((oc >> 1) & 1) * 4 + (y >> 1)) +
+           64 * ((oc >> 2) * 4 + (z >> 1));
+}
+
+template <class T, int MODE, int BPW>
+__global__ void __launch_bounds__(64 * BPW) k_hgs(DevMeta M, int b0, int nb, const T *ein, T *eout, const T *r,
+                                                  T *cp, double *phib, double *ffs)
+{
+    __shared__ T rows_all[BPW][RW * RW * RS];
+    // the wavefront's brick, wavefront-uniform (so its table entries come
+    // through scalar loads and the face kinds branch on the scalar unit)
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int k0 = xcd_remap(blockIdx.x, (nb + BPW - 1) / BPW) * BPW + w;
+    const bool active = k0 < nb;  // the last workgroup may hold fewer bricks
+    const int b = __builtin_amdgcn_readfirstlane(b0 + (active ? k0 : nb - 1));
+    T *rows = rows_all[w];
+    const int y = lane & 7, z = lane >> 3;
+    // face kinds: 0 a brick of the level, 1 the physical boundary (ghost
+    // abnd u_c), 2 coarse-fine (ghost 2/3 u_c + cp - u_in/5)
+    int nbf[6], kind[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        nbf[f] = M.nbr[b * 6 + f];
+        kind[f] = nbf[f] >= 0 ? 0 : ((-1 - nbf[f]) < M.nbc ? 1 : 2);
+    }
+    // the value of cell c of brick bb as this sweep starts from it (input,
+    // plus the injected parent correction with the fused prolongation)
+    auto src = [&](int bb, int c) -> T {
+        if (MODE & HG_ZERO) return (T)0;
+        double v = (double)ein[(size_t)bb * BRICK_CELLS + c];
+        if (MODE & HG_PROL) v += (double)ein[parent_cell(M.par[bb], c & 7, (c >> 3) & 7, c >> 6)];
+        return (T)v;
+    };
+    // halo slot of face f at face-local cell fl (first transverse axis
+    // fastest): the neighbour's value, 0 on the boundary (homogeneous cycle),
+    // or the coarse part of the coarse-fine ghost
+    auto slot = [&](int f, int fl) -> T {
+        const int d = f >> 1, md = (f & 1) ? 0 : 7;
+        if (kind[f] == 0) {
+            const int u = fl & 7, v = fl >> 3;
+            const int c = d == 0 ? md + 8 * u + 64 * v : (d == 1 ? u + 8 * md + 64 * v : u + 8 * v + 64 * md);
+            return src(nbf[f], c);
+        }
+        if (kind[f] == 1 || (MODE & HG_ZERO)) return (T)0;
+        const size_t cf = (size_t)(-1 - nbf[f] - M.nbc);
+        if (MODE & HG_CPIN) return (T)CpInline<T>{&M, ein, active ? cp : nullptr}(cf, fl);
+        return cp ? cp[cf * 64 + fl] : (T)0;
+    };
+    // every load first: right-hand sides, input, halo slots
+    const size_t rb = (size_t)b * BRICK_CELLS + 8 * lane;
+    T rr[8], er[8], hs[6];
+    Row8<T>::load(r + rb, rr);
     if (MODE & HG_ZERO) {
-        stage_tile<SrcZ, true, CpNone, NT, T>(M, b, SrcZ{}, CpNone{}, false, tile, alpha);
-    } else if (MODE & HG_PROL) {
-        if (MODE & HG_CPIN)
-            stage_tile<SrcProl<T>, false, CpInline<T>, NT, T>(M, b, SrcProl<T>{ein, M.par},
-                                                              CpInline<T>{&M, ein, cp}, false, tile, alpha);
-        else
-            stage_tile<SrcProl<T>, false, CpArr<T>, NT, T>(M, b, SrcProl<T>{ein, M.par}, CpArr<T>{cp}, false, tile,
-                                                           alpha);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) er[i] = (T)0;
     } else {
-        stage_tile<SrcB<T>, false, CpArr<T>, NT, T>(M, b, SrcB<T>{ein}, CpArr<T>{cp}, false, tile, alpha);
+        Row8<T>::load(ein + rb, er);
     }
-    T v[2][PER];
+    if (MODE & HG_PROL) {
+        const size_t pc = parent_cell(M.par[b], 0, y, z);
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < 4; ++k) {
+            const T pv = ein[pc + k];
+            er[2 * k] = (T)((double)er[2 * k] + (double)pv);
+            er[2 * k + 1] = (T)((double)er[2 * k + 1] + (double)pv);
+        }
+    }
 #pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            int x = cx[k][j], y = cyz[j] & 7, z = cyz[j] >> 3;
-            T num = rv[k][j], den = (T)0;
+    for (int f = 0; f < 6; ++f) hs[f] = slot(f, lane);
+    const LevelConst L = M.lc[M.org[b].w];
+    const T ih2x = (T)L.ih2[0], ih2y = (T)L.ih2[1], ih2z = (T)L.ih2[2];
+    const int rym = rrow(y - 1, z), ryp = rrow(y + 1, z), rzm = rrow(y, z - 1), rzp = rrow(y, z + 1), rme = rrow(y, z);
 #pragma unroll
-            for (int d = 0; d < 3; ++d)
+    for (int i = 0; i < 8; ++i) rows[rme + i] = er[i];
+    // y halo rows: face-local cell (x, z); z halo rows: (x, y)
+    rows[rrow(-1, lane >> 3) + (lane & 7)] = hs[2];
+    rows[rrow(8, lane >> 3) + (lane & 7)] = hs[3];
+    rows[rrow(lane >> 3, -1) + (lane & 7)] = hs[4];
+    rows[rrow(lane >> 3, 8) + (lane & 7)] = hs[5];
+    const T hxm = hs[0], hxp = hs[1];
+    // ghost coefficients a of the faces, and per row the weights that fold a
+    // coarse-fine ghost's -u_in/5 into the neighbour inside
+    const T cf5 = (T)0.2;
+    T ag[6];
 #pragma unroll
-                for (int s = -1; s <= 1; s += 2) {
-                    T a, bv;
-                    tile_ab(tile, alpha, x, y, z, d, s, a, bv);
-                    num += ih2[d] * bv;
-                    den += ih2[d] * ((T)1 - a);
-                }
-            v[k][j] = num / den;
-            tile[tix(x, y, z)] = v[k][j];
+    for (int f = 0; f < 6; ++f) ag[f] = kind[f] == 1 ? (T)L.abnd[f >> 1] : (kind[f] == 2 ? (T)(2.0 / 3.0) : (T)0);
+    const T aym = y == 0 ? ag[2] : (T)0, ayp = y == 7 ? ag[3] : (T)0;
+    const T azm = z == 0 ? ag[4] : (T)0, azp = z == 7 ? ag[5] : (T)0;
+    const T wyp = (y == 0 && kind[2] == 2) ? (T)1 - cf5 : (T)1, wym = (y == 7 && kind[3] == 2) ? (T)1 - cf5 : (T)1;
+    const T wzp = (z == 0 && kind[4] == 2) ? (T)1 - cf5 : (T)1, wzm = (z == 7 && kind[5] == 2) ? (T)1 - cf5 : (T)1;
+    const T wxp0 = kind[0] == 2 ? (T)1 - cf5 : (T)1, wxm7 = kind[1] == 2 ? (T)1 - cf5 : (T)1;
+    const T den = ih2y * ((T)2 - aym - ayp) + ih2z * ((T)2 - azm - azp) + (T)2 * ih2x;
+    const T inv_mid = (T)1 / den, inv_x0 = (T)1 / (den - ih2x * ag[0]), inv_x7 = (T)1 / (den - ih2x * ag[1]);
+    __syncthreads();
+    // red (colour 0) then black: cell x of row (y, z) has colour (x + y + z)
+    // & 1.  Every lane evaluates all 8 cells of its row and keeps the results
+    // of the pass's colour, so the row's registers are indexed only by
+    // compile-time constants (a lane-dependent choice between two of them
+    // would be turned into an indexed access to private memory).
+    const int q = (y + z) & 1;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        T nv[8];
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const T xm = x == 0 ? hxm : er[x - 1];
+            const T xp = x == 7 ? hxp : er[x + 1];
+            const T wxm = x == 7 ? wxm7 : (T)1, wxp = x == 0 ? wxp0 : (T)1;
+            const T inv = x == 0 ? inv_x0 : (x == 7 ? inv_x7 : inv_mid);
+            const T num = rr[x] + ih2x * (wxm * xm + wxp * xp) +
+                          ih2y * (wym * rows[rym + x] + wyp * rows[ryp + x]) +
+                          ih2z * (wzm * rows[rzm + x] + wzp * rows[rzp + x]);
+            nv[x] = num * inv;
+        }
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const bool mine = ((x + q + c) & 1) == 0;
+            er[x] = mine ? nv[x] : er[x];
+            if (mine) rows[rme + x] = nv[x];
         }
         __syncthreads();
     }
-#pragma unroll
-    for (int j = 0; j < PER; ++j)
-#pragma unroll
-        for (int k = 0; k < 2; ++k) eout[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]] = v[k][j];
+    if (!active) return;
+    Row8<T>::store(eout + rb, er);
     if ((MODE & HG_PHI) && L.amr >= 0) {
+        double ph[8];
+        Row8<double>::load(phib + rb, ph);
 #pragma unroll
-        for (int j = 0; j < PER; ++j)
-#pragma unroll
-            for (int k = 0; k < 2; ++k) phib[(size_t)b * BRICK_CELLS + cx[k][j] + 8 * cyz[j]] += (double)v[k][j];
+        for (int i = 0; i < 8; ++i) ph[i] += (double)er[i];
+        Row8<double>::store(phib + rb, ph);
     }
     // fine sums of the new e on the brick's coarse-fine faces (the coarse
     // correction, and so the ghosts' coarse parts, are zero at the
     // restriction that reads them)
     if (MODE & HG_FFS) {
-        for (int t = threadIdx.x; t < 96; t += NT) {
+        for (int t = lane; t < 96; t += 64) {
             const int f = t >> 4;
-            if (alpha[f] > (T)0) {
-                const double c[4] = {0.0, 0.0, 0.0, 0.0};
-                const int m = t & 15;
-                ffs[((size_t)b * 6 + f) * 16 + m] = face_sum(TileAcc<T>{tile}, b, f, m, c);
-            }
+            if (kind[f] == 2) ffs[((size_t)b * 6 + f) * 16 + (t & 15)] = row_face_sum(rows, f, t & 15);
         }
     }
 }
@@ -1946,22 +2061,27 @@ void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, doubl
     AMRMG_LAUNCH(k_tag, dim3(blocks_for(n, 256)), dim3(256), 0, st, v, n, scratch, lambda, tags);
 }
 
-int hgs_rule_threads(int nb) { return nb <= HGS_SMALL_LEVEL ? BT_SMALL : BT; }
+// the size rule: one wavefront (brick) per workgroup
+int hgs_rule_threads(int) { return 64; }
 
 template <class T>
 void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,
                 double *phib, double *ffs, int mode, int nt)
 {
     if (nb <= 0) return;
-    const bool small = (nt ? nt : hgs_rule_threads(nb)) == BT_SMALL;
-    dim3 g(nb), blk(small ? BT_SMALL : BT);
-#define AMRMG_HGS(MD)                                                                                        \
-    case MD:                                                                                                 \
-        if (small)                                                                                           \
-            AMRMG_LAUNCH((k_hgs<T, MD, BT_SMALL>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib, ffs);    \
-        else                                                                                                 \
-            AMRMG_LAUNCH((k_hgs<T, MD, BT>), g, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib, ffs);          \
-        return;
+    const int bpw = (nt ? nt : hgs_rule_threads(nb)) / 64;
+    const dim3 blk(64 * bpw), grid((nb + bpw - 1) / bpw);
+#define AMRMG_HGS_BPW(MD, B)                                                                                     \
+    if (bpw == B) {                                                                                              \
+        AMRMG_LAUNCH((k_hgs<T, MD, B>), grid, blk, 0, st, M, b0, nb, ein, eout, r, cp, phib, ffs);               \
+        return;                                                                                                  \
+    }
+#define AMRMG_HGS(MD)        \
+    case MD:                 \
+        AMRMG_HGS_BPW(MD, 1) \
+        AMRMG_HGS_BPW(MD, 2) \
+        AMRMG_HGS_BPW(MD, 4) \
+        break;
     switch (mode) {
         AMRMG_HGS(0)
         AMRMG_HGS(HG_ZERO)
@@ -1973,7 +2093,8 @@ void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, 
     default: break;
     }
 #undef AMRMG_HGS
-    fprintf(stderr, "libamrmg: no sweep kernel for mode %d\n", mode);
+#undef AMRMG_HGS_BPW
+    fprintf(stderr, "libamrmg: no sweep kernel for mode %d and %d threads per workgroup\n", mode, 64 * bpw);
     abort();
 }
 

@@ -147,8 +147,8 @@ template <class T>
 void launch_copy(hipStream_t st, const T *a, T *b, int64_t n);
 // brick-hybrid Gauss-Seidel sweep; mode = bits of HG_ZERO 1, HG_PROL 2, HG_CPIN 4, HG_PHI 8,
 // HG_FFS 16 (fine sums of the result into ffs)
-// nt: threads per brick (128 or 256), or 0 for the size rule
-// hgs_rule_threads (256 up to 4096 bricks, else 128)
+// one wavefront per brick; nt: threads per workgroup (64, 128 or 256, i.e.
+// 1, 2 or 4 bricks per workgroup), or 0 for the size rule hgs_rule_threads
 int hgs_rule_threads(int nb);
 template <class T>
 void launch_hgs(hipStream_t st, const DevMeta &M, int b0, int nb, const T *ein, T *eout, const T *r, T *cp,

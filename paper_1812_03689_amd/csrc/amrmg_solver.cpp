@@ -121,14 +121,15 @@ extern "C" amrmg_status amrmg_set_workspace(amrmg_ctx *ctx, void *dev, size_t by
 // replay the outer iteration as a hipGraph (AMRMG_NO_GRAPH=1 disables)
 static bool g_use_graphs = getenv("AMRMG_NO_GRAPH") == nullptr;
 
-// Threads per brick of the sweep kernel, tuned on the device: for each
-// launch size class (bricks per launch, rounded up to a power of two) and
-// cycle precision the first solve that meets it times a plain sweep with
-// 128 and with 256 threads per brick and keeps the faster; later solves and
-// captured graphs read the choice.  Process-wide (one GPU per process);
+// Workgroup shape of the sweep kernel (one wavefront per brick, 1, 2 or 4
+// bricks per workgroup), tuned on the device: for each launch size class
+// (bricks per launch, rounded up to a power of two) and cycle precision the
+// first solve that meets it times a plain sweep with each shape and keeps the
+// fastest unless the size rule's is within 3 %; later solves and captured
+// graphs read the choice.  Process-wide (one GPU per process);
 // AMRMG_NO_TUNE=1 keeps the size rule instead.
 static std::mutex g_tune_mu;
-static std::map<std::pair<int, int>, int> g_hgs_nt;  // (sizeof(T), log2 bricks) -> threads
+static std::map<std::pair<int, int>, int> g_hgs_nt;  // (sizeof(T), log2 bricks) -> threads per workgroup
 static const bool g_tune = getenv("AMRMG_NO_TUNE") == nullptr;
 
 static int size_class(int nb)
@@ -197,9 +198,10 @@ struct Driver {
     }
     int hgs_nt(int k) const { return tuned_nt((int)sizeof(T), step_nb(k)); }
 
-    // time the sweep of every level with each block size not yet tuned for
-    // its size class (plain sweeps from e into et: both are scratch before
-    // the cycle starts)
+    // time the sweep of every level with each workgroup shape (1, 2 or 4
+    // bricks per workgroup, one wavefront each) not yet tuned for its size
+    // class (plain sweeps from e into et: both are scratch before the cycle
+    // starts)
     amrmg_status tune()
     {
         if (!g_tune) return AMRMG_OK;
@@ -209,10 +211,10 @@ struct Driver {
             hipEvent_t a, z;
             HIP_TRY(hipEventCreate(&a));
             HIP_TRY(hipEventCreate(&z));
-            constexpr int REPS = 5;
-            float each[2] = {0.f, 0.f};
-            const int cand[2] = {128, 256};
-            for (int i = 0; i < 2; ++i) {
+            constexpr int REPS = 5, NC = 3;
+            const int cand[NC] = {64, 128, 256};
+            float each[NC] = {0.f, 0.f, 0.f};
+            for (int i = 0; i < NC; ++i) {
                 launch_hgs<T>(st, D.M, b0, nb, e, et, r, cpe, D.phib, D.ffs, 0, cand[i]);  // warm
                 HIP_TRY(hipEventRecord(a, st));
                 for (int rep = 0; rep < REPS; ++rep)
@@ -221,15 +223,22 @@ struct Driver {
                 HIP_TRY(hipEventSynchronize(z));
                 HIP_TRY(hipEventElapsedTime(&each[i], a, z));
             }
-            // the size rule's choice unless the other is clearly faster
-            const int rule = hgs_rule_threads(nb) == cand[1] ? 1 : 0, other = 1 - rule;
-            const int pick = each[other] < 0.97f * each[rule] ? cand[other] : cand[rule];
+            // the size rule's shape unless another is clearly faster
+            int rule = 0;
+            for (int i = 0; i < NC; ++i)
+                if (cand[i] == hgs_rule_threads(nb)) rule = i;
+            int best = rule;
+            for (int i = 0; i < NC; ++i)
+                if (each[i] < each[best]) best = i;
+            const int pick = each[best] < 0.97f * each[rule] ? cand[best] : cand[rule];
             (void)hipEventDestroy(a);
             (void)hipEventDestroy(z);
             HIP_TRY(hipGetLastError());
             if (getenv("AMRMG_TUNE_LOG"))
-                fprintf(stderr, "libamrmg: sweep of %d bricks (%d-byte cycle): 128 threads %.4f ms, 256 threads %.4f ms -> %d\n",
-                        nb, (int)sizeof(T), each[0] / REPS, each[1] / REPS, pick);
+                fprintf(stderr,
+                        "libamrmg: sweep of %d bricks (%d-byte cycle): 1, 2, 4 bricks per workgroup %.4f, %.4f, "
+                        "%.4f ms -> %d threads\n",
+                        nb, (int)sizeof(T), each[0] / REPS, each[1] / REPS, each[2] / REPS, pick);
             std::lock_guard<std::mutex> lk(g_tune_mu);
             g_hgs_nt.emplace(std::make_pair((int)sizeof(T), size_class(nb)), pick);
         }
