@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamrmg.so")
 SOURCES = ["amrmg_kernels.hip", "amrmg_meta.hip", "amrmg_sort.hip", "amrmg_transform.hip", "amrmg_hier.cpp",
            "amrmg_api.cpp", "amrmg_build.cpp", "amrmg_particles.cpp", "amrmg_solver.cpp",
-           "amrmg_noalloc.hip"]
+           "amrmg_noalloc.hip", "amrmg_scan.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

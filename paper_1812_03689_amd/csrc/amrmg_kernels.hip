@@ -374,6 +374,51 @@ __device__ __forceinline__ double face_sum(const U &u, int F, int dir, int m, co
     return sum;
 }
 
+// The row layout of the sweep and the outer residual: one wavefront per
+// brick.  Lane (y, z) = (lane & 7, lane >> 3) owns the brick's x-row (y, z):
+// its 8 cells, their right-hand sides and, for x = 0 and x = 7, the x halo
+// slots stay in registers, so x-neighbours need no LDS.  The rows of the
+// brick and the y and z halo rows sit in LDS, row (y', z') for y', z' in
+// -1..8 at rows[((y' + 1) + 10 (z' + 1)) * 9]: rows are 9 words apart, so the
+// 64 lanes reading the same x of their neighbouring rows fall in different
+// banks.  Row r of the brick starts at cell 8 r of its slab, so the global
+// row loads and stores are whole coalesced vectors.  A workgroup holds BPW
+// bricks (one per wavefront).
+constexpr int RW = 10, RS = 9;
+__device__ __forceinline__ int rrow(int y, int z) { return ((y + 1) + RW * (z + 1)) * RS; }
+
+template <class T>
+struct Row8;
+template <>
+struct Row8<float> {
+    static __device__ __forceinline__ void load(const float *p, float (&v)[8])
+    {
+        const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 4);
+        v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+    }
+    static __device__ __forceinline__ void store(float *p, const float (&v)[8])
+    {
+        *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
+        *(float4 *)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+    }
+};
+template <>
+struct Row8<double> {
+    static __device__ __forceinline__ void load(const double *p, double (&v)[8])
+    {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double2 a = *(const double2 *)(p + 2 * i);
+            v[2 * i] = a.x, v[2 * i + 1] = a.y;
+        }
+    }
+    static __device__ __forceinline__ void store(double *p, const double (&v)[8])
+    {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) *(double2 *)(p + 2 * i) = make_double2(v[2 * i], v[2 * i + 1]);
+    }
+};
+
 // Composite residual r = rho/eps0 - A_comp phi on uncovered cells (zero on
 // covered ones) of a range or list of AMR bricks, from FP64 phi and rho in
 // brick layout, written as T in brick layout (r_out) and/or FP64 in the
@@ -393,85 +438,149 @@ __device__ __forceinline__ double ghost_shift(double a, double uc, double uin)
     return a > 0.0 ? a * uc - 0.2 * uin : (a < 0.0 ? (a + 2.0) * uc : 0.0);
 }
 
-template <class T, bool ZERO>
-__global__ void __launch_bounds__(RT) k_outer_residual(DevMeta M, int b0, int nb, const double *phib,
-                                                       const double *rhob, double inv_eps0, const double *cp_phi,
-                                                       T *r_out, double *part, int norm_p, const int32_t *list,
-                                                       double *const *r_user, const double *ffs)
+// One wavefront per brick, lane (y, z) holding the x-row (y, z) of phi and
+// rho in registers and the rows of phi with the y and z halo rows in LDS, as
+// the sweep kernel does (rrow); the face kinds and the covered-octant masks
+// of the brick and of its face neighbours come through scalar loads.  Each lane writes its row of r and one partial norm per brick
+// (part[2 b]; part[2 b + 1] = 0).
+template <class T, bool ZERO, int BPW>
+__global__ void __launch_bounds__(64 * BPW) k_outer_residual(DevMeta M, int b0, int nb, const double *phib,
+                                                             const double *rhob, double inv_eps0,
+                                                             const double *cp_phi, T *r_out, double *part, int norm_p,
+                                                             const int32_t *list, double *const *r_user,
+                                                             const double *ffs)
 {
-    __shared__ double tile[TE * TE * TE];
-    __shared__ double alpha[6];
-    __shared__ int nbk[6];
-    __shared__ int kids[56];
-    __shared__ uint8_t ncm[6];
-    constexpr int PER = BRICK_CELLS / RT;
-    const int b = pick_brick(b0, nb, list, blockIdx.x);
-    const LevelConst L = M.lc[M.org[b].w];
-    const uint8_t cm = M.cmask[b];
-    if (threadIdx.x < 6) {
-        int f = M.nbr[b * 6 + threadIdx.x];
-        nbk[threadIdx.x] = f;
-        ncm[threadIdx.x] = f >= 0 ? M.cmask[f] : 0;
-    }
-    if (!ZERO) stage_kids(M, b, kids);
-    double rv[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) rv[k] = rhob[(size_t)b * BRICK_CELLS + threadIdx.x + RT * k] * inv_eps0;
-    stage_tile<SrcB<double>, ZERO, CpArr<double>, RT>(M, b, SrcB<double>{phib},
-                                                      CpArr<double>{ZERO ? nullptr : cp_phi}, true, tile, alpha);
+    __shared__ double rows_all[BPW][RW * RW * RS];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int k0 = xcd_remap(blockIdx.x, (nb + BPW - 1) / BPW) * BPW + w;
+    const bool active = k0 < nb;
+    const int kk = active ? k0 : nb - 1;
+    const int b = __builtin_amdgcn_readfirstlane(list ? list[kk] : b0 + kk);
+    double *rows = rows_all[w];
+    const int y = lane & 7, z = lane >> 3;
+    const int lev = M.org[b].w;
+    const LevelConst L = M.lc[lev];
+    const uint32_t cm = M.cmask[b];
+    int nbf[6], kind[6];
+    uint32_t ncm[6];
     bool any_cov = cm != 0;
-    for (int f = 0; f < 6; ++f) any_cov = any_cov || ncm[f] != 0;  // uniform over the workgroup
-    double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int c = threadIdx.x + RT * k;
-        const int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
-        double r = 0.0;
-        if (!((cm >> oct_of(x, y, z)) & 1)) {
-            const double uc = tile[tix(x, y, z)];
-            double Au = 0.0;
-            if (!any_cov) {
-                Au = L.ih2[0] * (2.0 * uc - tile[tix(x - 1, y, z)] - tile[tix(x + 1, y, z)]) +
-                     L.ih2[1] * (2.0 * uc - tile[tix(x, y - 1, z)] - tile[tix(x, y + 1, z)]) +
-                     L.ih2[2] * (2.0 * uc - tile[tix(x, y, z - 1)] - tile[tix(x, y, z + 1)]);
-                if (x == 0) Au -= L.ih2[0] * ghost_shift(alpha[0], uc, tile[tix(1, y, z)]);
-                if (x == 7) Au -= L.ih2[0] * ghost_shift(alpha[1], uc, tile[tix(6, y, z)]);
-                if (y == 0) Au -= L.ih2[1] * ghost_shift(alpha[2], uc, tile[tix(x, 1, z)]);
-                if (y == 7) Au -= L.ih2[1] * ghost_shift(alpha[3], uc, tile[tix(x, 6, z)]);
-                if (z == 0) Au -= L.ih2[2] * ghost_shift(alpha[4], uc, tile[tix(x, y, 1)]);
-                if (z == 7) Au -= L.ih2[2] * ghost_shift(alpha[5], uc, tile[tix(x, y, 6)]);
-            } else {
+    for (int f = 0; f < 6; ++f) {
+        nbf[f] = M.nbr[b * 6 + f];
+        kind[f] = nbf[f] >= 0 ? 0 : ((-1 - nbf[f]) < M.nbc ? 1 : 2);
+        ncm[f] = kind[f] == 0 ? (uint32_t)M.cmask[nbf[f]] : 0u;
+        any_cov = any_cov || ncm[f] != 0;
+    }
+    const size_t rb = (size_t)b * BRICK_CELLS + 8 * lane;
+    // every cell covered (wavefront-uniform): r = 0, nothing to load; the
+    // wavefront still takes part in the workgroup's barrier
+    const bool all_cov = cm == 0xffu;
+    double rv[8], u[8], hs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int f = 0; f < 6; ++f) {
-                    const int d = f >> 1, s = (f & 1) ? 1 : -1;
-                    int qx = x + (d == 0 ? s : 0), qy = y + (d == 1 ? s : 0), qz = z + (d == 2 ? s : 0);
-                    bool inside = ((qx | qy | qz) & ~7) == 0;
-                    bool cov = ((inside ? cm : ncm[f]) >> oct_of(qx & 7, qy & 7, qz & 7)) & 1;
-                    if (!cov) {
-                        double a, bv;
-                        tile_ab(tile, alpha, x, y, z, d, s, a, bv);
-                        Au += L.ih2[d] * ((1.0 - a) * uc - bv);
-                    } else if (!ZERO) {
-                        const int nl[3] = {qx & 7, qy & 7, qz & 7};
-                        Au += -0.5 * L.ih2[d] * ffs_at(ffs, kids, inside, f, nl, d, s);
-                    }
+    for (int i = 0; i < 8; ++i) rv[i] = u[i] = 0.0;
+    if (!all_cov) {
+        Row8<double>::load(rhob + rb, rv);
+        if (!ZERO) Row8<double>::load(phib + rb, u);
+    }
+    // halo slots: the neighbour's phi, 2 g on the boundary (the Dirichlet
+    // data enter here), or the coarse part of the coarse-fine ghost
+#pragma unroll
+    for (int f = 0; f < 6 && !all_cov; ++f) {
+        const int d = f >> 1, md = (f & 1) ? 0 : 7;
+        const int uu = lane & 7, vv = lane >> 3;
+        if (kind[f] == 0) {
+            const int c = d == 0 ? md + 8 * uu + 64 * vv : (d == 1 ? uu + 8 * md + 64 * vv : uu + 8 * vv + 64 * md);
+            hs[f] = ZERO ? 0.0 : phib[(size_t)nbf[f] * BRICK_CELLS + c];
+        } else if (kind[f] == 1) {
+            hs[f] = 2.0 * M.gbc[(size_t)(-1 - nbf[f]) * 64 + lane];
+        } else {
+            hs[f] = (ZERO || !cp_phi) ? 0.0 : cp_phi[(size_t)(-1 - nbf[f] - M.nbc) * 64 + lane];
+        }
+    }
+    const int rym = rrow(y - 1, z), ryp = rrow(y + 1, z), rzm = rrow(y, z - 1), rzp = rrow(y, z + 1), rme = rrow(y, z);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) rows[rme + i] = u[i];
+    rows[rrow(-1, lane >> 3) + (lane & 7)] = hs[2];
+    rows[rrow(8, lane >> 3) + (lane & 7)] = hs[3];
+    rows[rrow(lane >> 3, -1) + (lane & 7)] = hs[4];
+    rows[rrow(lane >> 3, 8) + (lane & 7)] = hs[5];
+    // ghost coefficients and the per-row weights (as in the sweep)
+    double ag[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) ag[f] = kind[f] == 1 ? L.abnd[f >> 1] : (kind[f] == 2 ? 2.0 / 3.0 : 0.0);
+    const double ih2x = L.ih2[0], ih2y = L.ih2[1], ih2z = L.ih2[2];
+    const double aym = y == 0 ? ag[2] : 0.0, ayp = y == 7 ? ag[3] : 0.0;
+    const double azm = z == 0 ? ag[4] : 0.0, azp = z == 7 ? ag[5] : 0.0;
+    const double wyp = (y == 0 && kind[2] == 2) ? 0.8 : 1.0, wym = (y == 7 && kind[3] == 2) ? 0.8 : 1.0;
+    const double wzp = (z == 0 && kind[4] == 2) ? 0.8 : 1.0, wzm = (z == 7 && kind[5] == 2) ? 0.8 : 1.0;
+    const double wxp0 = kind[0] == 2 ? 0.8 : 1.0, wxm7 = kind[1] == 2 ? 0.8 : 1.0;
+    const double den = ih2y * (2.0 - aym - ayp) + ih2z * (2.0 - azm - azp) + 2.0 * ih2x;
+    __syncthreads();
+    double r[8], acc = 0.0;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        r[x] = 0.0;
+        if (all_cov) continue;
+        const double uc = u[x];
+        const double xm = x == 0 ? hs[0] : u[x - 1], xp = x == 7 ? hs[1] : u[x + 1];
+        const double wxm = x == 7 ? wxm7 : 1.0, wxp = x == 0 ? wxp0 : 1.0;
+        const double dc = den - (x == 0 ? ih2x * ag[0] : 0.0) - (x == 7 ? ih2x * ag[1] : 0.0);
+        const double ym = rows[rym + x], yp = rows[ryp + x], zm = rows[rzm + x], zp = rows[rzp + x];
+        double Au = dc * uc - (ih2x * (wxm * xm + wxp * xp) + ih2y * (wym * ym + wyp * yp) +
+                               ih2z * (wzm * zm + wzp * zp));
+        const int oc = (x >> 2) | ((y >> 2) << 1) | ((z >> 2) << 2);
+        const bool mine_cov = (cm >> oc) & 1;
+        if (any_cov && !mine_cov) {
+            // a face towards a covered cell of this level: the flux through
+            // it is the mean of the four fine fluxes (the fine sums), in
+            // place of the same-level term ih2 (u_c - u_nb)
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                const int d = f >> 1, sg = (f & 1) ? 1 : -1;
+                const int qx = x + (d == 0 ? sg : 0), qy = y + (d == 1 ? sg : 0), qz = z + (d == 2 ? sg : 0);
+                const bool inside = ((qx | qy | qz) & ~7) == 0;
+                if (!inside && kind[f] != 0) continue;
+                const int lx = qx & 7, ly = qy & 7, lz = qz & 7;
+                const int qo = (lx >> 2) | ((ly >> 2) << 1) | ((lz >> 2) << 2);
+                if (!(((inside ? cm : ncm[f]) >> qo) & 1)) continue;
+                const double unb = d == 0 ? (f & 1 ? xp : xm) : (d == 1 ? (f & 1 ? yp : ym) : (f & 1 ? zp : zm));
+                const double ih2 = d == 0 ? ih2x : (d == 1 ? ih2y : ih2z);
+                Au -= ih2 * (uc - unb);
+                if (!ZERO) {
+                    // the child covering that cell: of this brick, or of the face neighbour
+                    const int F = M.child[(inside ? b : nbf[f]) * 8 + qo];
+                    const int m = d == 0 ? (ly & 3) + 4 * (lz & 3) : (d == 1 ? (lx & 3) + 4 * (lz & 3)
+                                                                                 : (lx & 3) + 4 * (ly & 3));
+                    Au += -0.5 * ih2 * ffs[((size_t)F * 6 + 2 * d + (sg < 0)) * 16 + m];
                 }
             }
-            r = rv[k] - Au;
         }
-        if (r_out) r_out[(size_t)b * BRICK_CELLS + c] = (T)r;
-        if (r_user) {
-            int2 us = M.ustr[b];
-            r_user[M.org[b].w][M.ubase[b] + x + (int64_t)us.x * y + (int64_t)us.y * z] = r;
-        }
-        double av = fabs(r);
+        r[x] = mine_cov ? 0.0 : rv[x] * inv_eps0 - Au;
+        const double av = fabs(r[x]);
         acc = norm_p == 2 ? acc + av * av : norm_p == 1 ? acc + av : fmax(acc, av);
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        double w = __shfl_xor(acc, o, 64);
-        acc = norm_p == 0 ? fmax(acc, w) : acc + w;
+    if (active) {
+        if (r_out) {
+            T rt[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) rt[i] = (T)r[i];
+            Row8<T>::store(r_out + rb, rt);
+        }
+        if (r_user) {
+            const int2 us = M.ustr[b];
+            double *ru = r_user[lev] + M.ubase[b] + (int64_t)us.x * y + (int64_t)us.y * z;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) ru[i] = r[i];
+        }
     }
-    if ((threadIdx.x & 63) == 0) part[2 * (size_t)b + (threadIdx.x >> 6)] = acc;
+    for (int o = 32; o > 0; o >>= 1) {
+        const double v = __shfl_xor(acc, o, 64);
+        acc = norm_p == 0 ? fmax(acc, v) : acc + v;
+    }
+    if (active && lane == 0) {
+        part[2 * (size_t)b] = acc;
+        part[2 * (size_t)b + 1] = 0.0;
+    }
 }
 
 // Copies between the caller's box-list layout and brick layout on a range or
@@ -682,51 +791,6 @@ struct SrcProl {
 // 8 phi += result on AMR bricks (fused phi update; phi in brick layout);
 // 16 the fine sums of the result on the brick's coarse-fine faces into ffs.
 enum { HG_ZERO = 1, HG_PROL = 2, HG_CPIN = 4, HG_PHI = 8, HG_FFS = 16 };
-
-// The sweep runs one wavefront per brick.  Lane (y, z) = (lane & 7, lane >> 3)
-// owns the brick's x-row (y, z): its 8 cells, their right-hand sides and, for
-// x = 0 and x = 7, the x halo slots stay in registers, so x-neighbours need no
-// LDS.  The rows of the brick and the y and z halo rows sit in LDS, row
-// (y', z') for y', z' in -1..8 at rows[((y' + 1) + 10 (z' + 1)) * 9]: rows are
-// 9 words apart, so the 64 lanes reading the same x of their neighbouring rows
-// fall in different banks.  Row r of the brick starts at cell 8 r of its slab,
-// so the global row loads and stores are whole coalesced vectors.  A
-// workgroup holds BPW bricks (one per wavefront); the bricks per workgroup are
-// tuned.
-constexpr int RW = 10, RS = 9;
-__device__ __forceinline__ int rrow(int y, int z) { return ((y + 1) + RW * (z + 1)) * RS; }
-
-template <class T>
-struct Row8;
-template <>
-struct Row8<float> {
-    static __device__ __forceinline__ void load(const float *p, float (&v)[8])
-    {
-        const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 4);
-        v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
-    }
-    static __device__ __forceinline__ void store(float *p, const float (&v)[8])
-    {
-        *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
-        *(float4 *)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
-    }
-};
-template <>
-struct Row8<double> {
-    static __device__ __forceinline__ void load(const double *p, double (&v)[8])
-    {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const double2 a = *(const double2 *)(p + 2 * i);
-            v[2 * i] = a.x, v[2 * i + 1] = a.y;
-        }
-    }
-    static __device__ __forceinline__ void store(double *p, const double (&v)[8])
-    {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) *(double2 *)(p + 2 * i) = make_double2(v[2 * i], v[2 * i + 1]);
-    }
-};
 
 // face_sum of a brick held in the row layout with zero coarse parts: over the
 // four fine cells of coarse cell m of face f, u_f/3 + u_in/5 (u_in the cell
@@ -1895,12 +1959,24 @@ void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, con
                            int norm_p, bool zero_phi, double *const *r_user, const double *ffs)
 {
     if (nb <= 0) return;
-    if (zero_phi)
-        AMRMG_LAUNCH((k_outer_residual<T, true>), dim3(nb), dim3(RT), 0, st, M, b0, nb, phib, rhob, inv_eps0,
-                     cp_phi, r_out, part, norm_p, list, r_user, ffs);
-    else
-        AMRMG_LAUNCH((k_outer_residual<T, false>), dim3(nb), dim3(RT), 0, st, M, b0, nb, phib, rhob, inv_eps0,
-                     cp_phi, r_out, part, norm_p, list, r_user, ffs);
+    // four bricks per workgroup on levels far larger than the chip (the
+    // sweep's tuning finds the same), one otherwise
+    if (nb > 16384) {
+        const dim3 g((nb + 3) / 4), blk(256);
+        if (zero_phi)
+            AMRMG_LAUNCH((k_outer_residual<T, true, 4>), g, blk, 0, st, M, b0, nb, phib, rhob, inv_eps0, cp_phi,
+                         r_out, part, norm_p, list, r_user, ffs);
+        else
+            AMRMG_LAUNCH((k_outer_residual<T, false, 4>), g, blk, 0, st, M, b0, nb, phib, rhob, inv_eps0, cp_phi,
+                         r_out, part, norm_p, list, r_user, ffs);
+    } else {
+        if (zero_phi)
+            AMRMG_LAUNCH((k_outer_residual<T, true, 1>), dim3(nb), dim3(64), 0, st, M, b0, nb, phib, rhob, inv_eps0,
+                         cp_phi, r_out, part, norm_p, list, r_user, ffs);
+        else
+            AMRMG_LAUNCH((k_outer_residual<T, false, 1>), dim3(nb), dim3(64), 0, st, M, b0, nb, phib, rhob,
+                         inv_eps0, cp_phi, r_out, part, norm_p, list, r_user, ffs);
+    }
 }
 
 void launch_user_brick(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, bool to_brick,

@@ -84,6 +84,13 @@ struct MetaBuild {
     unsigned *hseq;
     unsigned seq;
 };
+// exclusive prefix sums out[i] = in[0] + ... + in[i-1] of n values (two
+// launches, amrmg_scan.hip); temp: scan_temp_bytes<V>(n) bytes of device
+// memory; in and out must not overlap
+template <class V>
+size_t scan_temp_bytes(int64_t n);
+template <class V>
+hipError_t exclusive_scan(hipStream_t st, const V *in, V *out, int64_t n, void *temp, size_t temp_bytes);
 size_t meta_scan_temp_bytes(int nbrick);
 hipError_t launch_meta_build(hipStream_t st, const MetaBuild &B);
 // Dirichlet values of the boundary faces (gbc) and the coarse-fine windows

@@ -13,8 +13,6 @@
 // and device select from one definition.
 #include <hip/hip_runtime.h>
 
-#include <hipcub/hipcub.hpp>
-
 #include "amrmg_internal.hpp"
 #include "amrmg_kernels.hpp"
 
@@ -346,9 +344,7 @@ __global__ void __launch_bounds__(1024) k_meta_summary(int nent, int nbrick, con
 
 size_t meta_scan_temp_bytes(int nbrick)
 {
-    size_t a = 0, b = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, a, (const uint64_t *)nullptr, (uint64_t *)nullptr, nbrick + 1);
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const uint32_t *)nullptr, (uint32_t *)nullptr, nbrick + 1);
+    const size_t a = scan_temp_bytes<uint64_t>(nbrick + 1), b = scan_temp_bytes<uint32_t>(nbrick + 1);
     return a > b ? a : b;
 }
 
@@ -363,15 +359,13 @@ hipError_t launch_meta_build(hipStream_t st, const MetaBuild &B)
                        B.ubase, B.ustr, B.child, B.par);
     hipLaunchKernelGGL(k_meta_links, dim3(g1), dim3(256), 0, st, B.nbrick, B.ent, B.pool, B.org, B.nbr, B.child,
                        B.par, B.cnt, B.err);
-    size_t tb = B.temp_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(B.temp, tb, B.cnt, B.off, B.nbrick + 1, st);
+    e = exclusive_scan<uint64_t>(st, B.cnt, B.off, B.nbrick + 1, B.temp, B.temp_bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_meta_faces, dim3(g1), dim3(256), 0, st, B.nbrick, B.ent, B.org, B.off, B.nbr, B.gf_owner,
                        B.child, B.cmask);
     hipLaunchKernelGGL(k_meta_reflux, dim3(g1), dim3(256), 0, st, B.nbrick, B.ent, B.org, B.nbr, B.cmask, B.flag,
                        B.dof, B.amr_list);
-    tb = B.temp_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(B.temp, tb, B.flag, B.roff, B.nbrick + 1, st);
+    e = exclusive_scan<uint32_t>(st, B.flag, B.roff, B.nbrick + 1, B.temp, B.temp_bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_meta_list, dim3(g1), dim3(256), 0, st, B.nbrick, B.flag, B.roff, B.reflux);
     hipLaunchKernelGGL(k_meta_summary, dim3(1), dim3(1024), 0, st, B.nent, B.nbrick, B.ent, B.off, B.roff, B.dof,

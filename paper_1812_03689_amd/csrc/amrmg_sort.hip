@@ -7,11 +7,9 @@
 // deposit of a workgroup stays inside a small LDS tile on every level; the
 // order inside a bucket does not matter (it is the order in which the
 // particles claimed their slots).  Passes: count with slot claims, the
-// counts in bucket order, exclusive scan (hipCUB), scatter of the order,
-// ordered copy.
+// counts in bucket order, exclusive scan (amrmg_scan.hip), scatter of the
+// order, ordered copy.
 #include <hip/hip_runtime.h>
-
-#include <hipcub/hipcub.hpp>
 
 #include "amrmg_kernels.hpp"
 
@@ -126,13 +124,7 @@ size_t order_count_entries(const double *lo, const double *hi, const int *n0)
 
 int order_bucket_shift(const double *lo, const double *hi, const int *n0) { return bucket_grid(lo, hi, n0).shift; }
 
-size_t order_temp_bytes(size_t entries)
-{
-    size_t b = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                           (int)entries);
-    return b;
-}
+size_t order_temp_bytes(size_t entries) { return scan_temp_bytes<uint32_t>((int64_t)entries); }
 
 hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
                           const double *q, const double *lo, const double *hi, const int *n0, uint32_t *key,
@@ -153,8 +145,7 @@ hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x,
                            (const double *)y, (const double *)z, G, count, key, slot);
     uint32_t *ordered = count + entries;
     hipLaunchKernelGGL(k_bucket_gather, dim3((entries + 255) / 256), dim3(256), 0, st, G, count, ordered);
-    size_t tb = temp_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(temp, tb, ordered, start, entries, st);
+    e = exclusive_scan<uint32_t>(st, ordered, start, entries, temp, temp_bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bucket_scatter, dim3(g), dim3(256), 0, st, n, key, slot, start, perm);
     if (xs) launch_copy_ordered(st, pos_f32, n, perm, x, y, z, q, xs, ys, zs, qs);
