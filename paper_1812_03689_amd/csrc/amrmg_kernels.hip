@@ -976,44 +976,74 @@ __device__ __forceinline__ double cell_residual(const DevMeta &M, const LevelCon
 }
 
 // r^{l-1} on covered cells = mean over the 8 children of (r^l - A_nf e^l)
-// (Alg. 3, restriction onto the covered domain; e^{l-1} = 0 at that point).
-// One fine brick per workgroup of 128 threads: two threads per coarse cell,
-// each with the four children of one z layer, combined by a shuffle.
+// (Alg. 3, restriction onto the covered domain; e^{l-1} = 0 at that point,
+// so the coarse parts of the coarse-fine ghosts are zero).  One wavefront
+// per fine brick in the row layout: lane (y, z) computes the residual of its
+// row, adds x pairs, then the y and z pairs of the lanes 1 and 8 apart; the
+// lanes with even y and z write four coarse cells of their parent's row.
 template <class T>
-__device__ __forceinline__ void restrict_brick(const DevMeta &M, int b, const T *e, const T *r, T *rc, T *tile,
-                                               T *alpha)
+__device__ __forceinline__ void restrict_brick(const DevMeta &M, int b, bool active, const T *e, T *r, T *rows)
 {
-    LevelConst L = M.lc[M.org[b].w];
-    const T ih2[3] = {(T)L.ih2[0], (T)L.ih2[1], (T)L.ih2[2]};
-    const int cc = threadIdx.x >> 1, h = threadIdx.x & 1;
-    const int cx = cc & 3, cy = (cc >> 2) & 3, cz = cc >> 4;
-    const int z = 2 * cz + h;
-    T rv[4];
+    const int lane = threadIdx.x & 63, y = lane & 7, z = lane >> 3;
+    const LevelConst L = M.lc[M.org[b].w];
+    int nbf[6], kind[6];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        rv[q] = r[(size_t)b * BRICK_CELLS + (2 * cx + (q & 1)) + 8 * (2 * cy + (q >> 1)) + 64 * z];
-    stage_tile<SrcB<T>, false, CpNone, RT, T>(M, b, SrcB<T>{e}, CpNone{}, false, tile, alpha);
-    T sum = (T)0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int x = 2 * cx + (q & 1), y = 2 * cy + (q >> 1);
-        T uc = tile[tix(x, y, z)], Au = (T)0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-            for (int s = -1; s <= 1; s += 2) {
-                T a, bv;
-                tile_ab(tile, alpha, x, y, z, d, s, a, bv);
-                Au += ih2[d] * (((T)1 - a) * uc - bv);
-            }
-        sum += rv[q] - Au;
+    for (int f = 0; f < 6; ++f) {
+        nbf[f] = M.nbr[b * 6 + f];
+        kind[f] = nbf[f] >= 0 ? 0 : ((-1 - nbf[f]) < M.nbc ? 1 : 2);
     }
-    sum += __shfl_xor(sum, 1, 64);
-    if (h == 0) {
-        int par = M.par[b];
-        int pb = par >> 3, oc = par & 7;
-        int X = (oc & 1) * 4 + cx, Y = ((oc >> 1) & 1) * 4 + cy, Z = (oc >> 2) * 4 + cz;
-        rc[(size_t)pb * BRICK_CELLS + X + 8 * Y + 64 * Z] = (T)0.125 * sum;
+    const size_t rb = (size_t)b * BRICK_CELLS + 8 * lane;
+    T rr[8], u[8], hs[6];
+    Row8<T>::load(r + rb, rr);
+    Row8<T>::load(e + rb, u);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, md = (f & 1) ? 0 : 7, uu = lane & 7, vv = lane >> 3;
+        const int c = d == 0 ? md + 8 * uu + 64 * vv : (d == 1 ? uu + 8 * md + 64 * vv : uu + 8 * vv + 64 * md);
+        hs[f] = kind[f] == 0 ? e[(size_t)nbf[f] * BRICK_CELLS + c] : (T)0;
+    }
+    const int rym = rrow(y - 1, z), ryp = rrow(y + 1, z), rzm = rrow(y, z - 1), rzp = rrow(y, z + 1), rme = rrow(y, z);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) rows[rme + i] = u[i];
+    rows[rrow(-1, lane >> 3) + (lane & 7)] = hs[2];
+    rows[rrow(8, lane >> 3) + (lane & 7)] = hs[3];
+    rows[rrow(lane >> 3, -1) + (lane & 7)] = hs[4];
+    rows[rrow(lane >> 3, 8) + (lane & 7)] = hs[5];
+    T ag[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) ag[f] = kind[f] == 1 ? (T)L.abnd[f >> 1] : (kind[f] == 2 ? (T)(2.0 / 3.0) : (T)0);
+    const T ih2x = (T)L.ih2[0], ih2y = (T)L.ih2[1], ih2z = (T)L.ih2[2], cf5 = (T)0.2;
+    const T aym = y == 0 ? ag[2] : (T)0, ayp = y == 7 ? ag[3] : (T)0;
+    const T azm = z == 0 ? ag[4] : (T)0, azp = z == 7 ? ag[5] : (T)0;
+    const T wyp = (y == 0 && kind[2] == 2) ? (T)1 - cf5 : (T)1, wym = (y == 7 && kind[3] == 2) ? (T)1 - cf5 : (T)1;
+    const T wzp = (z == 0 && kind[4] == 2) ? (T)1 - cf5 : (T)1, wzm = (z == 7 && kind[5] == 2) ? (T)1 - cf5 : (T)1;
+    const T wxp0 = kind[0] == 2 ? (T)1 - cf5 : (T)1, wxm7 = kind[1] == 2 ? (T)1 - cf5 : (T)1;
+    const T den = ih2y * ((T)2 - aym - ayp) + ih2z * ((T)2 - azm - azp) + (T)2 * ih2x;
+    __syncthreads();
+    T s4[4];
+#pragma unroll
+    for (int cx = 0; cx < 4; ++cx) {
+        T pair = (T)0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int x = 2 * cx + q;
+            const T xm = x == 0 ? hs[0] : u[x - 1], xp = x == 7 ? hs[1] : u[x + 1];
+            const T wxm = x == 7 ? wxm7 : (T)1, wxp = x == 0 ? wxp0 : (T)1;
+            const T dc = den - (x == 0 ? ih2x * ag[0] : (T)0) - (x == 7 ? ih2x * ag[1] : (T)0);
+            const T Au = dc * u[x] - (ih2x * (wxm * xm + wxp * xp) + ih2y * (wym * rows[rym + x] + wyp * rows[ryp + x]) +
+                                      ih2z * (wzm * rows[rzm + x] + wzp * rows[rzp + x]));
+            pair += rr[x] - Au;
+        }
+        pair += __shfl_xor(pair, 1, 64);
+        pair += __shfl_xor(pair, 8, 64);
+        s4[cx] = (T)0.125 * pair;
+    }
+    if (active && !(y & 1) && !(z & 1)) {
+        const int p = M.par[b], oc = p & 7;
+        const int Y = ((oc >> 1) & 1) * 4 + (y >> 1), Z = (oc >> 2) * 4 + (z >> 1);
+        T *dst = r + (size_t)(p >> 3) * BRICK_CELLS + (oc & 1) * 4 + 8 * Y + 64 * Z;
+#pragma unroll
+        for (int cx = 0; cx < 4; ++cx) dst[cx] = s4[cx];
     }
 }
 
@@ -1059,18 +1089,23 @@ __device__ __forceinline__ void reflux_brick(const DevMeta &M, int b, const doub
 // into their parents (covered coarse cells), then the coarse-fine update of
 // the nrf listed coarse bricks (uncovered cells) -- disjoint cells, so the
 // two kinds of workgroups run together.
+// Workgroups of 128 threads: the first (nb + 1) / 2 restrict two fine bricks
+// each (one per wavefront), the others update one listed coarse brick each.
 template <class T>
-__global__ void __launch_bounds__(RT) k_restrict(DevMeta M, int b0, int nb, const int32_t *rlist, int nrf,
-                                                 const T *e, T *r, const double *ffs)
+__global__ void __launch_bounds__(128) k_restrict(DevMeta M, int b0, int nb, const int32_t *rlist, int nrf,
+                                                  const T *e, T *r, const double *ffs)
 {
-    __shared__ T tile[TE * TE * TE];
-    __shared__ T alpha[6];
+    __shared__ T rows[2][RW * RW * RS];
     __shared__ int kids[56];
     __shared__ uint8_t ncm[6];
-    if ((int)blockIdx.x < nb)
-        restrict_brick<T>(M, b0 + xcd_remap(blockIdx.x, nb), e, r, r, tile, alpha);
-    else
-        reflux_brick<T>(M, rlist[xcd_remap(blockIdx.x - nb, nrf)], ffs, r, kids, ncm);
+    const int nwr = (nb + 1) / 2;
+    if ((int)blockIdx.x < nwr) {
+        const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int k = xcd_remap(blockIdx.x, nwr) * 2 + w;
+        restrict_brick<T>(M, __builtin_amdgcn_readfirstlane(b0 + (k < nb ? k : nb - 1)), k < nb, e, r, rows[w]);
+    } else {
+        reflux_brick<T>(M, rlist[xcd_remap(blockIdx.x - nwr, nrf)], ffs, r, kids, ncm);
+    }
 }
 
 // e^l += I e^{l-1}: piecewise-constant injection of the parent value
@@ -2032,7 +2067,7 @@ void launch_restrict(hipStream_t st, const DevMeta &M, int b0, int nb, const int
                      T *r, const double *ffs)
 {
     if (nb + nrf <= 0) return;
-    AMRMG_LAUNCH((k_restrict<T>), dim3(nb + nrf), dim3(RT), 0, st, M, b0, nb, rlist, nrf, e, r, ffs);
+    AMRMG_LAUNCH((k_restrict<T>), dim3((nb + 1) / 2 + nrf), dim3(128), 0, st, M, b0, nb, rlist, nrf, e, r, ffs);
 }
 
 template <class T>
