@@ -271,7 +271,12 @@ amrmg_status amrmg_solve_noalloc(amrmg_ctx *ctx, double *const *rho, double *con
 
 /* Interpolate E to particles with the deposit's CIC weights, on the finest
  * level whose boxes hold all 8 stencil cells.  Ex, Ey, Ez device [n];
- * particles outside the domain get 0. */
+ * particles outside the domain get 0.  When n equals the particle count of
+ * the last build, its spatial visiting order is used (the arrays are taken
+ * to hold the same particles, perhaps moved): E is computed in that order
+ * into a staging buffer of 32 n bytes, which the context allocates on first
+ * use and keeps, and then written in the caller's order; when the buffer
+ * cannot be allocated E is written at its places directly (same values). */
 amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y,
                           const void *z, int64_t n, double *const *E, double *Ex, double *Ey,
                           double *Ez);
@@ -281,7 +286,8 @@ amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *x, const vo
  * build's copy of them in spatial order instead of the caller's arrays: the
  * gather of a PIC step at the positions it deposited (Sec. 1's particle-mesh
  * cycle), with coalesced position reads; only the writes of E follow the
- * caller's order.  Ex, Ey, Ez device [n], n the particle count of that
+ * caller's order (through the staging buffer of amrmg_gather).  Ex, Ey, Ez
+ * device [n], n the particle count of that
  * build, in its order.  AMRMG_E_STATE when no hierarchy is built or the
  * build kept no copy (as amrmg_deposit_built).  The particle arrays given to
  * the build may have changed since: the result is that at the build's

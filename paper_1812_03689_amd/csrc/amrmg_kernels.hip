@@ -1862,15 +1862,48 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
     }
 }
 
+// Two cells adjacent along x in one row of a box: one 16-byte load (8-byte
+// alignment is enough for a global load on CDNA).
+typedef double dpair __attribute__((ext_vector_type(2)));
+typedef dpair dpair_a8 __attribute__((aligned(8)));
+
+// Corners of a CIC stencil: bit d of c selects the upper cell along axis d;
+// st[d]: the stencil crosses a brick face along d.  A corner is "fresh"
+// when every upper axis of it crosses, so that its brick differs from the
+// bricks of the corners below it; spread_corners copies the value of each
+// fresh corner to the corners in the same brick (the bits of axes without a
+// crossing cleared), with fixed indices only.
+__device__ __forceinline__ bool corner_fresh(int c, const bool *st)
+{
+    return (!(c & 1) || st[0]) && (!(c & 2) || st[1]) && (!(c & 4) || st[2]);
+}
+
+template <class V>
+__device__ __forceinline__ void spread_corners(const bool *st, V *v)
+{
+    v[1] = st[0] ? v[1] : v[0];
+    v[2] = st[1] ? v[2] : v[0];
+    v[3] = st[1] ? (st[0] ? v[3] : v[2]) : v[1];
+    v[4] = st[2] ? v[4] : v[0];
+    v[5] = st[2] ? (st[0] ? v[5] : v[4]) : v[1];
+    v[6] = st[2] ? (st[1] ? v[6] : v[4]) : v[2];
+    v[7] = st[2] ? (st[1] ? (st[0] ? v[7] : v[6]) : v[5]) : v[3];
+}
+
 // E at every particle from the finest level whose boxes hold all 8 cells of
 // its CIC stencil; particles are visited in the given (spatially sorted)
 // order so that neighbouring threads read neighbouring field cells.  ORD:
 // the positions are already in that order (x[i] is particle perm[i]), so
-// only the writes go through perm.
+// only the writes go through perm, or, with rec, E goes to rec[i] in the
+// visiting order for k_unpermute.  Boxes are unions of whole bricks, so the
+// stencil's 8 cells lie in at most two bricks per axis: each distinct brick
+// is looked up once (mostly one brick in all), and when the two x cells of
+// the stencil share a brick row they are read together.  Same sums in the
+// same order as cell by cell.
 template <class P, bool ORD>
 __global__ void __launch_bounds__(256) k_gather(int64_t n, const P *x, const P *y, const P *z, const uint32_t *perm,
                                                 GatherArgs G, const int64_t *ubase, const int2 *ustr, double *Ex,
-                                                double *Ey, double *Ez)
+                                                double *Ey, double *Ez, double4 *rec)
 {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
@@ -1883,24 +1916,102 @@ __global__ void __launch_bounds__(256) k_gather(int64_t n, const P *x, const P *
         int i0[3], i1[3];
         double f[3];
         if (!cic_stencil<P>(D, X, Y, Z, i0, i1, f)) break;
-        int64_t u[8];
-        bool ok = true;
-        for (int c = 0; c < 8; ++c) {
-            u[c] = user_index(D, ubase, ustr, (c & 1) ? i1[0] : i0[0], (c & 2) ? i1[1] : i0[1],
-                              (c & 4) ? i1[2] : i0[2]);
-            ok = ok && u[c] >= 0;
+        // st[d]: the stencil crosses a brick face along d
+        const int bstride[3] = {1, D.nbk[0], D.nbk[0] * D.nbk[1]};
+        bool st[3];
+        int base = 0, off[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            base += (i0[d] >> 3) * bstride[d];
+            st[d] = (i1[d] >> 3) != (i0[d] >> 3);
+            off[d] = st[d] ? bstride[d] : 0;
         }
+        // brick of corner c (bit d of c: the upper cell along d), looked up
+        // for the corners whose upper axes all cross a brick face; every
+        // other corner shares the brick of one of those
+        int g[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            g[c] = -1;
+            if (corner_fresh(c, st))
+                g[c] = D.bmap[base + ((c & 1) ? off[0] : 0) + ((c & 2) ? off[1] : 0) + ((c & 4) ? off[2] : 0)];
+        }
+        spread_corners(st, g);
+        bool ok = true;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) ok = ok && g[c] >= 0;
         if (!ok) continue;
+        int64_t u[8];
+        {
+            int64_t ub[8];
+            int usx[8], usy[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                ub[c] = 0;
+                usx[c] = usy[c] = 0;
+                if (corner_fresh(c, st)) {
+                    ub[c] = ubase[g[c]];
+                    const int2 t = ustr[g[c]];
+                    usx[c] = t.x;
+                    usy[c] = t.y;
+                }
+            }
+            spread_corners(st, ub);
+            spread_corners(st, usx);
+            spread_corners(st, usy);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int ci = (c & 1) ? i1[0] : i0[0], cj = (c & 2) ? i1[1] : i0[1], ck = (c & 4) ? i1[2] : i0[2];
+                u[c] = ub[c] + (ci & 7) + (int64_t)usx[c] * (cj & 7) + (int64_t)usy[c] * (ck & 7);
+            }
+        }
+        // the field values of the 8 cells, x pairs with one load each when
+        // the upper x cell follows the lower one in the same brick row
+        double v[3][8];
+        if (!st[0] && i1[0] == i0[0] + 1) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int c = 0; c < 8; c += 2) {
+                    const dpair t = *(const dpair_a8 *)(G.E[3 * l + d] + u[c]);
+                    v[d][c] = t.x;
+                    v[d][c + 1] = t.y;
+                }
+        } else {
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) v[d][c] = G.E[3 * l + d][u[c]];
+        }
+#pragma unroll
         for (int c = 0; c < 8; ++c) {
             double w = ((c & 1) ? f[0] : 1.0 - f[0]) * ((c & 2) ? f[1] : 1.0 - f[1]) *
                        ((c & 4) ? f[2] : 1.0 - f[2]);
-            for (int d = 0; d < 3; ++d) e[d] += w * G.E[3 * l + d][u[c]];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) e[d] += w * v[d][c];
         }
         break;
+    }
+    if (rec) {
+        rec[i] = make_double4(e[0], e[1], e[2], 0.0);
+        return;
     }
     Ex[p] = e[0];
     Ey[p] = e[1];
     Ez[p] = e[2];
+}
+
+// E of particle p from its record in the visiting order (iperm[p] = its
+// place there): one 32-byte read at a scattered place, three coalesced writes
+__global__ void __launch_bounds__(256) k_unpermute(int64_t n, const uint32_t *iperm, const double4 *rec, double *Ex,
+                                                   double *Ey, double *Ez)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const double4 r = rec[iperm[p]];
+    Ex[p] = r.x;
+    Ey[p] = r.y;
+    Ez[p] = r.z;
 }
 
 // max |rho| over a level (per-workgroup partials, then one workgroup)
@@ -2138,28 +2249,30 @@ void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const
 template <class P, bool ORD>
 static void launch_gather_t(hipStream_t st, unsigned g, int64_t n, const void *x, const void *y, const void *z,
                             const uint32_t *perm, const GatherArgs &G, const int64_t *ubase, const int2 *ustr,
-                            double *Ex, double *Ey, double *Ez)
+                            double *Ex, double *Ey, double *Ez, double4 *rec)
 {
     AMRMG_LAUNCH((k_gather<P, ORD>), dim3(g), dim3(256), 0, st, n, (const P *)x, (const P *)y, (const P *)z, perm, G,
-                 ubase, ustr, Ex, Ey, Ez);
+                 ubase, ustr, Ex, Ey, Ez, rec);
 }
 
 void launch_gather(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
-                   const uint32_t *perm, const GatherArgs &G, const int64_t *ubase, const int2 *ustr, double *Ex,
-                   double *Ey, double *Ez, bool ordered)
+                   const uint32_t *perm, const uint32_t *iperm, const GatherArgs &G, const int64_t *ubase,
+                   const int2 *ustr, double *Ex, double *Ey, double *Ez, double4 *rec, bool ordered)
 {
     if (n <= 0) return;
     unsigned g = blocks_for(n, 256);
+    if (!perm || !iperm) rec = nullptr;
     if (ordered && perm) {
         if (pos_f32)
-            launch_gather_t<float, true>(st, g, n, x, y, z, perm, G, ubase, ustr, Ex, Ey, Ez);
+            launch_gather_t<float, true>(st, g, n, x, y, z, perm, G, ubase, ustr, Ex, Ey, Ez, rec);
         else
-            launch_gather_t<double, true>(st, g, n, x, y, z, perm, G, ubase, ustr, Ex, Ey, Ez);
+            launch_gather_t<double, true>(st, g, n, x, y, z, perm, G, ubase, ustr, Ex, Ey, Ez, rec);
     } else if (pos_f32) {
-        launch_gather_t<float, false>(st, g, n, x, y, z, perm, G, ubase, ustr, Ex, Ey, Ez);
+        launch_gather_t<float, false>(st, g, n, x, y, z, perm, G, ubase, ustr, Ex, Ey, Ez, rec);
     } else {
-        launch_gather_t<double, false>(st, g, n, x, y, z, perm, G, ubase, ustr, Ex, Ey, Ez);
+        launch_gather_t<double, false>(st, g, n, x, y, z, perm, G, ubase, ustr, Ex, Ey, Ez, rec);
     }
+    if (rec) AMRMG_LAUNCH(k_unpermute, dim3(g), dim3(256), 0, st, n, iperm, rec, Ex, Ey, Ez);
 }
 
 void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, double *scratch, uint8_t *tags)

@@ -185,17 +185,21 @@ void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const
                     bool big_tile = false);
 void launch_zero_levels(hipStream_t st, const DepArgs &A);
 // ordered: x, y, z are already in the order perm gives (x[i] is particle
-// perm[i], the build's ordered copy); E is written at perm[i]
+// perm[i], the build's ordered copy); E is written at perm[i].  With perm,
+// its inverse iperm and rec ([n] staging records), E goes to rec in the
+// visiting order first and then to the caller's order by a second pass that
+// reads rec through iperm (coalesced writes instead of scattered ones).
 void launch_gather(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
-                   const uint32_t *perm, const GatherArgs &G, const int64_t *ubase, const int2 *ustr, double *Ex,
-                   double *Ey, double *Ez, bool ordered = false);
+                   const uint32_t *perm, const uint32_t *iperm, const GatherArgs &G, const int64_t *ubase,
+                   const int2 *ustr, double *Ex, double *Ey, double *Ez, double4 *rec, bool ordered = false);
 void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, double *scratch, uint8_t *tags);
 void launch_fill(hipStream_t st, double *v, int64_t n, double val);
 // spatial visiting order of particles (counting sort into Morton-ordered
 // buckets of the level-0 grid n0, at most 128 per axis): perm [n]; with xs,
 // also the particles in that order (xs, ys, zs in the position type, qs).
-// key, slot: [n] each; count: [2 order_count_entries], start:
-// [order_count_entries]; temp: order_temp_bytes(order_count_entries) bytes
+// key, slot: [n] each (on return slot is the inverse of perm: perm[slot[p]]
+// == p); count: [2 order_count_entries], start: [order_count_entries];
+// temp: order_temp_bytes(order_count_entries) bytes
 size_t order_count_entries(const double *lo, const double *hi, const int *n0);
 // log2 of the visiting-order bucket edge in level-0 cells
 int order_bucket_shift(const double *lo, const double *hi, const int *n0);

@@ -49,6 +49,7 @@ amrmg_status compute_order(amrmg_ctx *ctx, int pos_dtype, const void *x, const v
                                   const void **zs, const double **qs)
 {
     ctx->perm = nullptr;
+    ctx->iperm = nullptr;
     ctx->perm_n = -1;
     if (n <= 0 || n > (int64_t)0x7fffffff) return AMRMG_OK;
     const amrmg_params &P = ctx->P;
@@ -73,6 +74,7 @@ amrmg_status compute_order(amrmg_ctx *ctx, int pos_dtype, const void *x, const v
                            cnt + 2 * entries, (uint32_t *)ctx->sort_vals.p, ctx->sort_tmp.p, ctx->sort_tmp.cap, nullptr,
                            nullptr, nullptr, nullptr));
     ctx->perm = (uint32_t *)ctx->sort_vals.p;
+    ctx->iperm = key + n;
     ctx->perm_n = n;
     if (copy) {
         *xs = cx;
@@ -199,6 +201,18 @@ static amrmg_status gather_args(const amrmg_ctx *ctx, double *const *E, GatherAr
     return AMRMG_OK;
 }
 
+// staging records of a gather of n particles in visiting order, or nullptr
+// (then the gather writes E at its scattered places directly)
+static double4 *gather_records(amrmg_ctx *ctx, int64_t n)
+{
+    if (n <= 0 || !ctx->iperm) return nullptr;
+    if (ctx->gather_rec.ensure(sizeof(double4) * (size_t)n) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return (double4 *)ctx->gather_rec.p;
+}
+
 extern "C" amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *x, const void *y, const void *z,
                                      int64_t n, double *const *E, double *Ex, double *Ey, double *Ez)
 {
@@ -208,9 +222,11 @@ extern "C" amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *
     if (!E || n < 0 || (n > 0 && (!x || !y || !z || !Ex || !Ey || !Ez))) return fail(AMRMG_E_INVALID, "bad arguments");
     GatherArgs G;
     ST_TRY(gather_args(ctx, E, G));
+    const bool ord = ctx->perm_n == n;
+    double4 *rec = ord ? gather_records(ctx, n) : nullptr;
     ctx->prof.begin(AMRMG_K_GATHER);
-    launch_gather(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, ctx->perm_n == n ? ctx->perm : nullptr, G,
-                  ctx->ds.M.ubase, ctx->ds.M.ustr, Ex, Ey, Ez);
+    launch_gather(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, ord ? ctx->perm : nullptr,
+                  ord ? ctx->iperm : nullptr, G, ctx->ds.M.ubase, ctx->ds.M.ustr, Ex, Ey, Ez, rec);
     ctx->prof.end(AMRMG_K_GATHER, (double)n * (3.0 * (pos_dtype == AMRMG_POS_F32 ? 4 : 8) + 24.0));
     HIP_TRY(hipGetLastError());
     return AMRMG_OK;
@@ -231,9 +247,10 @@ extern "C" amrmg_status amrmg_gather_built(amrmg_ctx *ctx, double *const *E, dou
     const char *base = (const char *)ctx->sorted.p;
     const char *xs = base + align256((size_t)n * 8), *ys = xs + align256((size_t)n * ps),
                *zs = ys + align256((size_t)n * ps);
+    double4 *rec = gather_records(ctx, n);
     ctx->prof.begin(AMRMG_K_GATHER);
-    launch_gather(ctx->st, pos == AMRMG_POS_F32, n, xs, ys, zs, ctx->perm, G, ctx->ds.M.ubase, ctx->ds.M.ustr, Ex, Ey,
-                  Ez, true);
+    launch_gather(ctx->st, pos == AMRMG_POS_F32, n, xs, ys, zs, ctx->perm, ctx->iperm, G, ctx->ds.M.ubase,
+                  ctx->ds.M.ustr, Ex, Ey, Ez, rec, true);
     ctx->prof.end(AMRMG_K_GATHER, (double)n * (3.0 * ps + 4.0 + 24.0));
     HIP_TRY(hipGetLastError());
     return AMRMG_OK;

@@ -8,7 +8,7 @@
 // order inside a bucket does not matter (it is the order in which the
 // particles claimed their slots).  Passes: count with slot claims, the
 // counts in bucket order, exclusive scan (amrmg_scan.hip), scatter of the
-// order, ordered copy.
+// order (which also leaves its inverse), ordered copy.
 #include <hip/hip_runtime.h>
 
 #include "amrmg_kernels.hpp"
@@ -73,14 +73,16 @@ __global__ void __launch_bounds__(256) k_bucket_gather(BucketGrid G, const uint3
     if (k <= G.nbkt) ordered[k] = count[counter_of(G, k)];
 }
 
-// perm[dst] = p at dst = start of p's bucket + p's slot
-__global__ void __launch_bounds__(256) k_bucket_scatter(int64_t n, const uint32_t *key, const uint32_t *slot,
+// perm[dst] = p at dst = start of p's bucket + p's slot; the slot is then
+// replaced by dst, so that slot holds the inverse order (a coalesced write)
+__global__ void __launch_bounds__(256) k_bucket_scatter(int64_t n, const uint32_t *key, uint32_t *slot,
                                                         const uint32_t *start, uint32_t *perm)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
     const uint32_t dst = start[key[p]] + slot[p];
     perm[dst] = (uint32_t)p;
+    slot[p] = dst;
 }
 
 // the particles in visiting order (random reads, coalesced writes: faster

@@ -318,7 +318,11 @@ struct amrmg_ctx {
     DBuf sort_keys, sort_vals, sort_cnt, sort_tmp;
     DBuf sorted;  // the particles of the last build in visiting order (charges, x, y, z)
     uint32_t *perm = nullptr;
+    uint32_t *iperm = nullptr;  // its inverse (perm[iperm[p]] == p)
     int64_t perm_n = -1;
+    // E of a gather in visiting order (one double4 per particle), before it
+    // is written in the caller's order
+    DBuf gather_rec;
     DBuf dep_count;
     // what the last build keeps for amrmg_deposit_built: the charge of each
     // level it deposited for tagging (caller's layout), the particle count

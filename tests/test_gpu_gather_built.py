@@ -52,6 +52,23 @@ def test_gather_built_equals_gather_and_oracle(pos_dtype):
         assert np.abs(g.cpu().numpy() - o).max() <= 1e-12 * np.abs(o).max()
 
 
+def test_visiting_order_and_caller_order_agree_bit_for_bit():
+    """The gather in the build's visiting order (E staged per particle, then
+    written in the caller's order through the inverse order) and the single
+    pass in the caller's order (taken for a particle count other than the
+    build's) give the same E bit for bit on the particles they share."""
+    w = workload()
+    ctx, (x, y, z), E = built(w, torch.float32)
+    a = ctx.gather_built(E)
+    m = x.numel() - 1
+    b = ctx.gather(x[:m], y[:m], z[:m], E)
+    c = ctx.gather(x, y, z, E)
+    torch.cuda.synchronize()
+    for u, v, t in zip(a, b, c):
+        assert torch.equal(u[:m], v)
+        assert torch.equal(u, t)
+
+
 def test_gather_built_after_the_arrays_change():
     w = workload()
     ctx, (x, y, z), E = built(w, torch.float64)
