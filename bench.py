@@ -400,12 +400,15 @@ def bench_paper(args):
             return W.Particles(*(a.cpu().numpy() for a in xyz), p.q)
 
         t0c = time.perf_counter()
+        print("oracle check: building the oracle's hierarchy", file=sys.stderr, flush=True)
         wb = W.Workload(w.name, host_particles(sets[state["built_from"]]), w.n0, w.max_level, w.tag_rel, [],
                         w.tol, max_grid_size=w.max_grid_size, lo=w.lo, hi=w.hi)
         H = O.hierarchy_from_workload(wb)
         same = H.nlev == info["nlevels"] and all(np.array_equal(H.boxes(l)[0], cm.boxes(l)[0])
                                                  for l in range(H.nlev))
+        print(f"oracle check: boxes equal {same}; depositing", file=sys.stderr, flush=True)
         orho = H.deposit_all(host_particles(sets[-1]))
+        print("oracle check: composite residual of the GPU solution", file=sys.stderr, flush=True)
         dep_err = [float(np.linalg.norm(rho[l].cpu().numpy() - orho[l]) / np.linalg.norm(orho[l]))
                    for l in range(H.nlev)]
         r = H.residual(orho, gphi)

@@ -451,12 +451,14 @@ __global__ void __launch_bounds__(64 * BPW) k_outer_residual(DevMeta M, int b0, 
                                                              const double *ffs)
 {
     __shared__ double rows_all[BPW][RW * RW * RS];
+    __shared__ int kids_all[BPW][56];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int k0 = xcd_remap(blockIdx.x, (nb + BPW - 1) / BPW) * BPW + w;
     const bool active = k0 < nb;
     const int kk = active ? k0 : nb - 1;
     const int b = __builtin_amdgcn_readfirstlane(list ? list[kk] : b0 + kk);
     double *rows = rows_all[w];
+    int *kids = kids_all[w];
     const int y = lane & 7, z = lane >> 3;
     const int lev = M.org[b].w;
     const LevelConst L = M.lc[lev];
@@ -475,6 +477,13 @@ __global__ void __launch_bounds__(64 * BPW) k_outer_residual(DevMeta M, int b0, 
     // every cell covered (wavefront-uniform): r = 0, nothing to load; the
     // wavefront still takes part in the workgroup's barrier
     const bool all_cov = cm == 0xffu;
+    // the children of the brick and of its face neighbours, for the fine
+    // sums of covered faces: kids[8 f + o] of face neighbour f, kids[48 + o]
+    // of the brick (-1 where none); read after the barrier below
+    if (!ZERO && any_cov && !all_cov && lane < 56) {
+        const int nbl = lane < 48 ? M.nbr[b * 6 + (lane >> 3)] : b;
+        kids[lane] = nbl >= 0 ? M.child[nbl * 8 + (lane & 7)] : -1;
+    }
     double rv[8], u[8], hs[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < 8; ++i) rv[i] = u[i] = 0.0;
@@ -548,7 +557,7 @@ __global__ void __launch_bounds__(64 * BPW) k_outer_residual(DevMeta M, int b0, 
                 Au -= ih2 * (uc - unb);
                 if (!ZERO) {
                     // the child covering that cell: of this brick, or of the face neighbour
-                    const int F = M.child[(inside ? b : nbf[f]) * 8 + qo];
+                    const int F = kids[inside ? 48 + qo : 8 * f + qo];
                     const int m = d == 0 ? (ly & 3) + 4 * (lz & 3) : (d == 1 ? (lx & 3) + 4 * (lz & 3)
                                                                                  : (lx & 3) + 4 * (ly & 3));
                     Au += -0.5 * ih2 * ffs[((size_t)F * 6 + 2 * d + (sg < 0)) * 16 + m];
@@ -605,48 +614,63 @@ __global__ void __launch_bounds__(256) k_user_brick(DevMeta M, int b0, int nb, c
 }
 
 // Norm of each listed brick range (one AMR level of one problem) from the
-// partials (two per brick), in a fixed order, by one workgroup.  With hout
-// set, the norms are also written to host-visible memory followed by a
-// sequence number (the device counter plus one), so that the host can poll
-// for them without synchronising the stream.
+// partials (two per brick), in a fixed order, by one workgroup.  The ranges
+// go in chunks of NORM_CHUNK: every wavefront sums its share of each range
+// of the chunk, then one thread per range adds the 16 wavefront sums (one
+// barrier per chunk, not two per range).  With hout set, the norms are also
+// written to host-visible memory followed by a sequence number (the device
+// counter plus one, read at the start so that its latency overlaps the
+// sums), so that the host can poll for them without synchronising the
+// stream.
+constexpr int NORM_CHUNK = 64;
 __global__ void __launch_bounds__(1024) k_level_norms(const int2 *ranges, int n, const double *part, double *out,
                                                       int norm_p, double *hout, unsigned *hseq, unsigned *counter)
 {
-    __shared__ double sh[16];
+    __shared__ double sh[16][NORM_CHUNK];
     const bool mx = norm_p == 0;
-    for (int l = 0; l < n; ++l) {
-        const int b0 = 2 * ranges[l].x, b1 = 2 * (ranges[l].x + ranges[l].y);
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int b = b0 + (int)threadIdx.x;
-        for (; b + 3 * 1024 < b1; b += 4 * 1024) {
-            double v0 = part[b], v1 = part[b + 1024], v2 = part[b + 2048], v3 = part[b + 3072];
-            a0 = mx ? fmax(a0, v0) : a0 + v0;
-            a1 = mx ? fmax(a1, v1) : a1 + v1;
-            a2 = mx ? fmax(a2, v2) : a2 + v2;
-            a3 = mx ? fmax(a3, v3) : a3 + v3;
+    const int wave = threadIdx.x >> 6;
+    unsigned seq = 0;
+    if (hout && threadIdx.x == 0) seq = *counter;
+    for (int l0 = 0; l0 < n; l0 += NORM_CHUNK) {
+        const int nl = n - l0 < NORM_CHUNK ? n - l0 : NORM_CHUNK;
+        for (int j = 0; j < nl; ++j) {
+            const int2 rg = ranges[l0 + j];
+            const int b0 = 2 * rg.x, b1 = 2 * (rg.x + rg.y);
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int b = b0 + (int)threadIdx.x;
+            for (; b + 3 * 1024 < b1; b += 4 * 1024) {
+                double v0 = part[b], v1 = part[b + 1024], v2 = part[b + 2048], v3 = part[b + 3072];
+                a0 = mx ? fmax(a0, v0) : a0 + v0;
+                a1 = mx ? fmax(a1, v1) : a1 + v1;
+                a2 = mx ? fmax(a2, v2) : a2 + v2;
+                a3 = mx ? fmax(a3, v3) : a3 + v3;
+            }
+            for (; b < b1; b += 1024) a0 = mx ? fmax(a0, part[b]) : a0 + part[b];
+            double acc = mx ? fmax(fmax(a0, a1), fmax(a2, a3)) : (a0 + a1) + (a2 + a3);
+            for (int o = 32; o > 0; o >>= 1) {
+                double w = __shfl_xor(acc, o, 64);
+                acc = mx ? fmax(acc, w) : acc + w;
+            }
+            if ((threadIdx.x & 63) == 0) sh[wave][j] = acc;
         }
-        for (; b < b1; b += 1024) a0 = mx ? fmax(a0, part[b]) : a0 + part[b];
-        double acc = mx ? fmax(fmax(a0, a1), fmax(a2, a3)) : (a0 + a1) + (a2 + a3);
-        for (int o = 32; o > 0; o >>= 1) {
-            double w = __shfl_xor(acc, o, 64);
-            acc = mx ? fmax(acc, w) : acc + w;
-        }
-        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double r = sh[0];
-            for (int i = 1; i < 16; ++i) r = mx ? fmax(r, sh[i]) : r + sh[i];
+        if ((int)threadIdx.x < nl) {
+            const int j = threadIdx.x;
+            double r = sh[0][j];
+            for (int i = 1; i < 16; ++i) r = mx ? fmax(r, sh[i][j]) : r + sh[i][j];
             r = norm_p == 2 ? sqrt(r) : r;
-            out[l] = r;
-            if (hout) hout[l] = r;
+            out[l0 + j] = r;
+            if (hout) {
+                hout[l0 + j] = r;
+                __threadfence_system();
+            }
         }
         __syncthreads();
     }
     if (hout && threadIdx.x == 0) {
         __threadfence_system();
-        const unsigned s = *counter + 1;
-        *counter = s;
-        *(volatile unsigned *)hseq = s;
+        *counter = seq + 1;
+        *(volatile unsigned *)hseq = seq + 1;
     }
 }
 
@@ -821,6 +845,25 @@ __device__ __forceinline__ size_t parent_cell(int p, int x, int y, int z)
            64 * ((oc >> 2) * 4 + (z >> 1));
 }
 
+// Lane-wise choice of a (lane's bit of m clear) or b (set), m a wavefront
+// mask from a ballot, as v_cndmask in asm: a choice between two elements of
+// a register array written as C++ is rewritten by the compiler into one
+// access at a computed index, which moves the array into private memory.
+__device__ __forceinline__ float lane_pick(uint64_t m, float a, float b)
+{
+    float r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(m));
+    return r;
+}
+__device__ __forceinline__ double lane_pick(uint64_t m, double a, double b)
+{
+    const uint64_t ia = (uint64_t)__double_as_longlong(a), ib = (uint64_t)__double_as_longlong(b);
+    uint32_t lo, hi;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(lo) : "v"((uint32_t)ia), "v"((uint32_t)ib), "s"(m));
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(hi) : "v"((uint32_t)(ia >> 32)), "v"((uint32_t)(ib >> 32)), "s"(m));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 template <class T, int MODE, int BPW>
 __global__ void __launch_bounds__(64 * BPW) k_hgs(DevMeta M, int b0, int nb, const T *ein, T *eout, const T *r,
                                                   T *cp, double *phib, double *ffs)
@@ -912,30 +955,33 @@ __global__ void __launch_bounds__(64 * BPW) k_hgs(DevMeta M, int b0, int nb, con
     const T inv_mid = (T)1 / den, inv_x0 = (T)1 / (den - ih2x * ag[0]), inv_x7 = (T)1 / (den - ih2x * ag[1]);
     __syncthreads();
     // red (colour 0) then black: cell x of row (y, z) has colour (x + y + z)
-    // & 1.  Every lane evaluates all 8 cells of its row and keeps the results
-    // of the pass's colour, so the row's registers are indexed only by
-    // compile-time constants (a lane-dependent choice between two of them
-    // would be turned into an indexed access to private memory).
+    // & 1, so in each pair of cells (2k, 2k + 1) of the row exactly one
+    // takes part in a pass, the one at x = 2k + p with p = (y + z + pass) &
+    // 1.  Its operands are chosen from the row's registers by selects
+    // between fixed elements (a lane-dependent register index would be
+    // turned into an indexed access to private memory); its LDS neighbours
+    // are read at the lane's own offset.
     const int q = (y + z) & 1;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        T nv[8];
+        const bool p = ((q + c) & 1) != 0;
+        const uint64_t pm = __builtin_amdgcn_ballot_w64(p);
 #pragma unroll
-        for (int x = 0; x < 8; ++x) {
-            const T xm = x == 0 ? hxm : er[x - 1];
-            const T xp = x == 7 ? hxp : er[x + 1];
-            const T wxm = x == 7 ? wxm7 : (T)1, wxp = x == 0 ? wxp0 : (T)1;
-            const T inv = x == 0 ? inv_x0 : (x == 7 ? inv_x7 : inv_mid);
-            const T num = rr[x] + ih2x * (wxm * xm + wxp * xp) +
+        for (int k = 0; k < 4; ++k) {
+            const int x = 2 * k + (p ? 1 : 0);
+            const T xm = lane_pick(pm, k == 0 ? hxm : er[2 * k - 1], er[2 * k]);
+            const T xp = lane_pick(pm, er[2 * k + 1], k == 3 ? hxp : er[2 * k + 2]);
+            const T rx = lane_pick(pm, rr[2 * k], rr[2 * k + 1]);
+            const T wxm = k == 3 ? lane_pick(pm, (T)1, wxm7) : (T)1;
+            const T wxp = k == 0 ? lane_pick(pm, wxp0, (T)1) : (T)1;
+            const T inv = k == 0 ? lane_pick(pm, inv_x0, inv_mid) : (k == 3 ? lane_pick(pm, inv_mid, inv_x7) : inv_mid);
+            const T num = rx + ih2x * (wxm * xm + wxp * xp) +
                           ih2y * (wym * rows[rym + x] + wyp * rows[ryp + x]) +
                           ih2z * (wzm * rows[rzm + x] + wzp * rows[rzp + x]);
-            nv[x] = num * inv;
-        }
-#pragma unroll
-        for (int x = 0; x < 8; ++x) {
-            const bool mine = ((x + q + c) & 1) == 0;
-            er[x] = mine ? nv[x] : er[x];
-            if (mine) rows[rme + x] = nv[x];
+            const T nv = num * inv;
+            er[2 * k] = p ? er[2 * k] : nv;
+            er[2 * k + 1] = p ? nv : er[2 * k + 1];
+            rows[rme + x] = nv;
         }
         __syncthreads();
     }
