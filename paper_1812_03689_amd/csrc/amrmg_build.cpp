@@ -478,7 +478,6 @@ static amrmg_status tag_geometry(amrmg_ctx *ctx, const HostLevel &L, TagGeom &G)
     G.ng = (size_t)G.g.x * G.g.y * G.g.z;
     HIP_TRY(ctx->tag_scratch.ensure(sizeof(double) * 1040));
     HIP_TRY(ctx->tag_marks.ensure(G.ng));
-    HIP_TRY(ctx->tag_host.ensure(G.ng));
     HIP_TRY(hipMemsetAsync(ctx->tag_marks.p, 0, G.ng, st));
     return AMRMG_OK;
 }
@@ -492,14 +491,22 @@ static void tag_mark(amrmg_ctx *ctx, const TagGeom &G, const double *v, double l
                        (uint8_t *)ctx->tag_marks.p);
 }
 
-// the marks to the host, then proper nesting and the greedy merge
+// proper nesting on the device, the nested marks to the host as bits (one
+// per block), then the greedy merge
 static amrmg_status tag_boxes(amrmg_ctx *ctx, const HostLevel &L, const TagGeom &G, std::vector<Box> &boxes)
 {
     const amrmg_params &P = ctx->P;
-    HIP_TRY(hipMemcpyAsync(ctx->tag_host.p, ctx->tag_marks.p, G.ng, hipMemcpyDeviceToHost, ctx->st));
+    const size_t nw = (G.ng + 63) / 64;
+    HIP_TRY(ctx->tag_bits.ensure(8 * nw));
+    HIP_TRY(ctx->tag_host.ensure(8 * nw));
+    launch_nest_pack(ctx->st, (const uint8_t *)ctx->tag_marks.p, (int64_t)G.ng, G.g, G.bmap,
+                     make_int3(L.n[0], L.n[1], L.n[2]), make_int3(L.nbk[0], L.nbk[1], L.nbk[2]),
+                     P.blocking_factor / 2, P.n_proper, (uint64_t *)ctx->tag_bits.p);
+    HIP_TRY(hipMemcpyAsync(ctx->tag_host.p, ctx->tag_bits.p, 8 * nw, hipMemcpyDeviceToHost, ctx->st));
     HIP_TRY(hipStreamSynchronize(ctx->st));
     HIP_TRY(hipGetLastError());
-    boxes = merge_blocks(L, (uint8_t *)ctx->tag_host.p, P.n_proper, P.blocking_factor, P.max_grid_size);
+    const int g[3] = {G.g.x, G.g.y, G.g.z};
+    boxes = merge_block_bits(g, (uint64_t *)ctx->tag_host.p, P.blocking_factor, P.max_grid_size);
     return AMRMG_OK;
 }
 

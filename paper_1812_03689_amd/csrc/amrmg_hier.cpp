@@ -123,23 +123,19 @@ void mark_blocks(const HostLevel &L, const uint8_t *tags, int n_buffer, int bf, 
     }
 }
 
-std::vector<Box> merge_blocks(const HostLevel &L, uint8_t *mark, int n_proper, int bf, int max_grid_size)
+void nest_blocks(const HostLevel &L, uint8_t *mark, int n_proper, int bf)
 {
     const int half = bf / 2;
     int g[3];
     for (int d = 0; d < 3; ++d) g[d] = 2 * L.n[d] / bf;
-    auto at = [&](int x, int y, int z) { return (size_t)x + (size_t)g[0] * ((size_t)y + (size_t)g[1] * z); };
-    // the scans below visit blocks in linear order (z slowest, x fastest) and
-    // skip eight blocks at a time where a word of marks holds none they want
     const size_t total = (size_t)g[0] * g[1] * g[2];
-    auto word = [&](size_t t) {
-        uint64_t w;
-        std::memcpy(&w, mark + t, 8);
-        return w;
-    };
-    // 3: proper nesting
+    // skip eight blocks at a time where a word of marks holds none
     for (size_t t0 = 0; t0 < total; t0 += 8) {
-        if (t0 + 8 <= total && word(t0) == 0) continue;
+        if (t0 + 8 <= total) {
+            uint64_t w;
+            std::memcpy(&w, mark + t0, 8);
+            if (w == 0) continue;
+        }
         for (size_t t = t0; t < std::min(t0 + 8, total); ++t) {
             if (!mark[t]) continue;
             int blk[3] = {(int)(t % g[0]), (int)((t / g[0]) % g[1]), (int)(t / ((size_t)g[0] * g[1]))}, lo[3], hi[3];
@@ -147,46 +143,96 @@ std::vector<Box> merge_blocks(const HostLevel &L, uint8_t *mark, int n_proper, i
             if (!region_inside(L, lo, hi)) mark[t] = 0;
         }
     }
-    // 4-5: greedy merge, z slowest, x fastest; mark value 2 = taken
+}
+
+// bit t of a block bit array (block t = x + g0 (y + g1 z)): word t / 64, bit t % 64
+static bool bits_all_set(const uint64_t *b, size_t t, int e)
+{
+    while (e > 0) {
+        const size_t w = t >> 6;
+        const int o = (int)(t & 63), k = std::min(e, 64 - o);
+        const uint64_t m = (k == 64 ? ~0ull : ((1ull << k) - 1)) << o;
+        if ((b[w] & m) != m) return false;
+        t += k;
+        e -= k;
+    }
+    return true;
+}
+
+static void bits_clear(uint64_t *b, size_t t, int e)
+{
+    while (e > 0) {
+        const size_t w = t >> 6;
+        const int o = (int)(t & 63), k = std::min(e, 64 - o);
+        b[w] &= ~((k == 64 ? ~0ull : ((1ull << k) - 1)) << o);
+        t += k;
+        e -= k;
+    }
+}
+
+// the number of consecutive set bits from t, at most lim
+static int bits_run(const uint64_t *b, size_t t, int lim)
+{
+    int run = 0;
+    while (run < lim) {
+        const size_t w = t >> 6;
+        const int o = (int)(t & 63), k = std::min(lim - run, 64 - o);
+        const uint64_t v = ~(b[w] >> o);  // clear where the bits are set; the o vacated top bits read as clear blocks
+        const int ones = std::min(v == 0 ? 64 : __builtin_ctzll(v), k);
+        run += ones;
+        if (ones < k) break;
+        t += k;
+    }
+    return run;
+}
+
+std::vector<Box> merge_block_bits(const int g[3], uint64_t *bits, int bf, int max_grid_size)
+{
     const int maxb = max_grid_size / bf;
+    const size_t total = (size_t)g[0] * g[1] * g[2], nw = (total + 63) / 64;
+    auto at = [&](int x, int y, int z) { return (size_t)x + (size_t)g[0] * ((size_t)y + (size_t)g[1] * z); };
     std::vector<Box> out;
-    auto avail = [&](int x, int y, int z) { return mark[at(x, y, z)] == 1; };
-    for (size_t t0 = 0; t0 < total; t0 += 8) {
-        if (t0 + 8 <= total && (word(t0) & 0x0101010101010101ull) == 0) continue;  // no mark 1 (marks are 0, 1, 2)
-        for (size_t t = t0; t < std::min(t0 + 8, total); ++t) {
+    for (size_t w = 0; w < nw; ++w) {
+        // the lowest available block starts a box; a box clears only blocks
+        // after it in linear order, so taking the lowest set bit of the word
+        // again visits the blocks in the same order as a linear scan
+        while (bits[w]) {
+            const size_t t = w * 64 + (size_t)__builtin_ctzll(bits[w]);
             const int x = (int)(t % g[0]), y = (int)((t / g[0]) % g[1]), z = (int)(t / ((size_t)g[0] * g[1]));
-            {
-                if (!avail(x, y, z)) continue;
-                int ex = 1, ey = 1, ez = 1;
-                while (x + ex < g[0] && ex < maxb && avail(x + ex, y, z)) ++ex;
-                while (y + ey < g[1] && ey < maxb) {
-                    bool row = true;
-                    for (int a = 0; a < ex && row; ++a) row = avail(x + a, y + ey, z);
-                    if (!row) break;
-                    ++ey;
-                }
-                while (z + ez < g[2] && ez < maxb) {
-                    bool slab = true;
-                    for (int c = 0; c < ey && slab; ++c)
-                        for (int a = 0; a < ex && slab; ++a) slab = avail(x + a, y + c, z + ez);
-                    if (!slab) break;
-                    ++ez;
-                }
-                for (int c3 = 0; c3 < ez; ++c3)
-                    for (int c2 = 0; c2 < ey; ++c2)
-                        for (int c1 = 0; c1 < ex; ++c1) mark[at(x + c1, y + c2, z + c3)] = 2;
-                Box B;
-                B.lo[0] = x * bf;
-                B.lo[1] = y * bf;
-                B.lo[2] = z * bf;
-                B.hi[0] = (x + ex) * bf;
-                B.hi[1] = (y + ey) * bf;
-                B.hi[2] = (z + ez) * bf;
-                out.push_back(B);
+            const int ex = bits_run(bits, t, std::min(maxb, g[0] - x));
+            int ey = 1, ez = 1;
+            while (y + ey < g[1] && ey < maxb && bits_all_set(bits, at(x, y + ey, z), ex)) ++ey;
+            while (z + ez < g[2] && ez < maxb) {
+                bool slab = true;
+                for (int c = 0; c < ey && slab; ++c) slab = bits_all_set(bits, at(x, y + c, z + ez), ex);
+                if (!slab) break;
+                ++ez;
             }
+            for (int c3 = 0; c3 < ez; ++c3)
+                for (int c2 = 0; c2 < ey; ++c2) bits_clear(bits, at(x, y + c2, z + c3), ex);
+            Box B;
+            B.lo[0] = x * bf;
+            B.lo[1] = y * bf;
+            B.lo[2] = z * bf;
+            B.hi[0] = (x + ex) * bf;
+            B.hi[1] = (y + ey) * bf;
+            B.hi[2] = (z + ez) * bf;
+            out.push_back(B);
         }
     }
     return out;
+}
+
+std::vector<Box> merge_blocks(const HostLevel &L, uint8_t *mark, int n_proper, int bf, int max_grid_size)
+{
+    nest_blocks(L, mark, n_proper, bf);
+    int g[3];
+    for (int d = 0; d < 3; ++d) g[d] = 2 * L.n[d] / bf;
+    const size_t total = (size_t)g[0] * g[1] * g[2];
+    std::vector<uint64_t> bits((total + 63) / 64, 0);
+    for (size_t t = 0; t < total; ++t)
+        if (mark[t] == 1) bits[t >> 6] |= 1ull << (t & 63);
+    return merge_block_bits(g, bits.data(), bf, max_grid_size);
 }
 
 std::vector<Box> generate_boxes(const HostLevel &L, const uint8_t *tags, int n_buffer, int n_proper, int bf,

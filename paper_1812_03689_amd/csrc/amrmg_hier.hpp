@@ -52,6 +52,13 @@ std::vector<Box> generate_boxes(const HostLevel &L, const uint8_t *tags, int n_b
 // block mask (which it modifies)
 void mark_blocks(const HostLevel &L, const uint8_t *tags, int n_buffer, int bf, std::vector<uint8_t> &mark);
 std::vector<Box> merge_blocks(const HostLevel &L, uint8_t *mark, int n_proper, int bf, int max_grid_size);
+// the two steps of merge_blocks: proper nesting (unmarks blocks whose coarse
+// footprint grown by n_proper cells leaves the bricks of L), and the greedy
+// merge of a nested mask given as bits in linear block order (bit t % 64 of
+// word t / 64 for block t = x + g0 (y + g1 z), g = 2 n / bf blocks per
+// axis; the bits are consumed)
+void nest_blocks(const HostLevel &L, uint8_t *mark, int n_proper, int bf);
+std::vector<Box> merge_block_bits(const int g[3], uint64_t *bits, int bf, int max_grid_size);
 
 // Check boxes of a refined level against its coarser level: 8-alignment,
 // inside the index space, disjoint, and proper nesting.  Empty string = ok.

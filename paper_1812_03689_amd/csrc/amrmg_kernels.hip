@@ -2134,6 +2134,37 @@ __global__ void __launch_bounds__(256) k_fill_multi(DepArgs A, int64_t total, co
     (void)total;
 }
 
+// Proper nesting of the marked blocks of the finer level: a block stays
+// marked when its footprint on the coarse level (half coarse cells per block
+// edge), grown by np cells and clipped to the level's index space cn, lies
+// in bricks of the coarse level (cbmap over its brick grid cnbk).  The marks
+// are packed into bits in linear block order, word t / 64 holding block t at
+// bit t % 64, for the greedy merge on the host.
+__global__ void __launch_bounds__(256) k_nest_pack(const uint8_t *marks, int64_t total, int3 g, const int32_t *cbmap,
+                                                   int3 cn, int3 cnbk, int half, int np, uint64_t *bits)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool keep = false;
+    if (t < total && marks[t]) {
+        const int blk[3] = {(int)(t % g.x), (int)((t / g.x) % g.y), (int)(t / ((int64_t)g.x * g.y))};
+        const int nn[3] = {cn.x, cn.y, cn.z};
+        int b0[3], b1[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int lo = max(0, blk[d] * half - np), hi = min(nn[d], (blk[d] + 1) * half + np);
+            b0[d] = lo >> 3;
+            b1[d] = (hi - 1) >> 3;
+        }
+        keep = true;
+        for (int bz = b0[2]; bz <= b1[2] && keep; ++bz)
+            for (int by = b0[1]; by <= b1[1] && keep; ++by)
+                for (int bx = b0[0]; bx <= b1[0] && keep; ++bx)
+                    keep = cbmap[bx + (int64_t)cnbk.x * (by + (int64_t)cnbk.y * bz)] >= 0;
+    }
+    const uint64_t m = __ballot(keep);
+    if ((threadIdx.x & 63) == 0 && t < total) bits[t >> 6] = m;
+}
+
 __global__ void __launch_bounds__(256) k_fill(double *v, int64_t n, double val)
 {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -2409,6 +2440,14 @@ void launch_copy(hipStream_t st, const T *a, T *b, int64_t n)
 {
     if (n <= 0) return;
     AMRMG_LAUNCH((k_copy<T>), dim3(blocks_for(n, 256)), dim3(256), 0, st, a, b, n);
+}
+
+void launch_nest_pack(hipStream_t st, const uint8_t *marks, int64_t total, int3 g, const int32_t *cbmap, int3 cn,
+                      int3 cnbk, int half, int np, uint64_t *bits)
+{
+    if (total <= 0) return;
+    AMRMG_LAUNCH(k_nest_pack, dim3(blocks_for(total, 256)), dim3(256), 0, st, marks, total, g, cbmap, cn, cnbk, half, np,
+                 bits);
 }
 
 void launch_mark_blocks(hipStream_t st, const double *rho, int64_t ncell, const int4 *borg, const int64_t *ubase,

@@ -211,6 +211,12 @@ hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x,
                           const double *q, const double *lo, const double *hi, const int *n0, uint32_t *key,
                           uint32_t *slot, uint32_t *count, uint32_t *start, uint32_t *perm, void *temp,
                           size_t temp_bytes, void *xs, void *ys, void *zs, double *qs);
+// proper nesting of the block marks of the finer level (g blocks per axis,
+// total = their product) against the coarse level (index extent cn, brick
+// map cbmap over cnbk bricks; half coarse cells per block edge, nesting by np
+// cells), packed into bits [(total + 63) / 64] in linear block order
+void launch_nest_pack(hipStream_t st, const uint8_t *marks, int64_t total, int3 g, const int32_t *cbmap, int3 cn,
+                      int3 cnbk, int half, int np, uint64_t *bits);
 void launch_mark_blocks(hipStream_t st, const double *rho, int64_t ncell, const int4 *borg, const int64_t *ubase,
                         const int2 *ustr, int nb, double lambda, int nbuf, int half, int3 n, int3 g, double *scratch,
                         uint8_t *marks);

@@ -311,7 +311,7 @@ struct amrmg_ctx {
     bool built = false;
     DevState ds;
     // scratch of the tagging passes of build_hierarchy
-    DBuf tag_marks, tag_scratch, tag_geom, tag_fields;
+    DBuf tag_marks, tag_scratch, tag_geom, tag_fields, tag_bits;
     PBuf tag_stage, tag_host;
     // spatial visiting order of the particles (a performance hint for the
     // deposit; any order gives the same sums up to rounding)
