@@ -31,6 +31,26 @@ extern "C" int hs_generate_boxes(const int32_t *n, int nb, const int32_t *boxes,
     return (int)o.size();
 }
 
+// greedy merge of a block mask (bytes, 1 = available, x fastest over g[0] x
+// g[1] x g[2] blocks) through the product's bit-array merge; returns the box
+// count (boxes in block units: lo, hi) or -1 when out holds too few rows
+extern "C" int hs_merge_block_bits(const int32_t *g, const uint8_t *mask, int maxb, int32_t *out, int cap)
+{
+    const size_t total = (size_t)g[0] * g[1] * g[2];
+    std::vector<uint64_t> bits((total + 63) / 64, 0);
+    for (size_t t = 0; t < total; ++t)
+        if (mask[t]) bits[t >> 6] |= 1ull << (t & 63);
+    const int gg[3] = {g[0], g[1], g[2]};
+    std::vector<Box> o = merge_block_bits(gg, bits.data(), 1, maxb);
+    if ((int)o.size() > cap) return -1;
+    for (size_t b = 0; b < o.size(); ++b)
+        for (int d = 0; d < 3; ++d) {
+            out[6 * b + d] = o[b].lo[d];
+            out[6 * b + 3 + d] = o[b].hi[d];
+        }
+    return (int)o.size();
+}
+
 // levels given as box lists; returns rows (i,j,k,d,s,pattern) of the CF ghost
 // faces of AMR level `level`
 extern "C" long hs_cf_patterns(const int32_t *n0, int nlev, const int32_t *nbox, const int32_t *boxes, int level,

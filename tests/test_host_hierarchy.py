@@ -27,6 +27,7 @@ def shim(tmp_path_factory):
                                     C.c_int, C.c_void_p, C.c_int]
     L.hs_cf_patterns.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_long]
     L.hs_cf_patterns.restype = C.c_long
+    L.hs_merge_block_bits.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int]
     L.hs_tables.argtypes = [C.c_void_p, C.c_void_p]
     L.hs_direct_tables.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_long]
     L.hs_direct_tables.restype = C.c_long
@@ -108,6 +109,54 @@ HIERS = {
     "touch_boundary": ((16, 16, 16), [[(0, 8, 8, 16, 24, 16), (16, 8, 8, 24, 16, 24)]]),
     "corner_blocks": ((32, 32, 32), [[(16, 16, 16, 32, 32, 32), (32, 32, 16, 48, 48, 32), (32, 16, 32, 48, 32, 48)]]),
 }
+
+
+def greedy_merge_reference(mask, g, maxb):
+    """The greedy merge written out on a byte mask: blocks in linear order (x
+    fastest); an available block starts a box that grows along x, then y,
+    then z while whole rows (slabs) are available, at most maxb blocks per
+    axis; its blocks are then taken."""
+    m = mask.reshape(g[2], g[1], g[0]).copy()
+    boxes = []
+    for z in range(g[2]):
+        for y in range(g[1]):
+            for x in range(g[0]):
+                if m[z, y, x] != 1:
+                    continue
+                ex = 1
+                while x + ex < g[0] and ex < maxb and m[z, y, x + ex] == 1:
+                    ex += 1
+                ey = 1
+                while y + ey < g[1] and ey < maxb and (m[z, y + ey, x:x + ex] == 1).all():
+                    ey += 1
+                ez = 1
+                while z + ez < g[2] and ez < maxb and (m[z + ez, y:y + ey, x:x + ex] == 1).all():
+                    ez += 1
+                m[z:z + ez, y:y + ey, x:x + ex] = 2
+                boxes.append((x, y, z, x + ex, y + ey, z + ez))
+    return np.asarray(boxes, dtype=np.int32).reshape(-1, 6)
+
+
+@pytest.mark.parametrize("g,maxb,fill", [((70, 5, 4), 4, 0.7), ((13, 9, 7), 3, 0.5), ((130, 3, 3), 100, 0.95),
+                                          ((64, 4, 2), 64, 1.0), ((1, 1, 1), 4, 1.0), ((33, 17, 5), 8, 0.0)])
+def test_bit_array_merge_matches_byte_greedy(shim, g, maxb, fill):
+    """The product's greedy merge on a bit array (rows straddling 64-bit
+    words, runs longer than a word, ragged and empty masks) against the byte
+    greedy written out above."""
+    rng = np.random.default_rng(1812 + g[0])
+    mask = (rng.random(g[0] * g[1] * g[2]) < fill).astype(np.uint8)
+    gg = np.asarray(g, dtype=np.int32)
+    out = np.zeros((mask.size + 1, 6), dtype=np.int32)
+    nb = shim.hs_merge_block_bits(gg.ctypes.data, mask.ctypes.data, maxb, out.ctypes.data, out.shape[0])
+    assert nb >= 0
+    ref = greedy_merge_reference(mask, g, maxb)
+    assert np.array_equal(out[:nb], ref)
+    cover = np.zeros(mask.size, dtype=np.int32)
+    for x0, y0, z0, x1, y1, z1 in out[:nb]:
+        for z in range(z0, z1):
+            for y in range(y0, y1):
+                cover[x0 + g[0] * (y + g[1] * z):x1 + g[0] * (y + g[1] * z)] += 1
+    assert np.array_equal(cover, mask.astype(np.int32))
 
 
 @pytest.mark.parametrize("name", sorted(HIERS))
