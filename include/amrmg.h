@@ -294,6 +294,22 @@ amrmg_status amrmg_gather(amrmg_ctx *ctx, int pos_dtype, const void *x, const vo
  * particles. */
 amrmg_status amrmg_gather_built(amrmg_ctx *ctx, double *const *E, double *Ex, double *Ey, double *Ez);
 
+/* The spatial visiting order of the particles given to the last
+ * amrmg_build_hierarchy: the order in which the deposit, the tagging passes
+ * and the gather of those particles visit them, which keeps the particles of
+ * a workgroup in a few neighbouring cells (Sec. 1's particle-mesh cycle
+ * gains from it; the order itself is this library's choice).  The particles
+ * are sorted by the Morton code of their cell on the finest level's grid
+ * (the level-0 grid refined max_level times; beyond 1024 cells per axis,
+ * cells merged 2^3 at a time), stably: particles of one cell keep their index
+ * order.  A particle outside the domain takes the nearest cell.
+ *   perm   device [n]: perm[i] = the index of the i-th particle visited
+ *   n      the build's particle count
+ * Enqueued on the context's stream.  AMRMG_E_STATE when no hierarchy is
+ * built or the build kept no order (no particles, or more than 2^31 - 1);
+ * AMRMG_E_INVALID when n differs from the build's count. */
+amrmg_status amrmg_visiting_order(amrmg_ctx *ctx, uint32_t *perm, int64_t n);
+
 /* Domain transform (Sec. 4.1 of the paper): map particles from particle
  * space S_p into the computation space S_c = [-l0,l0] x [-l1,l1] x [-l2,l2]
  * around the reference position c.  With Gamma(x, l) = max_d |x_d - c_d| /

@@ -37,7 +37,7 @@ EXPORTED = ["amrmg_default_params", "amrmg_create", "amrmg_destroy", "amrmg_last
             "amrmg_build_hierarchy", "amrmg_hierarchy_info", "amrmg_get_boxes", "amrmg_cf_faces", "amrmg_brick_tables",
             "amrmg_workspace_size", "amrmg_set_workspace", "amrmg_deposit", "amrmg_deposit_built", "amrmg_solve",
             "amrmg_solve_noalloc",
-            "amrmg_gather", "amrmg_gather_built", "amrmg_residual", "amrmg_solve_batch", "amrmg_profile_enable",
+            "amrmg_gather", "amrmg_gather_built", "amrmg_visiting_order", "amrmg_residual", "amrmg_solve_batch", "amrmg_profile_enable",
             "amrmg_profile_read", "amrmg_profile_launches", "amrmg_transform_particles", "amrmg_rescale_fields"]
 KCLASS = ["gsrb", "jacobi", "restrict", "prolong", "reflux", "cpart", "residual", "phi_update", "bottom",
           "efield", "avgdown", "deposit", "gather"]
@@ -102,6 +102,7 @@ def lib():
         L.amrmg_solve_noalloc.argtypes = [vp, vp, vp, vp, dbl, C.POINTER(amrmg_solve_stats)]
         L.amrmg_gather.argtypes = [vp, C.c_int, vp, vp, vp, i64, vp, vp, vp, vp]
         L.amrmg_gather_built.argtypes = [vp, vp, vp, vp, vp]
+        L.amrmg_visiting_order.argtypes = [vp, vp, C.c_int64]
         L.amrmg_residual.argtypes = [vp, vp, vp, vp]
         L.amrmg_solve_batch.argtypes = [vp, i32, vp, vp, dbl, C.POINTER(amrmg_solve_stats)]
         L.amrmg_profile_enable.argtypes = [vp, C.c_uint32]
@@ -277,6 +278,10 @@ def amrmg_gather_built(h, E: Sequence, Ex, Ey, Ez) -> None:
     _check(lib().amrmg_gather_built(h, _ptrs(E), Ex.data_ptr(), Ey.data_ptr(), Ez.data_ptr()))
 
 
+def amrmg_visiting_order(h, perm, n: int) -> None:
+    _check(lib().amrmg_visiting_order(h, perm.data_ptr() if n > 0 else None, int(n)))
+
+
 def amrmg_residual(h, rho: Sequence, phi: Sequence, r: Sequence) -> None:
     _check(lib().amrmg_residual(h, _ptrs(rho), _ptrs(phi), _ptrs(r)))
 
@@ -434,6 +439,13 @@ class Context:
         Ex, Ey, Ez = (torch.empty(n, dtype=torch.float64, device=x.device) for _ in range(3))
         amrmg_gather(self.h, x, y, z, E, Ex, Ey, Ez)
         return Ex, Ey, Ez
+
+    def visiting_order(self):
+        """The build's visiting order as an int64 tensor (amrmg_visiting_order)."""
+        import torch
+        perm = torch.empty(max(self.built_n, 0), dtype=torch.int32, device="cuda")
+        amrmg_visiting_order(self.h, perm, self.built_n)
+        return perm.to(torch.int64) & 0xFFFFFFFF
 
     def gather_built(self, E):
         """E at the particles of the last build_hierarchy, in their order

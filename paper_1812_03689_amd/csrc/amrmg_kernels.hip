@@ -1796,6 +1796,9 @@ __device__ __forceinline__ void wave_atomic_add(double *rho, int64_t addr, doubl
 // benchmark: deposit 8.7 -> 5.3 ms; on the levels with small buckets the
 // larger tile only costs occupancy).
 constexpr int DEP_TILE = 4096, DEP_TILE_BIG = 8192;
+// bricks whose layout a tile flush stages in LDS (a tile of 4096 cells spans
+// at most 4 x 4 x 4 bricks unless it is elongated; longer ones look up each cell)
+constexpr int DEP_BRICKS = 64;
 
 __device__ __forceinline__ void wg_minmax6(int *v, int *red)
 {
@@ -1825,12 +1828,16 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
 {
     __shared__ double acc[TILE];
     __shared__ int red[24];
+    // the caller's-layout base and strides of the bricks the tile spans
+    // (when they are at most DEP_BRICKS), looked up once per tile
+    __shared__ int64_t tub[DEP_BRICKS];
+    __shared__ int2 tus[DEP_BRICKS];
     const int64_t first = (int64_t)blockIdx.x * 256 * PPT;
     double X[PPT], Y[PPT], Z[PPT], Q[PPT];
     bool valid[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        int64_t i = first + k * 256 + threadIdx.x;
+        int64_t i = first + (int64_t)threadIdx.x * PPT + k;  // consecutive particles per thread
         valid[k] = i < n;
         int64_t p = valid[k] ? (perm ? (int64_t)perm[i] : i) : 0;
         X[k] = valid[k] ? (double)x[p] : 0.0;
@@ -1867,25 +1874,64 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
         if (vol <= TILE) {
             for (int t = threadIdx.x; t < vol; t += 256) acc[t] = 0.0;
             __syncthreads();
+            // a thread's consecutive particles with the same stencil (base
+            // cell and clamping at the level's edge) are summed in registers
+            // first: in the visiting order they often share it on the coarse
+            // levels, where the LDS atomics of a workgroup would collide
+            double cacc[8];
+            int ckey = -1;
+            auto flush = [&]() {
+                if (ckey < 0) return;
+                const int b = ckey >> 3, dx = ckey & 1, dy = (ckey >> 1) & 1, dz = (ckey >> 2) & 1;
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    atomicAdd(&acc[b + ((c & 1) ? dx : 0) + ex * (((c & 2) ? dy : 0) + ey * ((c & 4) ? dz : 0))],
+                              cacc[c]);
+            };
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 if (!ok[k]) continue;
-                const double qv = Q[k] * D.ivol;
-                for (int c = 0; c < 8; ++c) {
-                    int ii = ((c & 1) ? i1[k][0] : i0[k][0]) - bb[0];
-                    int jj = ((c & 2) ? i1[k][1] : i0[k][1]) - bb[1];
-                    int kk = ((c & 4) ? i1[k][2] : i0[k][2]) - bb[2];
-                    double w = ((c & 1) ? f[k][0] : 1.0 - f[k][0]) * ((c & 2) ? f[k][1] : 1.0 - f[k][1]) *
-                               ((c & 4) ? f[k][2] : 1.0 - f[k][2]);
-                    atomicAdd(&acc[ii + ex * (jj + ey * kk)], qv * w);
+                const int key = (((i0[k][0] - bb[0]) + ex * ((i0[k][1] - bb[1]) + ey * (i0[k][2] - bb[2]))) << 3) |
+                                (i1[k][0] - i0[k][0]) | ((i1[k][1] - i0[k][1]) << 1) | ((i1[k][2] - i0[k][2]) << 2);
+                if (key != ckey) {
+                    flush();
+                    ckey = key;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) cacc[c] = 0.0;
                 }
+                const double qv = Q[k] * D.ivol;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const double w = ((c & 1) ? f[k][0] : 1.0 - f[k][0]) * ((c & 2) ? f[k][1] : 1.0 - f[k][1]) *
+                                     ((c & 4) ? f[k][2] : 1.0 - f[k][2]);
+                    cacc[c] += qv * w;
+                }
+            }
+            flush();
+            // the tile's bricks: (bx0, by0, bz0) + (0..nbx-1, 0..nby-1, 0..nbz-1)
+            const int bx0 = bb[0] >> 3, by0 = bb[1] >> 3, bz0 = bb[2] >> 3;
+            const int nbx = (bb[3] >> 3) - bx0 + 1, nby = (bb[4] >> 3) - by0 + 1, nbz = (bb[5] >> 3) - bz0 + 1;
+            const int nbt = nbx * nby * nbz;
+            if (nbt <= DEP_BRICKS && (int)threadIdx.x < nbt) {
+                const int t = threadIdx.x, ix = t % nbx, iy = (t / nbx) % nby, iz = t / (nbx * nby);
+                const int g = D.bmap[(bx0 + ix) + D.nbk[0] * ((by0 + iy) + D.nbk[1] * (bz0 + iz))];
+                tub[t] = g >= 0 ? ubase[g] : -1;
+                tus[t] = g >= 0 ? ustr[g] : make_int2(0, 0);
             }
             __syncthreads();
             for (int t = threadIdx.x; t < vol; t += 256) {
                 double v = acc[t];
                 if (v == 0.0) continue;
-                int ii = t % ex, r = t / ex, jj = r % ey, kk = r / ey;
-                int64_t u = user_index(D, ubase, ustr, bb[0] + ii, bb[1] + jj, bb[2] + kk);
+                const int ii = bb[0] + t % ex, r = t / ex, jj = bb[1] + r % ey, kk = bb[2] + r / ey;
+                int64_t u;
+                if (nbt <= DEP_BRICKS) {
+                    const int k = ((ii >> 3) - bx0) + nbx * (((jj >> 3) - by0) + nby * ((kk >> 3) - bz0));
+                    const int64_t b = tub[k];
+                    const int2 us = tus[k];
+                    u = b < 0 ? -1 : b + (ii & 7) + (int64_t)us.x * (jj & 7) + (int64_t)us.y * (kk & 7);
+                } else {
+                    u = user_index(D, ubase, ustr, ii, jj, kk);
+                }
                 if (u >= 0) atomicAdd(A.rho[l] + u, v);
             }
             __syncthreads();

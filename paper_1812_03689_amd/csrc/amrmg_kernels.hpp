@@ -194,23 +194,21 @@ void launch_gather(hipStream_t st, int pos_f32, int64_t n, const void *x, const 
                    const int2 *ustr, double *Ex, double *Ey, double *Ez, double4 *rec, bool ordered = false);
 void launch_tag(hipStream_t st, const double *v, int64_t n, double lambda, double *scratch, uint8_t *tags);
 void launch_fill(hipStream_t st, double *v, int64_t n, double val);
-// spatial visiting order of particles (counting sort into Morton-ordered
-// buckets of the level-0 grid n0, at most 128 per axis): perm [n]; with xs,
-// also the particles in that order (xs, ys, zs in the position type, qs).
-// key, slot: [n] each (on return slot is the inverse of perm: perm[slot[p]]
-// == p); count: [2 order_count_entries], start: [order_count_entries];
-// temp: order_temp_bytes(order_count_entries) bytes
-size_t order_count_entries(const double *lo, const double *hi, const int *n0);
-// log2 of the visiting-order bucket edge in level-0 cells
-int order_bucket_shift(const double *lo, const double *hi, const int *n0);
+// spatial visiting order of the particles (stable radix sort by the
+// Morton code of their cell on a sort grid: the level-0 grid n0 refined
+// towards about four particles per cell but at most levels times, at most
+// 1024 cells per axis): perm [n] (perm[i] = the i-th particle visited) and
+// its inverse iperm [n]; scratch: order_scratch_bytes(n) bytes of device
+// memory
+size_t order_scratch_bytes(int64_t n);
+hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
+                          const double *lo, const double *hi, const int *n0, int levels, void *scratch,
+                          size_t scratch_bytes, uint32_t *perm, uint32_t *iperm);
+// log2 of the edge of a sort cell in level-0 cells (negative: finer than level 0)
+int order_cell_shift(const double *lo, const double *hi, const int *n0, int levels, int64_t n);
 // the particles in the visiting order alone: xs[i] = x[perm[i]], ...
 void launch_copy_ordered(hipStream_t st, int pos_f32, int64_t n, const uint32_t *perm, const void *x, const void *y,
                          const void *z, const double *q, void *xs, void *ys, void *zs, double *qs);
-size_t order_temp_bytes(size_t entries);
-hipError_t particle_order(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
-                          const double *q, const double *lo, const double *hi, const int *n0, uint32_t *key,
-                          uint32_t *slot, uint32_t *count, uint32_t *start, uint32_t *perm, void *temp,
-                          size_t temp_bytes, void *xs, void *ys, void *zs, double *qs);
 // proper nesting of the block marks of the finer level (g blocks per axis,
 // total = their product) against the coarse level (index extent cn, brick
 // map cbmap over cnbk bricks; half coarse cells per block edge, nesting by np

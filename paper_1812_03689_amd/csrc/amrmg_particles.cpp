@@ -17,11 +17,13 @@
 #include "amrmg_state.hpp"
 
 
-// the deposit's larger LDS tile on levels where a visiting-order bucket spans
-// 8 or more cells per axis
+// the deposit's larger LDS tile on levels where a cell of the visiting
+// order (that of the last build's particle count) spans 8 or more cells per
+// axis
 bool big_tile(const amrmg_ctx *ctx, int level)
 {
-    return order_bucket_shift(ctx->P.lo, ctx->P.hi, ctx->P.n0) + level >= 3;
+    const int64_t n = ctx->perm_n > 0 ? ctx->perm_n : 1;
+    return order_cell_shift(ctx->P.lo, ctx->P.hi, ctx->P.n0, ctx->P.max_level, n) + level >= 3;
 }
 
 DepLevel dep_level(const Problem &P, const HostLevel &L, const int32_t *bmap)
@@ -39,8 +41,9 @@ DepLevel dep_level(const Problem &P, const HostLevel &L, const int32_t *bmap)
     return D;
 }
 
-// Visiting order of the particles (Morton-ordered buckets of the level-0
-// grid); with copy, also room for the particles in that order in
+// Visiting order of the particles (sorted by the Morton code of their cell
+// on the finest level's grid) and its inverse; with copy, also room for the
+// particles in that order in
 // ctx->sorted (charges first, then x, y, z), returned through xs, ys, zs,
 // qs: the caller writes the copy (the first tagging deposit does, while it
 // reads the particles anyway, or launch_copy_ordered)
@@ -53,11 +56,9 @@ amrmg_status compute_order(amrmg_ctx *ctx, int pos_dtype, const void *x, const v
     ctx->perm_n = -1;
     if (n <= 0 || n > (int64_t)0x7fffffff) return AMRMG_OK;
     const amrmg_params &P = ctx->P;
-    const size_t entries = order_count_entries(P.lo, P.hi, P.n0);
-    HIP_TRY(ctx->sort_keys.ensure(sizeof(uint32_t) * 2 * (size_t)n));
-    HIP_TRY(ctx->sort_vals.ensure(sizeof(uint32_t) * (size_t)n));
-    HIP_TRY(ctx->sort_cnt.ensure(sizeof(uint32_t) * 3 * entries));
-    HIP_TRY(ctx->sort_tmp.ensure(order_temp_bytes(entries) + 256));
+    const size_t sb = order_scratch_bytes(n);
+    HIP_TRY(ctx->sort_scratch.ensure(sb));
+    HIP_TRY(ctx->sort_vals.ensure(sizeof(uint32_t) * 2 * (size_t)n));
     char *cx = nullptr, *cy = nullptr, *cz = nullptr;
     double *cq = nullptr;
     if (copy) {
@@ -69,12 +70,11 @@ amrmg_status compute_order(amrmg_ctx *ctx, int pos_dtype, const void *x, const v
         cy = cx + align256((size_t)n * ps);
         cz = cy + align256((size_t)n * ps);
     }
-    uint32_t *key = (uint32_t *)ctx->sort_keys.p, *cnt = (uint32_t *)ctx->sort_cnt.p;
-    HIP_TRY(particle_order(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, q, P.lo, P.hi, P.n0, key, key + n, cnt,
-                           cnt + 2 * entries, (uint32_t *)ctx->sort_vals.p, ctx->sort_tmp.p, ctx->sort_tmp.cap, nullptr,
-                           nullptr, nullptr, nullptr));
-    ctx->perm = (uint32_t *)ctx->sort_vals.p;
-    ctx->iperm = key + n;
+    uint32_t *perm = (uint32_t *)ctx->sort_vals.p;
+    HIP_TRY(particle_order(ctx->st, pos_dtype == AMRMG_POS_F32, n, x, y, z, P.lo, P.hi, P.n0, P.max_level,
+                           ctx->sort_scratch.p, ctx->sort_scratch.cap, perm, perm + n));
+    ctx->perm = perm;
+    ctx->iperm = perm + n;
     ctx->perm_n = n;
     if (copy) {
         *xs = cx;
@@ -182,6 +182,17 @@ extern "C" amrmg_status amrmg_deposit_built(amrmg_ctx *ctx, double *const *rho, 
         HIP_TRY(hipStreamSynchronize(ctx->st));
         *n_outside = (int64_t)h;
     }
+    return AMRMG_OK;
+}
+
+extern "C" amrmg_status amrmg_visiting_order(amrmg_ctx *ctx, uint32_t *perm, int64_t n)
+{
+    if (!ctx) return fail(AMRMG_E_INVALID, "ctx is NULL");
+    if (!ctx->built || ctx->perm_n < 0 || !ctx->perm) return fail(AMRMG_E_STATE, "no visiting order kept");
+    if (n != ctx->perm_n) return fail(AMRMG_E_INVALID, "n differs from the build's particle count");
+    if (n > 0 && !perm) return fail(AMRMG_E_INVALID, "perm is NULL");
+    if (n > 0)
+        HIP_TRY(hipMemcpyAsync(perm, ctx->perm, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, ctx->st));
     return AMRMG_OK;
 }
 

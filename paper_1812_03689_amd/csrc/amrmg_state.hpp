@@ -315,7 +315,7 @@ struct amrmg_ctx {
     PBuf tag_stage, tag_host;
     // spatial visiting order of the particles (a performance hint for the
     // deposit; any order gives the same sums up to rounding)
-    DBuf sort_keys, sort_vals, sort_cnt, sort_tmp;
+    DBuf sort_scratch, sort_vals;  // the sort's work space; the order and its inverse
     DBuf sorted;  // the particles of the last build in visiting order (charges, x, y, z)
     uint32_t *perm = nullptr;
     uint32_t *iperm = nullptr;  // its inverse (perm[iperm[p]] == p)
