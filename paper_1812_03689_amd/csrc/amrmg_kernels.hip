@@ -1874,40 +1874,27 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
         if (vol <= TILE) {
             for (int t = threadIdx.x; t < vol; t += 256) acc[t] = 0.0;
             __syncthreads();
-            // a thread's consecutive particles with the same stencil (base
-            // cell and clamping at the level's edge) are summed in registers
-            // first: in the visiting order they often share it on the coarse
-            // levels, where the LDS atomics of a workgroup would collide
-            double cacc[8];
-            int ckey = -1;
-            auto flush = [&]() {
-                if (ckey < 0) return;
-                const int b = ckey >> 3, dx = ckey & 1, dy = (ckey >> 1) & 1, dz = (ckey >> 2) & 1;
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    atomicAdd(&acc[b + ((c & 1) ? dx : 0) + ex * (((c & 2) ? dy : 0) + ey * ((c & 4) ? dz : 0))],
-                              cacc[c]);
-            };
+            // the 8 corners of each stencil, in an order rotated by the
+            // lane: the particles of a wavefront often share a stencil (the
+            // visiting order keeps them together), and the same corner of
+            // one cell from every lane at once would serialise the LDS
+            // atomics on one address
+            const int rot = threadIdx.x & 7;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 if (!ok[k]) continue;
-                const int key = (((i0[k][0] - bb[0]) + ex * ((i0[k][1] - bb[1]) + ey * (i0[k][2] - bb[2]))) << 3) |
-                                (i1[k][0] - i0[k][0]) | ((i1[k][1] - i0[k][1]) << 1) | ((i1[k][2] - i0[k][2]) << 2);
-                if (key != ckey) {
-                    flush();
-                    ckey = key;
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) cacc[c] = 0.0;
-                }
                 const double qv = Q[k] * D.ivol;
+                const int b = (i0[k][0] - bb[0]) + ex * ((i0[k][1] - bb[1]) + ey * (i0[k][2] - bb[2]));
+                const int ox = i1[k][0] - i0[k][0], oy = i1[k][1] - i0[k][1], oz = i1[k][2] - i0[k][2];
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    const double w = ((c & 1) ? f[k][0] : 1.0 - f[k][0]) * ((c & 2) ? f[k][1] : 1.0 - f[k][1]) *
-                                     ((c & 4) ? f[k][2] : 1.0 - f[k][2]);
-                    cacc[c] += qv * w;
+                    const int ce = (c + rot) & 7;
+                    const bool ux = ce & 1, uy = ce & 2, uz = ce & 4;
+                    const double w = (ux ? f[k][0] : 1.0 - f[k][0]) * (uy ? f[k][1] : 1.0 - f[k][1]) *
+                                     (uz ? f[k][2] : 1.0 - f[k][2]);
+                    atomicAdd(&acc[b + (ux ? ox : 0) + ex * ((uy ? oy : 0) + ey * (uz ? oz : 0))], qv * w);
                 }
             }
-            flush();
             // the tile's bricks: (bx0, by0, bz0) + (0..nbx-1, 0..nby-1, 0..nbz-1)
             const int bx0 = bb[0] >> 3, by0 = bb[1] >> 3, bz0 = bb[2] >> 3;
             const int nbx = (bb[3] >> 3) - bx0 + 1, nby = (bb[4] >> 3) - by0 + 1, nbz = (bb[5] >> 3) - bz0 + 1;

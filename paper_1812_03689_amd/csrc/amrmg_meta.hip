@@ -153,6 +153,16 @@ __device__ __forceinline__ int pool_at(const EntryDev &E, const int32_t *pool, i
     return pool[E.bmap_off + bx + E.nbk[0] * (by + E.nbk[1] * bz)];
 }
 
+// the brick maps to -1, the composite cell counts and the error flag to 0
+__global__ void __launch_bounds__(256) k_meta_clear(int64_t npool, int32_t *pool, int nent, unsigned long long *dof,
+                                                    int *err)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < npool) pool[i] = -1;
+    if (i < nent) dof[i] = 0;
+    if (i == 0) *err = 0;
+}
+
 __global__ void __launch_bounds__(256) k_meta_bricks(int nbrick, int nbox, const BoxDev *boxes, const EntryDev *ent,
                                                      int32_t *pool, int4 *org, int64_t *ubase, int2 *ustr,
                                                      int32_t *child, int32_t *par)
@@ -304,21 +314,21 @@ __global__ void __launch_bounds__(256) k_meta_reflux(int nbrick, const EntryDev 
     flag[g] = want;
 }
 
-__global__ void __launch_bounds__(256) k_meta_list(int nbrick, const uint32_t *flag, const uint32_t *roff,
-                                                   int32_t *reflux)
+// The update list (every brick with its flag set, at its scanned place),
+// and, by the first workgroup, the summary for the host: per level id (cf0,
+// ncf, rf0, nrf) and the composite cell count; then the totals (boundary
+// faces, coarse-fine faces, update list length, nesting error) and, last,
+// the sequence number seq, all in host-visible memory.  (The list's writes
+// need not be seen by the host; later kernels are ordered after this one.)
+__global__ void __launch_bounds__(256) k_meta_list_summary(int nbrick, const uint32_t *flag, int32_t *reflux, int nent,
+                                                           const EntryDev *ent, const uint64_t *off,
+                                                           const uint32_t *roff, const unsigned long long *dof,
+                                                           const int *err, int32_t *hout, int64_t *hdof,
+                                                           unsigned *hseq, unsigned seq)
 {
     const int g = blockIdx.x * 256 + threadIdx.x;
     if (g < nbrick && flag[g]) reflux[roff[g]] = g;
-}
-
-// per level id: (cf0, ncf, rf0, nrf) and the composite cell count; then the
-// totals (boundary faces, coarse-fine faces, update list length, nesting
-// error) and, last, the sequence number seq, all in host-visible memory
-__global__ void __launch_bounds__(1024) k_meta_summary(int nent, int nbrick, const EntryDev *ent, const uint64_t *off,
-                                                       const uint32_t *roff, const unsigned long long *dof,
-                                                       const int *err, int32_t *hout, int64_t *hdof,
-                                                       unsigned *hseq, unsigned seq)
-{
+    if (blockIdx.x != 0) return;
     for (int e = threadIdx.x; e < nent; e += blockDim.x) {
         const EntryDev &E = ent[e];
         const uint32_t c0 = (uint32_t)(off[E.b0] >> 32), c1 = (uint32_t)(off[E.b0 + E.nb] >> 32);
@@ -335,6 +345,8 @@ __global__ void __launch_bounds__(1024) k_meta_summary(int nent, int nbrick, con
         hout[4 * nent + 2] = (int32_t)roff[nbrick];
         hout[4 * nent + 3] = *err;
     }
+    // every writer's host-visible stores complete before the sequence number
+    if ((int)threadIdx.x < nent || threadIdx.x == 0) __threadfence_system();
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence_system();
@@ -351,10 +363,10 @@ size_t meta_scan_temp_bytes(int nbrick)
 hipError_t launch_meta_build(hipStream_t st, const MetaBuild &B)
 {
     const unsigned g1 = (unsigned)((B.nbrick + 256) / 256);  // one thread more than bricks
-    hipError_t e = hipMemsetAsync(B.pool, 0xFF, sizeof(int32_t) * B.npool, st);
-    if (e == hipSuccess) e = hipMemsetAsync(B.dof, 0, sizeof(unsigned long long) * B.nent, st);
-    if (e == hipSuccess) e = hipMemsetAsync(B.err, 0, sizeof(int), st);
-    if (e != hipSuccess) return e;
+    const int64_t nclear = B.npool > B.nent ? B.npool : B.nent;
+    hipLaunchKernelGGL(k_meta_clear, dim3((unsigned)((nclear + 256) / 256)), dim3(256), 0, st, B.npool, B.pool,
+                       B.nent, B.dof, B.err);
+    hipError_t e;
     hipLaunchKernelGGL(k_meta_bricks, dim3(g1), dim3(256), 0, st, B.nbrick, B.nbox, B.boxes, B.ent, B.pool, B.org,
                        B.ubase, B.ustr, B.child, B.par);
     hipLaunchKernelGGL(k_meta_links, dim3(g1), dim3(256), 0, st, B.nbrick, B.ent, B.pool, B.org, B.nbr, B.child,
@@ -367,9 +379,8 @@ hipError_t launch_meta_build(hipStream_t st, const MetaBuild &B)
                        B.dof, B.amr_list);
     e = exclusive_scan<uint32_t>(st, B.flag, B.roff, B.nbrick + 1, B.temp, B.temp_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_meta_list, dim3(g1), dim3(256), 0, st, B.nbrick, B.flag, B.roff, B.reflux);
-    hipLaunchKernelGGL(k_meta_summary, dim3(1), dim3(1024), 0, st, B.nent, B.nbrick, B.ent, B.off, B.roff, B.dof,
-                       B.err, B.hout, B.hdof, B.hseq, B.seq);
+    hipLaunchKernelGGL(k_meta_list_summary, dim3(g1), dim3(256), 0, st, B.nbrick, B.flag, B.reflux, B.nent, B.ent,
+                       B.off, B.roff, B.dof, B.err, B.hout, B.hdof, B.hseq, B.seq);
     return hipGetLastError();
 }
 

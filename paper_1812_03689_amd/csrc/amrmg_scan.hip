@@ -1,6 +1,7 @@
 // amrmg_scan.hip -- exclusive prefix sums of unsigned integers on the device,
-// used by the particle visiting order (bucket starts) and the brick-table
-// build (face and update-list offsets).  Two launches:
+// used by the particle visiting order (the radix sort's tile offsets) and the
+// brick-table build (face and update-list offsets).  Up to 16384 values, one
+// workgroup in one launch; beyond, two launches:
 //   1. every workgroup sums its tile of SCAN_TILE consecutive values;
 //   2. every workgroup adds the sums of all tiles before its own (read by the
 //      whole workgroup and reduced in LDS) to the exclusive scan of its tile.
@@ -75,6 +76,39 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const V *in, int64_t n, 
     }
 }
 
+// Up to SCAN_ONE values: one workgroup of 1024 threads, each scanning 16
+// consecutive values, the threads' totals scanned across the workgroup (one
+// launch instead of two: short scans are launch-bound).
+constexpr int SCAN_ONE_NT = 1024, SCAN_ONE_PER = 16, SCAN_ONE = SCAN_ONE_NT * SCAN_ONE_PER;
+
+template <class V>
+__global__ void __launch_bounds__(SCAN_ONE_NT) k_scan_one(const V *in, int64_t n, V *out)
+{
+    __shared__ V lds[SCAN_ONE_NT];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)t * SCAN_ONE_PER;
+    V v[SCAN_ONE_PER], s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ONE_PER; ++i) {
+        v[i] = base + i < n ? in[base + i] : (V)0;
+        s += v[i];
+    }
+    lds[t] = s;
+    __syncthreads();
+    for (int off = 1; off < SCAN_ONE_NT; off <<= 1) {
+        const V add = t >= off ? lds[t - off] : (V)0;
+        __syncthreads();
+        lds[t] += add;
+        __syncthreads();
+    }
+    V run = lds[t] - s;
+#pragma unroll
+    for (int i = 0; i < SCAN_ONE_PER; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+}
+
 template <class V>
 size_t scan_temp_bytes(int64_t n)
 {
@@ -85,6 +119,10 @@ template <class V>
 hipError_t exclusive_scan(hipStream_t st, const V *in, V *out, int64_t n, void *temp, size_t temp_bytes)
 {
     if (n <= 0) return hipSuccess;
+    if (n <= SCAN_ONE) {
+        hipLaunchKernelGGL((k_scan_one<V>), dim3(1), dim3(SCAN_ONE_NT), 0, st, in, n, out);
+        return hipGetLastError();
+    }
     if (!temp || temp_bytes < scan_temp_bytes<V>(n)) return hipErrorInvalidValue;
     const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (tiles > INT32_MAX) return hipErrorInvalidValue;
