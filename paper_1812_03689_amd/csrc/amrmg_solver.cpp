@@ -482,21 +482,22 @@ struct SolveTimers {
     }
 };
 
-// noalloc: the solve may allocate nothing -- no sweep tuning (the tuned or
-// the size rule's threads per brick), no graph (eager launches), the events
-// of ev_fixed
+// ev_fixed: the context's pair of timing events (made with it), or nullptr
+// (two are made for this solve).  noalloc: the solve may allocate nothing --
+// no sweep tuning (the tuned or the size rule's threads per brick), no graph
+// (eager launches), the events of ev_fixed
 template <class T>
 static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, double tol,
                               std::vector<amrmg_solve_stats> &stats, bool want_E, Prof *prof,
-                              const hipEvent_t *ev_fixed = nullptr)
+                              const hipEvent_t *ev_fixed, bool noalloc)
 {
     const Meta &m = D.meta;
     Driver<T> drv(D, st, o, prof);
     const int nr = (int)D.range_prob.size();
     const int np = (int)m.prob_ent.size();
-    const bool noalloc = ev_fixed != nullptr;
+    if (noalloc && !ev_fixed) return fail(AMRMG_E_HIP, "a solve without allocation needs the context's events");
     SolveTimers evs;
-    if (noalloc) {
+    if (ev_fixed && ev_fixed[0] && ev_fixed[1]) {
         evs.ev[0] = ev_fixed[0];
         evs.ev[1] = ev_fixed[1];
     } else {
@@ -604,8 +605,8 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
     HIP_TRY(hipGetLastError());
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
-    int cgmax = 0;
-    HIP_TRY(hipMemcpy(&cgmax, D.cgit, sizeof(int), hipMemcpyDeviceToHost));
+    int cgmax = 0;  // only a CG bottom solve counts iterations
+    if (D.n_cg > 0) HIP_TRY(hipMemcpy(&cgmax, D.cgit, sizeof(int), hipMemcpyDeviceToHost));
     stats.assign(np, amrmg_solve_stats{});
     for (int p = 0; p < np; ++p) {
         amrmg_solve_stats &s = stats[p];
@@ -680,8 +681,7 @@ static amrmg_status bind_solve_levels(amrmg_ctx *ctx, double *const *rho, double
     return AMRMG_OK;
 }
 
-static amrmg_status solve_bound(amrmg_ctx *ctx, bool want_E, double tol, amrmg_solve_stats *stats,
-                                const hipEvent_t *ev_fixed)
+static amrmg_status solve_bound(amrmg_ctx *ctx, bool want_E, double tol, amrmg_solve_stats *stats, bool noalloc)
 {
     DevState &D = ctx->ds;
     ST_TRY(set_tables(D, ctx->st));
@@ -689,8 +689,8 @@ static amrmg_status solve_bound(amrmg_ctx *ctx, bool want_E, double tol, amrmg_s
     SolveOpts o = opts_of(ctx->P);
     Prof *pf = ctx->prof.mask ? &ctx->prof : nullptr;
     amrmg_status rc = ctx->P.precision == AMRMG_MIXED
-                          ? run_solve<float>(D, ctx->st, o, tol, sv, want_E, pf, ev_fixed)
-                          : run_solve<double>(D, ctx->st, o, tol, sv, want_E, pf, ev_fixed);
+                          ? run_solve<float>(D, ctx->st, o, tol, sv, want_E, pf, ctx->ev_solve, noalloc)
+                          : run_solve<double>(D, ctx->st, o, tol, sv, want_E, pf, ctx->ev_solve, noalloc);
     if (stats && !sv.empty()) *stats = sv[0];
     if (rc == AMRMG_E_NOT_CONVERGED) (void)fail(rc, "not converged within max_iters");
     return rc;
@@ -701,7 +701,7 @@ extern "C" amrmg_status amrmg_solve(amrmg_ctx *ctx, double *const *rho, double *
 {
     ST_TRY(bind_solve_levels(ctx, rho, phi, E, tol));
     ST_TRY(ensure_ws(ctx->ds, ctx->P.precision, ctx->user_ws, ctx->user_ws_bytes));
-    return solve_bound(ctx, E != nullptr, tol, stats, nullptr);
+    return solve_bound(ctx, E != nullptr, tol, stats, false);
 }
 
 static_assert(NOALLOC_SCRATCH_BYTES == AMRMG_NOALLOC_SCRATCH_BYTES, "header and array sizes differ");
@@ -722,7 +722,7 @@ extern "C" amrmg_status amrmg_solve_noalloc(amrmg_ctx *ctx, double *const *rho, 
         return fail(AMRMG_E_OOM, "the hierarchy needs " + std::to_string(need) + " bytes of workspace; "
                                  "amrmg_solve_noalloc has " + std::to_string(NOALLOC_SCRATCH_BYTES));
     ST_TRY(ensure_ws(ctx->ds, ctx->P.precision, scr, NOALLOC_SCRATCH_BYTES));
-    return solve_bound(ctx, E != nullptr, tol, stats, ctx->ev_solve);
+    return solve_bound(ctx, E != nullptr, tol, stats, true);
 }
 
 extern "C" amrmg_status amrmg_residual(amrmg_ctx *ctx, double *const *rho, double *const *phi, double *const *r)
@@ -811,8 +811,9 @@ extern "C" amrmg_status amrmg_solve_batch(amrmg_ctx *const *ctxs, int32_t nb, do
     ST_TRY(set_tables(D, c0->st));
     std::vector<amrmg_solve_stats> sv;
     SolveOpts o = opts_of(c0->P);
-    amrmg_status rc = c0->P.precision == AMRMG_MIXED ? run_solve<float>(D, c0->st, o, tol, sv, false, nullptr)
-                                                     : run_solve<double>(D, c0->st, o, tol, sv, false, nullptr);
+    amrmg_status rc = c0->P.precision == AMRMG_MIXED
+                          ? run_solve<float>(D, c0->st, o, tol, sv, false, nullptr, c0->ev_solve, false)
+                          : run_solve<double>(D, c0->st, o, tol, sv, false, nullptr, c0->ev_solve, false);
     if (stats)
         for (int i = 0; i < nb && i < (int)sv.size(); ++i) stats[i] = sv[i];
     if (rc == AMRMG_E_NOT_CONVERGED) (void)fail(rc, "not every problem converged within max_iters");
