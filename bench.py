@@ -197,7 +197,7 @@ def bench_batch(args):
     def step():
         for c, w, (x, y, z, q), r in zip(cm, ws, data, rho):
             c.build_hierarchy(x, y, z, q, tag_rel=w.tag_rel)
-            amrmg.amrmg_deposit_built(c.h, r)
+            amrmg.amrmg_deposit_built(c.h, r, count_outside=False)
         for ph in phi:
             for t in ph:
                 t.zero_()
@@ -305,6 +305,7 @@ def bench_paper(args):
         tot = sum(sizes)
         if key not in pool or pool[key].numel() < tot:
             pool[key] = torch.empty(int(tot * 1.25) + 1, dtype=torch.float64, device=dev)
+        state[key + "_flat"] = pool[key][:tot]
         return list(torch.split(pool[key][:tot], sizes))
 
     Ex, Ey, Ez = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
@@ -319,13 +320,12 @@ def bench_paper(args):
             state["rho"] = level_views(info, "rho")
             state["phi"] = level_views(info, "phi")
             state["E"] = level_views(info, "E", 3)
-            amrmg.amrmg_deposit_built(cm.h, state["rho"])
+            amrmg.amrmg_deposit_built(cm.h, state["rho"], count_outside=False)
             built = True
         else:
-            amrmg.amrmg_deposit(cm.h, x, y, z, q, state["rho"])
+            amrmg.amrmg_deposit(cm.h, x, y, z, q, state["rho"], count_outside=False)
             built = False
-        for t in state["phi"]:
-            t.zero_()
+        state["phi_flat"].zero_()
         st = amrmg.amrmg_solve(cm.h, state["rho"], state["phi"], state["E"], w.tol)
         if built:
             amrmg.amrmg_gather_built(cm.h, state["E"], Ex, Ey, Ez)
@@ -619,16 +619,17 @@ def main():
     info = cm.build_hierarchy(x, y, z, q, tag_rel=w.tag_rel, explicit_boxes=w.explicit_boxes)
     dof = info["ndof"]
     rho = cm.level_arrays()
-    phi = cm.level_arrays()
+    # phi: views of one buffer, so that a step zeroes it in one launch
+    phi_buf = torch.zeros(sum(info["ncells"]), dtype=torch.float64, device=dev)
+    phi = list(torch.split(phi_buf, info["ncells"]))
     E = cm.level_arrays(3)
     n = x.numel()
     Ex, Ey, Ez = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
 
     def step():
         cm.build_hierarchy(x, y, z, q, tag_rel=w.tag_rel, explicit_boxes=w.explicit_boxes)
-        amrmg.amrmg_deposit_built(cm.h, rho)
-        for t in phi:
-            t.zero_()
+        amrmg.amrmg_deposit_built(cm.h, rho, count_outside=False)
+        phi_buf.zero_()
         st = amrmg.amrmg_solve(cm.h, rho, phi, E, tol)
         amrmg.amrmg_gather_built(cm.h, E, Ex, Ey, Ez)
         return st
@@ -680,11 +681,10 @@ def main():
         cm.build_hierarchy(x, y, z, q, tag_rel=w.tag_rel, explicit_boxes=w.explicit_boxes)
         torch.cuda.synchronize()
         b = time.perf_counter()
-        amrmg.amrmg_deposit_built(cm.h, rho)
+        amrmg.amrmg_deposit_built(cm.h, rho, count_outside=False)
         torch.cuda.synchronize()
         c = time.perf_counter()
-        for t in phi:
-            t.zero_()
+        phi_buf.zero_()
         amrmg.amrmg_solve(cm.h, rho, phi, E, tol)
         torch.cuda.synchronize()
         d = time.perf_counter()

@@ -233,17 +233,20 @@ def amrmg_set_workspace(h, buf) -> None:
         _check(lib().amrmg_set_workspace(h, buf.data_ptr(), buf.numel() * buf.element_size()))
 
 
-def amrmg_deposit(h, x, y, z, q, rho: Sequence) -> int:
+def amrmg_deposit(h, x, y, z, q, rho: Sequence, count_outside: bool = True) -> Optional[int]:
+    """count_outside: return the number of particles outside the domain
+    (the call then waits for the deposit); else None and no wait."""
     nout = C.c_int64()
     _check(lib().amrmg_deposit(h, _pos_dtype(x), x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(),
-                               int(q.numel()), _ptrs(rho), C.byref(nout)))
-    return nout.value
+                               int(q.numel()), _ptrs(rho), C.byref(nout) if count_outside else None))
+    return nout.value if count_outside else None
 
 
-def amrmg_deposit_built(h, rho: Sequence) -> int:
+def amrmg_deposit_built(h, rho: Sequence, count_outside: bool = True) -> Optional[int]:
+    """count_outside as in amrmg_deposit."""
     nout = C.c_int64()
-    _check(lib().amrmg_deposit_built(h, _ptrs(rho), C.byref(nout)))
-    return nout.value
+    _check(lib().amrmg_deposit_built(h, _ptrs(rho), C.byref(nout) if count_outside else None))
+    return nout.value if count_outside else None
 
 
 def amrmg_solve(h, rho: Sequence, phi: Sequence, E: Optional[Sequence], tol: float, allow_not_converged=True):
