@@ -422,7 +422,7 @@ amrmg_status upload_meta(DevState &D, hipStream_t st, const std::vector<const Pr
     D.d_E = D.d_rout + ne;
     HIP_TRY(D.h_normbuf.ensure(sizeof(double) * 2 * (D.range_prob.size() + 1)));
     D.h_norm = (double *)D.h_normbuf.p;
-    HIP_TRY(D.pubbuf.ensure(sizeof(double) * (2 * D.range_prob.size() + 8)));
+    HIP_TRY(D.pubbuf.ensure(sizeof(double) * (4 * D.range_prob.size() + 8)));
     D.h_seq = (unsigned *)D.pubbuf.p;
     D.h_pub = (double *)D.pubbuf.p + 1;
     D.ws_prec = -1;  // carve the workspace again for the new hierarchy

@@ -621,16 +621,23 @@ __global__ void __launch_bounds__(256) k_user_brick(DevMeta M, int b0, int nb, c
 // written to host-visible memory followed by a sequence number (the device
 // counter plus one, read at the start so that its latency overlaps the
 // sums), so that the host can poll for them without synchronising the
-// stream.
+// stream.  The host copy goes to hout + alt when the counter is odd: two
+// publications in a row land in different slots, so the host can still read
+// one while the next is being written.
 constexpr int NORM_CHUNK = 64;
 __global__ void __launch_bounds__(1024) k_level_norms(const int2 *ranges, int n, const double *part, double *out,
-                                                      int norm_p, double *hout, unsigned *hseq, unsigned *counter)
+                                                      int norm_p, double *hout, int alt, unsigned *hseq,
+                                                      unsigned *counter)
 {
     __shared__ double sh[16][NORM_CHUNK];
+    __shared__ unsigned sseq;
     const bool mx = norm_p == 0;
     const int wave = threadIdx.x >> 6;
     unsigned seq = 0;
-    if (hout && threadIdx.x == 0) seq = *counter;
+    if (hout && threadIdx.x == 0) {
+        seq = *counter;
+        sseq = seq;
+    }
     for (int l0 = 0; l0 < n; l0 += NORM_CHUNK) {
         const int nl = n - l0 < NORM_CHUNK ? n - l0 : NORM_CHUNK;
         for (int j = 0; j < nl; ++j) {
@@ -661,7 +668,7 @@ __global__ void __launch_bounds__(1024) k_level_norms(const int2 *ranges, int n,
             r = norm_p == 2 ? sqrt(r) : r;
             out[l0 + j] = r;
             if (hout) {
-                hout[l0 + j] = r;
+                hout[(sseq & 1u) * alt + l0 + j] = r;
                 __threadfence_system();
             }
         }
@@ -2243,10 +2250,11 @@ void launch_user_brick(hipStream_t st, const DevMeta &M, int b0, int nb, const i
 }
 
 void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double *part, double *out, int norm_p,
-                        double *hout, unsigned *hseq, unsigned *counter)
+                        double *hout, int alt, unsigned *hseq, unsigned *counter)
 {
     if (n <= 0) return;
-    AMRMG_LAUNCH(k_level_norms, dim3(1), dim3(1024), 0, st, ranges, n, part, out, norm_p, hout, hseq, counter);
+    AMRMG_LAUNCH(k_level_norms, dim3(1), dim3(1024), 0, st, ranges, n, part, out, norm_p, hout, alt, hseq,
+                 counter);
 }
 
 template <class T>

@@ -116,9 +116,10 @@ void launch_outer_residual(hipStream_t st, const DevMeta &M, int b0, int nb, con
 void launch_user_brick(hipStream_t st, const DevMeta &M, int b0, int nb, const int32_t *list, bool to_brick,
                        double *const *a, double *ab, double *const *bu, double *bb);
 // per-range norms into out (device); with hout, also into host-visible
-// memory followed by the sequence number *counter + 1 at hseq
+// memory (at hout + alt when *counter is odd) followed by the sequence number
+// *counter + 1 at hseq
 void launch_level_norms(hipStream_t st, const int2 *ranges, int n, const double *part, double *out, int norm_p,
-                        double *hout = nullptr, unsigned *hseq = nullptr, unsigned *counter = nullptr);
+                        double *hout = nullptr, int alt = 0, unsigned *hseq = nullptr, unsigned *counter = nullptr);
 // coarse parts cp of the ghosts of coarse-fine faces [cf0, cf0 + ncf) from
 // the coarse values src; with ffs, also the fine sums from the fine values
 template <class T>

@@ -120,6 +120,9 @@ extern "C" amrmg_status amrmg_set_workspace(amrmg_ctx *ctx, void *dev, size_t by
 // ---------------------------------------------------------------------------
 // replay the outer iteration as a hipGraph (AMRMG_NO_GRAPH=1 disables)
 static bool g_use_graphs = getenv("AMRMG_NO_GRAPH") == nullptr;
+// an outer iteration is queued one ahead while the residual is this many
+// times above its target (a cycle reduces it by far less than this factor)
+constexpr double kAhead = 100.0;
 
 // Workgroup shape of the sweep kernel (one wavefront per brick, 1, 2 or 4
 // bricks per workgroup), tuned on the device: for each launch size class
@@ -246,8 +249,10 @@ struct Driver {
     }
 
     // outer FP64 residual of every AMR level; norms into dnorm[off ..] (and
-    // published to the host at h_pub[pub_off ..] when publish is set)
-    void outer(bool zero_phi, int noff, double *const *rout_user, bool publish = false, int pub_off = 0)
+    // published to the host at h_pub[pub_off ..] when publish is set, or
+    // pub_alt further on when the publication's sequence number is even)
+    void outer(bool zero_phi, int noff, double *const *rout_user, bool publish = false, int pub_off = 0,
+               int pub_alt = 0)
     {
         int b0, nb;
         const int32_t *list;
@@ -265,7 +270,7 @@ struct Driver {
                                  (zero_phi || rout_user) ? nullptr : r, D.part, o.norm_p, zero_phi, rout_user, D.ffs);
         pe(AMRMG_K_RESIDUAL, (double)nb * BRICK_CELLS * (zero_phi ? 8.0 : 16.0 + W));
         launch_level_norms(st, D.d_ranges, (int)D.range_prob.size(), D.part, D.dnorm + noff, o.norm_p,
-                           publish ? D.h_pub + pub_off : nullptr, D.h_seq, D.d_seqc);
+                           publish ? D.h_pub + pub_off : nullptr, pub_alt, D.h_seq, D.d_seqc);
     }
 
     void smooth(int k, int nu, bool pre)
@@ -421,10 +426,11 @@ struct Driver {
     }
 
     // one outer iteration: V-cycle, phi += e, FP64 residual and its norms
+    // (published to h_pub[2 nr ..] or h_pub[3 nr ..] in turn)
     void iteration(int nr)
     {
         vcycle();
-        outer(false, nr, nullptr, true);
+        outer(false, nr, nullptr, true, 2 * nr, nr);
     }
 };
 
@@ -516,7 +522,8 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
     *(volatile unsigned *)D.h_seq = 0;
     HIP_TRY(hipEventRecord(ev0, st));
     // norms of b (zero phi) to h_pub[nr ..], of the initial residual to
-    // h_pub[0 ..]; each publication bumps the sequence number
+    // h_pub[0 ..]; each publication bumps the sequence number, and those of
+    // the iterations alternate between two slots after these
     drv.to_bricks(true);
     drv.outer(true, 0, nullptr, true, nr);
     drv.outer(false, nr, nullptr, true, 0);
@@ -568,20 +575,54 @@ static amrmg_status run_solve(DevState &D, hipStream_t st, const SolveOpts &o, d
         }
         return all;
     };
-    int it = 0;
+    // the least converged level's residual in units of its target
+    auto worst = [&]() {
+        double w = 0.0;
+        for (int i = 0; i < nr; ++i) {
+            const double lim = tol * bn[i];
+            w = std::max(w, lim > 0.0 ? rn[i] / lim : (rn[i] > 0.0 ? HUGE_VAL : 0.0));
+        }
+        return w;
+    };
+    // the norms of the iteration whose publication was the last awaited
+    // (sequence numbers 3, 5, ... in h_pub[2 nr ..], 4, 6, ... in h_pub[3 nr ..])
+    auto read_iter = [&]() {
+        const double *src = D.h_pub + (2 + (D.seq & 1u ? 0 : 1)) * nr;
+        rn.assign(src, src + nr);
+    };
+    int it = 0, queued = first_queued ? 1 : 0;
     bool all = check(0);
     if (first_queued) {
         ST_TRY(wait_pub(++D.seq));
-        rn.assign(D.h_pub, D.h_pub + nr);
+        read_iter();
         it = 1;
         if (!all) all = check(1);
     }
     while (!all && it < o.max_iters) {
-        ST_TRY(iterate<T>(D, drv, st, nr, o, graphs));
+        if (queued == it) {
+            ST_TRY(iterate<T>(D, drv, st, nr, o, graphs));
+            ++queued;
+        }
+        // While the last norms lie more than kAhead times above the target,
+        // the iteration already queued cannot reach it (a V-cycle reduces
+        // the residual about tenfold), so the one after it will run too:
+        // queue it now, and the GPU does not wait for the host between them.
+        if (queued == it + 1 && queued < o.max_iters && worst() > kAhead) {
+            ST_TRY(iterate<T>(D, drv, st, nr, o, graphs));
+            ++queued;
+        }
         ST_TRY(wait_pub(++D.seq));
-        rn.assign(D.h_pub, D.h_pub + nr);
+        read_iter();
         ++it;
         all = check(it);
+    }
+    // an iteration queued beyond the last one read runs all the same: its
+    // norms are the solve's
+    while (it < queued) {
+        ST_TRY(wait_pub(++D.seq));
+        read_iter();
+        ++it;
+        all = check(it) || all;
     }
     // average down, finest first, then the field
     for (int k = m.K - 1; k >= 1; --k)
