@@ -1771,6 +1771,71 @@ __device__ __forceinline__ int64_t user_index(const DepLevel &D, const int64_t *
     return ubase[g] + (i & 7) + (int64_t)s.x * (j & 7) + (int64_t)s.y * (k & 7);
 }
 
+// Corners of a CIC stencil: bit d of c selects the upper cell along axis d;
+// st[d]: the stencil crosses a brick face along d.  A corner is "fresh"
+// when every upper axis of it crosses, so that its brick differs from the
+// bricks of the corners below it; spread_corners copies the value of each
+// fresh corner to the corners in the same brick (the bits of axes without a
+// crossing cleared), with fixed indices only.
+__device__ __forceinline__ bool corner_fresh(int c, const bool *st)
+{
+    return (!(c & 1) || st[0]) && (!(c & 2) || st[1]) && (!(c & 4) || st[2]);
+}
+
+template <class V>
+__device__ __forceinline__ void spread_corners(const bool *st, V *v)
+{
+    v[1] = st[0] ? v[1] : v[0];
+    v[2] = st[1] ? v[2] : v[0];
+    v[3] = st[1] ? (st[0] ? v[3] : v[2]) : v[1];
+    v[4] = st[2] ? v[4] : v[0];
+    v[5] = st[2] ? (st[0] ? v[5] : v[4]) : v[1];
+    v[6] = st[2] ? (st[1] ? v[6] : v[4]) : v[2];
+    v[7] = st[2] ? (st[1] ? (st[0] ? v[7] : v[6]) : v[5]) : v[3];
+}
+
+// Caller's-layout index of each corner of the CIC stencil (i0, i1) on level
+// D, -1 outside the level's boxes or for every corner when !ok.  Each
+// distinct brick of the stencil is looked up once (at most two per axis),
+// every lookup issued before any is used.
+__device__ __forceinline__ void corner_addresses(const DepLevel &D, const int64_t *ubase, const int2 *ustr, bool ok,
+                                                 const int *i0, const int *i1, int64_t (&u)[8])
+{
+    const bool st[3] = {(i0[0] >> 3) != (i1[0] >> 3), (i0[1] >> 3) != (i1[1] >> 3), (i0[2] >> 3) != (i1[2] >> 3)};
+    int g[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        g[c] = -1;
+        if (ok && corner_fresh(c, st)) {
+            const int bx = ((c & 1) ? i1[0] : i0[0]) >> 3, by = ((c & 2) ? i1[1] : i0[1]) >> 3,
+                      bz = ((c & 4) ? i1[2] : i0[2]) >> 3;
+            g[c] = D.bmap[bx + D.nbk[0] * (by + D.nbk[1] * bz)];
+        }
+    }
+    spread_corners(st, g);
+    int64_t ub[8];
+    int usx[8], usy[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        ub[c] = 0;
+        usx[c] = usy[c] = 0;
+        if (corner_fresh(c, st) && g[c] >= 0) {
+            ub[c] = ubase[g[c]];
+            const int2 s2 = ustr[g[c]];
+            usx[c] = s2.x;
+            usy[c] = s2.y;
+        }
+    }
+    spread_corners(st, ub);
+    spread_corners(st, usx);
+    spread_corners(st, usy);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int ii = (c & 1) ? i1[0] : i0[0], jj = (c & 2) ? i1[1] : i0[1], kk = (c & 4) ? i1[2] : i0[2];
+        u[c] = g[c] < 0 ? -1 : ub[c] + (ii & 7) + (int64_t)usx[c] * (jj & 7) + (int64_t)usy[c] * (kk & 7);
+    }
+}
+
 // Add v to rho[addr] for every active lane (addr >= 0), combining lanes of
 // the wavefront that share an address: up to 8 distinct addresses are summed
 // across the wavefront and issued as one atomic each by their first lane; the
@@ -1930,18 +1995,20 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
             }
             __syncthreads();
         } else {
+            // the stencils span more than the tile (sparse particles): each
+            // particle adds its corners with global atomics, their addresses
+            // found first with every table load in flight together
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const double qv = ok[k] ? Q[k] * D.ivol : 0.0;
+                int64_t u[8];
+                corner_addresses(D, ubase, ustr, ok[k], i0[k], i1[k], u);
                 // all lanes stay in the loop: the combination uses wavefront shuffles
+#pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    int ii = (c & 1) ? i1[k][0] : i0[k][0];
-                    int jj = (c & 2) ? i1[k][1] : i0[k][1];
-                    int kk = (c & 4) ? i1[k][2] : i0[k][2];
                     double w = ((c & 1) ? f[k][0] : 1.0 - f[k][0]) * ((c & 2) ? f[k][1] : 1.0 - f[k][1]) *
                                ((c & 4) ? f[k][2] : 1.0 - f[k][2]);
-                    int64_t u = ok[k] ? user_index(D, ubase, ustr, ii, jj, kk) : -1;
-                    wave_atomic_add(A.rho[l], u, qv * w);
+                    wave_atomic_add(A.rho[l], u[c], qv * w);
                 }
             }
         }
@@ -1952,29 +2019,6 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
 // alignment is enough for a global load on CDNA).
 typedef double dpair __attribute__((ext_vector_type(2)));
 typedef dpair dpair_a8 __attribute__((aligned(8)));
-
-// Corners of a CIC stencil: bit d of c selects the upper cell along axis d;
-// st[d]: the stencil crosses a brick face along d.  A corner is "fresh"
-// when every upper axis of it crosses, so that its brick differs from the
-// bricks of the corners below it; spread_corners copies the value of each
-// fresh corner to the corners in the same brick (the bits of axes without a
-// crossing cleared), with fixed indices only.
-__device__ __forceinline__ bool corner_fresh(int c, const bool *st)
-{
-    return (!(c & 1) || st[0]) && (!(c & 2) || st[1]) && (!(c & 4) || st[2]);
-}
-
-template <class V>
-__device__ __forceinline__ void spread_corners(const bool *st, V *v)
-{
-    v[1] = st[0] ? v[1] : v[0];
-    v[2] = st[1] ? v[2] : v[0];
-    v[3] = st[1] ? (st[0] ? v[3] : v[2]) : v[1];
-    v[4] = st[2] ? v[4] : v[0];
-    v[5] = st[2] ? (st[0] ? v[5] : v[4]) : v[1];
-    v[6] = st[2] ? (st[1] ? v[6] : v[4]) : v[2];
-    v[7] = st[2] ? (st[1] ? (st[0] ? v[7] : v[6]) : v[5]) : v[3];
-}
 
 // E at every particle from the finest level whose boxes hold all 8 cells of
 // its CIC stencil; particles are visited in the given (spatially sorted)
