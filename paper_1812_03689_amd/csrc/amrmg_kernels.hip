@@ -934,8 +934,14 @@ __global__ void __launch_bounds__(64 * BPW) k_hgs(DevMeta M, int b0, int nb, con
             er[2 * k + 1] = (T)((double)er[2 * k + 1] + (double)pv);
         }
     }
+    // x-neighbours held by the previous or the next wavefront of the
+    // workgroup (bricks are numbered x-fastest within a box): their starting
+    // values are the rows those wavefronts put in LDS, read from there below
+    // instead of from memory
+    const bool lx_m = BPW > 1 && w > 0 && kind[0] == 0 && nbf[0] == b - 1;
+    const bool lx_p = BPW > 1 && w + 1 < BPW && k0 + 1 < nb && kind[1] == 0 && nbf[1] == b + 1;
 #pragma unroll
-    for (int f = 0; f < 6; ++f) hs[f] = slot(f, lane);
+    for (int f = 0; f < 6; ++f) hs[f] = (f == 0 && lx_m) || (f == 1 && lx_p) ? (T)0 : slot(f, lane);
     const LevelConst L = M.lc[M.org[b].w];
     const T ih2x = (T)L.ih2[0], ih2y = (T)L.ih2[1], ih2z = (T)L.ih2[2];
     const int rym = rrow(y - 1, z), ryp = rrow(y + 1, z), rzm = rrow(y, z - 1), rzp = rrow(y, z + 1), rme = rrow(y, z);
@@ -946,7 +952,7 @@ __global__ void __launch_bounds__(64 * BPW) k_hgs(DevMeta M, int b0, int nb, con
     rows[rrow(8, lane >> 3) + (lane & 7)] = hs[3];
     rows[rrow(lane >> 3, -1) + (lane & 7)] = hs[4];
     rows[rrow(lane >> 3, 8) + (lane & 7)] = hs[5];
-    const T hxm = hs[0], hxp = hs[1];
+    T hxm = hs[0], hxp = hs[1];
     // ghost coefficients a of the faces, and per row the weights that fold a
     // coarse-fine ghost's -u_in/5 into the neighbour inside
     const T cf5 = (T)0.2;
@@ -961,6 +967,12 @@ __global__ void __launch_bounds__(64 * BPW) k_hgs(DevMeta M, int b0, int nb, con
     const T den = ih2y * ((T)2 - aym - ayp) + ih2z * ((T)2 - azm - azp) + (T)2 * ih2x;
     const T inv_mid = (T)1 / den, inv_x0 = (T)1 / (den - ih2x * ag[0]), inv_x7 = (T)1 / (den - ih2x * ag[1]);
     __syncthreads();
+    if (BPW > 1) {
+        // the neighbours' rows are read before any wavefront starts updating its own
+        if (lx_m) hxm = rows_all[w - 1][rme + 7];
+        if (lx_p) hxp = rows_all[w + 1][rme];
+        __syncthreads();
+    }
     // red (colour 0) then black: cell x of row (y, z) has colour (x + y + z)
     // & 1, so in each pair of cells (2k, 2k + 1) of the row exactly one
     // takes part in a pass, the one at x = 2k + p with p = (y + z + pass) &
