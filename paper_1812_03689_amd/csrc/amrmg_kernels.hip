@@ -641,19 +641,31 @@ __global__ void __launch_bounds__(1024) k_level_norms(const int2 *ranges, int n,
     for (int l0 = 0; l0 < n; l0 += NORM_CHUNK) {
         const int nl = n - l0 < NORM_CHUNK ? n - l0 : NORM_CHUNK;
         for (int j = 0; j < nl; ++j) {
+            // the range's partials as pairs (two per brick, 16-byte aligned):
+            // pair q of the range to thread q mod 1024, eight pairs in flight
             const int2 rg = ranges[l0 + j];
-            const int b0 = 2 * rg.x, b1 = 2 * (rg.x + rg.y);
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            int b = b0 + (int)threadIdx.x;
-            for (; b + 3 * 1024 < b1; b += 4 * 1024) {
-                double v0 = part[b], v1 = part[b + 1024], v2 = part[b + 2048], v3 = part[b + 3072];
-                a0 = mx ? fmax(a0, v0) : a0 + v0;
-                a1 = mx ? fmax(a1, v1) : a1 + v1;
-                a2 = mx ? fmax(a2, v2) : a2 + v2;
-                a3 = mx ? fmax(a3, v3) : a3 + v3;
+            const double2 *pp = (const double2 *)part + rg.x;
+            const int np = rg.y;
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = 0.0;
+            int q = (int)threadIdx.x;
+            for (; q + 7 * 1024 < np; q += 8 * 1024) {
+                double2 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = pp[q + u * 1024];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] = mx ? fmax(a[u], fmax(v[u].x, v[u].y)) : a[u] + (v[u].x + v[u].y);
             }
-            for (; b < b1; b += 1024) a0 = mx ? fmax(a0, part[b]) : a0 + part[b];
-            double acc = mx ? fmax(fmax(a0, a1), fmax(a2, a3)) : (a0 + a1) + (a2 + a3);
+            {  // the last fewer than eight pairs of this thread, also in flight together (partials are >= 0)
+                double2 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = q + u * 1024 < np ? pp[q + u * 1024] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] = mx ? fmax(a[u], fmax(v[u].x, v[u].y)) : a[u] + (v[u].x + v[u].y);
+            }
+            double acc = mx ? fmax(fmax(fmax(a[0], a[1]), fmax(a[2], a[3])), fmax(fmax(a[4], a[5]), fmax(a[6], a[7])))
+                            : ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
             for (int o = 32; o > 0; o >>= 1) {
                 double w = __shfl_xor(acc, o, 64);
                 acc = mx ? fmax(acc, w) : acc + w;
