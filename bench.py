@@ -135,7 +135,7 @@ def write_kernel_stats(args):
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
     with open(out_md, "w") as f:
         f.write(f"# rocprofv3 kernel statistics: bench.py, workload {tag}\n\n")
-        f.write("Command (from the repository root on the GPU box, `cd /tmp && export TMPDIR=/tmp` first):\n\n")
+        f.write("Command (from the repository root, `cd /tmp && export TMPDIR=/tmp` first):\n\n")
         f.write("```\n" + args.traffic_cmd.replace(";", "\n") + "\n```\n\n")
         f.write(f"- kernel source sha256: `{kernel_source_hash()}`\n\n")
         f.write("Per-kernel totals over the whole run (durations in microseconds):\n\n")
