@@ -1895,6 +1895,18 @@ constexpr int DEP_TILE = 4096, DEP_TILE_BIG = 8192;
 // bricks whose layout a tile flush stages in LDS (a tile of 4096 cells spans
 // at most 4 x 4 x 4 bricks unless it is elongated; longer ones look up each cell)
 constexpr int DEP_BRICKS = 64;
+// particles from which a deposit launch takes the per-wavefront tile passes
+constexpr int64_t DEP_WAVES_MIN = (int64_t)4 << 20;
+
+// v[0..2] minima, v[3..5] maxima over the wavefront
+__device__ __forceinline__ void wave_minmax6(int *v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        for (int a = 0; a < 6; ++a) {
+            int w = __shfl_xor(v[a], o, 64);
+            v[a] = a < 3 ? min(v[a], w) : max(v[a], w);
+        }
+}
 
 __device__ __forceinline__ void wg_minmax6(int *v, int *red)
 {
@@ -1916,7 +1928,7 @@ __device__ __forceinline__ void wg_minmax6(int *v, int *red)
     __syncthreads();
 }
 
-template <class P, int PPT, int TILE>
+template <class P, int PPT, int TILE, bool WAVES>
 __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P *y, const P *z, const double *q,
                                                  const uint32_t *perm, DepArgs A, const int64_t *ubase,
                                                  const int2 *ustr, unsigned long long *nout, P *xs, P *ys, P *zs,
@@ -1928,6 +1940,7 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
     // (when they are at most DEP_BRICKS), looked up once per tile
     __shared__ int64_t tub[DEP_BRICKS];
     __shared__ int2 tus[DEP_BRICKS];
+    __shared__ int wbox[4][6];  // the wavefronts' boxes when the workgroup's exceeds the tile
     const int64_t first = (int64_t)blockIdx.x * 256 * PPT;
     double X[PPT], Y[PPT], Z[PPT], Q[PPT];
     bool valid[PPT];
@@ -1963,11 +1976,18 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
                     bb[3 + d] = max(bb[3 + d], i1[k][d]);
                 }
         }
+        // this lane's own bounds, kept for the wavefront boxes below
+        int lb[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) lb[a] = bb[a];
         wg_minmax6(bb, red);
         if (bb[0] > bb[3]) continue;  // no particle of the workgroup inside the domain
-        const int ex = bb[3] - bb[0] + 1, ey = bb[4] - bb[1] + 1, ez = bb[5] - bb[2] + 1;
-        const int64_t vol = (int64_t)ex * ey * ez;
-        if (vol <= TILE) {
+        // One pass through the LDS tile over the box tb of cells: clear, add
+        // the stencils of the taking part lanes' particles (mine), add the
+        // tile's nonzero cells to rho.  Every thread of the workgroup runs it.
+        auto tile_pass = [&](const int *tb, bool mine) {
+            const int ex = tb[3] - tb[0] + 1, ey = tb[4] - tb[1] + 1, ez = tb[5] - tb[2] + 1;
+            const int vol = ex * ey * ez;
             for (int t = threadIdx.x; t < vol; t += 256) acc[t] = 0.0;
             __syncthreads();
             // the 8 corners of each stencil, in an order rotated by the
@@ -1978,9 +1998,9 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
             const int rot = threadIdx.x & 7;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                if (!ok[k]) continue;
+                if (!mine || !ok[k]) continue;
                 const double qv = Q[k] * D.ivol;
-                const int b = (i0[k][0] - bb[0]) + ex * ((i0[k][1] - bb[1]) + ey * (i0[k][2] - bb[2]));
+                const int b = (i0[k][0] - tb[0]) + ex * ((i0[k][1] - tb[1]) + ey * (i0[k][2] - tb[2]));
                 const int ox = i1[k][0] - i0[k][0], oy = i1[k][1] - i0[k][1], oz = i1[k][2] - i0[k][2];
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
@@ -1992,8 +2012,8 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
                 }
             }
             // the tile's bricks: (bx0, by0, bz0) + (0..nbx-1, 0..nby-1, 0..nbz-1)
-            const int bx0 = bb[0] >> 3, by0 = bb[1] >> 3, bz0 = bb[2] >> 3;
-            const int nbx = (bb[3] >> 3) - bx0 + 1, nby = (bb[4] >> 3) - by0 + 1, nbz = (bb[5] >> 3) - bz0 + 1;
+            const int bx0 = tb[0] >> 3, by0 = tb[1] >> 3, bz0 = tb[2] >> 3;
+            const int nbx = (tb[3] >> 3) - bx0 + 1, nby = (tb[4] >> 3) - by0 + 1, nbz = (tb[5] >> 3) - bz0 + 1;
             const int nbt = nbx * nby * nbz;
             if (nbt <= DEP_BRICKS && (int)threadIdx.x < nbt) {
                 const int t = threadIdx.x, ix = t % nbx, iy = (t / nbx) % nby, iz = t / (nbx * nby);
@@ -2005,7 +2025,7 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
             for (int t = threadIdx.x; t < vol; t += 256) {
                 double v = acc[t];
                 if (v == 0.0) continue;
-                const int ii = bb[0] + t % ex, r = t / ex, jj = bb[1] + r % ey, kk = bb[2] + r / ey;
+                const int ii = tb[0] + t % ex, r = t / ex, jj = tb[1] + r % ey, kk = tb[2] + r / ey;
                 int64_t u;
                 if (nbt <= DEP_BRICKS) {
                     const int k = ((ii >> 3) - bx0) + nbx * (((jj >> 3) - by0) + nby * ((kk >> 3) - bz0));
@@ -2018,22 +2038,49 @@ __global__ void __launch_bounds__(256) k_deposit(int64_t n, const P *x, const P 
                 if (u >= 0) atomicAdd(A.rho[l] + u, v);
             }
             __syncthreads();
-        } else {
-            // the stencils span more than the tile (sparse particles): each
-            // particle adds its corners with global atomics, their addresses
-            // found first with every table load in flight together
+        };
+        const int64_t vol = (int64_t)(bb[3] - bb[0] + 1) * (bb[4] - bb[1] + 1) * (bb[5] - bb[2] + 1);
+        if (vol <= TILE) {
+            tile_pass(bb, true);
+            continue;
+        }
+        // The stencils span more than the tile (sparse particles).  With
+        // WAVES the wavefronts take the tile in turn, each over the box of its
+        // own particles.  A wavefront whose box still exceeds the tile (every
+        // wavefront without WAVES) adds each corner with a global atomic, the
+        // addresses found first with every table load in flight together.
+        bool sparse = true;
+        if (WAVES) {
+            wave_minmax6(lb);
+            const int wave = threadIdx.x >> 6;
+            if ((threadIdx.x & 63) == 0)
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const double qv = ok[k] ? Q[k] * D.ivol : 0.0;
-                int64_t u[8];
-                corner_addresses(D, ubase, ustr, ok[k], i0[k], i1[k], u);
-                // all lanes stay in the loop: the combination uses wavefront shuffles
+                for (int a = 0; a < 6; ++a) wbox[wave][a] = lb[a];
+            __syncthreads();
+            sparse = false;  // this wavefront's box exceeds the tile too
+#pragma unroll 1
+            for (int wv = 0; wv < 4; ++wv) {
+                int tb[6];
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    double w = ((c & 1) ? f[k][0] : 1.0 - f[k][0]) * ((c & 2) ? f[k][1] : 1.0 - f[k][1]) *
-                               ((c & 4) ? f[k][2] : 1.0 - f[k][2]);
-                    wave_atomic_add(A.rho[l], u[c], qv * w);
-                }
+                for (int a = 0; a < 6; ++a) tb[a] = wbox[wv][a];
+                if (tb[0] > tb[3]) continue;  // no particle of that wavefront inside the domain
+                const int64_t wvol = (int64_t)(tb[3] - tb[0] + 1) * (tb[4] - tb[1] + 1) * (tb[5] - tb[2] + 1);
+                if (wvol <= TILE) tile_pass(tb, wave == wv);
+                else if (wave == wv) sparse = true;
+            }
+        }
+        if (!sparse) continue;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const double qv = ok[k] ? Q[k] * D.ivol : 0.0;
+            int64_t u[8];
+            corner_addresses(D, ubase, ustr, ok[k], i0[k], i1[k], u);
+            // all lanes stay in the loop: the combination uses wavefront shuffles
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                double w = ((c & 1) ? f[k][0] : 1.0 - f[k][0]) * ((c & 2) ? f[k][1] : 1.0 - f[k][1]) *
+                           ((c & 4) ? f[k][2] : 1.0 - f[k][2]);
+                wave_atomic_add(A.rho[l], u[c], qv * w);
             }
         }
     }
@@ -2409,12 +2456,23 @@ static void launch_deposit_tile(hipStream_t st, unsigned g, bool big, int64_t n,
                                 const int64_t *ubase, const int2 *ustr, unsigned long long *nout, void *xs, void *ys,
                                 void *zs, double *qs)
 {
-    if (big)
-        AMRMG_LAUNCH((k_deposit<P, PPT, DEP_TILE_BIG>), dim3(g), dim3(256), 0, st, n, (const P *)x, (const P *)y,
-                     (const P *)z, q, perm, A, ubase, ustr, nout, (P *)xs, (P *)ys, (P *)zs, qs);
-    else
-        AMRMG_LAUNCH((k_deposit<P, PPT, DEP_TILE>), dim3(g), dim3(256), 0, st, n, (const P *)x, (const P *)y,
-                     (const P *)z, q, perm, A, ubase, ustr, nout, (P *)xs, (P *)ys, (P *)zs, qs);
+    // the per-wavefront tile passes for sparse workgroups: measured faster
+    // with 9e6 and 1e7 particles (128^3 + 2 and + 3 levels: deposit -10 %
+    // and -5 %), slower with 1e6 (64^3 + 2: +3 %, and +15 us in the build),
+    // where a launch is a few rounds of workgroups and the serial passes of
+    // the sparse ones lengthen it
+    const bool waves = n >= DEP_WAVES_MIN;
+#define AMRMG_DEPOSIT(TL, WV)                                                                                     \
+    AMRMG_LAUNCH((k_deposit<P, PPT, TL, WV>), dim3(g), dim3(256), 0, st, n, (const P *)x, (const P *)y,            \
+                 (const P *)z, q, perm, A, ubase, ustr, nout, (P *)xs, (P *)ys, (P *)zs, qs)
+    if (big) {
+        if (waves) AMRMG_DEPOSIT(DEP_TILE_BIG, true);
+        else AMRMG_DEPOSIT(DEP_TILE_BIG, false);
+    } else {
+        if (waves) AMRMG_DEPOSIT(DEP_TILE, true);
+        else AMRMG_DEPOSIT(DEP_TILE, false);
+    }
+#undef AMRMG_DEPOSIT
 }
 
 void launch_deposit(hipStream_t st, int pos_f32, int64_t n, const void *x, const void *y, const void *z,
