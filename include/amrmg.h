@@ -113,7 +113,11 @@ typedef struct amrmg_params {
 
 /* Per-solve statistics. */
 typedef struct amrmg_solve_stats {
-    int32_t iters;              /* V-cycles performed */
+    int32_t iters;              /* V-cycles until every level met the tolerance (the
+                                   cycles run when not converged); phi and rel_residual
+                                   are those after the last cycle run, which can be a
+                                   later one in a batch, or when a cycle queued ahead
+                                   of the norms that stopped the solve ran as well */
     int32_t converged;          /* 1 when every level met the tolerance */
     int32_t nlevels;
     int32_t bottom_iters_max;   /* largest CG iteration count of one bottom solve */
