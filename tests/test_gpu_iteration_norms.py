@@ -59,10 +59,9 @@ def test_reported_norms_are_those_of_the_returned_phi(precision, max_iters):
     mine = rn / b
     print("reported", rep, "from phi", mine, "iters", st["iters"], flush=True)
     assert np.all(b > 0)
-    # the returned phi is the last iterate with its covered coarse cells set
-    # to the mean of their fine cells, which moves the residual of uncovered
-    # cells by rounding only: about 1e-17 relative to |b|, visible once the
-    # relative residual itself is near 1e-11
+    # two evaluations of the residual of one phi (the solve's last one and
+    # amrmg_residual's) agree to rounding, about 1e-17 relative to |b| here,
+    # which shows once the relative residual itself is near 1e-11
     np.testing.assert_allclose(rep, mine, rtol=1e-9, atol=1e-15)
     if converged:
         assert np.all(rep <= tol)
